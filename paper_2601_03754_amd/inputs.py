@@ -1,0 +1,125 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module holds input recipes only: it draws random blocks and assembles
+no part of the factorization or solve.  Both the GPU library's tests and
+benchmark and the CPU oracle's tests draw their inputs from here, so the two
+sides see identical bytes for a given seed.
+
+Recipe (the block-tridiagonal matrix of the section "Sequential Cholesky
+Factorization"; the paper never states how its own test matrices were drawn):
+    rng = numpy.random.default_rng(seed)          # PCG64
+    G   = rng.standard_normal((N, n, n))
+    D_i = G_i G_i^T / n + c I                      # symmetric positive definite
+    E   = rng.standard_normal((N-1, n, n)) / sqrt(n)
+    B   = rng.standard_normal((N, n, nrhs))
+With c = 4 the whole matrix is positive definite with a margin of about 1.3-1.7
+(smallest eigenvalue) for every shape used here.  For the conditioning sweep
+the shift is read as a spectral margin (``margin=True``): the identity shift is
+chosen so that the smallest eigenvalue of the assembled matrix equals c
+exactly, found with LAPACK's banded symmetric eigensolver.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    D: np.ndarray  # (N, n, n) float64, symmetric blocks
+    E: np.ndarray  # (N-1, n, n) float64, E[i-1] = block (i+1, i)
+    B: np.ndarray  # (N, n, nrhs) float64
+    c: float       # identity shift actually applied to the diagonal blocks
+
+    @property
+    def N(self) -> int:
+        return self.D.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.D.shape[1]
+
+    @property
+    def nrhs(self) -> int:
+        return self.B.shape[2]
+
+
+def sweep_seed(N: int, n: int) -> int:
+    """Seed used for the (N, n) sweep: 1000*log2(N) + n."""
+    return int(1000 * round(math.log2(N)) + n)
+
+
+def _draw(N: int, n: int, nrhs: int, seed: int):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((N, n, n))
+    GG = np.matmul(G, G.transpose(0, 2, 1)) / n
+    del G
+    E = rng.standard_normal((max(N - 1, 0), n, n)) / math.sqrt(n)
+    B = rng.standard_normal((N, n, nrhs))
+    return GG, E, B
+
+
+def band_lower(D: np.ndarray, E: np.ndarray) -> np.ndarray:
+    """Lower banded storage (LAPACK 'L', bandwidth 2n-1) of the assembled
+    block-tridiagonal matrix: band[d, j] = A[j+d, j]."""
+    N, n, _ = D.shape
+    dim = N * n
+    band = np.zeros((2 * n, dim))
+    j = np.arange(dim)
+    bj, cj = j // n, j % n
+    for d in range(2 * n):
+        i = j + d
+        ok = i < dim
+        bi, ri = i[ok] // n, i[ok] % n
+        same = bi == bj[ok]
+        vals = np.zeros(ok.sum())
+        vals[same] = D[bj[ok][same], ri[same], cj[ok][same]]
+        nxt = bi == bj[ok] + 1
+        vals[nxt] = E[bj[ok][nxt], ri[nxt], cj[ok][nxt]]
+        band[d, ok] = vals
+    return band
+
+
+def lambda_min(D: np.ndarray, E: np.ndarray) -> float:
+    """Smallest eigenvalue of the assembled matrix (LAPACK dsbevx)."""
+    from scipy.linalg import eigvals_banded
+    w = eigvals_banded(band_lower(D, E), lower=True, select="i", select_range=(0, 0))
+    return float(w[0])
+
+
+def block_tridiag(N: int, n: int, c: float = 4.0, seed: int = 0, nrhs: int = 1,
+                  margin: bool = False) -> Problem:
+    """One instance.  ``margin=False``: D_i = G G^T/n + c I (literal shift).
+    ``margin=True``: the shift is chosen so that lambda_min(Psi) == c."""
+    if N < 1 or n < 1:
+        raise ValueError("N and n must be positive")
+    GG, E, B = _draw(N, n, nrhs, seed)
+    eye = np.eye(n)
+    if margin:
+        lam0 = lambda_min(GG, E)
+        shift = c - lam0
+    else:
+        shift = c
+    D = GG + shift * eye[None, :, :]
+    return Problem(D=D, E=E, B=B, c=float(shift))
+
+
+def laplacian(N: int, n: int, nrhs: int = 1, seed: int = 0) -> Problem:
+    """Block Laplacian D_i = 2I, E_i = -I: Psi = T_N (x) I_n with
+    T_N = tridiag(-1, 2, -1), whose inverse and factors have closed forms."""
+    rng = np.random.default_rng(seed)
+    D = np.broadcast_to(2.0 * np.eye(n), (N, n, n)).copy()
+    E = np.broadcast_to(-np.eye(n), (max(N - 1, 0), n, n)).copy()
+    B = rng.standard_normal((N, n, nrhs))
+    return Problem(D=D, E=E, B=B, c=0.0)
+
+
+def batch_shapes(count: int = 512, seed: int = 0, N_range=(32, 2048),
+                 n_choices=(8, 16, 24, 32, 48)):
+    """(N, n) of the many-instance batch: N ~ U{N_lo..N_hi}, n ~ U(choices)."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.integers(N_range[0], N_range[1] + 1, size=count)
+    ns = rng.choice(np.asarray(n_choices), size=count)
+    return [(int(a), int(b)) for a, b in zip(Ns, ns)]
