@@ -1,0 +1,179 @@
+/*
+ * btc.h -- C ABI of libbtc: nested-dissection Cholesky factorization and solve
+ * of symmetric positive-definite block-tridiagonal matrices on AMD MI355X
+ * (gfx950), after Schwan, Kuhn, Jones, "GPU-Accelerated Cholesky
+ * Factorization of Block Tridiagonal Matrices" (arXiv 2601.03754).
+ *
+ * Problem (section "Sequential Cholesky Factorization"): Psi is N x N blocks
+ * of size n x n, diagonal blocks D_1..D_N symmetric, sub-diagonal blocks
+ * E_1..E_{N-1} with E_i at block position (i+1, i) and E_i^T at (i, i+1).
+ * The library computes P Psi P^T = L L^T with the multi-stage (nested
+ * dissection) permutation P of section "Multi-Stage Permutation"
+ * (Algorithm 4: floor(log2 N)+1 levels of per-block potrf/trsm/syrk/gemm),
+ * and solves Psi X = B with the level sweeps of section "Cholesky Solve"
+ * (Algorithm 6).
+ *
+ * Memory: unless stated otherwise every array argument is a DEVICE pointer
+ * (memory of the current HIP device), row-major, FP64, and owned by the
+ * caller.  Layouts:
+ *   A_diag  [N][n][n]   D_i at A_diag + (i-1)*n*n; only the LOWER triangle of
+ *                       each block is read (the upper one may hold anything).
+ *   A_off   [N-1][n][n] E_i at A_off + (i-1)*n*n (may be NULL when N == 1).
+ *   B, X    [N][n][nrhs] block i, row r, column q at ((i-1)*n + r)*nrhs + q.
+ * The library never writes A_diag, A_off or B.
+ *
+ * Streams: every call that launches work takes a hipStream_t (passed as
+ * void*, NULL = the default stream) and returns as soon as the work is
+ * enqueued; inputs must stay valid and unchanged until that work completes.
+ * Calls that must read a device result (btc_status, a non-NULL
+ * btc_solve_info) synchronise with the stream.
+ *
+ * Errors: functions return 0 on success, -k when argument k (1-based) is
+ * invalid, or one of the negative BTC_ERR_* codes.  A numerical breakdown
+ * (a pivot block that is not positive definite) is not an error code of
+ * btc_factor, which returns before the device work completes; it is reported
+ * by btc_status.
+ */
+#ifndef BTC_H
+#define BTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifndef BTC_API
+#define BTC_API __attribute__((visibility("default")))
+#endif
+
+#define BTC_OK 0
+#define BTC_ERR_HIP (-100)          /* a HIP runtime call failed */
+#define BTC_ERR_OOM (-101)          /* device memory allocation failed */
+#define BTC_ERR_NOT_SPD (-102)      /* solve requested on a failed factorization */
+#define BTC_ERR_UNSUPPORTED (-103)  /* block size or option not supported */
+
+/* Largest supported block size n. */
+#define BTC_MAX_BLOCK 64
+
+typedef struct btc_handle_s *btc_handle; /* opaque; owned by the library */
+
+/* Arithmetic of the factorization and solve. */
+typedef enum {
+    BTC_FP64 = 0 /* every step in FP64 */
+} btc_precision;
+
+typedef struct {
+    int32_t precision;  /* btc_precision */
+    int32_t reserved0;
+    double reserved1;
+} btc_options;
+
+typedef struct {
+    int32_t steps;      /* refinement steps taken (0 for BTC_FP64) */
+    int32_t converged;  /* 1 if the residual target was met */
+    double relres;      /* max over columns of ||b - Psi x||_2 / ||b||_2 (-1 if not computed) */
+} btc_solve_info;
+
+/*
+ * btc_factor -- factor P Psi P^T = L L^T (section "Multi-Stage Permutation",
+ * Algorithm 4) and return a handle that owns the factor.
+ *   A_diag, A_off  device inputs as above (A_off ignored when N == 1)
+ *   N >= 1, 1 <= n <= BTC_MAX_BLOCK
+ *   opt            NULL for FP64 defaults
+ *   stream         hipStream_t or NULL
+ *   out            receives the new handle (host pointer, not NULL)
+ * The handle allocates its device memory with hipMalloc here; it is freed by
+ * btc_destroy.  Argument errors: -1..-7 for the argument at that position.
+ */
+BTC_API int btc_factor(const double *A_diag, const double *A_off, int64_t N, int64_t n,
+               const btc_options *opt, void *stream, btc_handle *out);
+
+/*
+ * btc_refactor -- factor a new matrix of the same (N, n) into an existing
+ * handle, reusing its device memory (repeated factorizations, e.g. the
+ * re-linearised systems of successive model-predictive-control steps).
+ */
+BTC_API int btc_refactor(btc_handle h, const double *A_diag, const double *A_off, void *stream);
+
+/*
+ * btc_solve -- solve Psi X = B with the handle's factor: forward sweep over
+ * the levels in ascending order, backward sweep in descending order
+ * (section "Cholesky Solve", Algorithm 6).
+ *   B, X    device [N][n][nrhs]; X may alias B
+ *   nrhs >= 1 (nrhs == 0 is a no-op)
+ *   info    NULL, or a host struct; when non-NULL the call synchronises with
+ *           the stream and fills it.
+ * Returns BTC_ERR_NOT_SPD (without writing X) if the factorization is known
+ * to have broken down.  Solves on one handle must not run concurrently.
+ */
+BTC_API int btc_solve(btc_handle h, const double *B, double *X, int64_t nrhs, void *stream,
+              btc_solve_info *info);
+
+/*
+ * btc_status -- synchronise with the handle's last stream and report the
+ * numerical outcome of the last factorization: *info = 0 if every pivot block
+ * was positive definite, otherwise the 1-based ORIGINAL index of the first
+ * failing block in elimination order (lowest level first, then smallest
+ * index).
+ */
+BTC_API int btc_status(btc_handle h, int64_t *info);
+
+/* btc_destroy -- free the handle and its device memory (NULL is a no-op). */
+BTC_API void btc_destroy(btc_handle h);
+
+/*
+ * btc_footprint_bytes -- device bytes a handle of this shape holds after one
+ * solve with nrhs right-hand sides (for admission control).  0 on invalid
+ * arguments.
+ */
+BTC_API size_t btc_footprint_bytes(int64_t N, int64_t n, int32_t precision, int64_t nrhs);
+
+/*
+ * btc_export_factor -- copy the factor to HOST arrays, indexed by ORIGINAL
+ * block index (slot i-1 holds block i), each [N][n][n]:
+ *   Ld[i] = L_ii (lower; strict upper triangle returned as 0)
+ *   Rb[i] = R_i = factor block at (row i+s, column i), zero if i+s > N
+ *   Tb[i] = T_i = transpose of the factor block at (row i-s, column i),
+ *           zero if i <= s
+ * where s = 2^(number of trailing zero bits of i).  Synchronises.
+ * Any of the three pointers may be NULL.
+ */
+BTC_API int btc_export_factor(btc_handle h, double *Ld, double *Rb, double *Tb);
+
+/*
+ * btc_permutation -- the multi-stage permutation as a HOST array:
+ * order[p] = 1-based original index of the block at permuted position p
+ * (all odd blocks, then the odd multiples of 2, of 4, ...).
+ */
+BTC_API int btc_permutation(int64_t N, int64_t *order);
+
+/*
+ * btc_profile -- switch per-launch kernel timing of a handle on (1) or off
+ * (0).  While on, every kernel the handle launches is bracketed by two HIP
+ * events recorded on its launch stream; switching on clears the totals.
+ */
+BTC_API int btc_profile(btc_handle h, int enable);
+
+/*
+ * btc_profile_read -- synchronise with the handle's stream and report the
+ * accumulated kernel time since profiling was switched on, per level, for
+ * one phase: 0 = factorization, 1 = forward sweep, 2 = backward sweep.
+ *   ms[l], counts[l] (host arrays of max_levels entries, either may be NULL):
+ *   total milliseconds and number of launches of that phase at level l.
+ * Returns the number of levels of the handle (>= 0) or an error code.
+ */
+BTC_API int btc_profile_read(btc_handle h, int phase, double *ms, int64_t *counts, int max_levels);
+
+/* btc_error_string -- static text for a return code. */
+BTC_API const char *btc_error_string(int code);
+
+/* btc_version -- library ABI version (major*10000 + minor*100 + patch). */
+BTC_API int btc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BTC_H */

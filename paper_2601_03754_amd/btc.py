@@ -1,0 +1,240 @@
+"""Thin Python binding of libbtc (include/btc.h): ctypes marshalling of torch
+device tensors and streams into the C ABI.  Every computation runs in the HIP
+library; there is no CPU fallback, and every entry point raises when
+libbtc.so is missing.
+
+The functions carry the C names (btc_factor, btc_solve, ...).  ``Factor`` is a
+small convenience owner of a handle that also keeps the input tensors alive
+for as long as the device may read them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbtc.so")
+_lib = None
+
+BTC_FP64 = 0
+BTC_OK = 0
+BTC_ERR_HIP = -100
+BTC_ERR_OOM = -101
+BTC_ERR_NOT_SPD = -102
+BTC_ERR_UNSUPPORTED = -103
+BTC_MAX_BLOCK = 64
+
+i32, i64, dbl, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class btc_options(ctypes.Structure):
+    _fields_ = [("precision", i32), ("reserved0", i32), ("reserved1", dbl)]
+
+
+class btc_solve_info(ctypes.Structure):
+    _fields_ = [("steps", i32), ("converged", i32), ("relres", dbl)]
+
+
+class BtcError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__("%s failed: %d (%s)" % (what, code, btc_error_string(code)))
+        self.code = code
+
+
+def lib():
+    """The loaded libbtc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError("libbtc.so is not built (run: python -m paper_2601_03754_amd.build); "
+                               "there is no CPU fallback")
+        L = ctypes.CDLL(_LIB_PATH)
+        L.btc_factor.restype = ctypes.c_int
+        L.btc_factor.argtypes = [vp, vp, i64, i64, ctypes.POINTER(btc_options), vp, ctypes.POINTER(vp)]
+        L.btc_refactor.restype = ctypes.c_int
+        L.btc_refactor.argtypes = [vp, vp, vp, vp]
+        L.btc_solve.restype = ctypes.c_int
+        L.btc_solve.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(btc_solve_info)]
+        L.btc_status.restype = ctypes.c_int
+        L.btc_status.argtypes = [vp, ctypes.POINTER(i64)]
+        L.btc_destroy.restype = None
+        L.btc_destroy.argtypes = [vp]
+        L.btc_footprint_bytes.restype = ctypes.c_size_t
+        L.btc_footprint_bytes.argtypes = [i64, i64, i32, i64]
+        L.btc_export_factor.restype = ctypes.c_int
+        L.btc_export_factor.argtypes = [vp, vp, vp, vp]
+        L.btc_permutation.restype = ctypes.c_int
+        L.btc_permutation.argtypes = [i64, vp]
+        L.btc_error_string.restype = ctypes.c_char_p
+        L.btc_error_string.argtypes = [ctypes.c_int]
+        L.btc_profile.restype = ctypes.c_int
+        L.btc_profile.argtypes = [vp, ctypes.c_int]
+        L.btc_profile_read.restype = ctypes.c_int
+        L.btc_profile_read.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int]
+        L.btc_version.restype = ctypes.c_int
+        L.btc_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def btc_error_string(code: int) -> str:
+    return lib().btc_error_string(int(code)).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != BTC_OK:
+        raise BtcError(rc, what)
+
+
+def _dev(t: torch.Tensor, name: str, dtype=torch.float64) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def btc_factor(A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_FP64,
+               stream=None) -> int:
+    """Factor; returns the raw handle (int)."""
+    N, n, n2 = A_diag.shape
+    if n != n2:
+        raise ValueError("A_diag must be (N, n, n)")
+    pa = _dev(A_diag, "A_diag")
+    po = _dev(A_off, "A_off") if N > 1 else 0
+    if N > 1 and tuple(A_off.shape) != (N - 1, n, n):
+        raise ValueError("A_off must be (N-1, n, n)")
+    opt = btc_options(precision, 0, 0.0)
+    h = vp()
+    with torch.cuda.device(A_diag.device):
+        _check(lib().btc_factor(pa, po, N, n, ctypes.byref(opt), _stream(stream), ctypes.byref(h)),
+               "btc_factor")
+    return h.value
+
+
+def btc_refactor(h: int, A_diag: torch.Tensor, A_off: torch.Tensor, stream=None) -> None:
+    N = A_diag.shape[0]
+    po = _dev(A_off, "A_off") if N > 1 else 0
+    with torch.cuda.device(A_diag.device):
+        _check(lib().btc_refactor(h, _dev(A_diag, "A_diag"), po, _stream(stream)), "btc_refactor")
+
+
+def btc_solve(h: int, B: torch.Tensor, X: Optional[torch.Tensor] = None, stream=None,
+              want_info: bool = False):
+    """Solve into X (allocated like B when None); returns X, or (X, info)."""
+    if X is None:
+        X = torch.empty_like(B)
+    nrhs = B.shape[-1] if B.dim() == 3 else 1
+    info = btc_solve_info() if want_info else None
+    with torch.cuda.device(B.device):
+        rc = lib().btc_solve(h, _dev(B, "B"), _dev(X, "X"), nrhs, _stream(stream),
+                             ctypes.byref(info) if info is not None else None)
+    _check(rc, "btc_solve")
+    if want_info:
+        return X, {"steps": info.steps, "converged": bool(info.converged), "relres": info.relres}
+    return X
+
+
+def btc_status(h: int) -> int:
+    v = i64(0)
+    _check(lib().btc_status(h, ctypes.byref(v)), "btc_status")
+    return int(v.value)
+
+
+def btc_destroy(h: int) -> None:
+    if h:
+        lib().btc_destroy(h)
+
+
+def btc_footprint_bytes(N: int, n: int, precision: int = BTC_FP64, nrhs: int = 1) -> int:
+    return int(lib().btc_footprint_bytes(N, n, precision, nrhs))
+
+
+def btc_export_factor(h: int, N: int, n: int):
+    """(Ld, Rb, Tb) as host float64 arrays indexed by original block."""
+    out = [np.zeros((N, n, n)) for _ in range(3)]
+    _check(lib().btc_export_factor(h, *[a.ctypes.data for a in out]), "btc_export_factor")
+    return tuple(out)
+
+
+def btc_permutation(N: int) -> np.ndarray:
+    out = np.zeros(N, dtype=np.int64)
+    _check(lib().btc_permutation(N, out.ctypes.data), "btc_permutation")
+    return out
+
+
+def btc_profile(h: int, enable: bool) -> None:
+    _check(lib().btc_profile(h, 1 if enable else 0), "btc_profile")
+
+
+def btc_profile_read(h: int, phase: int):
+    """(ms per level, launches per level) accumulated since btc_profile(h, True)."""
+    ms = np.zeros(64)
+    cnt = np.zeros(64, dtype=np.int64)
+    L = lib().btc_profile_read(h, phase, ms.ctypes.data, cnt.ctypes.data, 64)
+    if L < 0:
+        _check(L, "btc_profile_read")
+    return ms[:L].copy(), cnt[:L].copy()
+
+
+def btc_version() -> int:
+    return int(lib().btc_version())
+
+
+class Factor:
+    """Owner of a libbtc handle.  Keeps the input tensors referenced while the
+    device may still read them."""
+
+    def __init__(self, A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_FP64,
+                 stream=None):
+        if A_off is None or A_off.numel() == 0:
+            A_off = torch.zeros((0, A_diag.shape[1], A_diag.shape[1]), dtype=A_diag.dtype,
+                                device=A_diag.device)
+        self.N, self.n = int(A_diag.shape[0]), int(A_diag.shape[1])
+        self.precision = precision
+        self._A = (A_diag, A_off)
+        self.handle = btc_factor(A_diag, A_off, precision, stream)
+
+    def refactor(self, A_diag: torch.Tensor, A_off: torch.Tensor, stream=None) -> "Factor":
+        btc_refactor(self.handle, A_diag, A_off, stream)
+        self._A = (A_diag, A_off)
+        return self
+
+    def solve(self, B: torch.Tensor, X: Optional[torch.Tensor] = None, stream=None,
+              want_info: bool = False):
+        return btc_solve(self.handle, B, X, stream, want_info)
+
+    @property
+    def info(self) -> int:
+        return btc_status(self.handle)
+
+    def export(self):
+        return btc_export_factor(self.handle, self.N, self.n)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            btc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def factor(A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_FP64, stream=None) -> Factor:
+    return Factor(A_diag, A_off, precision, stream)

@@ -1,0 +1,347 @@
+// FP64 level kernels of libbtc: one workgroup per block (node) of one level of
+// the multi-stage elimination tree.
+//
+// Factorization (section "Multi-Stage Permutation", Algorithm 4, the hybrid
+// left/right-looking form): at level l (stride s) node i
+//   1. applies the Schur update deferred from level l-1 by its right child:
+//        S_i     -= T_{i+s/2}^T T_{i+s/2}            (if l > 0, i+s/2 <= N)
+//   2. L_ii = chol(S_i)                               (potrf)
+//   3. R_i = C_{i+s,i} L_ii^{-T}, T_i = L_ii^{-1} C_{i,i-s}   (two trsm)
+//   4. updates the separator it owns (its right neighbour), first with the
+//      update deferred from level l-1, then with its own right-looking one:
+//        S_{i+s} -= T_{i+3s/2}^T T_{i+3s/2}  (if l > 0, i+3s/2 <= N)
+//        S_{i+s} -= R_i R_i^T
+//   5. writes the fill-in coupling of level l+1:  C_{i+s,i-s} = -R_i T_i.
+// Every separator has exactly one owner per level, so no two workgroups of a
+// launch write the same block and the result is deterministic (no atomics).
+//
+// Solve (section "Cholesky Solve", Algorithm 6), two launches per level:
+//   forward (levels ascending): y_i = L_ii^{-1}(b_i - pulled contributions),
+//     u_i = R_i y_i (for the right neighbour), v_i = T_i^T y_i (for the left
+//     one).  Instead of two nodes subtracting into the same y concurrently,
+//     node i PULLS the u/v vectors its children left for it at every lower
+//     level: i - 2^l' and i + 2^l' for l' < l, a fixed summation order.
+//   backward (levels descending): x_i = L_ii^{-T}(y_i - R_i^T x_{i+s} - T_i x_{i-s}).
+#include "btc_device.h"
+#include "btc_kernels.h"
+
+namespace btc {
+
+static constexpr unsigned long long kInfoOk = ~0ull;
+
+template <int NP>
+struct F64Cfg {
+    static constexpr int NT = (NP >= 64) ? 256 : 64;
+};
+
+template <int NP, int NT>
+__global__ __launch_bounds__(NT) void k_factor_level_f64(FactorParams P) {
+    constexpr int LD = NP + 1;
+    static_assert(NT >= 2 * NP, "one thread per trsm vector");
+    __shared__ double sA[NP * LD];  // S_i -> L_ii
+    __shared__ double sB[NP * LD];  // deferred T' -> C_{i+s,i} -> R_i
+    __shared__ double sC[NP * LD];  // S_{i+s}
+    __shared__ double sD[NP * LD];  // deferred T'' -> C_{i,i-s} -> T_i
+    __shared__ double invd[NP];
+    __shared__ double colbuf[kWave];
+    __shared__ int fail;
+
+    if (*P.info != kInfoOk) return;  // an earlier level broke down
+
+    const int tid = threadIdx.x;
+    const int lvl = P.level;
+    const int64_t N = P.N;
+    const int n = P.n;
+    const size_t nn = (size_t)n * n;
+    const int64_t s = (int64_t)1 << lvl;
+    const int64_t h = s >> 1;
+    const int64_t i = ((int64_t)blockIdx.x * 2 + 1) << lvl;
+    const bool has_r = i + s <= N;
+    const bool has_l = i > s;
+    const bool def_self = lvl > 0 && i + h <= N;
+    const bool def_sep = lvl > 0 && has_r && i + 3 * h <= N;
+    const int64_t pi = perm_pos(N, lvl, i);
+    const int64_t pr = has_r ? perm_pos(N, level_of(i + s), i + s) : 0;
+
+    // 1. stage S_i, S_{i+s} and the two deferred T blocks
+    if (lvl == 0)
+        lds_load<NP>(sA, P.A_diag + (size_t)(i - 1) * nn, n, true, 1.0, tid, NT);
+    else
+        lds_load<NP>(sA, P.Ld + (size_t)pi * nn, n, true, 1.0, tid, NT);
+    if (def_self) lds_load<NP>(sB, P.Tb + (size_t)perm_pos(N, lvl - 1, i + h) * nn, n, false, 0.0, tid, NT);
+    if (has_r) {
+        if (lvl == 0)
+            lds_load<NP>(sC, P.A_diag + (size_t)(i + s - 1) * nn, n, true, 1.0, tid, NT);
+        else
+            lds_load<NP>(sC, P.Ld + (size_t)pr * nn, n, true, 1.0, tid, NT);
+        if (def_sep) lds_load<NP>(sD, P.Tb + (size_t)perm_pos(N, lvl - 1, i + 3 * h) * nn, n, false, 0.0, tid, NT);
+    }
+    if (tid == 0) fail = 0;
+    __syncthreads();
+
+    // deferred (left-looking) syrk updates
+    using GridT = Grid<NP, NT>;
+    if (def_self) {
+        double acc[GridT::T][GridT::T];
+        tile_load<NP, NT>(acc, sA);
+        double t[GridT::T][GridT::T] = {};
+        mm_acc<NP, NT, true, false>(t, sB, sB);
+#pragma unroll
+        for (int x = 0; x < GridT::T; ++x)
+#pragma unroll
+            for (int y = 0; y < GridT::T; ++y) acc[x][y] -= t[x][y];
+        tile_store_lds<NP, NT>(acc, sA);
+    }
+    if (def_sep) {
+        double acc[GridT::T][GridT::T];
+        tile_load<NP, NT>(acc, sC);
+        double t[GridT::T][GridT::T] = {};
+        mm_acc<NP, NT, true, false>(t, sD, sD);
+#pragma unroll
+        for (int x = 0; x < GridT::T; ++x)
+#pragma unroll
+            for (int y = 0; y < GridT::T; ++y) acc[x][y] -= t[x][y];
+        tile_store_lds<NP, NT>(acc, sC);
+    }
+    __syncthreads();
+
+    // 2. potrf on wave 0 while the other waves stage the couplings
+    const double* Cr = (lvl == 0) ? P.A_off + (size_t)(i - 1) * nn : P.Rb + (size_t)pi * nn;
+    const double* Cl = (lvl == 0) ? P.A_off + (size_t)(i - 2) * nn : P.Tb + (size_t)pi * nn;
+    if (tid < kWave) {
+        const bool ok = potrf_wave<NP>(sA, invd, colbuf);
+        if (!ok && tid == 0) fail = 1;
+    }
+    if (NT > kWave) {
+        if (tid >= kWave) {
+            if (has_r) lds_load<NP>(sB, Cr, n, false, 0.0, tid - kWave, NT - kWave);
+            if (has_l) lds_load<NP>(sD, Cl, n, false, 0.0, tid - kWave, NT - kWave);
+        }
+        __syncthreads();
+    } else {
+        __syncthreads();
+        if (has_r) lds_load<NP>(sB, Cr, n, false, 0.0, tid, NT);
+        if (has_l) lds_load<NP>(sD, Cl, n, false, 0.0, tid, NT);
+        __syncthreads();
+    }
+    if (fail) {
+        if (tid == 0) atomicMin(P.info, (unsigned long long)i);
+        return;
+    }
+
+    // 3. two trsm: thread v < NP solves row v of R (R^T = L^{-1} C_r^T),
+    //    NP <= v < 2NP column v-NP of T (T = L^{-1} C_l); same recurrence.
+    {
+        const bool do_r = tid < NP && has_r;
+        const bool do_l = tid >= NP && tid < 2 * NP && has_l;
+        if (do_r || do_l) {
+            double* base = do_r ? sB + tid * LD : sD + (tid - NP);
+            const int stride = do_r ? 1 : LD;
+            double x[NP];
+#pragma unroll
+            for (int c = 0; c < NP; ++c) x[c] = base[c * stride];
+            trsv_lower_reg<NP>(sA, invd, x);
+#pragma unroll
+            for (int c = 0; c < NP; ++c) base[c * stride] = x[c];
+        }
+    }
+    __syncthreads();
+
+    // 4./5. separator update and fill-in, straight from registers to HBM
+    if (has_r) {
+        double acc[GridT::T][GridT::T];
+        tile_load<NP, NT>(acc, sC);
+        double t[GridT::T][GridT::T] = {};
+        mm_acc<NP, NT, false, true>(t, sB, sB);
+#pragma unroll
+        for (int x = 0; x < GridT::T; ++x)
+#pragma unroll
+            for (int y = 0; y < GridT::T; ++y) acc[x][y] -= t[x][y];
+        tile_store_global<NP, NT>(acc, P.Ld + (size_t)pr * nn, n, 1.0);
+    }
+    if (has_r && has_l) {
+        double t[GridT::T][GridT::T] = {};
+        mm_acc<NP, NT, false, false>(t, sB, sD);
+        const int64_t lft = i - s, rgt = i + s;
+        double* dst = (((lft >> (lvl + 1)) & 1) != 0) ? P.Rb + (size_t)perm_pos(N, lvl + 1, lft) * nn
+                                                      : P.Tb + (size_t)perm_pos(N, lvl + 1, rgt) * nn;
+        tile_store_global<NP, NT>(t, dst, n, -1.0);
+    }
+    lds_store<NP>(P.Ld + (size_t)pi * nn, sA, n, true, tid, NT);
+    if (has_r) lds_store<NP>(P.Rb + (size_t)pi * nn, sB, n, false, tid, NT);
+    if (has_l) lds_store<NP>(P.Tb + (size_t)pi * nn, sD, n, false, tid, NT);
+}
+
+// ---------------------------------------------------------------------------
+// Solve.  One workgroup per node; wavefront w handles right-hand-side columns
+// q = w, w + nwaves, ...; lane r owns row r of the block.
+
+template <int NP, int NT>
+__global__ __launch_bounds__(NT) void k_forward_level_f64(SolveParams P) {
+    constexpr int LD = NP + 1;
+    constexpr int NW = NT / kWave;
+    __shared__ double sL[NP * LD];
+    __shared__ double sR[NP * LD];
+    __shared__ double sT[NP * LD];
+    __shared__ double invd[NP];
+    __shared__ double sy[NW][NP];
+
+    if (*P.info != kInfoOk) return;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const int lvl = P.level;
+    const int64_t N = P.N;
+    const int n = P.n, m = P.m;
+    const size_t nn = (size_t)n * n, nm = (size_t)n * m;
+    const int64_t s = (int64_t)1 << lvl;
+    const int64_t i = ((int64_t)blockIdx.x * 2 + 1) << lvl;
+    const bool has_r = i + s <= N, has_l = i > s;
+    const int64_t pi = perm_pos(N, lvl, i);
+
+    lds_load<NP>(sL, P.Ld + (size_t)pi * nn, n, true, 1.0, tid, NT);
+    if (has_r) lds_load<NP>(sR, P.Rb + (size_t)pi * nn, n, false, 0.0, tid, NT);
+    if (has_l) lds_load<NP>(sT, P.Tb + (size_t)pi * nn, n, false, 0.0, tid, NT);
+    __syncthreads();
+    if (tid < NP) invd[tid] = 1.0 / sL[tid * LD + tid];
+    __syncthreads();
+
+    for (int q = w; q < m; q += NW) {
+        // right-hand side minus the contributions pulled from lower levels
+        double acc = 0.0;
+        if (lane < n) {
+            acc = P.B[((size_t)(i - 1) * n + lane) * m + q];
+            for (int l2 = 0; l2 < lvl; ++l2) {
+                const int64_t s2 = (int64_t)1 << l2;
+                acc -= P.U[(size_t)perm_pos(N, l2, i - s2) * nm + (size_t)lane * m + q];
+                if (i + s2 <= N) acc -= P.V[(size_t)perm_pos(N, l2, i + s2) * nm + (size_t)lane * m + q];
+            }
+        }
+        // y = L^{-1} acc: column sweep, pivot broadcast by readlane
+#pragma unroll 8
+        for (int j = 0; j < NP; ++j) {
+            const double yj = readlane_d(acc, j) * invd[j];
+            if (lane == j) acc = yj;
+            if (lane > j && lane < NP) acc = fma(-sL[lane * LD + j], yj, acc);
+        }
+        if (lane < NP) sy[w][lane] = acc;
+        wave_lds_sync();
+        if (lane < n) {
+            P.Y[(size_t)pi * nm + (size_t)lane * m + q] = acc;
+            if (has_r) {
+                double u = 0.0;
+                for (int c = 0; c < n; ++c) u = fma(sR[lane * LD + c], sy[w][c], u);
+                P.U[(size_t)pi * nm + (size_t)lane * m + q] = u;
+            }
+            if (has_l) {
+                double v = 0.0;
+                for (int c = 0; c < n; ++c) v = fma(sT[c * LD + lane], sy[w][c], v);
+                P.V[(size_t)pi * nm + (size_t)lane * m + q] = v;
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
+template <int NP, int NT>
+__global__ __launch_bounds__(NT) void k_backward_level_f64(SolveParams P) {
+    constexpr int LD = NP + 1;
+    constexpr int NW = NT / kWave;
+    __shared__ double sL[NP * LD];
+    __shared__ double sR[NP * LD];
+    __shared__ double sT[NP * LD];
+    __shared__ double invd[NP];
+    __shared__ double sxr[NW][NP];
+    __shared__ double sxl[NW][NP];
+
+    if (*P.info != kInfoOk) return;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const int lvl = P.level;
+    const int64_t N = P.N;
+    const int n = P.n, m = P.m;
+    const size_t nn = (size_t)n * n, nm = (size_t)n * m;
+    const int64_t s = (int64_t)1 << lvl;
+    const int64_t i = ((int64_t)blockIdx.x * 2 + 1) << lvl;
+    const bool has_r = i + s <= N, has_l = i > s;
+    const int64_t pi = perm_pos(N, lvl, i);
+
+    lds_load<NP>(sL, P.Ld + (size_t)pi * nn, n, true, 1.0, tid, NT);
+    if (has_r) lds_load<NP>(sR, P.Rb + (size_t)pi * nn, n, false, 0.0, tid, NT);
+    if (has_l) lds_load<NP>(sT, P.Tb + (size_t)pi * nn, n, false, 0.0, tid, NT);
+    __syncthreads();
+    if (tid < NP) invd[tid] = 1.0 / sL[tid * LD + tid];
+    __syncthreads();
+
+    for (int q = w; q < m; q += NW) {
+        double acc = 0.0;
+        if (lane < NP) {
+            sxr[w][lane] = (has_r && lane < n) ? P.X[((size_t)(i + s - 1) * n + lane) * m + q] : 0.0;
+            sxl[w][lane] = (has_l && lane < n) ? P.X[((size_t)(i - s - 1) * n + lane) * m + q] : 0.0;
+        }
+        wave_lds_sync();
+        if (lane < n) {
+            acc = P.Y[(size_t)pi * nm + (size_t)lane * m + q];
+            if (has_r)
+                for (int c = 0; c < n; ++c) acc = fma(-sR[c * LD + lane], sxr[w][c], acc);
+            if (has_l)
+                for (int c = 0; c < n; ++c) acc = fma(-sT[lane * LD + c], sxl[w][c], acc);
+        }
+        // x = L^{-T} acc: backward column sweep
+#pragma unroll 8
+        for (int j = NP - 1; j >= 0; --j) {
+            const double xj = readlane_d(acc, j) * invd[j];
+            if (lane == j) acc = xj;
+            if (lane < j) acc = fma(-sL[j * LD + lane], xj, acc);
+        }
+        if (lane < n) P.X[((size_t)(i - 1) * n + lane) * m + q] = acc;
+        wave_lds_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (one per level).
+
+template <int NP>
+static hipError_t launch_factor_np(const FactorParams& p, int64_t nodes, hipStream_t st) {
+    constexpr int NT = F64Cfg<NP>::NT;
+    hipLaunchKernelGGL((k_factor_level_f64<NP, NT>), dim3((unsigned)nodes), dim3(NT), 0, st, p);
+    return hipGetLastError();
+}
+
+template <int NP>
+static hipError_t launch_solve_np(const SolveParams& p, int64_t nodes, bool backward, hipStream_t st) {
+    constexpr int NT = F64Cfg<NP>::NT;
+    if (backward)
+        hipLaunchKernelGGL((k_backward_level_f64<NP, NT>), dim3((unsigned)nodes), dim3(NT), 0, st, p);
+    else
+        hipLaunchKernelGGL((k_forward_level_f64<NP, NT>), dim3((unsigned)nodes), dim3(NT), 0, st, p);
+    return hipGetLastError();
+}
+
+int padded_block(int n) {
+    if (n <= 8) return 8;
+    if (n <= 16) return 16;
+    if (n <= 32) return 32;
+    if (n <= 64) return 64;
+    return 0;
+}
+
+hipError_t launch_factor_level_f64(const FactorParams& p, int64_t nodes, hipStream_t st) {
+    switch (padded_block(p.n)) {
+        case 8: return launch_factor_np<8>(p, nodes, st);
+        case 16: return launch_factor_np<16>(p, nodes, st);
+        case 32: return launch_factor_np<32>(p, nodes, st);
+        case 64: return launch_factor_np<64>(p, nodes, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_solve_level_f64(const SolveParams& p, int64_t nodes, bool backward, hipStream_t st) {
+    switch (padded_block(p.n)) {
+        case 8: return launch_solve_np<8>(p, nodes, backward, st);
+        case 16: return launch_solve_np<16>(p, nodes, backward, st);
+        case 32: return launch_solve_np<32>(p, nodes, backward, st);
+        case 64: return launch_solve_np<64>(p, nodes, backward, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace btc

@@ -1,0 +1,81 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol include/btc.h declares, and its host-only helpers (permutation,
+footprint, error strings, argument checks that fail before any device call)
+behave as documented."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2601_03754_amd", "libbtc.so")
+
+
+def declared_symbols():
+    names = []
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if hdr.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", hdr)).read()
+            names += re.findall(r"^BTC_API\s+[\w\s\*]+?\b(btc_\w+)\s*\(", src, re.M)
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2601_03754_amd import build
+        build.build()
+    from paper_2601_03754_amd import btc
+    return btc
+
+
+def test_header_declares_entry_points():
+    names = declared_symbols()
+    for must in ("btc_factor", "btc_solve", "btc_refactor", "btc_status", "btc_destroy",
+                 "btc_footprint_bytes", "btc_export_factor", "btc_permutation"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    L = lib.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+        assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+
+
+def test_only_declared_symbols_are_exported(lib):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s(btc_\w+)", out))
+    assert exported == set(declared_symbols())
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 20, 1000, 4097])
+def test_permutation_matches_oracle(lib, N):
+    assert np.array_equal(lib.btc_permutation(N), oracle.nd_order(N))
+
+
+def test_footprint(lib):
+    assert lib.btc_footprint_bytes(16, 8, 0, 1) == 3 * 16 * 64 * 8 + 8 + 3 * 16 * 8 * 8
+    assert lib.btc_footprint_bytes(0, 8, 0, 1) == 0
+    assert lib.btc_footprint_bytes(16, 65, 0, 1) == 0
+
+
+def test_argument_errors_before_device_work(lib):
+    L = lib.lib()
+    h = ctypes.c_void_p()
+    # null A_diag -> -1, N < 1 -> -3, n < 1 -> -4, n too large -> unsupported, null out -> -7
+    assert L.btc_factor(None, None, 4, 4, None, None, ctypes.byref(h)) == -1
+    assert L.btc_factor(8, 8, 0, 4, None, None, ctypes.byref(h)) == -3
+    assert L.btc_factor(8, 8, 4, 0, None, None, ctypes.byref(h)) == -4
+    assert L.btc_factor(8, 8, 4, 65, None, None, ctypes.byref(h)) == lib.BTC_ERR_UNSUPPORTED
+    assert L.btc_factor(8, 8, 4, 4, None, None, None) == -7
+    assert L.btc_solve(None, 8, 8, 1, None, None) == -1
+    assert L.btc_status(None, None) == -1
+    L.btc_destroy(None)
+    assert "argument" in lib.btc_error_string(-3)
+    assert "positive definite" in lib.btc_error_string(lib.BTC_ERR_NOT_SPD)
