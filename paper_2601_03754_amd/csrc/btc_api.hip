@@ -140,7 +140,11 @@ int launch_factor(btc_handle h, const double* A_diag, const double* A_off, hipSt
     p.n = (int32_t)h->n;
     for (int l = 0; l < h->levels; ++l) {
         p.level = l;
-        e = timed(h, 0, l, st, [&] { return btc::launch_factor_level_f64(p, level_nodes(h->N, l), st); });
+        const int64_t nodes = level_nodes(h->N, l);
+        e = timed(h, 0, l, st, [&] {
+            return btc::padded_block((int)h->n) >= 16 ? btc::launch_factor_level_mfma(p, nodes, st)
+                                                      : btc::launch_factor_level_f64(p, nodes, st);
+        });
         if (e != hipSuccess) return to_code(e);
     }
     h->A_diag = A_diag;

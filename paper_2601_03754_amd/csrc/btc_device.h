@@ -68,6 +68,36 @@ __device__ __forceinline__ void lds_load(double* __restrict__ dst, const double*
     }
 }
 
+// Batched staging of one n x n row-major block by a fixed group of NTH
+// threads: fetch() issues all of the thread's global loads into registers (so
+// that every load of several blocks is in flight at once), put() writes them
+// to the padded LDS tile.  Same element mapping and padding as lds_load.
+template <int NP, int NTH>
+struct Stage {
+    static constexpr int PER = (NP * NP + NTH - 1) / NTH;
+    double v[PER];
+
+    __device__ __forceinline__ void fetch(const double* __restrict__ src, int n, bool lower_only,
+                                          double pad_diag, int t) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = t + NTH * k;
+            const int r = e / NP, c = e % NP;
+            double x = (r == c) ? pad_diag : 0.0;
+            if (e < NP * NP && r < n && c < n && (!lower_only || c <= r)) x = src[(size_t)r * n + c];
+            v[k] = x;
+        }
+    }
+
+    __device__ __forceinline__ void put(double* __restrict__ dst, int t) const {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = t + NTH * k;
+            if (e < NP * NP) dst[(e / NP) * (NP + 1) + e % NP] = v[k];
+        }
+    }
+};
+
 // Write the leading n x n part of an LDS tile to global memory
 // (lower_only: the strict upper triangle is written as 0).
 template <int NP>
@@ -79,82 +109,86 @@ __device__ __forceinline__ void lds_store(double* __restrict__ dst, const double
     }
 }
 
-// Register tiling of an NP x NP result over NT threads: a G x G thread grid,
-// each thread owning the T x T elements (tr + G*a, tc + G*b) (cyclic, so that
-// neighbouring lanes touch neighbouring LDS words and global addresses).
+// Register tiling of an NP x NP result over NT threads: a GR x GC thread
+// grid, each thread owning the TM x TN elements (tr + GR*a, tc + GC*b)
+// (cyclic, so that neighbouring lanes touch neighbouring LDS words and global
+// addresses).
 template <int NP, int NT>
 struct Grid {
-    static constexpr int G = (NT >= 256) ? 16 : 8;
-    static constexpr int T = NP / G;
-    static_assert(G * G == NT, "thread grid must cover the workgroup");
-    static_assert(T * G == NP, "tile must divide the block");
+    static constexpr int GR = (NT >= 256) ? 16 : 8;
+    static constexpr int GC = NT / GR;
+    static constexpr int TM = NP / GR;
+    static constexpr int TN = NP / GC;
+    static_assert(GR * GC == NT, "thread grid must cover the workgroup");
+    static_assert(TM * GR == NP && TN * GC == NP && TN > 0, "tile must divide the block");
 };
 
 template <int NP, int NT>
-using Acc = double[Grid<NP, NT>::T][Grid<NP, NT>::T];
+using Acc = double[Grid<NP, NT>::TM][Grid<NP, NT>::TN];
 
 // acc[a][b] += sum_k opA(A)[r][k] * opB(B)[k][c] over LDS tiles, with
 // opA(A)[r][k] = TA ? A[k][r] : A[r][k] and opB(B)[k][c] = TB ? B[c][k] : B[k][c].
 template <int NP, int NT, bool TA, bool TB>
 __device__ __forceinline__ void mm_acc(Acc<NP, NT>& acc,
                                        const double* __restrict__ A, const double* __restrict__ B) {
-    constexpr int G = Grid<NP, NT>::G, T = Grid<NP, NT>::T, LD = NP + 1;
-    const int tr = threadIdx.x / G, tc = threadIdx.x % G;
+    using Gd = Grid<NP, NT>;
+    constexpr int LD = NP + 1;
+    const int tr = threadIdx.x / Gd::GC, tc = threadIdx.x % Gd::GC;
 #pragma unroll 4
     for (int k = 0; k < NP; ++k) {
-        double a[T], b[T];
+        double a[Gd::TM], b[Gd::TN];
 #pragma unroll
-        for (int x = 0; x < T; ++x) {
-            const int r = tr + G * x;
+        for (int x = 0; x < Gd::TM; ++x) {
+            const int r = tr + Gd::GR * x;
             a[x] = TA ? A[k * LD + r] : A[r * LD + k];
         }
 #pragma unroll
-        for (int y = 0; y < T; ++y) {
-            const int c = tc + G * y;
+        for (int y = 0; y < Gd::TN; ++y) {
+            const int c = tc + Gd::GC * y;
             b[y] = TB ? B[c * LD + k] : B[k * LD + c];
         }
 #pragma unroll
-        for (int x = 0; x < T; ++x)
+        for (int x = 0; x < Gd::TM; ++x)
 #pragma unroll
-            for (int y = 0; y < T; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+            for (int y = 0; y < Gd::TN; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
     }
 }
 
 template <int NP, int NT>
-__device__ __forceinline__ void tile_load(Acc<NP, NT>& acc,
-                                          const double* __restrict__ S) {
-    constexpr int G = Grid<NP, NT>::G, T = Grid<NP, NT>::T, LD = NP + 1;
-    const int tr = threadIdx.x / G, tc = threadIdx.x % G;
+__device__ __forceinline__ void tile_load(Acc<NP, NT>& acc, const double* __restrict__ S) {
+    using Gd = Grid<NP, NT>;
+    constexpr int LD = NP + 1;
+    const int tr = threadIdx.x / Gd::GC, tc = threadIdx.x % Gd::GC;
 #pragma unroll
-    for (int x = 0; x < T; ++x)
+    for (int x = 0; x < Gd::TM; ++x)
 #pragma unroll
-        for (int y = 0; y < T; ++y) acc[x][y] = S[(tr + G * x) * LD + tc + G * y];
+        for (int y = 0; y < Gd::TN; ++y) acc[x][y] = S[(tr + Gd::GR * x) * LD + tc + Gd::GC * y];
 }
 
 template <int NP, int NT>
-__device__ __forceinline__ void tile_store_lds(const Acc<NP, NT>& acc,
-                                               double* __restrict__ S) {
-    constexpr int G = Grid<NP, NT>::G, T = Grid<NP, NT>::T, LD = NP + 1;
-    const int tr = threadIdx.x / G, tc = threadIdx.x % G;
+__device__ __forceinline__ void tile_store_lds(const Acc<NP, NT>& acc, double* __restrict__ S) {
+    using Gd = Grid<NP, NT>;
+    constexpr int LD = NP + 1;
+    const int tr = threadIdx.x / Gd::GC, tc = threadIdx.x % Gd::GC;
 #pragma unroll
-    for (int x = 0; x < T; ++x)
+    for (int x = 0; x < Gd::TM; ++x)
 #pragma unroll
-        for (int y = 0; y < T; ++y) S[(tr + G * x) * LD + tc + G * y] = acc[x][y];
+        for (int y = 0; y < Gd::TN; ++y) S[(tr + Gd::GR * x) * LD + tc + Gd::GC * y] = acc[x][y];
 }
 
 // Store the leading n x n part of a register tile to a row-major global block,
 // multiplied by `scale`.
 template <int NP, int NT>
-__device__ __forceinline__ void tile_store_global(const Acc<NP, NT>& acc,
-                                                  double* __restrict__ dst, int n, double scale) {
-    constexpr int G = Grid<NP, NT>::G, T = Grid<NP, NT>::T;
-    const int tr = threadIdx.x / G, tc = threadIdx.x % G;
+__device__ __forceinline__ void tile_store_global(const Acc<NP, NT>& acc, double* __restrict__ dst, int n,
+                                                  double scale) {
+    using Gd = Grid<NP, NT>;
+    const int tr = threadIdx.x / Gd::GC, tc = threadIdx.x % Gd::GC;
 #pragma unroll
-    for (int x = 0; x < T; ++x) {
-        const int r = tr + G * x;
+    for (int x = 0; x < Gd::TM; ++x) {
+        const int r = tr + Gd::GR * x;
 #pragma unroll
-        for (int y = 0; y < T; ++y) {
-            const int c = tc + G * y;
+        for (int y = 0; y < Gd::TN; ++y) {
+            const int c = tc + Gd::GC * y;
             if (r < n && c < n) dst[(size_t)r * n + c] = scale * acc[x][y];
         }
     }

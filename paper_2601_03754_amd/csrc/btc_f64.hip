@@ -29,9 +29,11 @@ namespace btc {
 
 static constexpr unsigned long long kInfoOk = ~0ull;
 
+// Threads per workgroup: one wavefront for NP <= 16; for larger blocks extra
+// wavefronts stage the couplings while wavefront 0 factors the pivot block.
 template <int NP>
 struct F64Cfg {
-    static constexpr int NT = (NP >= 64) ? 256 : 64;
+    static constexpr int NT = (NP >= 64) ? 256 : (NP >= 32 ? 128 : 64);
 };
 
 template <int NP, int NT>
@@ -63,18 +65,18 @@ __global__ __launch_bounds__(NT) void k_factor_level_f64(FactorParams P) {
     const int64_t pi = perm_pos(N, lvl, i);
     const int64_t pr = has_r ? perm_pos(N, level_of(i + s), i + s) : 0;
 
-    // 1. stage S_i, S_{i+s} and the two deferred T blocks
-    if (lvl == 0)
-        lds_load<NP>(sA, P.A_diag + (size_t)(i - 1) * nn, n, true, 1.0, tid, NT);
-    else
-        lds_load<NP>(sA, P.Ld + (size_t)pi * nn, n, true, 1.0, tid, NT);
-    if (def_self) lds_load<NP>(sB, P.Tb + (size_t)perm_pos(N, lvl - 1, i + h) * nn, n, false, 0.0, tid, NT);
-    if (has_r) {
-        if (lvl == 0)
-            lds_load<NP>(sC, P.A_diag + (size_t)(i + s - 1) * nn, n, true, 1.0, tid, NT);
-        else
-            lds_load<NP>(sC, P.Ld + (size_t)pr * nn, n, true, 1.0, tid, NT);
-        if (def_sep) lds_load<NP>(sD, P.Tb + (size_t)perm_pos(N, lvl - 1, i + 3 * h) * nn, n, false, 0.0, tid, NT);
+    // 1. stage S_i, S_{i+s} and the two deferred T blocks (all loads in flight)
+    {
+        Stage<NP, NT> a, b, c, d;
+        a.fetch(lvl == 0 ? P.A_diag + (size_t)(i - 1) * nn : P.Ld + (size_t)pi * nn, n, true, 1.0, tid);
+        if (def_self) b.fetch(P.Tb + (size_t)perm_pos(N, lvl - 1, i + h) * nn, n, false, 0.0, tid);
+        if (has_r)
+            c.fetch(lvl == 0 ? P.A_diag + (size_t)(i + s - 1) * nn : P.Ld + (size_t)pr * nn, n, true, 1.0, tid);
+        if (def_sep) d.fetch(P.Tb + (size_t)perm_pos(N, lvl - 1, i + 3 * h) * nn, n, false, 0.0, tid);
+        a.put(sA, tid);
+        if (def_self) b.put(sB, tid);
+        if (has_r) c.put(sC, tid);
+        if (def_sep) d.put(sD, tid);
     }
     if (tid == 0) fail = 0;
     __syncthreads();
@@ -82,25 +84,25 @@ __global__ __launch_bounds__(NT) void k_factor_level_f64(FactorParams P) {
     // deferred (left-looking) syrk updates
     using GridT = Grid<NP, NT>;
     if (def_self) {
-        double acc[GridT::T][GridT::T];
+        Acc<NP, NT> acc;
         tile_load<NP, NT>(acc, sA);
-        double t[GridT::T][GridT::T] = {};
+        Acc<NP, NT> t = {};
         mm_acc<NP, NT, true, false>(t, sB, sB);
 #pragma unroll
-        for (int x = 0; x < GridT::T; ++x)
+        for (int x = 0; x < GridT::TM; ++x)
 #pragma unroll
-            for (int y = 0; y < GridT::T; ++y) acc[x][y] -= t[x][y];
+            for (int y = 0; y < GridT::TN; ++y) acc[x][y] -= t[x][y];
         tile_store_lds<NP, NT>(acc, sA);
     }
     if (def_sep) {
-        double acc[GridT::T][GridT::T];
+        Acc<NP, NT> acc;
         tile_load<NP, NT>(acc, sC);
-        double t[GridT::T][GridT::T] = {};
+        Acc<NP, NT> t = {};
         mm_acc<NP, NT, true, false>(t, sD, sD);
 #pragma unroll
-        for (int x = 0; x < GridT::T; ++x)
+        for (int x = 0; x < GridT::TM; ++x)
 #pragma unroll
-            for (int y = 0; y < GridT::T; ++y) acc[x][y] -= t[x][y];
+            for (int y = 0; y < GridT::TN; ++y) acc[x][y] -= t[x][y];
         tile_store_lds<NP, NT>(acc, sC);
     }
     __syncthreads();
@@ -108,20 +110,27 @@ __global__ __launch_bounds__(NT) void k_factor_level_f64(FactorParams P) {
     // 2. potrf on wave 0 while the other waves stage the couplings
     const double* Cr = (lvl == 0) ? P.A_off + (size_t)(i - 1) * nn : P.Rb + (size_t)pi * nn;
     const double* Cl = (lvl == 0) ? P.A_off + (size_t)(i - 2) * nn : P.Tb + (size_t)pi * nn;
-    if (tid < kWave) {
-        const bool ok = potrf_wave<NP>(sA, invd, colbuf);
-        if (!ok && tid == 0) fail = 1;
-    }
-    if (NT > kWave) {
-        if (tid >= kWave) {
-            if (has_r) lds_load<NP>(sB, Cr, n, false, 0.0, tid - kWave, NT - kWave);
-            if (has_l) lds_load<NP>(sD, Cl, n, false, 0.0, tid - kWave, NT - kWave);
+    if constexpr (NT > kWave) {
+        if (tid < kWave) {
+            const bool ok = potrf_wave<NP>(sA, invd, colbuf);
+            if (!ok && tid == 0) fail = 1;
+        } else {
+            Stage<NP, NT - kWave> cr, cl;
+            if (has_r) cr.fetch(Cr, n, false, 0.0, tid - kWave);
+            if (has_l) cl.fetch(Cl, n, false, 0.0, tid - kWave);
+            if (has_r) cr.put(sB, tid - kWave);
+            if (has_l) cl.put(sD, tid - kWave);
         }
         __syncthreads();
     } else {
-        __syncthreads();
-        if (has_r) lds_load<NP>(sB, Cr, n, false, 0.0, tid, NT);
-        if (has_l) lds_load<NP>(sD, Cl, n, false, 0.0, tid, NT);
+        // a single wavefront: issue the coupling loads first, factor while they fly
+        Stage<NP, NT> cr, cl;
+        if (has_r) cr.fetch(Cr, n, false, 0.0, tid);
+        if (has_l) cl.fetch(Cl, n, false, 0.0, tid);
+        const bool ok = potrf_wave<NP>(sA, invd, colbuf);
+        if (!ok && tid == 0) fail = 1;
+        if (has_r) cr.put(sB, tid);
+        if (has_l) cl.put(sD, tid);
         __syncthreads();
     }
     if (fail) {
@@ -149,18 +158,18 @@ __global__ __launch_bounds__(NT) void k_factor_level_f64(FactorParams P) {
 
     // 4./5. separator update and fill-in, straight from registers to HBM
     if (has_r) {
-        double acc[GridT::T][GridT::T];
+        Acc<NP, NT> acc;
         tile_load<NP, NT>(acc, sC);
-        double t[GridT::T][GridT::T] = {};
+        Acc<NP, NT> t = {};
         mm_acc<NP, NT, false, true>(t, sB, sB);
 #pragma unroll
-        for (int x = 0; x < GridT::T; ++x)
+        for (int x = 0; x < GridT::TM; ++x)
 #pragma unroll
-            for (int y = 0; y < GridT::T; ++y) acc[x][y] -= t[x][y];
+            for (int y = 0; y < GridT::TN; ++y) acc[x][y] -= t[x][y];
         tile_store_global<NP, NT>(acc, P.Ld + (size_t)pr * nn, n, 1.0);
     }
     if (has_r && has_l) {
-        double t[GridT::T][GridT::T] = {};
+        Acc<NP, NT> t = {};
         mm_acc<NP, NT, false, false>(t, sB, sD);
         const int64_t lft = i - s, rgt = i + s;
         double* dst = (((lft >> (lvl + 1)) & 1) != 0) ? P.Rb + (size_t)perm_pos(N, lvl + 1, lft) * nn
@@ -197,9 +206,15 @@ __global__ __launch_bounds__(NT) void k_forward_level_f64(SolveParams P) {
     const bool has_r = i + s <= N, has_l = i > s;
     const int64_t pi = perm_pos(N, lvl, i);
 
-    lds_load<NP>(sL, P.Ld + (size_t)pi * nn, n, true, 1.0, tid, NT);
-    if (has_r) lds_load<NP>(sR, P.Rb + (size_t)pi * nn, n, false, 0.0, tid, NT);
-    if (has_l) lds_load<NP>(sT, P.Tb + (size_t)pi * nn, n, false, 0.0, tid, NT);
+    {
+        Stage<NP, NT> a, b, c;
+        a.fetch(P.Ld + (size_t)pi * nn, n, true, 1.0, tid);
+        if (has_r) b.fetch(P.Rb + (size_t)pi * nn, n, false, 0.0, tid);
+        if (has_l) c.fetch(P.Tb + (size_t)pi * nn, n, false, 0.0, tid);
+        a.put(sL, tid);
+        if (has_r) b.put(sR, tid);
+        if (has_l) c.put(sT, tid);
+    }
     __syncthreads();
     if (tid < NP) invd[tid] = 1.0 / sL[tid * LD + tid];
     __syncthreads();
@@ -209,10 +224,21 @@ __global__ __launch_bounds__(NT) void k_forward_level_f64(SolveParams P) {
         double acc = 0.0;
         if (lane < n) {
             acc = P.B[((size_t)(i - 1) * n + lane) * m + q];
-            for (int l2 = 0; l2 < lvl; ++l2) {
-                const int64_t s2 = (int64_t)1 << l2;
-                acc -= P.U[(size_t)perm_pos(N, l2, i - s2) * nm + (size_t)lane * m + q];
-                if (i + s2 <= N) acc -= P.V[(size_t)perm_pos(N, l2, i + s2) * nm + (size_t)lane * m + q];
+            // contributions of the children at every lower level, gathered
+            // eight levels at a time so the loads are in flight together
+            for (int l0 = 0; l0 < lvl; l0 += 8) {
+                double pu[8], pv[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int l2 = l0 + k;
+                    const int64_t s2 = (int64_t)1 << l2;
+                    pu[k] = (l2 < lvl) ? P.U[(size_t)perm_pos(N, l2, i - s2) * nm + (size_t)lane * m + q] : 0.0;
+                    pv[k] = (l2 < lvl && i + s2 <= N)
+                                ? P.V[(size_t)perm_pos(N, l2, i + s2) * nm + (size_t)lane * m + q]
+                                : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc -= pu[k] + pv[k];
             }
         }
         // y = L^{-1} acc: column sweep, pivot broadcast by readlane
@@ -263,9 +289,15 @@ __global__ __launch_bounds__(NT) void k_backward_level_f64(SolveParams P) {
     const bool has_r = i + s <= N, has_l = i > s;
     const int64_t pi = perm_pos(N, lvl, i);
 
-    lds_load<NP>(sL, P.Ld + (size_t)pi * nn, n, true, 1.0, tid, NT);
-    if (has_r) lds_load<NP>(sR, P.Rb + (size_t)pi * nn, n, false, 0.0, tid, NT);
-    if (has_l) lds_load<NP>(sT, P.Tb + (size_t)pi * nn, n, false, 0.0, tid, NT);
+    {
+        Stage<NP, NT> a, b, c;
+        a.fetch(P.Ld + (size_t)pi * nn, n, true, 1.0, tid);
+        if (has_r) b.fetch(P.Rb + (size_t)pi * nn, n, false, 0.0, tid);
+        if (has_l) c.fetch(P.Tb + (size_t)pi * nn, n, false, 0.0, tid);
+        a.put(sL, tid);
+        if (has_r) b.put(sR, tid);
+        if (has_l) c.put(sT, tid);
+    }
     __syncthreads();
     if (tid < NP) invd[tid] = 1.0 / sL[tid * LD + tid];
     __syncthreads();

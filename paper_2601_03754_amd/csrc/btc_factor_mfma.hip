@@ -1,0 +1,368 @@
+// FP64 factorization level kernel on matrix cores, for padded block sizes
+// NP in {16, 32, 64} (block sizes 9 <= n <= 64).  One workgroup of W = NP/16
+// wavefronts per node; every n x n block is treated as W x W tiles of 16 x 16
+// and every block product runs on v_mfma_f64_16x16x4f64.
+//
+// Per node i of level l (stride s), the same steps as the VALU kernel
+// (Algorithm 4, hybrid left/right-looking, deterministic ownership):
+//   P1  stage S_i, S_{i+s} and the deferred T blocks in LDS
+//   P2  S_i -= T'^T T',  S_{i+s} -= T''^T T''       (deferred syrk, MFMA;
+//       lower-triangle tiles only, spread round-robin over the wavefronts)
+//   P3  wavefront 0: L_ii = chol(S_i) (pivot chain in registers); the other
+//       wavefronts stage the couplings C_{i+s,i}, C_{i,i-s}
+//   P4  every wavefront inverts one 16 x 16 diagonal tile of L_ii
+//   P5  R_i = C_{i+s,i} L_ii^{-T} and T_i = L_ii^{-1} C_{i,i-s} as a blocked
+//       triangular solve over the tiles: each step is a tile product with the
+//       already solved tiles followed by a product with an inverted diagonal
+//       tile, all MFMA; wavefront w owns tile-row w of R and tile-column w of T,
+//       so no workgroup barrier is needed inside the solve
+//   P6  S_{i+s} -= R_i R_i^T (into the accumulators), fill -R_i T_i; stores.
+#include "btc_device.h"
+#include "btc_kernels.h"
+
+namespace btc {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr unsigned long long kInfoOk = ~0ull;
+constexpr int kT = 16;       // tile side
+constexpr int kLDI = kT + 1; // row stride of an inverted diagonal tile in LDS
+
+// f64 16x16x4 accumulator layout: register v of lane l holds tile element
+// (4v + l/16, l%16).  Operand layouts: A[i][k] in lane i + 16k, B[k][j] in
+// lane j + 16k.
+__device__ __forceinline__ int acc_r(int v, int lane) { return 4 * v + (lane >> 4); }
+__device__ __forceinline__ int acc_c(int lane) { return lane & 15; }
+
+// acc += (NEG ? -1 : 1) * sum_{kk<K} opA[ra+i][ka+kk] * opB[kb+kk][cb+j]
+//   opA[r][k] = TA ? A[k][r] : A[r][k],  opB[k][c] = TB ? B[c][k] : B[k][c]
+template <int LDA, int LDB, bool TA, bool TB, bool NEG>
+__device__ __forceinline__ void mma_tile(d4& acc, const double* __restrict__ A, int ra, int ka,
+                                         const double* __restrict__ B, int cb, int kb, int K) {
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 15, q = lane >> 4;
+#pragma unroll 4
+    for (int kk = 0; kk < K; kk += 4) {
+        const int k1 = ka + kk + q, k2 = kb + kk + q;
+        double a = TA ? A[k1 * LDA + ra + i] : A[(ra + i) * LDA + k1];
+        const double b = TB ? B[(cb + i) * LDB + k2] : B[k2 * LDB + cb + i];
+        if (NEG) a = -a;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+}
+
+template <int LD>
+__device__ __forceinline__ void acc_load_lds(d4& acc, const double* __restrict__ S, int r0, int c0) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = S[(r0 + acc_r(v, lane)) * LD + c0 + acc_c(lane)];
+}
+
+template <int LD>
+__device__ __forceinline__ void acc_store_lds(const d4& acc, double* __restrict__ S, int r0, int c0) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[(r0 + acc_r(v, lane)) * LD + c0 + acc_c(lane)] = acc[v];
+}
+
+// Load a tile of an n x n global block (lower triangle only, identity padding).
+__device__ __forceinline__ void acc_load_sym(d4& acc, const double* __restrict__ src, int n, int r0, int c0) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = r0 + acc_r(v, lane), c = c0 + acc_c(lane);
+        double x = (r == c) ? 1.0 : 0.0;
+        if (r < n && c < n && c <= r) x = src[(size_t)r * n + c];
+        acc[v] = x;
+    }
+}
+
+__device__ __forceinline__ void acc_store_global(const d4& acc, double* __restrict__ dst, int n, int r0, int c0) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = r0 + acc_r(v, lane), c = c0 + acc_c(lane);
+        if (r < n && c < n) dst[(size_t)r * n + c] = acc[v];
+    }
+}
+
+// k-th lower-triangle tile (a, b), b <= a, in row-major order of the triangle.
+__device__ __forceinline__ void tri_tile(int k, int& a, int& b) {
+    a = 0;
+    while ((a + 1) * (a + 2) / 2 <= k) ++a;
+    b = k - a * (a + 1) / 2;
+}
+
+// Cholesky of the lower triangle of an NP x NP LDS tile by one wavefront,
+// lane r holding row r in registers.  The pivot of step j+1 is formed right
+// after step j from two readlanes (the new column j value of row j+1 is its
+// own multiplier), so the pivot chain never waits for the LDS broadcast; the
+// rest of the column is broadcast through a double-buffered LDS column for
+// the trailing update.  1/sqrt of the pivot: hardware estimate refined by two
+// Newton steps.  Writes L (zero strict upper part) back and 1/L_jj to invd.
+template <int NP>
+__device__ __forceinline__ bool potrf_lookahead(double* __restrict__ A, double* __restrict__ invd,
+                                                double (*__restrict__ colbuf)[kWave]) {
+    static_assert(NP <= kWave, "one lane per row");
+    constexpr int LD = NP + 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    double a[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) a[c] = (lane < NP && c <= lane) ? A[lane * LD + c] : 0.0;
+    double piv = readlane_d(a[0], 0);
+    double myinv = 1.0;  // 1/L_rr of this lane's row r
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        ok = ok && (piv > 0.0);
+        double r = __builtin_amdgcn_rsq(piv);
+        double e = fma(-piv * r, r, 1.0);
+        r = fma(0.5 * r, e, r);
+        e = fma(-piv * r, r, 1.0);
+        r = fma(0.5 * r, e, r);
+        const double d = piv * r;
+        double l = a[j] * r;
+        l = (lane == j) ? d : l;
+        l = (lane < j) ? 0.0 : l;
+        myinv = (lane == j) ? r : myinv;
+        a[j] = l;
+        if (j + 1 < NP) {
+            double* cb = colbuf[j & 1];
+            cb[lane] = l;
+            const double lj1 = readlane_d(l, j + 1);
+            a[j + 1] = fma(-l, lj1, a[j + 1]);
+            piv = readlane_d(a[j + 1], j + 1);
+#pragma unroll
+            for (int c0 = (j + 2) & ~1; c0 < NP; c0 += 2) {
+                const double2 v = *reinterpret_cast<const double2*>(cb + c0);
+                if (c0 >= j + 2) a[c0] = fma(-l, v.x, a[c0]);
+                a[c0 + 1] = fma(-l, v.y, a[c0 + 1]);
+            }
+        }
+    }
+    if (lane < NP) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c) A[lane * LD + c] = (c <= lane) ? a[c] : 0.0;
+        invd[lane] = myinv;
+    }
+    return ok;
+}
+
+// Inverse of the 16 x 16 lower-triangular diagonal tile of L starting at
+// (r0, r0) into Dinv (row stride kLDI): lane c (< 16) forward-substitutes the
+// unit vector e_c.
+template <int LD>
+__device__ __forceinline__ void tile_inverse(const double* __restrict__ L, int r0, const double* __restrict__ invd,
+                                             double* __restrict__ Dinv) {
+    const int lane = threadIdx.x & 63;
+    const int c = lane & 15;
+    double x[kT];
+#pragma unroll
+    for (int j = 0; j < kT; ++j) x[j] = (j == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < kT; ++j) {
+        x[j] *= invd[r0 + j];
+#pragma unroll
+        for (int k = j + 1; k < kT; ++k) x[k] = fma(-L[(r0 + k) * LD + r0 + j], x[j], x[k]);
+    }
+    if (lane < kT) {
+#pragma unroll
+        for (int j = 0; j < kT; ++j) Dinv[j * kLDI + c] = x[j];
+    }
+}
+
+template <int NP>
+struct MfmaCfg {
+    static constexpr int W = NP / kT;             // wavefronts = tile rows
+    static constexpr int NT = W * kWave;
+    static constexpr int NTRI = W * (W + 1) / 2;  // lower-triangle tiles
+    static constexpr int TPW = (NTRI + W - 1) / W; // lower tiles per wavefront
+};
+
+template <int NP>
+__global__ __launch_bounds__(MfmaCfg<NP>::NT) void k_factor_level_mfma(FactorParams P) {
+    using Cfg = MfmaCfg<NP>;
+    constexpr int W = Cfg::W, NT = Cfg::NT, LD = NP + 1;
+    __shared__ double sS[NP * LD];         // S_i -> L_ii
+    __shared__ double sB[NP * LD];         // T' -> C_{i+s,i} -> R_i
+    __shared__ double sD[NP * LD];         // T'' -> C_{i,i-s} -> T_i
+    __shared__ double sC[NP * LD];         // S_{i+s}
+    __shared__ double sInv[W][kT * kLDI];  // inverted diagonal tiles of L_ii
+    __shared__ double invd[NP];
+    __shared__ __align__(16) double colbuf[2][kWave];
+    __shared__ int fail;
+
+    if (*P.info != kInfoOk) return;  // an earlier level broke down
+
+    const int tid = threadIdx.x;
+    const int w = tid / kWave;
+    const int lvl = P.level;
+    const int64_t N = P.N;
+    const int n = P.n;
+    const size_t nn = (size_t)n * n;
+    const int64_t s = (int64_t)1 << lvl;
+    const int64_t h = s >> 1;
+    const int64_t i = ((int64_t)blockIdx.x * 2 + 1) << lvl;
+    const bool has_r = i + s <= N;
+    const bool has_l = i > s;
+    const bool def_self = lvl > 0 && i + h <= N;
+    const bool def_sep = lvl > 0 && has_r && i + 3 * h <= N;
+    const int64_t pi = perm_pos(N, lvl, i);
+    const int64_t pr = has_r ? perm_pos(N, level_of(i + s), i + s) : 0;
+    const double* Ssep = (lvl == 0) ? P.A_diag + (size_t)(i + s - 1) * nn : P.Ld + (size_t)pr * nn;
+
+    // P1: stage S_i, S_{i+s} and the deferred T blocks (all loads in flight)
+    {
+        Stage<NP, NT> a, b, c, d;
+        a.fetch(lvl == 0 ? P.A_diag + (size_t)(i - 1) * nn : P.Ld + (size_t)pi * nn, n, true, 1.0, tid);
+        if (def_self) b.fetch(P.Tb + (size_t)perm_pos(N, lvl - 1, i + h) * nn, n, false, 0.0, tid);
+        if (has_r) c.fetch(Ssep, n, true, 1.0, tid);
+        if (def_sep) d.fetch(P.Tb + (size_t)perm_pos(N, lvl - 1, i + 3 * h) * nn, n, false, 0.0, tid);
+        a.put(sS, tid);
+        if (def_self) b.put(sB, tid);
+        if (has_r) c.put(sC, tid);
+        if (def_sep) d.put(sD, tid);
+    }
+    if (tid == 0) fail = 0;
+    __syncthreads();
+
+    // P2: deferred syrk updates (lower tiles, round-robin over wavefronts)
+#pragma unroll
+    for (int t = 0; t < Cfg::TPW; ++t) {
+        const int k = w + W * t;
+        if (k < Cfg::NTRI) {
+            int ta, tb;
+            tri_tile(k, ta, tb);
+            if (def_self) {
+                d4 acc;
+                acc_load_lds<LD>(acc, sS, ta * kT, tb * kT);
+                mma_tile<LD, LD, true, false, true>(acc, sB, ta * kT, 0, sB, tb * kT, 0, NP);
+                acc_store_lds<LD>(acc, sS, ta * kT, tb * kT);
+            }
+            if (def_sep) {
+                d4 acc;
+                acc_load_lds<LD>(acc, sC, ta * kT, tb * kT);
+                mma_tile<LD, LD, true, false, true>(acc, sD, ta * kT, 0, sD, tb * kT, 0, NP);
+                acc_store_lds<LD>(acc, sC, ta * kT, tb * kT);
+            }
+        }
+    }
+    __syncthreads();
+
+    // P3: potrf on wavefront 0 while the others stage the couplings
+    const double* Cr = (lvl == 0) ? P.A_off + (size_t)(i - 1) * nn : P.Rb + (size_t)pi * nn;
+    const double* Cl = (lvl == 0) ? P.A_off + (size_t)(i - 2) * nn : P.Tb + (size_t)pi * nn;
+    if constexpr (W > 1) {
+        if (w == 0) {
+            const bool ok = potrf_lookahead<NP>(sS, invd, colbuf);
+            if (!ok && tid == 0) fail = 1;
+        } else {
+            Stage<NP, NT - kWave> cr, cl;
+            if (has_r) cr.fetch(Cr, n, false, 0.0, tid - kWave);
+            if (has_l) cl.fetch(Cl, n, false, 0.0, tid - kWave);
+            if (has_r) cr.put(sB, tid - kWave);
+            if (has_l) cl.put(sD, tid - kWave);
+        }
+    } else {
+        Stage<NP, NT> cr, cl;
+        if (has_r) cr.fetch(Cr, n, false, 0.0, tid);
+        if (has_l) cl.fetch(Cl, n, false, 0.0, tid);
+        const bool ok = potrf_lookahead<NP>(sS, invd, colbuf);
+        if (!ok && tid == 0) fail = 1;
+        if (has_r) cr.put(sB, tid);
+        if (has_l) cl.put(sD, tid);
+    }
+    __syncthreads();
+    if (fail) {
+        if (tid == 0) atomicMin(P.info, (unsigned long long)i);
+        return;
+    }
+
+    // P4: invert the diagonal tiles of L_ii (one per wavefront)
+    tile_inverse<LD>(sS, w * kT, invd, sInv[w]);
+    __syncthreads();
+
+    // P5: blocked triangular solves; wavefront w owns tile-row w of R and
+    // tile-column w of T
+    if (has_r) {
+#pragma unroll
+        for (int p = 0; p < W; ++p) {
+            d4 acc;
+            acc_load_lds<LD>(acc, sB, w * kT, p * kT);
+#pragma unroll
+            for (int q = 0; q < p; ++q)  // - R[w,q] L[p,q]^T
+                mma_tile<LD, LD, false, true, true>(acc, sB, w * kT, q * kT, sS, p * kT, q * kT, kT);
+            acc_store_lds<LD>(acc, sB, w * kT, p * kT);
+            d4 out = {0.0, 0.0, 0.0, 0.0};  // Y Dinv_p^T
+            mma_tile<LD, kLDI, false, true, false>(out, sB, w * kT, p * kT, sInv[p], 0, 0, kT);
+            acc_store_lds<LD>(out, sB, w * kT, p * kT);
+        }
+    }
+    if (has_l) {
+#pragma unroll
+        for (int p = 0; p < W; ++p) {
+            d4 acc;
+            acc_load_lds<LD>(acc, sD, p * kT, w * kT);
+#pragma unroll
+            for (int q = 0; q < p; ++q)  // - L[p,q] T[q,w]
+                mma_tile<LD, LD, false, false, true>(acc, sS, p * kT, q * kT, sD, w * kT, q * kT, kT);
+            acc_store_lds<LD>(acc, sD, p * kT, w * kT);
+            d4 out = {0.0, 0.0, 0.0, 0.0};  // Dinv_p Y
+            mma_tile<kLDI, LD, false, false, false>(out, sInv[p], 0, 0, sD, w * kT, p * kT, kT);
+            acc_store_lds<LD>(out, sD, p * kT, w * kT);
+        }
+    }
+    __syncthreads();
+
+    // P6: separator update S_{i+s} -= R R^T, fill -R T, stores
+    if (has_r) {
+#pragma unroll
+        for (int t = 0; t < Cfg::TPW; ++t) {
+            const int k = w + W * t;
+            if (k < Cfg::NTRI) {
+                int ta, tb;
+                tri_tile(k, ta, tb);
+                d4 acc;
+                acc_load_lds<LD>(acc, sC, ta * kT, tb * kT);
+                mma_tile<LD, LD, false, true, true>(acc, sB, ta * kT, 0, sB, tb * kT, 0, NP);
+                acc_store_global(acc, P.Ld + (size_t)pr * nn, n, ta * kT, tb * kT);
+            }
+        }
+    }
+    if (has_r && has_l) {
+        const int64_t lft = i - s, rgt = i + s;
+        double* dst = (((lft >> (lvl + 1)) & 1) != 0) ? P.Rb + (size_t)perm_pos(N, lvl + 1, lft) * nn
+                                                      : P.Tb + (size_t)perm_pos(N, lvl + 1, rgt) * nn;
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            mma_tile<LD, LD, false, false, true>(acc, sB, w * kT, 0, sD, t * kT, 0, NP);
+            acc_store_global(acc, dst, n, w * kT, t * kT);
+        }
+    }
+    lds_store<NP>(P.Ld + (size_t)pi * nn, sS, n, true, tid, NT);
+    if (has_r) lds_store<NP>(P.Rb + (size_t)pi * nn, sB, n, false, tid, NT);
+    if (has_l) lds_store<NP>(P.Tb + (size_t)pi * nn, sD, n, false, tid, NT);
+}
+
+}  // namespace
+
+hipError_t launch_factor_level_mfma(const FactorParams& p, int64_t nodes, hipStream_t st) {
+    switch (padded_block(p.n)) {
+        case 16:
+            hipLaunchKernelGGL(k_factor_level_mfma<16>, dim3((unsigned)nodes), dim3(MfmaCfg<16>::NT), 0, st, p);
+            break;
+        case 32:
+            hipLaunchKernelGGL(k_factor_level_mfma<32>, dim3((unsigned)nodes), dim3(MfmaCfg<32>::NT), 0, st, p);
+            break;
+        case 64:
+            hipLaunchKernelGGL(k_factor_level_mfma<64>, dim3((unsigned)nodes), dim3(MfmaCfg<64>::NT), 0, st, p);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace btc

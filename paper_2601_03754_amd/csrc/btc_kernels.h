@@ -40,6 +40,8 @@ struct SolveParams {
 int padded_block(int n);
 
 hipError_t launch_factor_level_f64(const FactorParams& p, int64_t nodes, hipStream_t st);
+// Matrix-core variant for padded block sizes 16, 32, 64.
+hipError_t launch_factor_level_mfma(const FactorParams& p, int64_t nodes, hipStream_t st);
 hipError_t launch_solve_level_f64(const SolveParams& p, int64_t nodes, bool backward, hipStream_t st);
 
 }  // namespace btc
