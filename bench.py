@@ -34,22 +34,26 @@ FP64_PEAK_TFLOPS = 78.6
 FP64_RIDGE = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
 
 
-def level_work(N: int, n: int, m: int = 1):
-    """Algorithmic flops and HBM bytes of every level launch of the FP64 path.
+def level_work(N: int, n: int, m: int = 1, mixed: bool = False):
+    """Algorithmic flops and HBM bytes of every level launch.
 
     Factor, per node i at level l (stride s), with the block I/O the level step
-    of Algorithm 4 defines (each n x n block read or written once, 8n^2 bytes):
+    of Algorithm 4 defines (each n x n block read or written once):
       reads  S_i, C_{i+s,i} (if right), C_{i,i-s} (if left), T_{i+s/2} (if
              deferred), S_{i+s} (if right), T_{i+3s/2} (if deferred)
       writes L_ii, R_i, T_i, S_{i+s}, fill C_{i+s,i-s} (when present)
       flops  potrf n^3/3, trsm n^3 each, syrk n^3 each, gemm 2n^3
              (cost table of section "Computational Complexity").
+    Word sizes: 8 bytes for everything on the FP64 path; on the mixed path the
+    Schur complements S and the input blocks are FP64 (8 bytes) and the factor
+    blocks L, R, T and the fill couplings FP32 (4 bytes).
     Solve, per node and sweep: reads L_ii, R_i, T_i (when present) plus the
     n x m vectors it touches; flops n^2 m per triangular solve and 2n^2 m per
     block product (Algorithm 6)."""
     out = {"factor": [], "forward": [], "backward": []}
-    w = 8.0
-    nb = w * n * n
+    wS = 8.0
+    wF = 4.0 if mixed else 8.0
+    nn = n * n
     L = int(np.floor(np.log2(N))) + 1
     for l in range(L):
         s = 1 << l
@@ -60,16 +64,18 @@ def level_work(N: int, n: int, m: int = 1):
         d_self = (i + h <= N) & (l > 0)
         d_sep = (i + 3 * h <= N) & has_r & (l > 0)
         both = has_r & has_l
-        rd = len(i) + has_r.sum() * 2 + has_l.sum() + d_self.sum() + d_sep.sum()
-        wr = len(i) + has_r.sum() * 2 + has_l.sum() + both.sum()
+        wC = 8.0 if l == 0 else wF  # level 0 reads the couplings from the FP64 input
+        rd = nn * (wS * (len(i) + has_r.sum()) + wC * (has_r.sum() + has_l.sum())
+                   + wF * (d_self.sum() + d_sep.sum()))
+        wr = nn * (wS * has_r.sum() + wF * (len(i) + has_r.sum() + has_l.sum() + both.sum()))
         fl = n ** 3 * (len(i) / 3 + 2 * has_r.sum() + has_l.sum() + d_self.sum() + d_sep.sum()
                        + 2 * both.sum())
-        out["factor"].append({"bytes": float((rd + wr) * nb), "flops": float(fl), "nodes": len(i)})
-        vec = w * n * m
+        out["factor"].append({"bytes": float(rd + wr), "flops": float(fl), "nodes": len(i)})
+        vec = wF * n * m
         blocks = len(i) + has_r.sum() + has_l.sum()
         pulls = len(i) * 2 * l  # at most 2 small vectors per lower level
-        fwd_b = blocks * nb + vec * (len(i) + pulls) + vec * (len(i) + has_r.sum() + has_l.sum())
-        bwd_b = blocks * nb + vec * (len(i) + has_r.sum() + has_l.sum()) + vec * len(i)
+        fwd_b = blocks * nn * wF + vec * (len(i) + pulls) + vec * (len(i) + has_r.sum() + has_l.sum())
+        bwd_b = blocks * nn * wF + vec * (len(i) + has_r.sum() + has_l.sum()) + vec * len(i)
         sfl = n * n * m * (len(i) + 2 * has_r.sum() + 2 * has_l.sum())
         out["forward"].append({"bytes": float(fwd_b), "flops": float(sfl), "nodes": len(i)})
         out["backward"].append({"bytes": float(bwd_b), "flops": float(sfl), "nodes": len(i)})
@@ -106,6 +112,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_ir"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the method factors one block-tridiagonal system "
@@ -125,7 +132,8 @@ def main():
     B = torch.from_numpy(pr.B).to(dev)
     X = torch.empty_like(B)
     stream = torch.cuda.current_stream()
-    f = btc.Factor(D, E)
+    prec = btc.BTC_FP64 if args.precision == "fp64" else btc.BTC_FP32_IR
+    f = btc.Factor(D, E, precision=prec)
     for _ in range(args.warmup):
         f.refactor(D, E)
         f.solve(B, X)
@@ -155,16 +163,17 @@ def main():
         f.refactor(D, E)
         f.solve(B, X)
     torch.cuda.synchronize()
-    prof = {ph: btc.btc_profile_read(f.handle, k) for k, ph in enumerate(("factor", "forward", "backward"))}
+    prof = {ph: btc.btc_profile_read(f.handle, k) for k, ph in enumerate(("factor", "forward", "backward", "refine"))}
     btc.btc_profile(f.handle, False)
 
     # accuracy of the last step, checked by the oracle's FP64 residual
     relres = oracle.relres(pr.D, pr.E, X.cpu().numpy(), pr.B)
+    _, sinfo = f.solve(B, X, want_info=True)
 
     ms_step = wall * 1e3 / args.steps
     value = args.steps / wall
 
-    work = level_work(N, n, m)
+    work = level_work(N, n, m, mixed=args.precision != "fp64")
     best = None
     for ph in ("factor", "forward", "backward"):
         ms, cnt = prof[ph]
@@ -205,11 +214,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "plain FP64 factor+solve, single instance, refactor every step",
                    "N": N, "n": n, "nrhs": m, "diag_shift": 4.0, "seed": seed,
-                   "precision": "fp64"},
+                   "precision": args.precision},
+        "refine": sinfo,
         "relres": relres,
         "gpu_event_ms_per_step": gpu_ms / args.steps,
         "gflops_per_s": tot_fl / (ms_step * 1e-3) / 1e9,

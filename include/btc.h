@@ -59,21 +59,40 @@ extern "C" {
 
 typedef struct btc_handle_s *btc_handle; /* opaque; owned by the library */
 
-/* Arithmetic of the factorization and solve. */
+/* Defaults of the refinement options (used when the field is 0). */
+#define BTC_DEFAULT_MAX_REFINE 4
+#define BTC_DEFAULT_TOL 1e-10
+
+/*
+ * Arithmetic of the factorization and solve.  The paper computes in one
+ * precision throughout and names mixed precision as future work (section
+ * "Conclusion"); BTC_FP32_IR is that extension:
+ *   BTC_FP64     every step in FP64.
+ *   BTC_FP32_IR  Schur complements and the Cholesky factorization of every
+ *                pivot block in FP64; triangular solves, Schur/fill products
+ *                and the solve sweeps in FP32 (matrix cores, FP32
+ *                accumulation); the solution is refined in FP64: the residual
+ *                b - Psi x is formed in FP64 from the original blocks and a
+ *                correction solved in FP32 is added, until the target is met.
+ *                The handle keeps pointers to A_diag and A_off for the
+ *                residual, so they must stay valid and unchanged while the
+ *                handle is used for solves.
+ */
 typedef enum {
-    BTC_FP64 = 0 /* every step in FP64 */
+    BTC_FP64 = 0,
+    BTC_FP32_IR = 1
 } btc_precision;
 
 typedef struct {
-    int32_t precision;  /* btc_precision */
-    int32_t reserved0;
-    double reserved1;
+    int32_t precision;   /* btc_precision */
+    int32_t max_refine;  /* refinement corrections after the first solve (0: default) */
+    double tol;          /* target max-column relative residual (0: default 1e-10) */
 } btc_options;
 
 typedef struct {
-    int32_t steps;      /* refinement steps taken (0 for BTC_FP64) */
-    int32_t converged;  /* 1 if the residual target was met */
-    double relres;      /* max over columns of ||b - Psi x||_2 / ||b||_2 (-1 if not computed) */
+    int32_t steps;      /* refinement corrections applied (0 for BTC_FP64) */
+    int32_t converged;  /* 1 if the residual target was met (always 1 for BTC_FP64) */
+    double relres;      /* max over columns of ||b - Psi x||_2 / ||b||_2, FP64 */
 } btc_solve_info;
 
 /*
@@ -85,7 +104,8 @@ typedef struct {
  *   stream         hipStream_t or NULL
  *   out            receives the new handle (host pointer, not NULL)
  * The handle allocates its device memory with hipMalloc here; it is freed by
- * btc_destroy.  Argument errors: -1..-7 for the argument at that position.
+ * btc_destroy.  Argument errors: -1..-7 for the argument at that position
+ * (-5 for an unknown precision or a negative max_refine / tol).
  */
 BTC_API int btc_factor(const double *A_diag, const double *A_off, int64_t N, int64_t n,
                const btc_options *opt, void *stream, btc_handle *out);
@@ -100,13 +120,18 @@ BTC_API int btc_refactor(btc_handle h, const double *A_diag, const double *A_off
 /*
  * btc_solve -- solve Psi X = B with the handle's factor: forward sweep over
  * the levels in ascending order, backward sweep in descending order
- * (section "Cholesky Solve", Algorithm 6).
- *   B, X    device [N][n][nrhs]; X may alias B
+ * (section "Cholesky Solve", Algorithm 6); with BTC_FP32_IR followed by FP64
+ * iterative refinement (see btc_precision).
+ *   B, X    device [N][n][nrhs]; X may alias B for BTC_FP64 only
  *   nrhs >= 1 (nrhs == 0 is a no-op)
  *   info    NULL, or a host struct; when non-NULL the call synchronises with
- *           the stream and fills it.
- * Returns BTC_ERR_NOT_SPD (without writing X) if the factorization is known
- * to have broken down.  Solves on one handle must not run concurrently.
+ *           the stream and fills it (for BTC_FP64 it also computes the FP64
+ *           relative residual of the solution).
+ * Refinement stops on its own on the device (no host synchronisation) once
+ * the target is met, once a step reduces the residual by less than 2x, or
+ * after max_refine corrections.  Returns BTC_ERR_NOT_SPD (without writing X)
+ * if the factorization is known to have broken down.  Solves on one handle
+ * must not run concurrently.
  */
 BTC_API int btc_solve(btc_handle h, const double *B, double *X, int64_t nrhs, void *stream,
               btc_solve_info *info);
@@ -138,7 +163,8 @@ BTC_API size_t btc_footprint_bytes(int64_t N, int64_t n, int32_t precision, int6
  *   Tb[i] = T_i = transpose of the factor block at (row i-s, column i),
  *           zero if i <= s
  * where s = 2^(number of trailing zero bits of i).  Synchronises.
- * Any of the three pointers may be NULL.
+ * Any of the three pointers may be NULL.  For BTC_FP32_IR the FP32 factor
+ * blocks are returned (widened to FP64).
  */
 BTC_API int btc_export_factor(btc_handle h, double *Ld, double *Rb, double *Tb);
 
@@ -159,7 +185,8 @@ BTC_API int btc_profile(btc_handle h, int enable);
 /*
  * btc_profile_read -- synchronise with the handle's stream and report the
  * accumulated kernel time since profiling was switched on, per level, for
- * one phase: 0 = factorization, 1 = forward sweep, 2 = backward sweep.
+ * one phase: 0 = factorization, 1 = forward sweep, 2 = backward sweep,
+ * 3 = refinement (entry 0: set-up, 1: residual, 2: convergence test).
  *   ms[l], counts[l] (host arrays of max_levels entries, either may be NULL):
  *   total milliseconds and number of launches of that phase at level l.
  * Returns the number of levels of the handle (>= 0) or an error code.

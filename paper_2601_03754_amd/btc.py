@@ -20,6 +20,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbtc.so"
 _lib = None
 
 BTC_FP64 = 0
+BTC_FP32_IR = 1
 BTC_OK = 0
 BTC_ERR_HIP = -100
 BTC_ERR_OOM = -101
@@ -31,7 +32,7 @@ i32, i64, dbl, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_vo
 
 
 class btc_options(ctypes.Structure):
-    _fields_ = [("precision", i32), ("reserved0", i32), ("reserved1", dbl)]
+    _fields_ = [("precision", i32), ("max_refine", i32), ("tol", dbl)]
 
 
 class btc_solve_info(ctypes.Structure):
@@ -108,7 +109,7 @@ def _stream(stream) -> int:
 
 
 def btc_factor(A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_FP64,
-               stream=None) -> int:
+               stream=None, max_refine: int = 0, tol: float = 0.0) -> int:
     """Factor; returns the raw handle (int)."""
     N, n, n2 = A_diag.shape
     if n != n2:
@@ -117,7 +118,7 @@ def btc_factor(A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_F
     po = _dev(A_off, "A_off") if N > 1 else 0
     if N > 1 and tuple(A_off.shape) != (N - 1, n, n):
         raise ValueError("A_off must be (N-1, n, n)")
-    opt = btc_options(precision, 0, 0.0)
+    opt = btc_options(precision, max_refine, tol)
     h = vp()
     with torch.cuda.device(A_diag.device):
         _check(lib().btc_factor(pa, po, N, n, ctypes.byref(opt), _stream(stream), ctypes.byref(h)),
@@ -199,14 +200,14 @@ class Factor:
     device may still read them."""
 
     def __init__(self, A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_FP64,
-                 stream=None):
+                 stream=None, max_refine: int = 0, tol: float = 0.0):
         if A_off is None or A_off.numel() == 0:
             A_off = torch.zeros((0, A_diag.shape[1], A_diag.shape[1]), dtype=A_diag.dtype,
                                 device=A_diag.device)
         self.N, self.n = int(A_diag.shape[0]), int(A_diag.shape[1])
         self.precision = precision
         self._A = (A_diag, A_off)
-        self.handle = btc_factor(A_diag, A_off, precision, stream)
+        self.handle = btc_factor(A_diag, A_off, precision, stream, max_refine, tol)
 
     def refactor(self, A_diag: torch.Tensor, A_off: torch.Tensor, stream=None) -> "Factor":
         btc_refactor(self.handle, A_diag, A_off, stream)
@@ -236,5 +237,6 @@ class Factor:
             pass
 
 
-def factor(A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_FP64, stream=None) -> Factor:
-    return Factor(A_diag, A_off, precision, stream)
+def factor(A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_FP64, stream=None,
+           max_refine: int = 0, tol: float = 0.0) -> Factor:
+    return Factor(A_diag, A_off, precision, stream, max_refine, tol)

@@ -72,24 +72,24 @@ __device__ __forceinline__ void lds_load(double* __restrict__ dst, const double*
 // threads: fetch() issues all of the thread's global loads into registers (so
 // that every load of several blocks is in flight at once), put() writes them
 // to the padded LDS tile.  Same element mapping and padding as lds_load.
-template <int NP, int NTH>
+template <int NP, int NTH, class V = double>
 struct Stage {
     static constexpr int PER = (NP * NP + NTH - 1) / NTH;
-    double v[PER];
+    V v[PER];
 
-    __device__ __forceinline__ void fetch(const double* __restrict__ src, int n, bool lower_only,
-                                          double pad_diag, int t) {
+    template <class S>
+    __device__ __forceinline__ void fetch(const S* __restrict__ src, int n, bool lower_only, double pad_diag, int t) {
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int e = t + NTH * k;
             const int r = e / NP, c = e % NP;
-            double x = (r == c) ? pad_diag : 0.0;
-            if (e < NP * NP && r < n && c < n && (!lower_only || c <= r)) x = src[(size_t)r * n + c];
+            V x = (V)((r == c) ? pad_diag : 0.0);
+            if (e < NP * NP && r < n && c < n && (!lower_only || c <= r)) x = (V)src[(size_t)r * n + c];
             v[k] = x;
         }
     }
 
-    __device__ __forceinline__ void put(double* __restrict__ dst, int t) const {
+    __device__ __forceinline__ void put(V* __restrict__ dst, int t) const {
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int e = t + NTH * k;
@@ -97,6 +97,16 @@ struct Stage {
         }
     }
 };
+
+// Store the leading n x n part of an LDS tile of type S as type D.
+template <int NP, class D, class S>
+__device__ __forceinline__ void lds_store_as(D* __restrict__ dst, const S* __restrict__ src, int n, bool lower_only,
+                                             int t, int nt) {
+    for (int idx = t; idx < NP * NP; idx += nt) {
+        const int r = idx / NP, c = idx % NP;
+        if (r < n && c < n) dst[(size_t)r * n + c] = (D)((!lower_only || c <= r) ? src[r * (NP + 1) + c] : S(0));
+    }
+}
 
 // Write the leading n x n part of an LDS tile to global memory
 // (lower_only: the strict upper triangle is written as 0).

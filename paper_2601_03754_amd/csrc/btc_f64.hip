@@ -1,5 +1,6 @@
-// FP64 level kernels of libbtc: one workgroup per block (node) of one level of
-// the multi-stage elimination tree.
+// FP64 factorization level kernel on the vector ALUs (used for block sizes
+// n <= 8): one workgroup per block (node) of one level of the multi-stage
+// elimination tree.
 //
 // Factorization (section "Multi-Stage Permutation", Algorithm 4, the hybrid
 // left/right-looking form): at level l (stride s) node i
@@ -15,13 +16,6 @@
 // Every separator has exactly one owner per level, so no two workgroups of a
 // launch write the same block and the result is deterministic (no atomics).
 //
-// Solve (section "Cholesky Solve", Algorithm 6), two launches per level:
-//   forward (levels ascending): y_i = L_ii^{-1}(b_i - pulled contributions),
-//     u_i = R_i y_i (for the right neighbour), v_i = T_i^T y_i (for the left
-//     one).  Instead of two nodes subtracting into the same y concurrently,
-//     node i PULLS the u/v vectors its children left for it at every lower
-//     level: i - 2^l' and i + 2^l' for l' < l, a fixed summation order.
-//   backward (levels descending): x_i = L_ii^{-T}(y_i - R_i^T x_{i+s} - T_i x_{i-s}).
 #include "btc_device.h"
 #include "btc_kernels.h"
 
@@ -182,169 +176,12 @@ __global__ __launch_bounds__(NT) void k_factor_level_f64(FactorParams P) {
 }
 
 // ---------------------------------------------------------------------------
-// Solve.  One workgroup per node; wavefront w handles right-hand-side columns
-// q = w, w + nwaves, ...; lane r owns row r of the block.
-
-template <int NP, int NT>
-__global__ __launch_bounds__(NT) void k_forward_level_f64(SolveParams P) {
-    constexpr int LD = NP + 1;
-    constexpr int NW = NT / kWave;
-    __shared__ double sL[NP * LD];
-    __shared__ double sR[NP * LD];
-    __shared__ double sT[NP * LD];
-    __shared__ double invd[NP];
-    __shared__ double sy[NW][NP];
-
-    if (*P.info != kInfoOk) return;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-    const int lvl = P.level;
-    const int64_t N = P.N;
-    const int n = P.n, m = P.m;
-    const size_t nn = (size_t)n * n, nm = (size_t)n * m;
-    const int64_t s = (int64_t)1 << lvl;
-    const int64_t i = ((int64_t)blockIdx.x * 2 + 1) << lvl;
-    const bool has_r = i + s <= N, has_l = i > s;
-    const int64_t pi = perm_pos(N, lvl, i);
-
-    {
-        Stage<NP, NT> a, b, c;
-        a.fetch(P.Ld + (size_t)pi * nn, n, true, 1.0, tid);
-        if (has_r) b.fetch(P.Rb + (size_t)pi * nn, n, false, 0.0, tid);
-        if (has_l) c.fetch(P.Tb + (size_t)pi * nn, n, false, 0.0, tid);
-        a.put(sL, tid);
-        if (has_r) b.put(sR, tid);
-        if (has_l) c.put(sT, tid);
-    }
-    __syncthreads();
-    if (tid < NP) invd[tid] = 1.0 / sL[tid * LD + tid];
-    __syncthreads();
-
-    for (int q = w; q < m; q += NW) {
-        // right-hand side minus the contributions pulled from lower levels
-        double acc = 0.0;
-        if (lane < n) {
-            acc = P.B[((size_t)(i - 1) * n + lane) * m + q];
-            // contributions of the children at every lower level, gathered
-            // eight levels at a time so the loads are in flight together
-            for (int l0 = 0; l0 < lvl; l0 += 8) {
-                double pu[8], pv[8];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int l2 = l0 + k;
-                    const int64_t s2 = (int64_t)1 << l2;
-                    pu[k] = (l2 < lvl) ? P.U[(size_t)perm_pos(N, l2, i - s2) * nm + (size_t)lane * m + q] : 0.0;
-                    pv[k] = (l2 < lvl && i + s2 <= N)
-                                ? P.V[(size_t)perm_pos(N, l2, i + s2) * nm + (size_t)lane * m + q]
-                                : 0.0;
-                }
-#pragma unroll
-                for (int k = 0; k < 8; ++k) acc -= pu[k] + pv[k];
-            }
-        }
-        // y = L^{-1} acc: column sweep, pivot broadcast by readlane
-#pragma unroll 8
-        for (int j = 0; j < NP; ++j) {
-            const double yj = readlane_d(acc, j) * invd[j];
-            if (lane == j) acc = yj;
-            if (lane > j && lane < NP) acc = fma(-sL[lane * LD + j], yj, acc);
-        }
-        if (lane < NP) sy[w][lane] = acc;
-        wave_lds_sync();
-        if (lane < n) {
-            P.Y[(size_t)pi * nm + (size_t)lane * m + q] = acc;
-            if (has_r) {
-                double u = 0.0;
-                for (int c = 0; c < n; ++c) u = fma(sR[lane * LD + c], sy[w][c], u);
-                P.U[(size_t)pi * nm + (size_t)lane * m + q] = u;
-            }
-            if (has_l) {
-                double v = 0.0;
-                for (int c = 0; c < n; ++c) v = fma(sT[c * LD + lane], sy[w][c], v);
-                P.V[(size_t)pi * nm + (size_t)lane * m + q] = v;
-            }
-        }
-        wave_lds_sync();
-    }
-}
-
-template <int NP, int NT>
-__global__ __launch_bounds__(NT) void k_backward_level_f64(SolveParams P) {
-    constexpr int LD = NP + 1;
-    constexpr int NW = NT / kWave;
-    __shared__ double sL[NP * LD];
-    __shared__ double sR[NP * LD];
-    __shared__ double sT[NP * LD];
-    __shared__ double invd[NP];
-    __shared__ double sxr[NW][NP];
-    __shared__ double sxl[NW][NP];
-
-    if (*P.info != kInfoOk) return;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-    const int lvl = P.level;
-    const int64_t N = P.N;
-    const int n = P.n, m = P.m;
-    const size_t nn = (size_t)n * n, nm = (size_t)n * m;
-    const int64_t s = (int64_t)1 << lvl;
-    const int64_t i = ((int64_t)blockIdx.x * 2 + 1) << lvl;
-    const bool has_r = i + s <= N, has_l = i > s;
-    const int64_t pi = perm_pos(N, lvl, i);
-
-    {
-        Stage<NP, NT> a, b, c;
-        a.fetch(P.Ld + (size_t)pi * nn, n, true, 1.0, tid);
-        if (has_r) b.fetch(P.Rb + (size_t)pi * nn, n, false, 0.0, tid);
-        if (has_l) c.fetch(P.Tb + (size_t)pi * nn, n, false, 0.0, tid);
-        a.put(sL, tid);
-        if (has_r) b.put(sR, tid);
-        if (has_l) c.put(sT, tid);
-    }
-    __syncthreads();
-    if (tid < NP) invd[tid] = 1.0 / sL[tid * LD + tid];
-    __syncthreads();
-
-    for (int q = w; q < m; q += NW) {
-        double acc = 0.0;
-        if (lane < NP) {
-            sxr[w][lane] = (has_r && lane < n) ? P.X[((size_t)(i + s - 1) * n + lane) * m + q] : 0.0;
-            sxl[w][lane] = (has_l && lane < n) ? P.X[((size_t)(i - s - 1) * n + lane) * m + q] : 0.0;
-        }
-        wave_lds_sync();
-        if (lane < n) {
-            acc = P.Y[(size_t)pi * nm + (size_t)lane * m + q];
-            if (has_r)
-                for (int c = 0; c < n; ++c) acc = fma(-sR[c * LD + lane], sxr[w][c], acc);
-            if (has_l)
-                for (int c = 0; c < n; ++c) acc = fma(-sT[lane * LD + c], sxl[w][c], acc);
-        }
-        // x = L^{-T} acc: backward column sweep
-#pragma unroll 8
-        for (int j = NP - 1; j >= 0; --j) {
-            const double xj = readlane_d(acc, j) * invd[j];
-            if (lane == j) acc = xj;
-            if (lane < j) acc = fma(-sL[j * LD + lane], xj, acc);
-        }
-        if (lane < n) P.X[((size_t)(i - 1) * n + lane) * m + q] = acc;
-        wave_lds_sync();
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Host-side launchers (one per level).
 
 template <int NP>
 static hipError_t launch_factor_np(const FactorParams& p, int64_t nodes, hipStream_t st) {
     constexpr int NT = F64Cfg<NP>::NT;
     hipLaunchKernelGGL((k_factor_level_f64<NP, NT>), dim3((unsigned)nodes), dim3(NT), 0, st, p);
-    return hipGetLastError();
-}
-
-template <int NP>
-static hipError_t launch_solve_np(const SolveParams& p, int64_t nodes, bool backward, hipStream_t st) {
-    constexpr int NT = F64Cfg<NP>::NT;
-    if (backward)
-        hipLaunchKernelGGL((k_backward_level_f64<NP, NT>), dim3((unsigned)nodes), dim3(NT), 0, st, p);
-    else
-        hipLaunchKernelGGL((k_forward_level_f64<NP, NT>), dim3((unsigned)nodes), dim3(NT), 0, st, p);
     return hipGetLastError();
 }
 
@@ -362,16 +199,6 @@ hipError_t launch_factor_level_f64(const FactorParams& p, int64_t nodes, hipStre
         case 16: return launch_factor_np<16>(p, nodes, st);
         case 32: return launch_factor_np<32>(p, nodes, st);
         case 64: return launch_factor_np<64>(p, nodes, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_solve_level_f64(const SolveParams& p, int64_t nodes, bool backward, hipStream_t st) {
-    switch (padded_block(p.n)) {
-        case 8: return launch_solve_np<8>(p, nodes, backward, st);
-        case 16: return launch_solve_np<16>(p, nodes, backward, st);
-        case 32: return launch_solve_np<32>(p, nodes, backward, st);
-        case 64: return launch_solve_np<64>(p, nodes, backward, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -19,158 +19,13 @@
 //   P6  S_{i+s} -= R_i R_i^T (into the accumulators), fill -R_i T_i; stores.
 #include "btc_device.h"
 #include "btc_kernels.h"
+#include "btc_tiles.h"
 
 namespace btc {
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
+using namespace tiles;
 constexpr unsigned long long kInfoOk = ~0ull;
-constexpr int kT = 16;       // tile side
-constexpr int kLDI = kT + 1; // row stride of an inverted diagonal tile in LDS
-
-// f64 16x16x4 accumulator layout: register v of lane l holds tile element
-// (4v + l/16, l%16).  Operand layouts: A[i][k] in lane i + 16k, B[k][j] in
-// lane j + 16k.
-__device__ __forceinline__ int acc_r(int v, int lane) { return 4 * v + (lane >> 4); }
-__device__ __forceinline__ int acc_c(int lane) { return lane & 15; }
-
-// acc += (NEG ? -1 : 1) * sum_{kk<K} opA[ra+i][ka+kk] * opB[kb+kk][cb+j]
-//   opA[r][k] = TA ? A[k][r] : A[r][k],  opB[k][c] = TB ? B[c][k] : B[k][c]
-template <int LDA, int LDB, bool TA, bool TB, bool NEG>
-__device__ __forceinline__ void mma_tile(d4& acc, const double* __restrict__ A, int ra, int ka,
-                                         const double* __restrict__ B, int cb, int kb, int K) {
-    const int lane = threadIdx.x & 63;
-    const int i = lane & 15, q = lane >> 4;
-#pragma unroll 4
-    for (int kk = 0; kk < K; kk += 4) {
-        const int k1 = ka + kk + q, k2 = kb + kk + q;
-        double a = TA ? A[k1 * LDA + ra + i] : A[(ra + i) * LDA + k1];
-        const double b = TB ? B[(cb + i) * LDB + k2] : B[k2 * LDB + cb + i];
-        if (NEG) a = -a;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    }
-}
-
-template <int LD>
-__device__ __forceinline__ void acc_load_lds(d4& acc, const double* __restrict__ S, int r0, int c0) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] = S[(r0 + acc_r(v, lane)) * LD + c0 + acc_c(lane)];
-}
-
-template <int LD>
-__device__ __forceinline__ void acc_store_lds(const d4& acc, double* __restrict__ S, int r0, int c0) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) S[(r0 + acc_r(v, lane)) * LD + c0 + acc_c(lane)] = acc[v];
-}
-
-// Load a tile of an n x n global block (lower triangle only, identity padding).
-__device__ __forceinline__ void acc_load_sym(d4& acc, const double* __restrict__ src, int n, int r0, int c0) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int r = r0 + acc_r(v, lane), c = c0 + acc_c(lane);
-        double x = (r == c) ? 1.0 : 0.0;
-        if (r < n && c < n && c <= r) x = src[(size_t)r * n + c];
-        acc[v] = x;
-    }
-}
-
-__device__ __forceinline__ void acc_store_global(const d4& acc, double* __restrict__ dst, int n, int r0, int c0) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int r = r0 + acc_r(v, lane), c = c0 + acc_c(lane);
-        if (r < n && c < n) dst[(size_t)r * n + c] = acc[v];
-    }
-}
-
-// k-th lower-triangle tile (a, b), b <= a, in row-major order of the triangle.
-__device__ __forceinline__ void tri_tile(int k, int& a, int& b) {
-    a = 0;
-    while ((a + 1) * (a + 2) / 2 <= k) ++a;
-    b = k - a * (a + 1) / 2;
-}
-
-// Cholesky of the lower triangle of an NP x NP LDS tile by one wavefront,
-// lane r holding row r in registers.  The pivot of step j+1 is formed right
-// after step j from two readlanes (the new column j value of row j+1 is its
-// own multiplier), so the pivot chain never waits for the LDS broadcast; the
-// rest of the column is broadcast through a double-buffered LDS column for
-// the trailing update.  1/sqrt of the pivot: hardware estimate refined by two
-// Newton steps.  Writes L (zero strict upper part) back and 1/L_jj to invd.
-template <int NP>
-__device__ __forceinline__ bool potrf_lookahead(double* __restrict__ A, double* __restrict__ invd,
-                                                double (*__restrict__ colbuf)[kWave]) {
-    static_assert(NP <= kWave, "one lane per row");
-    constexpr int LD = NP + 1;
-    const int lane = threadIdx.x & (kWave - 1);
-    double a[NP];
-#pragma unroll
-    for (int c = 0; c < NP; ++c) a[c] = (lane < NP && c <= lane) ? A[lane * LD + c] : 0.0;
-    double piv = readlane_d(a[0], 0);
-    double myinv = 1.0;  // 1/L_rr of this lane's row r
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        ok = ok && (piv > 0.0);
-        double r = __builtin_amdgcn_rsq(piv);
-        double e = fma(-piv * r, r, 1.0);
-        r = fma(0.5 * r, e, r);
-        e = fma(-piv * r, r, 1.0);
-        r = fma(0.5 * r, e, r);
-        const double d = piv * r;
-        double l = a[j] * r;
-        l = (lane == j) ? d : l;
-        l = (lane < j) ? 0.0 : l;
-        myinv = (lane == j) ? r : myinv;
-        a[j] = l;
-        if (j + 1 < NP) {
-            double* cb = colbuf[j & 1];
-            cb[lane] = l;
-            const double lj1 = readlane_d(l, j + 1);
-            a[j + 1] = fma(-l, lj1, a[j + 1]);
-            piv = readlane_d(a[j + 1], j + 1);
-#pragma unroll
-            for (int c0 = (j + 2) & ~1; c0 < NP; c0 += 2) {
-                const double2 v = *reinterpret_cast<const double2*>(cb + c0);
-                if (c0 >= j + 2) a[c0] = fma(-l, v.x, a[c0]);
-                a[c0 + 1] = fma(-l, v.y, a[c0 + 1]);
-            }
-        }
-    }
-    if (lane < NP) {
-#pragma unroll
-        for (int c = 0; c < NP; ++c) A[lane * LD + c] = (c <= lane) ? a[c] : 0.0;
-        invd[lane] = myinv;
-    }
-    return ok;
-}
-
-// Inverse of the 16 x 16 lower-triangular diagonal tile of L starting at
-// (r0, r0) into Dinv (row stride kLDI): lane c (< 16) forward-substitutes the
-// unit vector e_c.
-template <int LD>
-__device__ __forceinline__ void tile_inverse(const double* __restrict__ L, int r0, const double* __restrict__ invd,
-                                             double* __restrict__ Dinv) {
-    const int lane = threadIdx.x & 63;
-    const int c = lane & 15;
-    double x[kT];
-#pragma unroll
-    for (int j = 0; j < kT; ++j) x[j] = (j == c) ? 1.0 : 0.0;
-#pragma unroll
-    for (int j = 0; j < kT; ++j) {
-        x[j] *= invd[r0 + j];
-#pragma unroll
-        for (int k = j + 1; k < kT; ++k) x[k] = fma(-L[(r0 + k) * LD + r0 + j], x[j], x[k]);
-    }
-    if (lane < kT) {
-#pragma unroll
-        for (int j = 0; j < kT; ++j) Dinv[j * kLDI + c] = x[j];
-    }
-}
 
 template <int NP>
 struct MfmaCfg {

@@ -60,9 +60,14 @@ def test_permutation_matches_oracle(lib, N):
 
 
 def test_footprint(lib):
-    assert lib.btc_footprint_bytes(16, 8, 0, 1) == 3 * 16 * 64 * 8 + 8 + 3 * 16 * 8 * 8
+    fp64 = lib.btc_footprint_bytes(16, 8, lib.BTC_FP64, 0)
+    assert fp64 == 3 * 16 * 64 * 8 + 8  # three n x n FP64 blocks per node + info word
+    mixed = lib.btc_footprint_bytes(16, 8, lib.BTC_FP32_IR, 0)
+    assert mixed == 16 * 64 * (8 + 3 * 4) + 8  # FP64 Schur complements + FP32 factor
+    assert lib.btc_footprint_bytes(16, 8, lib.BTC_FP64, 4) > lib.btc_footprint_bytes(16, 8, lib.BTC_FP64, 1) > fp64
     assert lib.btc_footprint_bytes(0, 8, 0, 1) == 0
     assert lib.btc_footprint_bytes(16, 65, 0, 1) == 0
+    assert lib.btc_footprint_bytes(16, 8, 7, 1) == 0
 
 
 def test_argument_errors_before_device_work(lib):
