@@ -111,6 +111,13 @@ BTC_API int btc_factor(const double *A_diag, const double *A_off, int64_t N, int
                const btc_options *opt, void *stream, btc_handle *out);
 
 /*
+ * btc_create -- allocate a handle for systems of this shape and precision
+ * without factoring anything yet (for btc_refactor, the batched entry points
+ * and the step runner).  Same argument rules as btc_factor.
+ */
+BTC_API int btc_create(int64_t N, int64_t n, const btc_options *opt, btc_handle *out);
+
+/*
  * btc_refactor -- factor a new matrix of the same (N, n) into an existing
  * handle, reusing its device memory (repeated factorizations, e.g. the
  * re-linearised systems of successive model-predictive-control steps).
@@ -192,6 +199,87 @@ BTC_API int btc_profile(btc_handle h, int enable);
  * Returns the number of levels of the handle (>= 0) or an error code.
  */
 BTC_API int btc_profile_read(btc_handle h, int phase, double *ms, int64_t *counts, int max_levels);
+
+/* ------------------------------------------------------------------------
+ * Many instances per launch.
+ *
+ * The elimination of section "Multi-Stage Permutation" is a sequence of
+ * level steps; steps of different instances are independent.  A runner
+ * executes a list of level steps of many handles (of any sizes, at any
+ * levels) with one kernel launch per operation and block-size class, each
+ * launch carrying the work items (nodes, block rows) of all its steps.
+ * Batched factorization / solve of independent instances and continuous
+ * batching of requests (new requests joining while others are mid-tree) are
+ * built on it.  All runner work is enqueued on the runner's stream; handles
+ * used with a runner adopt that stream.
+ */
+typedef struct btc_runner_s *btc_runner;
+
+typedef enum {
+    BTC_OP_FACTOR = 0,       /* one level of the factorization (level 0 also resets the status) */
+    BTC_OP_FORWARD = 1,      /* one level of the forward sweep */
+    BTC_OP_BACKWARD = 2,     /* one level of the backward sweep */
+    BTC_OP_RESIDUAL = 3,     /* FP64 residual b - Psi x and its column norms */
+    BTC_OP_REFINE_INIT = 4,  /* reset the refinement state of a solve */
+    BTC_OP_REFINE_TEST = 5   /* convergence test of the refinement */
+} btc_op;
+
+typedef struct {
+    btc_handle h;
+    int32_t op;             /* btc_op */
+    int32_t level;          /* FACTOR / FORWARD / BACKWARD: level 0 .. floor(log2 N) */
+    const double *A_diag;   /* FACTOR at level 0: the matrix (device; kept for RESIDUAL) */
+    const double *A_off;
+    const double *B;        /* sweeps / RESIDUAL: right-hand side [N][n][nrhs] (device) */
+    double *X;              /* sweeps / RESIDUAL: solution / iterate (device) */
+    int64_t nrhs;           /* >= 1 for every op but FACTOR */
+    int32_t first;          /* BTC_FP32_IR sweeps: 1 for the first solve (reads B, sets X) */
+    int32_t pad;
+} btc_step;
+
+/* btc_runner_create -- a runner enqueuing on `stream` (hipStream_t or NULL). */
+BTC_API int btc_runner_create(void *stream, btc_runner *out);
+
+/*
+ * btc_runner_run -- enqueue `count` steps (host array).  Steps of one call
+ * must not depend on each other (at most one step per handle per call);
+ * calls are executed in order.  Returns once the work is enqueued; -3 for an
+ * invalid step (unknown op, level out of range, missing pointers, a sweep or
+ * residual on a handle never factored).
+ */
+BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step *steps);
+
+/* btc_runner_query -- 1 if all enqueued work has finished, 0 if not. */
+BTC_API int btc_runner_query(btc_runner r);
+
+/* btc_runner_sync -- wait for all enqueued work. */
+BTC_API int btc_runner_sync(btc_runner r);
+
+/* btc_runner_destroy -- wait for the runner's work and free it (NULL: no-op). */
+BTC_API void btc_runner_destroy(btc_runner r);
+
+/*
+ * btc_factor_batched -- factor `count` independent instances (handles from
+ * btc_create, host arrays of device pointers), walking their levels together.
+ */
+BTC_API int btc_factor_batched(btc_runner r, int32_t count, const btc_handle *h, const double *const *A_diag,
+                               const double *const *A_off);
+
+/*
+ * btc_solve_batched -- solve `count` independent instances, nrhs columns
+ * each (BTC_FP32_IR handles are refined in FP64 as in btc_solve; X must not
+ * alias B for them).  Status per handle: btc_status; refinement outcome:
+ * btc_refine_info.
+ */
+BTC_API int btc_solve_batched(btc_runner r, int32_t count, const btc_handle *h, const double *const *B,
+                              double *const *X, int64_t nrhs);
+
+/*
+ * btc_refine_info -- synchronise with the handle's stream and report the
+ * outcome of its last solve made through a runner (steps, converged, relres
+ * as in btc_solve_info).
+ */
+BTC_API int btc_refine_info(btc_handle h, btc_solve_info *info);
 
 /* btc_error_string -- static text for a return code. */
 BTC_API const char *btc_error_string(int code);

@@ -39,6 +39,15 @@ class btc_solve_info(ctypes.Structure):
     _fields_ = [("steps", i32), ("converged", i32), ("relres", dbl)]
 
 
+BTC_OP_FACTOR, BTC_OP_FORWARD, BTC_OP_BACKWARD = 0, 1, 2
+BTC_OP_RESIDUAL, BTC_OP_REFINE_INIT, BTC_OP_REFINE_TEST = 3, 4, 5
+
+
+class btc_step(ctypes.Structure):
+    _fields_ = [("h", vp), ("op", i32), ("level", i32), ("A_diag", vp), ("A_off", vp), ("B", vp), ("X", vp),
+                ("nrhs", i64), ("first", i32), ("pad", i32)]
+
+
 class BtcError(RuntimeError):
     def __init__(self, code: int, what: str):
         super().__init__("%s failed: %d (%s)" % (what, code, btc_error_string(code)))
@@ -75,6 +84,24 @@ def lib():
         L.btc_profile.argtypes = [vp, ctypes.c_int]
         L.btc_profile_read.restype = ctypes.c_int
         L.btc_profile_read.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int]
+        L.btc_create.restype = ctypes.c_int
+        L.btc_create.argtypes = [i64, i64, ctypes.POINTER(btc_options), ctypes.POINTER(vp)]
+        L.btc_runner_create.restype = ctypes.c_int
+        L.btc_runner_create.argtypes = [vp, ctypes.POINTER(vp)]
+        L.btc_runner_run.restype = ctypes.c_int
+        L.btc_runner_run.argtypes = [vp, i32, ctypes.POINTER(btc_step)]
+        L.btc_runner_query.restype = ctypes.c_int
+        L.btc_runner_query.argtypes = [vp]
+        L.btc_runner_sync.restype = ctypes.c_int
+        L.btc_runner_sync.argtypes = [vp]
+        L.btc_runner_destroy.restype = None
+        L.btc_runner_destroy.argtypes = [vp]
+        L.btc_factor_batched.restype = ctypes.c_int
+        L.btc_factor_batched.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
+        L.btc_solve_batched.restype = ctypes.c_int
+        L.btc_solve_batched.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i64]
+        L.btc_refine_info.restype = ctypes.c_int
+        L.btc_refine_info.argtypes = [vp, ctypes.POINTER(btc_solve_info)]
         L.btc_version.restype = ctypes.c_int
         L.btc_version.argtypes = []
         _lib = L
@@ -189,6 +216,83 @@ def btc_profile_read(h: int, phase: int):
     if L < 0:
         _check(L, "btc_profile_read")
     return ms[:L].copy(), cnt[:L].copy()
+
+
+def btc_create(N: int, n: int, precision: int = BTC_FP64, max_refine: int = 0, tol: float = 0.0) -> int:
+    """Allocate a handle (no factorization) on the current device."""
+    h = vp()
+    opt = btc_options(precision, max_refine, tol)
+    _check(lib().btc_create(N, n, ctypes.byref(opt), ctypes.byref(h)), "btc_create")
+    return h.value
+
+
+def btc_refine_info(h: int) -> dict:
+    info = btc_solve_info()
+    _check(lib().btc_refine_info(h, ctypes.byref(info)), "btc_refine_info")
+    return {"steps": info.steps, "converged": bool(info.converged), "relres": info.relres}
+
+
+def _ptr_array(vals):
+    arr = (vp * max(1, len(vals)))()
+    for k, v in enumerate(vals):
+        arr[k] = v
+    return arr
+
+
+class Runner:
+    """A libbtc step runner bound to one stream (default: torch's current
+    stream of the current device)."""
+
+    def __init__(self, stream=None):
+        self.stream = _stream(stream)
+        r = vp()
+        _check(lib().btc_runner_create(self.stream, ctypes.byref(r)), "btc_runner_create")
+        self.handle = r.value
+
+    def run(self, steps) -> None:
+        arr = (btc_step * max(1, len(steps)))(*steps)
+        _check(lib().btc_runner_run(self.handle, len(steps), arr), "btc_runner_run")
+
+    def query(self) -> bool:
+        rc = lib().btc_runner_query(self.handle)
+        if rc < 0:
+            _check(rc, "btc_runner_query")
+        return rc == 1
+
+    def sync(self) -> None:
+        _check(lib().btc_runner_sync(self.handle), "btc_runner_sync")
+
+    def factor_batched(self, handles, A_diags, A_offs) -> None:
+        n = len(handles)
+        _check(lib().btc_factor_batched(self.handle, n, _ptr_array(handles),
+                                        _ptr_array([_dev(a, "A_diag") for a in A_diags]),
+                                        _ptr_array([_dev(a, "A_off") if a.numel() else 0 for a in A_offs])),
+               "btc_factor_batched")
+
+    def solve_batched(self, handles, Bs, Xs, nrhs: int) -> None:
+        n = len(handles)
+        _check(lib().btc_solve_batched(self.handle, n, _ptr_array(handles),
+                                       _ptr_array([_dev(b, "B") for b in Bs]),
+                                       _ptr_array([_dev(x, "X") for x in Xs]), nrhs),
+               "btc_solve_batched")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().btc_runner_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def step(h: int, op: int, level: int = 0, A_diag=None, A_off=None, B=None, X=None, nrhs: int = 0,
+         first: bool = False) -> btc_step:
+    """One level step for Runner.run (tensor arguments are device tensors)."""
+    ptr = lambda t: (t.data_ptr() if (t is not None and t.numel()) else 0)
+    return btc_step(h, op, level, ptr(A_diag), ptr(A_off), ptr(B), ptr(X), nrhs, 1 if first else 0, 0)
 
 
 def btc_version() -> int:

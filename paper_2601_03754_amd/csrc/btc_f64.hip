@@ -31,7 +31,7 @@ struct F64Cfg {
 };
 
 template <int NP, int NT>
-__global__ __launch_bounds__(NT) void k_factor_level_f64(FactorParams P) {
+__global__ __launch_bounds__(NT) void k_factor_level_f64(Launch<FactorDesc> L) {
     constexpr int LD = NP + 1;
     static_assert(NT >= 2 * NP, "one thread per trsm vector");
     __shared__ double sA[NP * LD];  // S_i -> L_ii
@@ -42,16 +42,19 @@ __global__ __launch_bounds__(NT) void k_factor_level_f64(FactorParams P) {
     __shared__ double colbuf[kWave];
     __shared__ int fail;
 
+    FactorDesc P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
     if (*P.info != kInfoOk) return;  // an earlier level broke down
 
     const int tid = threadIdx.x;
-    const int lvl = P.level;
     const int64_t N = P.N;
     const int n = P.n;
     const size_t nn = (size_t)n * n;
     const int64_t s = (int64_t)1 << lvl;
     const int64_t h = s >> 1;
-    const int64_t i = ((int64_t)blockIdx.x * 2 + 1) << lvl;
+    const int64_t i = (kk * 2 + 1) << lvl;
     const bool has_r = i + s <= N;
     const bool has_l = i > s;
     const bool def_self = lvl > 0 && i + h <= N;
@@ -178,13 +181,6 @@ __global__ __launch_bounds__(NT) void k_factor_level_f64(FactorParams P) {
 // ---------------------------------------------------------------------------
 // Host-side launchers (one per level).
 
-template <int NP>
-static hipError_t launch_factor_np(const FactorParams& p, int64_t nodes, hipStream_t st) {
-    constexpr int NT = F64Cfg<NP>::NT;
-    hipLaunchKernelGGL((k_factor_level_f64<NP, NT>), dim3((unsigned)nodes), dim3(NT), 0, st, p);
-    return hipGetLastError();
-}
-
 int padded_block(int n) {
     if (n <= 8) return 8;
     if (n <= 16) return 16;
@@ -193,14 +189,16 @@ int padded_block(int n) {
     return 0;
 }
 
-hipError_t launch_factor_level_f64(const FactorParams& p, int64_t nodes, hipStream_t st) {
-    switch (padded_block(p.n)) {
-        case 8: return launch_factor_np<8>(p, nodes, st);
-        case 16: return launch_factor_np<16>(p, nodes, st);
-        case 32: return launch_factor_np<32>(p, nodes, st);
-        case 64: return launch_factor_np<64>(p, nodes, st);
+hipError_t launch_factor_valu(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st) {
+    const dim3 g((unsigned)items);
+    switch (np) {
+        case 8: hipLaunchKernelGGL((k_factor_level_f64<8, F64Cfg<8>::NT>), g, dim3(F64Cfg<8>::NT), 0, st, p); break;
+        case 16: hipLaunchKernelGGL((k_factor_level_f64<16, F64Cfg<16>::NT>), g, dim3(F64Cfg<16>::NT), 0, st, p); break;
+        case 32: hipLaunchKernelGGL((k_factor_level_f64<32, F64Cfg<32>::NT>), g, dim3(F64Cfg<32>::NT), 0, st, p); break;
+        case 64: hipLaunchKernelGGL((k_factor_level_f64<64, F64Cfg<64>::NT>), g, dim3(F64Cfg<64>::NT), 0, st, p); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
 }
 
 }  // namespace btc

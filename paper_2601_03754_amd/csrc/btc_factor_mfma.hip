@@ -36,7 +36,7 @@ struct MfmaCfg {
 };
 
 template <int NP>
-__global__ __launch_bounds__(MfmaCfg<NP>::NT) void k_factor_level_mfma(FactorParams P) {
+__global__ __launch_bounds__(MfmaCfg<NP>::NT) void k_factor_level_mfma(Launch<FactorDesc> L) {
     using Cfg = MfmaCfg<NP>;
     constexpr int W = Cfg::W, NT = Cfg::NT, LD = NP + 1;
     __shared__ double sS[NP * LD];         // S_i -> L_ii
@@ -48,17 +48,20 @@ __global__ __launch_bounds__(MfmaCfg<NP>::NT) void k_factor_level_mfma(FactorPar
     __shared__ __align__(16) double colbuf[2][kWave];
     __shared__ int fail;
 
+    FactorDesc P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
     if (*P.info != kInfoOk) return;  // an earlier level broke down
 
     const int tid = threadIdx.x;
     const int w = tid / kWave;
-    const int lvl = P.level;
     const int64_t N = P.N;
     const int n = P.n;
     const size_t nn = (size_t)n * n;
     const int64_t s = (int64_t)1 << lvl;
     const int64_t h = s >> 1;
-    const int64_t i = ((int64_t)blockIdx.x * 2 + 1) << lvl;
+    const int64_t i = (kk * 2 + 1) << lvl;
     const bool has_r = i + s <= N;
     const bool has_l = i > s;
     const bool def_self = lvl > 0 && i + h <= N;
@@ -203,19 +206,13 @@ __global__ __launch_bounds__(MfmaCfg<NP>::NT) void k_factor_level_mfma(FactorPar
 
 }  // namespace
 
-hipError_t launch_factor_level_mfma(const FactorParams& p, int64_t nodes, hipStream_t st) {
-    switch (padded_block(p.n)) {
-        case 16:
-            hipLaunchKernelGGL(k_factor_level_mfma<16>, dim3((unsigned)nodes), dim3(MfmaCfg<16>::NT), 0, st, p);
-            break;
-        case 32:
-            hipLaunchKernelGGL(k_factor_level_mfma<32>, dim3((unsigned)nodes), dim3(MfmaCfg<32>::NT), 0, st, p);
-            break;
-        case 64:
-            hipLaunchKernelGGL(k_factor_level_mfma<64>, dim3((unsigned)nodes), dim3(MfmaCfg<64>::NT), 0, st, p);
-            break;
-        default:
-            return hipErrorInvalidValue;
+hipError_t launch_factor_mfma(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st) {
+    const dim3 g((unsigned)items);
+    switch (np) {
+        case 16: hipLaunchKernelGGL(k_factor_level_mfma<16>, g, dim3(MfmaCfg<16>::NT), 0, st, p); break;
+        case 32: hipLaunchKernelGGL(k_factor_level_mfma<32>, g, dim3(MfmaCfg<32>::NT), 0, st, p); break;
+        case 64: hipLaunchKernelGGL(k_factor_level_mfma<64>, g, dim3(MfmaCfg<64>::NT), 0, st, p); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -1,0 +1,361 @@
+// Internal host-side definitions of libbtc shared by the C-ABI entry points
+// (btc_api.hip) and the step runner (btc_runner.hip): the handle, its device
+// memory and workspace layout, and the descriptors its kernels take.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "btc.h"
+#include "btc_device.h"
+#include "btc_kernels.h"
+
+namespace btc_host {
+
+constexpr unsigned long long kInfoOk = ~0ull;
+
+__global__ void k_set_u64(unsigned long long* p, unsigned long long v);
+
+}  // namespace btc_host
+
+struct btc_handle_s {
+    int64_t N = 0;
+    int64_t n = 0;
+    int32_t precision = BTC_FP64;
+    int32_t max_refine = 0;
+    double tol = 0.0;
+    int levels = 0;  // floor(log2 N) + 1
+    int device = 0;
+    // FP64 factor (BTC_FP64)
+    double* Ld = nullptr;
+    double* Rb = nullptr;
+    double* Tb = nullptr;
+    // mixed factor (BTC_FP32_IR): FP64 Schur complements, FP32 factor
+    double* S64 = nullptr;
+    float* L32 = nullptr;
+    float* R32 = nullptr;
+    float* T32 = nullptr;
+    unsigned long long* info = nullptr;
+    // solve workspace, grown on demand (one allocation)
+    void* ws = nullptr;
+    int64_t ws_m = 0;
+    hipStream_t stream = nullptr;  // stream of the last call
+    bool factored = false;
+    bool failed_known = false;     // a status check saw a breakdown
+    const double* A_diag = nullptr;
+    const double* A_off = nullptr;
+    // optional per-launch timing
+    struct Timed {
+        hipEvent_t a, b;
+        int phase, level;
+    };
+    bool prof = false;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> pool;
+    double prof_ms[4][64] = {};
+    int64_t prof_n[4][64] = {};
+};
+
+namespace btc_host {
+
+inline bool is_mixed(int32_t p) { return p == BTC_FP32_IR; }
+
+inline int num_levels(int64_t N) {
+    int L = 0;
+    while ((((int64_t)1) << (L + 1)) <= N) ++L;
+    return L + 1;
+}
+
+inline int64_t level_nodes(int64_t N, int l) {
+    const int64_t s = (int64_t)1 << l;
+    return (N + s) / (2 * s);
+}
+
+inline int to_code(hipError_t e) {
+    if (e == hipSuccess) return BTC_OK;
+    if (e == hipErrorOutOfMemory) return BTC_ERR_OOM;
+    return BTC_ERR_HIP;
+}
+
+template <class P>
+inline void dfree(P*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+inline void free_all(btc_handle h) {
+    if (!h) return;
+    for (auto& t : h->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    h->pending.clear();
+    for (auto e : h->pool) (void)hipEventDestroy(e);
+    h->pool.clear();
+    dfree(h->Ld);
+    dfree(h->Rb);
+    dfree(h->Tb);
+    dfree(h->S64);
+    dfree(h->L32);
+    dfree(h->R32);
+    dfree(h->T32);
+    dfree(h->info);
+    dfree(h->ws);
+}
+
+inline hipEvent_t take_event(btc_handle h) {
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch wrapper: brackets the launch with events when profiling is on.
+// Phases: 0 factor, 1 forward sweep, 2 backward sweep, 3 residual/refinement.
+template <class F>
+inline hipError_t timed(btc_handle h, int phase, int level, hipStream_t st, F&& launch) {
+    if (!h->prof) return launch();
+    hipEvent_t a = take_event(h), b = take_event(h);
+    if (!a || !b) return hipErrorOutOfMemory;
+    (void)hipEventRecord(a, st);
+    hipError_t e = launch();
+    (void)hipEventRecord(b, st);
+    h->pending.push_back({a, b, phase, level});
+    return e;
+}
+
+inline void drain_profile(btc_handle h) {
+    for (auto& t : h->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess && t.level < 64) {
+            h->prof_ms[t.phase][t.level] += ms;
+            h->prof_n[t.phase][t.level] += 1;
+        }
+        h->pool.push_back(t.a);
+        h->pool.push_back(t.b);
+    }
+    h->pending.clear();
+}
+
+inline size_t factor_bytes(int64_t N, int64_t n, int32_t prec) {
+    const size_t nn = (size_t)N * (size_t)n * (size_t)n;
+    if (is_mixed(prec)) return nn * (sizeof(double) + 3 * sizeof(float));
+    return 3 * nn * sizeof(double);
+}
+
+// Solve workspace: FP64 path: Y, U, V (FP64); mixed: r, y, u, v, d (FP32);
+// both: partial norms (FP64, N x m x 2) and the refinement state.
+inline size_t workspace_bytes(int64_t N, int64_t n, int32_t prec, int64_t m) {
+    const size_t v = (size_t)N * (size_t)n * (size_t)m;
+    const size_t tail = 2 * (size_t)N * (size_t)m * sizeof(double) + 256 + 256 + 256;
+    if (is_mixed(prec)) return 5 * v * sizeof(float) + tail;
+    return 3 * v * sizeof(double) + tail;
+}
+
+struct Workspace {
+    double *Y = nullptr, *U = nullptr, *V = nullptr;                              // FP64 path
+    float *r = nullptr, *y = nullptr, *u = nullptr, *v = nullptr, *d = nullptr;  // mixed
+    double* part = nullptr;
+    btc::IrState* ir = nullptr;
+};
+
+inline Workspace carve(btc_handle h, int64_t m) {
+    Workspace w;
+    const size_t v = (size_t)h->N * (size_t)h->n * (size_t)m;
+    char* p = (char*)h->ws;
+    auto align = [](char* q) { return (char*)(((uintptr_t)q + 255) & ~(uintptr_t)255); };
+    if (is_mixed(h->precision)) {
+        w.r = (float*)p;
+        p += v * sizeof(float);
+        w.y = (float*)p;
+        p += v * sizeof(float);
+        w.u = (float*)p;
+        p += v * sizeof(float);
+        w.v = (float*)p;
+        p += v * sizeof(float);
+        w.d = (float*)p;
+        p += v * sizeof(float);
+    } else {
+        w.Y = (double*)p;
+        p += v * sizeof(double);
+        w.U = (double*)p;
+        p += v * sizeof(double);
+        w.V = (double*)p;
+        p += v * sizeof(double);
+    }
+    p = align(p);
+    w.part = (double*)p;
+    p += 2 * (size_t)h->N * (size_t)m * sizeof(double);
+    p = align(p);
+    w.ir = (btc::IrState*)p;
+    return w;
+}
+
+inline int ensure_workspace(btc_handle h, int64_t m) {
+    if (m <= h->ws_m && h->ws) return BTC_OK;
+    if (h->ws) {
+        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        dfree(h->ws);
+    }
+    h->ws_m = 0;
+    hipError_t e = hipMalloc(&h->ws, workspace_bytes(h->N, h->n, h->precision, m));
+    if (e != hipSuccess) {
+        h->ws = nullptr;
+        return to_code(e);
+    }
+    h->ws_m = m;
+    return BTC_OK;
+}
+
+inline btc::FactorDesc factor_desc(btc_handle h, const double* A_diag, const double* A_off) {
+    btc::FactorDesc d{};
+    d.A_diag = A_diag;
+    d.A_off = A_off;
+    if (is_mixed(h->precision)) {
+        d.Ld = h->S64;
+        d.L32 = h->L32;
+        d.R32 = h->R32;
+        d.T32 = h->T32;
+    } else {
+        d.Ld = h->Ld;
+        d.Rb = h->Rb;
+        d.Tb = h->Tb;
+    }
+    d.info = h->info;
+    d.N = h->N;
+    d.n = (int32_t)h->n;
+    return d;
+}
+
+// Padded block size of the factor kernel of a handle.
+inline int factor_np(btc_handle h) {
+    return is_mixed(h->precision) ? btc::padded_block_mixed((int)h->n) : btc::padded_block((int)h->n);
+}
+
+inline hipError_t launch_factor_any(btc_handle h, const btc::Launch<btc::FactorDesc>& L, int64_t items, hipStream_t st) {
+    const int np = factor_np(h);
+    if (is_mixed(h->precision)) return btc::launch_factor_mixed(L, np, items, st);
+    return np >= 16 ? btc::launch_factor_mfma(L, np, items, st) : btc::launch_factor_valu(L, np, items, st);
+}
+
+inline int launch_factor(btc_handle h, const double* A_diag, const double* A_off, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, h->info, kInfoOk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return to_code(e);
+    btc::Launch<btc::FactorDesc> L{};
+    L.single = factor_desc(h, A_diag, A_off);
+    for (int l = 0; l < h->levels; ++l) {
+        L.level = l;
+        const int64_t nodes = level_nodes(h->N, l);
+        e = timed(h, 0, l, st, [&] { return launch_factor_any(h, L, nodes, st); });
+        if (e != hipSuccess) return to_code(e);
+    }
+    h->A_diag = A_diag;
+    h->A_off = A_off;
+    h->stream = st;
+    h->factored = true;
+    h->failed_known = false;
+    return BTC_OK;
+}
+
+template <class T>
+inline hipError_t sweeps(btc_handle h, const btc::SweepDesc<T>& d, hipStream_t st) {
+    btc::Launch<btc::SweepDesc<T>> L{};
+    L.single = d;
+    const int np = btc::padded_block((int)h->n);
+    for (int l = 0; l < h->levels; ++l) {
+        L.level = l;
+        hipError_t e = timed(h, 1, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), false, st); });
+        if (e != hipSuccess) return e;
+    }
+    for (int l = h->levels - 1; l >= 0; --l) {
+        L.level = l;
+        hipError_t e = timed(h, 2, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), true, st); });
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+inline btc::SweepDesc<double> sweep_desc64(btc_handle h, const Workspace& w, const double* B, double* X, int64_t m) {
+    btc::SweepDesc<double> p{};
+    p.Ld = h->Ld;
+    p.Rb = h->Rb;
+    p.Tb = h->Tb;
+    p.B = B;
+    p.X = X;
+    p.Y = w.Y;
+    p.U = w.U;
+    p.V = w.V;
+    p.info = h->info;
+    p.N = h->N;
+    p.n = (int32_t)h->n;
+    p.m = (int32_t)m;
+    return p;
+}
+
+inline btc::SweepDesc<float> sweep_desc32(btc_handle h, const Workspace& w, const double* B, double* X, int64_t m,
+                                   bool first) {
+    btc::SweepDesc<float> p{};
+    p.Ld = h->L32;
+    p.Rb = h->R32;
+    p.Tb = h->T32;
+    p.B = w.r;
+    p.B64 = first ? B : nullptr;
+    p.X = w.d;
+    p.Y = w.y;
+    p.U = w.u;
+    p.V = w.v;
+    p.X64 = X;
+    p.info = h->info;
+    p.skip = &w.ir->done;
+    p.N = h->N;
+    p.n = (int32_t)h->n;
+    p.m = (int32_t)m;
+    p.first = first ? 1 : 0;
+    return p;
+}
+
+inline btc::ResidualDesc residual_desc(btc_handle h, const Workspace& w, const double* B, const double* X, int64_t m,
+                                bool to_fp32) {
+    btc::ResidualDesc r{};
+    r.A_diag = h->A_diag;
+    r.A_off = h->A_off;
+    r.B = B;
+    r.X = X;
+    r.R32 = to_fp32 ? w.r : nullptr;
+    r.part = w.part;
+    r.state = w.ir;
+    r.N = h->N;
+    r.n = (int32_t)h->n;
+    r.m = (int32_t)m;
+    return r;
+}
+
+inline btc::IrDesc ir_desc(btc_handle h, const Workspace& w, int64_t m, double tol, int max_steps) {
+    btc::IrDesc d{};
+    d.state = w.ir;
+    d.part = w.part;
+    d.N = h->N;
+    d.n = (int32_t)h->n;
+    d.m = (int32_t)m;
+    d.tol = tol;
+    d.max_steps = max_steps;
+    return d;
+}
+
+inline int read_info(btc_handle h, hipStream_t st, unsigned long long* v) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return to_code(e);
+    e = hipMemcpy(v, h->info, sizeof(*v), hipMemcpyDeviceToHost);
+    return to_code(e);
+}
+
+
+}  // namespace btc_host

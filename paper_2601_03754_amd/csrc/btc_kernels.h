@@ -1,4 +1,14 @@
 // Internal interface between the libbtc host code and its kernels.
+//
+// Every kernel is driven by work items.  An item names one node (or one block
+// row, or one instance) of one instance at one level; the instance itself is
+// described by a descriptor.  A launch either processes the implicit items
+// (0, level, k = blockIdx.x) of a single instance whose descriptor travels by
+// value in the kernel arguments, or an explicit device array of items whose
+// descriptors live in a device array.  Explicit items let one launch serve
+// many instances of different sizes, at different levels, at once (batched
+// factorizations and continuous batching of requests); every item of one
+// launch shares the padded block size the kernel was compiled for.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -6,57 +16,75 @@
 
 namespace btc {
 
-// One level of the factorization of one instance.
-struct FactorParams {
+struct WorkItem {
+    int32_t inst;   // index into the descriptor array
+    int32_t level;  // level of the node (ignored by per-row / per-instance kernels)
+    int64_t k;      // node index within its level (block row for the residual)
+};
+
+template <class D>
+struct Launch {
+    D single;               // descriptor of the implicit-item launch
+    const D* descs;         // explicit mode: descriptor array (device)
+    const WorkItem* items;  // explicit mode: item array (device); nullptr = implicit
+    int32_t level;          // implicit mode: level of every item
+};
+
+template <class D>
+__device__ __forceinline__ void fetch_item(const Launch<D>& P, D& d, int& level, int64_t& k) {
+    if (P.items) {
+        const WorkItem it = P.items[blockIdx.x];
+        d = P.descs[it.inst];
+        level = it.level;
+        k = it.k;
+    } else {
+        d = P.single;
+        level = P.level;
+        k = blockIdx.x;
+    }
+}
+
+// Factorization of one instance.  FP64 path: S_i then L_ii in Ld, couplings
+// then R_i / T_i in Rb / Tb.  Mixed path: FP64 Schur complements in Ld, FP32
+// factor in L32 / R32 / T32.  All arrays [N][n][n], permuted order.
+struct FactorDesc {
     const double* A_diag;      // [N][n][n] user input (lower triangles)
     const double* A_off;       // [N-1][n][n] user input
-    double* Ld;                // [N][n][n] permuted: S_i, then L_ii
-    double* Rb;                // [N][n][n] permuted: right coupling, then R_i
-    double* Tb;                // [N][n][n] permuted: left coupling, then T_i
+    double* Ld;
+    double* Rb;
+    double* Tb;
+    float* L32;
+    float* R32;
+    float* T32;
     unsigned long long* info;  // ~0 = ok, else smallest failing 1-based block
     int64_t N;
     int32_t n;
-    int32_t level;
+    int32_t pad;
 };
 
-// Mixed-precision factor storage: S_i in FP64 during the elimination, the
-// factor itself (L_ii, R_i, T_i and the fill couplings) in FP32.
-struct FactorParamsMixed {
-    const double* A_diag;      // [N][n][n] user input (lower triangles)
-    const double* A_off;       // [N-1][n][n] user input
-    double* S64;               // [N][n][n] permuted: running Schur complements (FP64)
-    float* L32;                // [N][n][n] permuted: L_ii rounded to FP32
-    float* R32;                // [N][n][n] permuted: right coupling, then R_i
-    float* T32;                // [N][n][n] permuted: left coupling, then T_i
-    unsigned long long* info;
-    int64_t N;
-    int32_t n;
-    int32_t level;
-};
-
-// One level of a forward or backward sweep of one instance; T is the storage
-// type of the factor and of the vectors (double or float).
+// Sweeps of one instance; T is the storage type of the factor and vectors.
 template <class T>
-struct SweepParams {
+struct SweepDesc {
     const T* Ld;
     const T* Rb;
     const T* Tb;
     const T* B;                // [N][n][m] right-hand side (original order)
+    const double* B64;         // optional: read the right-hand side from this FP64 array instead
     T* X;                      // [N][n][m] solution (original order)
     T* Y;                      // [N][n][m] permuted: forward-sweep result y
     T* U;                      // [N][n][m] permuted: R_i y_i left for i+s
     T* V;                      // [N][n][m] permuted: T_i^T y_i left for i-s
     double* X64;               // optional: X64 = X (first) or X64 += X after the backward sweep
     const unsigned long long* info;
-    const int* skip;           // optional: the launch does nothing while *skip != 0
+    const int* skip;           // optional: the item does nothing while *skip != 0
     int64_t N;
     int32_t n;
     int32_t m;
-    int32_t level;
     int32_t first;
+    int32_t pad;
 };
 
-// Device-side state of iterative refinement.
+// Device-side state of iterative refinement of one solve.
 struct IrState {
     int done;        // no further refinement work (converged, stalled, NaN or budget spent)
     int steps;       // low-precision solves applied so far
@@ -69,7 +97,8 @@ struct IrState {
     int pad;
 };
 
-struct ResidualParams {
+// FP64 residual of one instance (items: k = 0-based block row).
+struct ResidualDesc {
     const double* A_diag;
     const double* A_off;
     const double* B;           // [N][n][m] FP64 right-hand side
@@ -82,18 +111,31 @@ struct ResidualParams {
     int32_t m;
 };
 
+// Refinement set-up / convergence test of one instance (items: one per instance).
+struct IrDesc {
+    IrState* state;
+    const double* part;        // [N][m][2]
+    const double* B;           // FP64 right-hand side (set-up)
+    float* R32;                // FP32 copy of B (set-up; may be null)
+    int64_t N;
+    int32_t n;
+    int32_t m;
+    double tol;
+    int32_t max_steps;
+    int32_t pad;
+};
+
 // Padded compute tile for block size n (0 when unsupported).
 int padded_block(int n);
+int padded_block_mixed(int n);
 
-hipError_t launch_factor_level_f64(const FactorParams& p, int64_t nodes, hipStream_t st);
-// Matrix-core variant for padded block sizes 16, 32, 64.
-hipError_t launch_factor_level_mfma(const FactorParams& p, int64_t nodes, hipStream_t st);
-hipError_t launch_factor_level_mixed(const FactorParamsMixed& p, int64_t nodes, hipStream_t st);
-hipError_t launch_sweep(const SweepParams<double>& p, int64_t nodes, bool backward, hipStream_t st);
-hipError_t launch_sweep(const SweepParams<float>& p, int64_t nodes, bool backward, hipStream_t st);
-hipError_t launch_residual(const ResidualParams& p, hipStream_t st);
-hipError_t launch_ir_check(IrState* state, const double* part, int64_t N, int m, hipStream_t st);
-hipError_t launch_ir_init(IrState* state, double tol, int max_steps, const double* B, float* R32, size_t count,
-                          hipStream_t st);
+hipError_t launch_factor_valu(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st);
+hipError_t launch_factor_mfma(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st);
+hipError_t launch_factor_mixed(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st);
+hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t items, bool backward, hipStream_t st);
+hipError_t launch_sweep(const Launch<SweepDesc<float>>& p, int np, int64_t items, bool backward, hipStream_t st);
+hipError_t launch_residual(const Launch<ResidualDesc>& p, int np, int64_t items, hipStream_t st);
+hipError_t launch_ir_init(const Launch<IrDesc>& p, int64_t items, hipStream_t st);
+hipError_t launch_ir_check(const Launch<IrDesc>& p, int64_t items, hipStream_t st);
 
 }  // namespace btc

@@ -43,7 +43,7 @@ __device__ __forceinline__ void tile64_store_global_acc32(const double* __restri
 }
 
 template <int NP>
-__global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(FactorParamsMixed P) {
+__global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(Launch<FactorDesc> L) {
     using Cfg = MixCfg<NP>;
     constexpr int W = Cfg::W, NT = Cfg::NT, LD = NP + 1;
     __shared__ double sS[NP * LD];  // S_i -> L_ii (FP64)
@@ -56,30 +56,33 @@ __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(FactorPar
     __shared__ __align__(16) double colbuf[2][kWave];
     __shared__ int fail;
 
+    FactorDesc P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
     if (*P.info != kInfoOk) return;
 
     const int tid = threadIdx.x;
     const int w = tid / kWave;
-    const int lvl = P.level;
     const int64_t N = P.N;
     const int n = P.n;
     const size_t nn = (size_t)n * n;
     const int64_t s = (int64_t)1 << lvl;
     const int64_t h = s >> 1;
-    const int64_t i = ((int64_t)blockIdx.x * 2 + 1) << lvl;
+    const int64_t i = (kk * 2 + 1) << lvl;
     const bool has_r = i + s <= N;
     const bool has_l = i > s;
     const bool def_self = lvl > 0 && i + h <= N;
     const bool def_sep = lvl > 0 && has_r && i + 3 * h <= N;
     const int64_t pi = perm_pos(N, lvl, i);
     const int64_t pr = has_r ? perm_pos(N, level_of(i + s), i + s) : 0;
-    const double* Ssep = (lvl == 0) ? P.A_diag + (size_t)(i + s - 1) * nn : P.S64 + (size_t)pr * nn;
+    const double* Ssep = (lvl == 0) ? P.A_diag + (size_t)(i + s - 1) * nn : P.Ld + (size_t)pr * nn;
 
     // P1: stage S_i, S_{i+s} (FP64) and the deferred T blocks (FP32)
     {
         Stage<NP, NT> a, c;
         Stage<NP, NT, float> b, d;
-        a.fetch(lvl == 0 ? P.A_diag + (size_t)(i - 1) * nn : P.S64 + (size_t)pi * nn, n, true, 1.0, tid);
+        a.fetch(lvl == 0 ? P.A_diag + (size_t)(i - 1) * nn : P.Ld + (size_t)pi * nn, n, true, 1.0, tid);
         if (def_self) b.fetch(P.T32 + (size_t)perm_pos(N, lvl - 1, i + h) * nn, n, false, 0.0, tid);
         if (has_r) c.fetch(Ssep, n, true, 1.0, tid);
         if (def_sep) d.fetch(P.T32 + (size_t)perm_pos(N, lvl - 1, i + 3 * h) * nn, n, false, 0.0, tid);
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(FactorPar
                 f4 acc = {0.f, 0.f, 0.f, 0.f};
                 mma_tile32<LD, LD, false, true, false>(acc, fB, ta * kT, 0, fB, tb * kT, 0, NP);
                 acc32_sub_from_lds64<LD>(acc, sC, ta * kT, tb * kT);
-                tile64_store_global_acc32<LD>(sC, P.S64 + (size_t)pr * nn, n, ta * kT, tb * kT);
+                tile64_store_global_acc32<LD>(sC, P.Ld + (size_t)pr * nn, n, ta * kT, tb * kT);
             }
         }
     }
@@ -228,19 +231,13 @@ int padded_block_mixed(int n) {
     return (np != 0 && np < 16) ? 16 : np;
 }
 
-hipError_t launch_factor_level_mixed(const FactorParamsMixed& p, int64_t nodes, hipStream_t st) {
-    switch (padded_block_mixed(p.n)) {
-        case 16:
-            hipLaunchKernelGGL(k_factor_level_mixed<16>, dim3((unsigned)nodes), dim3(MixCfg<16>::NT), 0, st, p);
-            break;
-        case 32:
-            hipLaunchKernelGGL(k_factor_level_mixed<32>, dim3((unsigned)nodes), dim3(MixCfg<32>::NT), 0, st, p);
-            break;
-        case 64:
-            hipLaunchKernelGGL(k_factor_level_mixed<64>, dim3((unsigned)nodes), dim3(MixCfg<64>::NT), 0, st, p);
-            break;
-        default:
-            return hipErrorInvalidValue;
+hipError_t launch_factor_mixed(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st) {
+    const dim3 g((unsigned)items);
+    switch (np) {
+        case 16: hipLaunchKernelGGL(k_factor_level_mixed<16>, g, dim3(MixCfg<16>::NT), 0, st, p); break;
+        case 32: hipLaunchKernelGGL(k_factor_level_mixed<32>, g, dim3(MixCfg<32>::NT), 0, st, p); break;
+        case 64: hipLaunchKernelGGL(k_factor_level_mixed<64>, g, dim3(MixCfg<64>::NT), 0, st, p); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

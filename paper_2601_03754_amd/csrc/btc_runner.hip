@@ -1,0 +1,406 @@
+// Step runner: executes a list of level steps of many handles with one
+// kernel launch per (operation, kernel, padded block size) group.  Each step
+// contributes its work items (the nodes of one level, the block rows of a
+// residual, or one refinement test) and its descriptor; descriptors and items
+// of a call are packed into one upload from a pinned staging buffer
+// (double-buffered, so the host can prepare the next call while the device
+// runs the current one).  Batched factorization and solve of many
+// independent instances, and the continuous-batching server, are built on it.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "btc.h"
+#include "btc_handle.h"
+#include "btc_kernels.h"
+
+using namespace btc_host;
+
+namespace {
+
+__global__ void k_reset_infos(unsigned long long* const* __restrict__ ptrs, int count) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) *ptrs[t] = kInfoOk;
+}
+
+// One group = one launch.
+struct Group {
+    int op;    // btc_op
+    int kind;  // FACTOR: 0 VALU f64, 1 MFMA f64, 2 mixed; sweeps: 0 double, 1 float
+    int np;
+    std::vector<char> descs;  // packed descriptors (all of one type)
+    size_t desc_size = 0;
+    std::vector<btc::WorkItem> items;
+    size_t off_desc = 0, off_items = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct btc_runner_s {
+    hipStream_t st = nullptr;
+    struct Slot {
+        char* host = nullptr;
+        size_t hcap = 0;
+        char* dev = nullptr;
+        size_t dcap = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    } slot[2];
+    int cur = 0;
+};
+
+namespace {
+
+int slot_reserve(btc_runner r, btc_runner_s::Slot& s, size_t bytes) {
+    if (s.pending) {
+        if (hipEventSynchronize(s.ev) != hipSuccess) return BTC_ERR_HIP;
+        s.pending = false;
+    }
+    if (bytes > s.hcap) {
+        if (s.host) (void)hipHostFree(s.host);
+        s.host = nullptr;
+        const size_t cap = std::max(bytes, (size_t)1 << 16) * 2;
+        if (hipHostMalloc((void**)&s.host, cap, hipHostMallocDefault) != hipSuccess) {
+            s.hcap = 0;
+            return BTC_ERR_OOM;
+        }
+        s.hcap = cap;
+    }
+    if (bytes > s.dcap) {
+        // the device buffer may still be read by launches of an earlier call
+        if (hipStreamSynchronize(r->st) != hipSuccess) return BTC_ERR_HIP;
+        if (s.dev) (void)hipFree(s.dev);
+        s.dev = nullptr;
+        const size_t cap = std::max(bytes, (size_t)1 << 16) * 2;
+        if (hipMalloc((void**)&s.dev, cap) != hipSuccess) {
+            s.dcap = 0;
+            return BTC_ERR_OOM;
+        }
+        s.dcap = cap;
+    }
+    return BTC_OK;
+}
+
+template <class D>
+void push_desc(Group& g, const D& d) {
+    g.desc_size = sizeof(D);
+    const size_t o = g.descs.size();
+    g.descs.resize(o + sizeof(D));
+    memcpy(g.descs.data() + o, &d, sizeof(D));
+}
+
+template <class D>
+btc::Launch<D> make_launch(const Group& g, char* dev) {
+    btc::Launch<D> L{};
+    L.descs = (const D*)(dev + g.off_desc);
+    L.items = (const btc::WorkItem*)(dev + g.off_items);
+    return L;
+}
+
+int validate(const btc_step& s) {
+    btc_handle h = s.h;
+    if (!h) return -3;
+    if (s.op < BTC_OP_FACTOR || s.op > BTC_OP_REFINE_TEST) return -3;
+    if (s.op == BTC_OP_FACTOR || s.op == BTC_OP_FORWARD || s.op == BTC_OP_BACKWARD) {
+        if (s.level < 0 || s.level >= h->levels) return -3;
+    }
+    if (s.op == BTC_OP_FACTOR) {
+        if (s.level == 0 && (!s.A_diag || (h->N > 1 && !s.A_off))) return -3;
+        if (s.level > 0 && !h->A_diag) return -3;
+    } else {
+        if (s.nrhs < 1) return -3;
+        if (s.op != BTC_OP_REFINE_INIT && s.op != BTC_OP_REFINE_TEST && (!s.B || !s.X)) return -3;
+        if (s.op == BTC_OP_RESIDUAL && !h->A_diag) return -3;
+    }
+    return BTC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+BTC_API int btc_runner_create(void* stream, btc_runner* out) {
+    if (!out) return -2;
+    *out = nullptr;
+    btc_runner r = new (std::nothrow) btc_runner_s();
+    if (!r) return BTC_ERR_OOM;
+    r->st = (hipStream_t)stream;
+    for (auto& s : r->slot) {
+        if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
+            btc_runner_destroy(r);
+            return BTC_ERR_HIP;
+        }
+    }
+    *out = r;
+    return BTC_OK;
+}
+
+BTC_API void btc_runner_destroy(btc_runner r) {
+    if (!r) return;
+    (void)hipStreamSynchronize(r->st);
+    for (auto& s : r->slot) {
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+    }
+    delete r;
+}
+
+BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
+    if (!r) return -1;
+    if (count < 0) return -2;
+    if (count > 0 && !steps) return -3;
+    if (count == 0) return BTC_OK;
+    hipStream_t st = r->st;
+
+    // workspaces first: growing one synchronises, before anything is queued
+    for (int32_t k = 0; k < count; ++k) {
+        const int rc = validate(steps[k]);
+        if (rc != BTC_OK) return rc;
+        btc_handle h = steps[k].h;
+        if (steps[k].op != BTC_OP_FACTOR) {
+            if (steps[k].nrhs > h->ws_m || !h->ws) {
+                if (h->ws) (void)hipStreamSynchronize(st);
+                h->stream = st;
+                const int e = ensure_workspace(h, steps[k].nrhs);
+                if (e != BTC_OK) return e;
+            }
+        }
+    }
+
+    std::map<std::tuple<int, int, int>, Group> groups;
+    std::vector<unsigned long long*> resets;
+    for (int32_t k = 0; k < count; ++k) {
+        const btc_step& s = steps[k];
+        btc_handle h = s.h;
+        const bool mixed = is_mixed(h->precision);
+        h->stream = st;
+        if (s.op == BTC_OP_FACTOR) {
+            if (s.level == 0) {
+                resets.push_back(h->info);
+                h->A_diag = s.A_diag;
+                h->A_off = s.A_off;
+                h->factored = true;
+                h->failed_known = false;
+            }
+            const int np = factor_np(h);
+            const int kind = mixed ? 2 : (np >= 16 ? 1 : 0);
+            Group& g = groups[std::make_tuple(s.op, kind, np)];
+            g.op = s.op;
+            g.kind = kind;
+            g.np = np;
+            const int32_t inst = (int32_t)(g.descs.size() / sizeof(btc::FactorDesc));
+            push_desc(g, factor_desc(h, h->A_diag, h->A_off));
+            const int64_t nodes = level_nodes(h->N, s.level);
+            for (int64_t q = 0; q < nodes; ++q) g.items.push_back({inst, s.level, q});
+            continue;
+        }
+        const Workspace w = carve(h, h->ws_m);
+        const int np = btc::padded_block((int)h->n);
+        if (s.op == BTC_OP_FORWARD || s.op == BTC_OP_BACKWARD) {
+            Group& g = groups[std::make_tuple(s.op, mixed ? 1 : 0, np)];
+            g.op = s.op;
+            g.kind = mixed ? 1 : 0;
+            g.np = np;
+            int32_t inst;
+            if (mixed) {
+                inst = (int32_t)(g.descs.size() / sizeof(btc::SweepDesc<float>));
+                push_desc(g, sweep_desc32(h, w, s.B, s.X, s.nrhs, s.first != 0));
+            } else {
+                inst = (int32_t)(g.descs.size() / sizeof(btc::SweepDesc<double>));
+                push_desc(g, sweep_desc64(h, w, s.B, s.X, s.nrhs));
+            }
+            const int64_t nodes = level_nodes(h->N, s.level);
+            for (int64_t q = 0; q < nodes; ++q) g.items.push_back({inst, s.level, q});
+        } else if (s.op == BTC_OP_RESIDUAL) {
+            Group& g = groups[std::make_tuple(s.op, 0, np)];
+            g.op = s.op;
+            g.kind = 0;
+            g.np = np;
+            const int32_t inst = (int32_t)(g.descs.size() / sizeof(btc::ResidualDesc));
+            push_desc(g, residual_desc(h, w, s.B, s.X, s.nrhs, mixed));
+            for (int64_t q = 0; q < h->N; ++q) g.items.push_back({inst, 0, q});
+        } else {
+            Group& g = groups[std::make_tuple(s.op, 0, 0)];
+            g.op = s.op;
+            g.kind = 0;
+            g.np = 0;
+            const int32_t inst = (int32_t)(g.descs.size() / sizeof(btc::IrDesc));
+            const double tol = mixed ? h->tol : 0.0;
+            const int steps_budget = mixed ? 1 + h->max_refine : 1;
+            push_desc(g, ir_desc(h, w, s.nrhs, tol, steps_budget));
+            g.items.push_back({inst, 0, 0});
+        }
+    }
+
+    // pack: reset pointers, then descriptors and items of every group
+    size_t bytes = align256(resets.size() * sizeof(unsigned long long*));
+    for (auto& kv : groups) {
+        Group& g = kv.second;
+        g.off_desc = bytes;
+        bytes = align256(bytes + g.descs.size());
+        g.off_items = bytes;
+        bytes = align256(bytes + g.items.size() * sizeof(btc::WorkItem));
+    }
+    btc_runner_s::Slot& sl = r->slot[r->cur];
+    int rc = slot_reserve(r, sl, bytes);
+    if (rc != BTC_OK) return rc;
+    if (!resets.empty()) memcpy(sl.host, resets.data(), resets.size() * sizeof(unsigned long long*));
+    for (auto& kv : groups) {
+        Group& g = kv.second;
+        memcpy(sl.host + g.off_desc, g.descs.data(), g.descs.size());
+        memcpy(sl.host + g.off_items, g.items.data(), g.items.size() * sizeof(btc::WorkItem));
+    }
+    hipError_t e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return to_code(e);
+    (void)hipEventRecord(sl.ev, st);
+    sl.pending = true;
+    r->cur ^= 1;
+
+    if (!resets.empty()) {
+        const int n = (int)resets.size();
+        hipLaunchKernelGGL(k_reset_infos, dim3((n + 255) / 256), dim3(256), 0, st,
+                           (unsigned long long* const*)sl.dev, n);
+        e = hipGetLastError();
+        if (e != hipSuccess) return to_code(e);
+    }
+    // std::map orders groups by op: factor, forward, backward, residual, refine init, refine test
+    for (auto& kv : groups) {
+        const Group& g = kv.second;
+        const int64_t items = (int64_t)g.items.size();
+        switch (g.op) {
+            case BTC_OP_FACTOR: {
+                auto L = make_launch<btc::FactorDesc>(g, sl.dev);
+                e = g.kind == 2 ? btc::launch_factor_mixed(L, g.np, items, st)
+                                : g.kind == 1 ? btc::launch_factor_mfma(L, g.np, items, st)
+                                              : btc::launch_factor_valu(L, g.np, items, st);
+                break;
+            }
+            case BTC_OP_FORWARD:
+            case BTC_OP_BACKWARD: {
+                const bool bwd = g.op == BTC_OP_BACKWARD;
+                if (g.kind == 1)
+                    e = btc::launch_sweep(make_launch<btc::SweepDesc<float>>(g, sl.dev), g.np, items, bwd, st);
+                else
+                    e = btc::launch_sweep(make_launch<btc::SweepDesc<double>>(g, sl.dev), g.np, items, bwd, st);
+                break;
+            }
+            case BTC_OP_RESIDUAL:
+                e = btc::launch_residual(make_launch<btc::ResidualDesc>(g, sl.dev), g.np, items, st);
+                break;
+            case BTC_OP_REFINE_INIT:
+                e = btc::launch_ir_init(make_launch<btc::IrDesc>(g, sl.dev), items, st);
+                break;
+            default:
+                e = btc::launch_ir_check(make_launch<btc::IrDesc>(g, sl.dev), items, st);
+                break;
+        }
+        if (e != hipSuccess) return to_code(e);
+    }
+    return BTC_OK;
+}
+
+BTC_API int btc_runner_query(btc_runner r) {
+    if (!r) return -1;
+    const hipError_t e = hipStreamQuery(r->st);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return to_code(e);
+}
+
+BTC_API int btc_runner_sync(btc_runner r) {
+    if (!r) return -1;
+    return to_code(hipStreamSynchronize(r->st));
+}
+
+// ---------------------------------------------------------------------------
+// Batched factorization and solve of independent instances on a runner: the
+// levels of every instance are walked together, one group of launches per
+// level, so that each launch carries the nodes of all instances at that level.
+
+BTC_API int btc_factor_batched(btc_runner r, int32_t count, const btc_handle* h, const double* const* A_diag,
+                               const double* const* A_off) {
+    if (!r) return -1;
+    if (count < 0) return -2;
+    if (count > 0 && (!h || !A_diag || !A_off)) return -3;
+    int levels = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        if (!h[k]) return -3;
+        levels = std::max(levels, h[k]->levels);
+    }
+    std::vector<btc_step> steps;
+    for (int l = 0; l < levels; ++l) {
+        steps.clear();
+        for (int32_t k = 0; k < count; ++k) {
+            if (l >= h[k]->levels) continue;
+            btc_step s{};
+            s.h = h[k];
+            s.op = BTC_OP_FACTOR;
+            s.level = l;
+            s.A_diag = A_diag[k];
+            s.A_off = A_off[k];
+            steps.push_back(s);
+        }
+        const int rc = btc_runner_run(r, (int32_t)steps.size(), steps.data());
+        if (rc != BTC_OK) return rc;
+    }
+    return BTC_OK;
+}
+
+BTC_API int btc_solve_batched(btc_runner r, int32_t count, const btc_handle* h, const double* const* B,
+                              double* const* X, int64_t nrhs) {
+    if (!r) return -1;
+    if (count < 0) return -2;
+    if (count > 0 && (!h || !B || !X)) return -3;
+    if (nrhs < 1) return -6;
+    int levels = 0, rounds = 1;
+    bool any_mixed = false;
+    for (int32_t k = 0; k < count; ++k) {
+        if (!h[k] || !h[k]->factored) return -3;
+        if (is_mixed(h[k]->precision) && B[k] == X[k]) return -4;
+        levels = std::max(levels, h[k]->levels);
+        if (is_mixed(h[k]->precision)) {
+            any_mixed = true;
+            rounds = std::max(rounds, 1 + h[k]->max_refine);
+        }
+    }
+    std::vector<btc_step> steps;
+    auto run_op = [&](int op, int level, bool mixed_only, int first) -> int {
+        steps.clear();
+        for (int32_t k = 0; k < count; ++k) {
+            if ((op == BTC_OP_FORWARD || op == BTC_OP_BACKWARD) && level >= h[k]->levels) continue;
+            if (mixed_only && !is_mixed(h[k]->precision)) continue;
+            btc_step s{};
+            s.h = h[k];
+            s.op = op;
+            s.level = level;
+            s.B = B[k];
+            s.X = X[k];
+            s.nrhs = nrhs;
+            s.first = first;
+            steps.push_back(s);
+        }
+        return btc_runner_run(r, (int32_t)steps.size(), steps.data());
+    };
+    int rc = BTC_OK;
+    if (any_mixed) rc = run_op(BTC_OP_REFINE_INIT, 0, true, 0);
+    for (int round = 0; round < rounds && rc == BTC_OK; ++round) {
+        // FP64 instances take part in the first round only
+        const bool only_mixed = round > 0;
+        for (int l = 0; l < levels && rc == BTC_OK; ++l) rc = run_op(BTC_OP_FORWARD, l, only_mixed, round == 0);
+        for (int l = levels - 1; l >= 0 && rc == BTC_OK; --l) rc = run_op(BTC_OP_BACKWARD, l, only_mixed, round == 0);
+        if (any_mixed && rc == BTC_OK) rc = run_op(BTC_OP_RESIDUAL, 0, true, 0);
+        if (any_mixed && rc == BTC_OK) rc = run_op(BTC_OP_REFINE_TEST, 0, true, 0);
+    }
+    return rc;
+}
+
+}  // extern "C"

@@ -30,14 +30,14 @@ __device__ __forceinline__ float bcast(float v, int lane) {
 }
 
 template <class T>
-__device__ __forceinline__ bool skip_launch(const SweepParams<T>& P) {
+__device__ __forceinline__ bool skip_launch(const SweepDesc<T>& P) {
     if (*P.info != kInfoOk) return true;
     if (P.skip && *P.skip) return true;
     return false;
 }
 
 template <int NP, int NT, class T>
-__global__ __launch_bounds__(NT) void k_forward(SweepParams<T> P) {
+__global__ __launch_bounds__(NT) void k_forward(Launch<SweepDesc<T>> L) {
     constexpr int LD = NP + 1;
     constexpr int NW = NT / kWave;
     __shared__ T sL[NP * LD];
@@ -46,14 +46,17 @@ __global__ __launch_bounds__(NT) void k_forward(SweepParams<T> P) {
     __shared__ T invd[NP];
     __shared__ T sy[NW][NP];
 
+    SweepDesc<T> P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
     if (skip_launch(P)) return;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-    const int lvl = P.level;
     const int64_t N = P.N;
     const int n = P.n, m = P.m;
     const size_t nn = (size_t)n * n, nm = (size_t)n * m;
     const int64_t s = (int64_t)1 << lvl;
-    const int64_t i = ((int64_t)blockIdx.x * 2 + 1) << lvl;
+    const int64_t i = (kk * 2 + 1) << lvl;
     const bool has_r = i + s <= N, has_l = i > s;
     const int64_t pi = perm_pos(N, lvl, i);
 
@@ -75,7 +78,8 @@ __global__ __launch_bounds__(NT) void k_forward(SweepParams<T> P) {
         // lower level, gathered eight levels at a time so the loads overlap
         T acc = T(0);
         if (lane < n) {
-            acc = P.B[((size_t)(i - 1) * n + lane) * m + q];
+            const size_t bidx = ((size_t)(i - 1) * n + lane) * m + q;
+            acc = P.B64 ? (T)P.B64[bidx] : P.B[bidx];
             for (int l0 = 0; l0 < lvl; l0 += 8) {
                 T pu[8], pv[8];
 #pragma unroll
@@ -118,7 +122,7 @@ __global__ __launch_bounds__(NT) void k_forward(SweepParams<T> P) {
 }
 
 template <int NP, int NT, class T>
-__global__ __launch_bounds__(NT) void k_backward(SweepParams<T> P) {
+__global__ __launch_bounds__(NT) void k_backward(Launch<SweepDesc<T>> L) {
     constexpr int LD = NP + 1;
     constexpr int NW = NT / kWave;
     __shared__ T sL[NP * LD];
@@ -128,14 +132,17 @@ __global__ __launch_bounds__(NT) void k_backward(SweepParams<T> P) {
     __shared__ T sxr[NW][NP];
     __shared__ T sxl[NW][NP];
 
+    SweepDesc<T> P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
     if (skip_launch(P)) return;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-    const int lvl = P.level;
     const int64_t N = P.N;
     const int n = P.n, m = P.m;
     const size_t nn = (size_t)n * n, nm = (size_t)n * m;
     const int64_t s = (int64_t)1 << lvl;
-    const int64_t i = ((int64_t)blockIdx.x * 2 + 1) << lvl;
+    const int64_t i = (kk * 2 + 1) << lvl;
     const bool has_r = i + s <= N, has_l = i > s;
     const int64_t pi = perm_pos(N, lvl, i);
 
@@ -183,22 +190,22 @@ __global__ __launch_bounds__(NT) void k_backward(SweepParams<T> P) {
 }
 
 template <int NP, class T>
-hipError_t launch_sweep_np(const SweepParams<T>& p, int64_t nodes, bool backward, hipStream_t st) {
+hipError_t launch_sweep_np(const Launch<SweepDesc<T>>& p, int64_t items, bool backward, hipStream_t st) {
     constexpr int NT = SweepCfg<NP>::NT;
     if (backward)
-        hipLaunchKernelGGL((k_backward<NP, NT, T>), dim3((unsigned)nodes), dim3(NT), 0, st, p);
+        hipLaunchKernelGGL((k_backward<NP, NT, T>), dim3((unsigned)items), dim3(NT), 0, st, p);
     else
-        hipLaunchKernelGGL((k_forward<NP, NT, T>), dim3((unsigned)nodes), dim3(NT), 0, st, p);
+        hipLaunchKernelGGL((k_forward<NP, NT, T>), dim3((unsigned)items), dim3(NT), 0, st, p);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_sweep_t(const SweepParams<T>& p, int64_t nodes, bool backward, hipStream_t st) {
-    switch (padded_block(p.n)) {
-        case 8: return launch_sweep_np<8, T>(p, nodes, backward, st);
-        case 16: return launch_sweep_np<16, T>(p, nodes, backward, st);
-        case 32: return launch_sweep_np<32, T>(p, nodes, backward, st);
-        case 64: return launch_sweep_np<64, T>(p, nodes, backward, st);
+hipError_t launch_sweep_t(const Launch<SweepDesc<T>>& p, int np, int64_t items, bool backward, hipStream_t st) {
+    switch (np) {
+        case 8: return launch_sweep_np<8, T>(p, items, backward, st);
+        case 16: return launch_sweep_np<16, T>(p, items, backward, st);
+        case 32: return launch_sweep_np<32, T>(p, items, backward, st);
+        case 64: return launch_sweep_np<64, T>(p, items, backward, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -211,7 +218,7 @@ hipError_t launch_sweep_t(const SweepParams<T>& p, int64_t nodes, bool backward,
 // squared column norms of r and b, reduced later in a fixed order.
 
 template <int NP, int NT>
-__global__ __launch_bounds__(NT) void k_residual(ResidualParams P) {
+__global__ __launch_bounds__(NT) void k_residual(Launch<ResidualDesc> L) {
     constexpr int LD = NP + 1;
     constexpr int NW = NT / kWave;
     __shared__ double sDg[NP * LD];
@@ -219,12 +226,16 @@ __global__ __launch_bounds__(NT) void k_residual(ResidualParams P) {
     __shared__ double sEr[NP * LD];
     __shared__ double sx[NW][3][kWave];
 
+    ResidualDesc P;
+    int lvl_unused;
+    int64_t row;
+    fetch_item(L, P, lvl_unused, row);
     if (P.state && P.state->done) return;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const int64_t N = P.N;
     const int n = P.n, m = P.m;
     const size_t nn = (size_t)n * n;
-    const int64_t i = (int64_t)blockIdx.x + 1;
+    const int64_t i = row + 1;
     const bool lft = i > 1, rgt = i < N;
     {
         Stage<NP, NT> a, b, c;
@@ -270,19 +281,26 @@ __global__ __launch_bounds__(NT) void k_residual(ResidualParams P) {
     }
 }
 
-// Reduce the partial norms in a fixed order, form max_q ||r_q||/||b_q|| and
-// advance the refinement state: converged when <= tol, stalled when the
-// residual fell by less than 2x in the last step, done when either holds or
-// the step budget is spent.
-__global__ __launch_bounds__(256) void k_ir_check(IrState* st, const double* __restrict__ part, int64_t N, int m) {
+// Reduce the partial norms of one instance in a fixed order, form
+// max_q ||r_q||/||b_q|| and advance its refinement state: converged when
+// <= tol, stalled when the residual fell by less than 2x in the last step,
+// done when either holds or the step budget is spent.
+__global__ __launch_bounds__(256) void k_ir_check(Launch<IrDesc> L) {
     __shared__ double red[2][256];
+    IrDesc P;
+    int lvl_unused;
+    int64_t k_unused;
+    fetch_item(L, P, lvl_unused, k_unused);
+    IrState* st = P.state;
     if (st->done) return;
+    const int64_t N = P.N;
+    const int m = P.m;
     double worst = 0.0;
     for (int q = 0; q < m; ++q) {
         double rr = 0.0, bb = 0.0;
         for (int64_t i = threadIdx.x; i < N; i += 256) {
-            rr += part[((size_t)i * m + q) * 2 + 0];
-            bb += part[((size_t)i * m + q) * 2 + 1];
+            rr += P.part[((size_t)i * m + q) * 2 + 0];
+            bb += P.part[((size_t)i * m + q) * 2 + 1];
         }
         red[0][threadIdx.x] = rr;
         red[1][threadIdx.x] = bb;
@@ -317,36 +335,38 @@ __global__ __launch_bounds__(256) void k_ir_check(IrState* st, const double* __r
     }
 }
 
-// Reset the refinement state and round the right-hand side to FP32.
-__global__ void k_ir_init(IrState* st, double tol, int max_steps, const double* __restrict__ B,
-                          float* __restrict__ R32, size_t count) {
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) {
+// Reset the refinement state of one instance.
+__global__ void k_ir_init(Launch<IrDesc> L) {
+    IrDesc P;
+    int lvl_unused;
+    int64_t k_unused;
+    fetch_item(L, P, lvl_unused, k_unused);
+    if (threadIdx.x == 0) {
+        IrState* st = P.state;
         st->done = 0;
         st->steps = 0;
         st->converged = 0;
         st->stalled = 0;
         st->relres = -1.0;
         st->prev = __builtin_inf();
-        st->tol = tol;
-        st->max_steps = max_steps;
+        st->tol = P.tol;
+        st->max_steps = P.max_steps;
     }
-    for (size_t k = t; k < count; k += (size_t)gridDim.x * blockDim.x) R32[k] = (float)B[k];
 }
 
 }  // namespace
 
-hipError_t launch_sweep(const SweepParams<double>& p, int64_t nodes, bool backward, hipStream_t st) {
-    return launch_sweep_t<double>(p, nodes, backward, st);
+hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t items, bool backward, hipStream_t st) {
+    return launch_sweep_t<double>(p, np, items, backward, st);
 }
 
-hipError_t launch_sweep(const SweepParams<float>& p, int64_t nodes, bool backward, hipStream_t st) {
-    return launch_sweep_t<float>(p, nodes, backward, st);
+hipError_t launch_sweep(const Launch<SweepDesc<float>>& p, int np, int64_t items, bool backward, hipStream_t st) {
+    return launch_sweep_t<float>(p, np, items, backward, st);
 }
 
-hipError_t launch_residual(const ResidualParams& p, hipStream_t st) {
-    const dim3 g((unsigned)p.N);
-    switch (padded_block(p.n)) {
+hipError_t launch_residual(const Launch<ResidualDesc>& p, int np, int64_t items, hipStream_t st) {
+    const dim3 g((unsigned)items);
+    switch (np) {
         case 8: hipLaunchKernelGGL((k_residual<8, SweepCfg<8>::NT>), g, dim3(SweepCfg<8>::NT), 0, st, p); break;
         case 16: hipLaunchKernelGGL((k_residual<16, SweepCfg<16>::NT>), g, dim3(SweepCfg<16>::NT), 0, st, p); break;
         case 32: hipLaunchKernelGGL((k_residual<32, SweepCfg<32>::NT>), g, dim3(SweepCfg<32>::NT), 0, st, p); break;
@@ -356,17 +376,13 @@ hipError_t launch_residual(const ResidualParams& p, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_ir_check(IrState* state, const double* part, int64_t N, int m, hipStream_t st) {
-    hipLaunchKernelGGL(k_ir_check, dim3(1), dim3(256), 0, st, state, part, N, m);
+hipError_t launch_ir_check(const Launch<IrDesc>& p, int64_t items, hipStream_t st) {
+    hipLaunchKernelGGL(k_ir_check, dim3((unsigned)items), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 
-hipError_t launch_ir_init(IrState* state, double tol, int max_steps, const double* B, float* R32, size_t count,
-                          hipStream_t st) {
-    size_t blocks = (count + 255) / 256;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_ir_init, dim3((unsigned)blocks), dim3(256), 0, st, state, tol, max_steps, B, R32, count);
+hipError_t launch_ir_init(const Launch<IrDesc>& p, int64_t items, hipStream_t st) {
+    hipLaunchKernelGGL(k_ir_init, dim3((unsigned)items), dim3(64), 0, st, p);
     return hipGetLastError();
 }
 

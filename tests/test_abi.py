@@ -36,7 +36,8 @@ def lib():
 def test_header_declares_entry_points():
     names = declared_symbols()
     for must in ("btc_factor", "btc_solve", "btc_refactor", "btc_status", "btc_destroy",
-                 "btc_footprint_bytes", "btc_export_factor", "btc_permutation"):
+                 "btc_footprint_bytes", "btc_export_factor", "btc_permutation", "btc_create",
+                 "btc_runner_create", "btc_runner_run", "btc_factor_batched", "btc_solve_batched"):
         assert must in names
 
 
@@ -82,5 +83,14 @@ def test_argument_errors_before_device_work(lib):
     assert L.btc_solve(None, 8, 8, 1, None, None) == -1
     assert L.btc_status(None, None) == -1
     L.btc_destroy(None)
+    assert L.btc_create(0, 4, None, ctypes.byref(h)) == -1
+    assert L.btc_create(4, 65, None, ctypes.byref(h)) == lib.BTC_ERR_UNSUPPORTED
+    assert L.btc_runner_run(None, 0, None) == -1
+    assert L.btc_runner_create(None, None) == -2
+    assert L.btc_runner_query(None) == -1
+    assert L.btc_factor_batched(None, 0, None, None, None) == -1
+    assert L.btc_solve_batched(None, 0, None, None, None, 1) == -1
+    assert L.btc_refine_info(None, None) == -1
+    L.btc_runner_destroy(None)
     assert "argument" in lib.btc_error_string(-3)
     assert "positive definite" in lib.btc_error_string(lib.BTC_ERR_NOT_SPD)
