@@ -281,6 +281,74 @@ BTC_API int btc_solve_batched(btc_runner r, int32_t count, const btc_handle *h, 
  */
 BTC_API int btc_refine_info(btc_handle h, btc_solve_info *info);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of factor and solve requests.
+ *
+ * Not part of the paper, which factors one system at a time; it serves the
+ * use the paper motivates (repeated solves of structured systems in model
+ * predictive control).  A client owns one system shape (N, n) and a factor
+ * kept resident on the device.  Requests are "refactor + solve" (a new matrix
+ * of the client's shape) or "solve" (against the resident factor).  Every
+ * btc_server_step call admits queued requests and enqueues the next level
+ * step of every request in flight as one runner call, so requests at
+ * different levels and phases share launches and new requests join at the
+ * next step.  Admission is in arrival order, one request in flight per
+ * client (so a client's requests complete in order), within an HBM budget on
+ * the resident factors + workspaces: idle clients are evicted least recently
+ * used first, and a later "solve" of an evicted client is run as
+ * "refactor + solve" with its last matrix (which must therefore stay valid).
+ * Mixed-precision requests are refined in FP64 as by btc_solve; a request
+ * whose refinement has converged is retired as soon as its flag comes back.
+ * Times are host steady-clock seconds.
+ */
+typedef struct btc_server_s *btc_server;
+
+typedef struct {
+    int32_t precision;   /* btc_precision of every client */
+    int32_t max_refine;  /* as in btc_options (0: default) */
+    double tol;          /* as in btc_options (0: default) */
+    size_t hbm_budget;   /* bytes for resident factors + workspaces (btc_footprint_bytes) */
+    int32_t max_active;  /* cap on requests in flight (0: no cap) */
+    int32_t pad;
+} btc_server_options;
+
+typedef struct {
+    int64_t ticket;
+    int64_t client;
+    double t_submit;     /* btc_server_submit */
+    double t_admit;      /* admission (memory and the client's previous request permitting) */
+    double t_done;       /* the device finished the request's last step (observed by step/poll) */
+    int32_t refactored;  /* 1 if the request factored (new matrix, or a re-admitted client) */
+    int32_t pad;
+} btc_server_completion;
+
+BTC_API int btc_server_create(const btc_server_options *opt, void *stream, btc_server *out);
+
+/* Register a client of shape (N, n); *client receives its id (0, 1, ...). */
+BTC_API int btc_server_add_client(btc_server s, int64_t N, int64_t n, int64_t *client);
+
+/*
+ * Queue a request (device pointers, valid until the request completes):
+ * A_diag / A_off non-NULL for "refactor + solve", NULL for "solve" (the first
+ * request of a client must bring a matrix); B, X [N][n][nrhs].
+ */
+BTC_API int btc_server_submit(btc_server s, int64_t client, const double *A_diag, const double *A_off,
+                              const double *B, double *X, int64_t nrhs, int64_t *ticket);
+
+/* Admit and enqueue one step of every request in flight; returns the number
+ * of requests queued or in flight (>= 0) or an error code. */
+BTC_API int btc_server_step(btc_server s);
+
+/* Hand out up to `max` completions (wait != 0: first wait for all enqueued work). */
+BTC_API int btc_server_poll(btc_server s, btc_server_completion *out, int32_t max, int32_t *count, int wait);
+
+BTC_API int btc_server_stats(btc_server s, int64_t *queued, int64_t *in_flight, size_t *resident_bytes);
+
+/* The resident handle of a client (NULL if not resident); owned by the server. */
+BTC_API btc_handle btc_server_client_handle(btc_server s, int64_t client);
+
+BTC_API void btc_server_destroy(btc_server s);
+
 /* btc_error_string -- static text for a return code. */
 BTC_API const char *btc_error_string(int code);
 

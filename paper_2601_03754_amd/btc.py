@@ -48,6 +48,16 @@ class btc_step(ctypes.Structure):
                 ("nrhs", i64), ("first", i32), ("pad", i32)]
 
 
+class btc_server_options(ctypes.Structure):
+    _fields_ = [("precision", i32), ("max_refine", i32), ("tol", dbl), ("hbm_budget", ctypes.c_size_t),
+                ("max_active", i32), ("pad", i32)]
+
+
+class btc_server_completion(ctypes.Structure):
+    _fields_ = [("ticket", i64), ("client", i64), ("t_submit", dbl), ("t_admit", dbl), ("t_done", dbl),
+                ("refactored", i32), ("pad", i32)]
+
+
 class BtcError(RuntimeError):
     def __init__(self, code: int, what: str):
         super().__init__("%s failed: %d (%s)" % (what, code, btc_error_string(code)))
@@ -102,6 +112,23 @@ def lib():
         L.btc_solve_batched.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i64]
         L.btc_refine_info.restype = ctypes.c_int
         L.btc_refine_info.argtypes = [vp, ctypes.POINTER(btc_solve_info)]
+        L.btc_server_create.restype = ctypes.c_int
+        L.btc_server_create.argtypes = [ctypes.POINTER(btc_server_options), vp, ctypes.POINTER(vp)]
+        L.btc_server_add_client.restype = ctypes.c_int
+        L.btc_server_add_client.argtypes = [vp, i64, i64, ctypes.POINTER(i64)]
+        L.btc_server_submit.restype = ctypes.c_int
+        L.btc_server_submit.argtypes = [vp, i64, vp, vp, vp, vp, i64, ctypes.POINTER(i64)]
+        L.btc_server_step.restype = ctypes.c_int
+        L.btc_server_step.argtypes = [vp]
+        L.btc_server_poll.restype = ctypes.c_int
+        L.btc_server_poll.argtypes = [vp, ctypes.POINTER(btc_server_completion), i32, ctypes.POINTER(i32),
+                                      ctypes.c_int]
+        L.btc_server_stats.restype = ctypes.c_int
+        L.btc_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)]
+        L.btc_server_client_handle.restype = vp
+        L.btc_server_client_handle.argtypes = [vp, i64]
+        L.btc_server_destroy.restype = None
+        L.btc_server_destroy.argtypes = [vp]
         L.btc_version.restype = ctypes.c_int
         L.btc_version.argtypes = []
         _lib = L
@@ -293,6 +320,78 @@ def step(h: int, op: int, level: int = 0, A_diag=None, A_off=None, B=None, X=Non
     """One level step for Runner.run (tensor arguments are device tensors)."""
     ptr = lambda t: (t.data_ptr() if (t is not None and t.numel()) else 0)
     return btc_step(h, op, level, ptr(A_diag), ptr(A_off), ptr(B), ptr(X), nrhs, 1 if first else 0, 0)
+
+
+class Server:
+    """Continuous-batching request server (btc_server_*).  Keeps the tensors of
+    every request referenced until the request has completed."""
+
+    def __init__(self, precision: int = BTC_FP64, hbm_budget: int = 1 << 40, max_refine: int = 0,
+                 tol: float = 0.0, max_active: int = 0, stream=None):
+        self.stream = _stream(stream)
+        opt = btc_server_options(precision, max_refine, tol, hbm_budget, max_active, 0)
+        h = vp()
+        _check(lib().btc_server_create(ctypes.byref(opt), self.stream, ctypes.byref(h)), "btc_server_create")
+        self.handle = h.value
+        self._live = {}
+        self._buf = (btc_server_completion * 4096)()
+
+    def add_client(self, N: int, n: int) -> int:
+        c = i64()
+        _check(lib().btc_server_add_client(self.handle, N, n, ctypes.byref(c)), "btc_server_add_client")
+        return c.value
+
+    def submit(self, client: int, B: torch.Tensor, X: torch.Tensor, A=None) -> int:
+        t = i64()
+        nrhs = B.shape[-1] if B.dim() == 3 else 1
+        pa = _dev(A[0], "A_diag") if A is not None else 0
+        po = (_dev(A[1], "A_off") if A[1].numel() else 0) if A is not None else 0
+        _check(lib().btc_server_submit(self.handle, client, pa, po, _dev(B, "B"), _dev(X, "X"), nrhs,
+                                       ctypes.byref(t)), "btc_server_submit")
+        self._live[t.value] = (B, X, A)
+        return t.value
+
+    def step(self) -> int:
+        rc = lib().btc_server_step(self.handle)
+        if rc < 0:
+            _check(rc, "btc_server_step")
+        return rc
+
+    def poll(self, wait: bool = False):
+        out = []
+        while True:
+            cnt = i32()
+            _check(lib().btc_server_poll(self.handle, self._buf, len(self._buf), ctypes.byref(cnt),
+                                         1 if wait else 0), "btc_server_poll")
+            for k in range(cnt.value):
+                d = self._buf[k]
+                out.append({"ticket": d.ticket, "client": d.client, "t_submit": d.t_submit,
+                            "t_admit": d.t_admit, "t_done": d.t_done, "refactored": bool(d.refactored)})
+                self._live.pop(d.ticket, None)
+            if cnt.value < len(self._buf):
+                return out
+            wait = False
+
+    def stats(self):
+        q, a, b = i64(), i64(), ctypes.c_size_t()
+        _check(lib().btc_server_stats(self.handle, ctypes.byref(q), ctypes.byref(a), ctypes.byref(b)),
+               "btc_server_stats")
+        return {"queued": q.value, "in_flight": a.value, "resident_bytes": b.value}
+
+    def client_handle(self, client: int) -> int:
+        return lib().btc_server_client_handle(self.handle, client) or 0
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().btc_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def btc_version() -> int:

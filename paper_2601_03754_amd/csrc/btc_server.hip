@@ -1,0 +1,426 @@
+// Request server with continuous batching.
+//
+// Clients own one block-tridiagonal system shape each (N, n) and a resident
+// factor (a handle).  Requests are either "refactor + solve" (a new matrix of
+// the client's shape, then a solve) or "solve" against the resident factor.
+// Every request is a plan of level steps (factor levels, forward / backward
+// sweep levels, and for the mixed-precision path the FP64 residual and
+// convergence test of each refinement round).  A tick takes the next step of
+// every in-flight request and hands them to the step runner as one list, so
+// requests at different levels and phases share launches, and a request that
+// arrives while others are mid-tree starts at the next tick.
+//
+// Admission: requests are admitted in arrival order, subject to
+//   * one request in flight per client (the handle and its workspace are the
+//     client's; this also keeps each client's requests in order);
+//   * the HBM budget: a client's factor + workspace is allocated when its
+//     first request is admitted and stays resident; when the budget would be
+//     exceeded, resident clients with no request in flight are evicted, least
+//     recently used first, and a later "solve" request of an evicted client is
+//     run as "refactor + solve" with the client's last matrix.
+// Completion: each tick records an event; a request completes when the event
+// of the tick holding its last step has fired.  A mixed-precision request
+// whose refinement has converged is retired early: the convergence flag of
+// every test step is copied back asynchronously and read when its tick's
+// event fires; the steps still queued for that request would only have
+// returned at once.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <new>
+#include <vector>
+
+#include "btc.h"
+#include "btc_handle.h"
+#include "btc_kernels.h"
+
+using namespace btc_host;
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Client {
+    int64_t N = 0, n = 0;
+    btc_handle h = nullptr;
+    const double* A_diag = nullptr;  // matrix of the resident factor (or the last one seen)
+    const double* A_off = nullptr;
+    bool busy = false;
+    uint64_t last_use = 0;
+    size_t bytes = 0;
+};
+
+struct Req {
+    int64_t ticket = 0;
+    int64_t client = 0;
+    const double* A_diag = nullptr;
+    const double* A_off = nullptr;
+    const double* B = nullptr;
+    double* X = nullptr;
+    int64_t nrhs = 1;
+    double t_submit = 0.0;
+    double t_admit = 0.0;
+    std::vector<btc_step> plan;
+    size_t pc = 0;
+    bool refactored = false;
+    bool retired = false;
+    uint64_t last_tick = 0;  // id of the newest tick that references this request
+};
+
+struct Tick {
+    uint64_t id = 0;
+    hipEvent_t ev = nullptr;
+    std::vector<Req*> finishing;                  // last plan step in this tick
+    std::vector<std::pair<Req*, int>> polls;      // refinement flag copies (request, pinned slot)
+};
+
+}  // namespace
+
+struct btc_server_s {
+    btc_server_options opt{};
+    hipStream_t st = nullptr;
+    btc_runner runner = nullptr;
+    std::vector<Client> clients;
+    std::deque<Req*> pending;
+    std::vector<Req*> active;
+    std::deque<Tick> ticks;
+    std::vector<hipEvent_t> ev_pool;
+    int32_t* flags = nullptr;  // pinned ring of refinement flags
+    int flag_cap = 0, flag_next = 0;
+    size_t resident = 0;
+    uint64_t clock = 0;
+    uint64_t next_tick = 1;
+    int64_t next_ticket = 1;
+    std::vector<btc_server_completion> done;
+    std::vector<btc_step> scratch;
+};
+
+namespace {
+
+int admit_client(btc_server s, Client& c, int64_t nrhs) {
+    const int32_t prec = s->opt.precision;
+    if (c.h) {
+        if (nrhs > c.h->ws_m) {
+            const size_t more = btc_footprint_bytes(c.N, c.n, prec, nrhs) - c.bytes;
+            if (s->resident + more > s->opt.hbm_budget) return 1;
+            if (ensure_workspace(c.h, nrhs) != BTC_OK) return BTC_ERR_OOM;
+            s->resident += more;
+            c.bytes += more;
+        }
+        return BTC_OK;
+    }
+    const size_t need = btc_footprint_bytes(c.N, c.n, prec, nrhs);
+    if (need == 0) return BTC_ERR_UNSUPPORTED;
+    while (s->resident + need > s->opt.hbm_budget) {
+        // evict the least recently used idle resident client
+        Client* victim = nullptr;
+        for (auto& o : s->clients)
+            if (o.h && !o.busy && (!victim || o.last_use < victim->last_use)) victim = &o;
+        if (!victim) return 1;  // wait for memory
+        (void)hipStreamSynchronize(s->st);
+        btc_destroy(victim->h);
+        victim->h = nullptr;
+        s->resident -= victim->bytes;
+        victim->bytes = 0;
+    }
+    btc_options o{};
+    o.precision = prec;
+    o.max_refine = s->opt.max_refine;
+    o.tol = s->opt.tol;
+    btc_handle h = nullptr;
+    int rc = btc_create(c.N, c.n, &o, &h);
+    if (rc != BTC_OK) return rc;
+    h->stream = s->st;
+    rc = ensure_workspace(h, nrhs);
+    if (rc != BTC_OK) {
+        btc_destroy(h);
+        return rc;
+    }
+    c.h = h;
+    c.bytes = need;
+    s->resident += need;
+    return BTC_OK;
+}
+
+void build_plan(btc_server s, Req* r, Client& c) {
+    btc_handle h = c.h;
+    const int L = h->levels;
+    const bool factor = r->A_diag != nullptr || !h->factored;
+    if (r->A_diag) {
+        c.A_diag = r->A_diag;
+        c.A_off = r->A_off;
+    }
+    btc_step t{};
+    t.h = h;
+    if (factor) {
+        r->refactored = true;
+        for (int l = 0; l < L; ++l) {
+            t.op = BTC_OP_FACTOR;
+            t.level = l;
+            t.A_diag = c.A_diag;
+            t.A_off = c.A_off;
+            r->plan.push_back(t);
+        }
+    }
+    t = btc_step{};
+    t.h = h;
+    t.B = r->B;
+    t.X = r->X;
+    t.nrhs = r->nrhs;
+    const bool mixed = is_mixed(h->precision);
+    const int rounds = mixed ? 1 + h->max_refine : 1;
+    if (mixed) {
+        t.op = BTC_OP_REFINE_INIT;
+        r->plan.push_back(t);
+    }
+    for (int k = 0; k < rounds; ++k) {
+        t.first = (k == 0) ? 1 : 0;
+        for (int l = 0; l < L; ++l) {
+            t.op = BTC_OP_FORWARD;
+            t.level = l;
+            r->plan.push_back(t);
+        }
+        for (int l = L - 1; l >= 0; --l) {
+            t.op = BTC_OP_BACKWARD;
+            t.level = l;
+            r->plan.push_back(t);
+        }
+        if (mixed) {
+            t.level = 0;
+            t.op = BTC_OP_RESIDUAL;
+            r->plan.push_back(t);
+            t.op = BTC_OP_REFINE_TEST;
+            r->plan.push_back(t);
+        }
+    }
+}
+
+void complete(btc_server s, Req* r, double t) {
+    if (r->retired) return;
+    r->retired = true;
+    Client& c = s->clients[(size_t)r->client];
+    c.busy = false;
+    c.last_use = ++s->clock;
+    btc_server_completion d{};
+    d.ticket = r->ticket;
+    d.client = r->client;
+    d.t_submit = r->t_submit;
+    d.t_admit = r->t_admit;
+    d.t_done = t;
+    d.refactored = r->refactored ? 1 : 0;
+    s->done.push_back(d);
+}
+
+// Retire every tick whose event has fired (in order).
+void harvest(btc_server s, bool wait) {
+    while (!s->ticks.empty()) {
+        Tick& t = s->ticks.front();
+        if (wait) {
+            (void)hipEventSynchronize(t.ev);
+        } else if (hipEventQuery(t.ev) != hipSuccess) {
+            break;
+        }
+        const double tn = now_s();
+        for (auto& p : t.polls)
+            if (s->flags[p.second] != 0) complete(s, p.first, tn);
+        for (Req* r : t.finishing) complete(s, r, tn);
+        s->ev_pool.push_back(t.ev);
+        s->ticks.pop_front();
+    }
+    // drop retired requests that no outstanding tick refers to any more
+    const uint64_t oldest = s->ticks.empty() ? UINT64_MAX : s->ticks.front().id;
+    auto it = std::remove_if(s->active.begin(), s->active.end(), [oldest](Req* r) {
+        if (r->retired && r->last_tick < oldest) {
+            delete r;
+            return true;
+        }
+        return false;
+    });
+    s->active.erase(it, s->active.end());
+}
+
+}  // namespace
+
+extern "C" {
+
+BTC_API int btc_server_create(const btc_server_options* opt, void* stream, btc_server* out) {
+    if (!opt) return -1;
+    if (opt->precision != BTC_FP64 && !is_mixed(opt->precision)) return -1;
+    if (opt->max_refine < 0 || opt->max_active < 0 || !(opt->tol >= 0.0)) return -1;
+    if (!out) return -3;
+    *out = nullptr;
+    btc_server s = new (std::nothrow) btc_server_s();
+    if (!s) return BTC_ERR_OOM;
+    s->opt = *opt;
+    if (s->opt.max_refine == 0) s->opt.max_refine = BTC_DEFAULT_MAX_REFINE;
+    if (s->opt.tol == 0.0) s->opt.tol = BTC_DEFAULT_TOL;
+    if (s->opt.max_active == 0) s->opt.max_active = 1 << 20;
+    s->st = (hipStream_t)stream;
+    int rc = btc_runner_create(stream, &s->runner);
+    if (rc == BTC_OK) {
+        s->flag_cap = 1 << 16;
+        if (hipHostMalloc((void**)&s->flags, sizeof(int32_t) * s->flag_cap, hipHostMallocDefault) != hipSuccess)
+            rc = BTC_ERR_OOM;
+    }
+    if (rc != BTC_OK) {
+        btc_server_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return BTC_OK;
+}
+
+BTC_API int btc_server_add_client(btc_server s, int64_t N, int64_t n, int64_t* client) {
+    if (!s) return -1;
+    if (N < 1) return -2;
+    if (n < 1) return -3;
+    if (n > BTC_MAX_BLOCK) return BTC_ERR_UNSUPPORTED;
+    if (!client) return -4;
+    Client c;
+    c.N = N;
+    c.n = n;
+    s->clients.push_back(c);
+    *client = (int64_t)s->clients.size() - 1;
+    return BTC_OK;
+}
+
+BTC_API int btc_server_submit(btc_server s, int64_t client, const double* A_diag, const double* A_off,
+                              const double* B, double* X, int64_t nrhs, int64_t* ticket) {
+    if (!s) return -1;
+    if (client < 0 || client >= (int64_t)s->clients.size()) return -2;
+    const Client& c = s->clients[(size_t)client];
+    if (A_diag && c.N > 1 && !A_off) return -4;
+    if (!A_diag && !c.A_diag) return -3;  // a first request must bring the matrix
+    if (!B) return -5;
+    if (!X || (is_mixed(s->opt.precision) && X == B)) return -6;
+    if (nrhs < 1) return -7;
+    Req* r = new (std::nothrow) Req();
+    if (!r) return BTC_ERR_OOM;
+    r->ticket = s->next_ticket++;
+    r->client = client;
+    r->A_diag = A_diag;
+    r->A_off = A_off;
+    r->B = B;
+    r->X = X;
+    r->nrhs = nrhs;
+    r->t_submit = now_s();
+    if (A_diag) {
+        // the newest matrix of the client is what an eviction falls back to
+        s->clients[(size_t)client].A_diag = A_diag;
+        s->clients[(size_t)client].A_off = A_off;
+    }
+    s->pending.push_back(r);
+    if (ticket) *ticket = r->ticket;
+    return BTC_OK;
+}
+
+BTC_API int btc_server_step(btc_server s) {
+    if (!s) return -1;
+    harvest(s, false);
+
+    // admission, in arrival order
+    for (auto it = s->pending.begin(); it != s->pending.end();) {
+        if ((int)s->active.size() >= s->opt.max_active) break;
+        Req* r = *it;
+        Client& c = s->clients[(size_t)r->client];
+        if (c.busy) {
+            ++it;
+            continue;
+        }
+        const int rc = admit_client(s, c, r->nrhs);
+        if (rc == 1) break;  // out of budget: keep arrival order
+        if (rc != BTC_OK) return rc;
+        c.busy = true;
+        c.last_use = ++s->clock;
+        r->t_admit = now_s();
+        build_plan(s, r, c);
+        s->active.push_back(r);
+        it = s->pending.erase(it);
+    }
+
+    // one step of every in-flight request
+    Tick t;
+    t.id = s->next_tick++;
+    s->scratch.clear();
+    for (Req* r : s->active) {
+        if (r->retired || r->pc >= r->plan.size()) continue;  // done, or waiting for its last tick
+        r->last_tick = t.id;
+        const btc_step& st = r->plan[r->pc++];
+        s->scratch.push_back(st);
+        if (st.op == BTC_OP_REFINE_TEST && r->pc < r->plan.size()) {
+            t.polls.push_back({r, s->flag_next});
+            s->flag_next = (s->flag_next + 1) % s->flag_cap;
+        }
+        if (r->pc == r->plan.size()) t.finishing.push_back(r);
+    }
+    if (s->scratch.empty()) return (int)(s->pending.size() + s->active.size());
+    int rc = btc_runner_run(s->runner, (int32_t)s->scratch.size(), s->scratch.data());
+    if (rc != BTC_OK) return rc;
+    for (auto& p : t.polls) {
+        const Workspace w = carve(p.first->plan[0].h, p.first->plan[0].h->ws_m);
+        s->flags[p.second] = 0;
+        if (hipMemcpyAsync(&s->flags[p.second], &w.ir->done, sizeof(int32_t), hipMemcpyDeviceToHost, s->st) !=
+            hipSuccess)
+            return BTC_ERR_HIP;
+    }
+    if (!s->ev_pool.empty()) {
+        t.ev = s->ev_pool.back();
+        s->ev_pool.pop_back();
+    } else if (hipEventCreateWithFlags(&t.ev, hipEventDisableTiming) != hipSuccess) {
+        return BTC_ERR_HIP;
+    }
+    if (hipEventRecord(t.ev, s->st) != hipSuccess) return BTC_ERR_HIP;
+    s->ticks.push_back(std::move(t));
+    return (int)(s->pending.size() + s->active.size());
+}
+
+BTC_API int btc_server_poll(btc_server s, btc_server_completion* out, int32_t max, int32_t* count, int wait) {
+    if (!s) return -1;
+    if (max < 0) return -3;
+    if (!count) return -4;
+    harvest(s, wait != 0);
+    const int32_t k = std::min<int32_t>(max, (int32_t)s->done.size());
+    if (k > 0 && !out) return -2;
+    for (int32_t i = 0; i < k; ++i) out[i] = s->done[(size_t)i];
+    s->done.erase(s->done.begin(), s->done.begin() + k);
+    *count = k;
+    return BTC_OK;
+}
+
+BTC_API int btc_server_stats(btc_server s, int64_t* queued, int64_t* in_flight, size_t* resident_bytes) {
+    if (!s) return -1;
+    if (queued) *queued = (int64_t)s->pending.size();
+    if (in_flight) *in_flight = (int64_t)s->active.size();
+    if (resident_bytes) *resident_bytes = s->resident;
+    return BTC_OK;
+}
+
+BTC_API btc_handle btc_server_client_handle(btc_server s, int64_t client) {
+    if (!s || client < 0 || client >= (int64_t)s->clients.size()) return nullptr;
+    return s->clients[(size_t)client].h;
+}
+
+BTC_API void btc_server_destroy(btc_server s) {
+    if (!s) return;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    for (Req* r : s->pending) delete r;
+    for (Req* r : s->active) delete r;
+    for (auto& t : s->ticks)
+        if (t.ev) (void)hipEventDestroy(t.ev);
+    for (auto e : s->ev_pool) (void)hipEventDestroy(e);
+    for (auto& c : s->clients)
+        if (c.h) btc_destroy(c.h);
+    if (s->runner) btc_runner_destroy(s->runner);
+    if (s->flags) (void)hipHostFree(s->flags);
+    delete s;
+}
+
+}  // extern "C"
