@@ -55,7 +55,7 @@ extern "C" {
 #define BTC_ERR_UNSUPPORTED (-103)  /* block size or option not supported */
 
 /* Largest supported block size n. */
-#define BTC_MAX_BLOCK 64
+#define BTC_MAX_BLOCK 128
 
 typedef struct btc_handle_s *btc_handle; /* opaque; owned by the library */
 

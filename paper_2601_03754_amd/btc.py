@@ -26,7 +26,7 @@ BTC_ERR_HIP = -100
 BTC_ERR_OOM = -101
 BTC_ERR_NOT_SPD = -102
 BTC_ERR_UNSUPPORTED = -103
-BTC_MAX_BLOCK = 64
+BTC_MAX_BLOCK = 128
 
 i32, i64, dbl, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 

@@ -186,6 +186,8 @@ int padded_block(int n) {
     if (n <= 16) return 16;
     if (n <= 32) return 32;
     if (n <= 64) return 64;
+    if (n <= 96) return 96;
+    if (n <= 128) return 128;
     return 0;
 }
 

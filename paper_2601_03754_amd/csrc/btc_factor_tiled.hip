@@ -1,0 +1,488 @@
+// Tile-parallel factorization level step for large blocks (padded sizes 96
+// and 128), FP64 or mixed precision.
+//
+// A node whose four n x n blocks no longer fit in LDS together is split over
+// several workgroups and four launches per level (the same per-node algebra
+// as the single-kernel paths, Algorithm 4):
+//   K1  deferred syrk: S_i -= T'^T T' and S_{i+s} -= T''^T T'', one 256-thread
+//       workgroup per 32 x 32 lower tile (panels of T' staged in LDS)
+//   K2  one workgroup per node: the whole pivot block in LDS (FP64), blocked
+//       Cholesky (64-row leading factorization, matrix-core solve and update
+//       of the trailing rows, factorization of the trailing block), and the
+//       inverses of its 16 x 16 diagonal tiles, written to a per-node scratch
+//   K3  one wavefront per 16-row strip of R_i = C_{i+s,i} L_ii^{-T} and per
+//       16-column strip of T_i = L_ii^{-1} C_{i,i-s}: blocked substitution over
+//       the tiles with the inverted diagonal tiles (all products MFMA)
+//   K4  one 256-thread workgroup per 32 x 32 tile of S_{i+s} -= R_i R_i^T
+//       (lower tiles) and of the fill -R_i T_i
+// In mixed precision the Schur complements and K2 stay FP64 and the products
+// of K1, K3, K4 run on FP32 matrix cores (FP32 factor storage).
+#include "btc_device.h"
+#include "btc_kernels.h"
+#include "btc_tiles.h"
+
+namespace btc {
+namespace {
+
+using namespace tiles;
+constexpr unsigned long long kInfoOk = ~0ull;
+
+template <bool MIXED>
+struct Prec;
+
+template <>
+struct Prec<false> {
+    using F = double;
+    using Acc = d4;
+    __device__ static int row(int v, int lane) { return 4 * v + (lane >> 4); }
+    __device__ static Acc mma(F a, F b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static F* Lf(const FactorDesc& d) { return d.Ld; }
+    __device__ static F* Rf(const FactorDesc& d) { return d.Rb; }
+    __device__ static F* Tf(const FactorDesc& d) { return d.Tb; }
+};
+
+template <>
+struct Prec<true> {
+    using F = float;
+    using Acc = f4;
+    __device__ static int row(int v, int lane) { return 4 * (lane >> 4) + v; }
+    __device__ static Acc mma(F a, F b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static F* Lf(const FactorDesc& d) { return d.L32; }
+    __device__ static F* Rf(const FactorDesc& d) { return d.R32; }
+    __device__ static F* Tf(const FactorDesc& d) { return d.T32; }
+};
+
+template <int NP>
+struct TiledCfg {
+    static constexpr int W32 = NP / 32;               // 32-wide tile rows
+    static constexpr int NTRI32 = W32 * (W32 + 1) / 2;  // lower 32 x 32 tiles
+    static constexpr int NT16 = NP / 16;              // 16-wide tiles per side
+};
+
+struct Node {
+    int lvl;
+    int64_t i, s, h, pi, pr, N;
+    int n;
+    size_t nn;
+    bool has_r, has_l, def_self, def_sep;
+};
+
+__device__ __forceinline__ Node node_of(const FactorDesc& P, int lvl, int64_t kk) {
+    Node d;
+    d.lvl = lvl;
+    d.N = P.N;
+    d.n = P.n;
+    d.nn = (size_t)P.n * P.n;
+    d.s = (int64_t)1 << lvl;
+    d.h = d.s >> 1;
+    d.i = (kk * 2 + 1) << lvl;
+    d.has_r = d.i + d.s <= d.N;
+    d.has_l = d.i > d.s;
+    d.def_self = lvl > 0 && d.i + d.h <= d.N;
+    d.def_sep = lvl > 0 && d.has_r && d.i + 3 * d.h <= d.N;
+    d.pi = perm_pos(d.N, lvl, d.i);
+    d.pr = d.has_r ? perm_pos(d.N, level_of(d.i + d.s), d.i + d.s) : 0;
+    return d;
+}
+
+// Stage rows [r0, r0+R) (all NP columns) of an n x n block into LDS as
+// dst[r][k] (row stride LDD), zero padded; or, when COLS, columns [c0, c0+R)
+// (all NP rows) as dst[k][c] (row stride LDD).  NT threads; loads are issued
+// eight at a time per thread before the LDS writes, so they overlap.
+template <int NP, int R, int LDD, bool COLS, int NT, class S, class F>
+__device__ __forceinline__ void stage_panel(F* __restrict__ dst, const S* __restrict__ src, int n, int r0, int t) {
+    constexpr int TOTAL = NP * R;
+    constexpr int CH = 8;
+    for (int base = 0; base < TOTAL; base += NT * CH) {
+        F v[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = base + t + NT * u;
+            F x = F(0);
+            if (e < TOTAL) {
+                if (COLS) {
+                    const int k = e / R, gc = r0 + e % R;
+                    if (k < n && gc < n) x = (F)src[(size_t)k * n + gc];
+                } else {
+                    const int gr = r0 + e / NP, k = e % NP;
+                    if (gr < n && k < n) x = (F)src[(size_t)gr * n + k];
+                }
+            }
+            v[u] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = base + t + NT * u;
+            if (e < TOTAL) {
+                if (COLS)
+                    dst[(e / R) * LDD + e % R] = v[u];
+                else
+                    dst[(e / NP) * LDD + e % NP] = v[u];
+            }
+        }
+    }
+}
+
+// Whole lower triangle of an n x n FP64 block into an NP x NP LDS tile
+// (identity padding), loads batched as in stage_panel.
+template <int NP, int NT>
+__device__ __forceinline__ void stage_lower(double* __restrict__ dst, const double* __restrict__ src, int n, int t) {
+    constexpr int CH = 8;
+    for (int base = 0; base < NP * NP; base += NT * CH) {
+        double v[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = base + t + NT * u, r = e / NP, c = e % NP;
+            double x = (r == c) ? 1.0 : 0.0;
+            if (e < NP * NP && r < n && c <= r) x = src[(size_t)r * n + c];
+            v[u] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = base + t + NT * u;
+            if (e < NP * NP) dst[(e / NP) * (NP + 1) + e % NP] = v[u];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K1: deferred syrk.  blockIdx.y < NTRI32: tile of S_i; else tile of S_{i+s}.
+template <int NP, bool MIXED>
+__global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> L) {
+    using Pr = Prec<MIXED>;
+    using F = typename Pr::F;
+    using Cfg = TiledCfg<NP>;
+    constexpr int LDP = 33;
+    __shared__ F pa[NP * LDP];
+    __shared__ F pb[NP * LDP];
+    FactorDesc P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
+    if (*P.info != kInfoOk) return;
+    const Node d = node_of(P, lvl, kk);
+    const bool self = (int)blockIdx.y < Cfg::NTRI32;
+    if (self ? !d.def_self : !d.def_sep) return;
+    int a, b;
+    tri_tile(self ? blockIdx.y : blockIdx.y - Cfg::NTRI32, a, b);
+    const int64_t src_node = self ? d.i + d.h : d.i + 3 * d.h;
+    const F* Tsrc = Pr::Tf(P) + (size_t)perm_pos(d.N, lvl - 1, src_node) * d.nn;
+    double* S = P.Ld + (size_t)(self ? d.pi : d.pr) * d.nn;
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid & 63;
+    stage_panel<NP, 32, LDP, true, 256>(pa, Tsrc, d.n, 32 * a, tid);
+    stage_panel<NP, 32, LDP, true, 256>(pb, Tsrc, d.n, 32 * b, tid);
+    __syncthreads();
+    const int sr = w >> 1, sc = w & 1;
+    if (a == b && sr < sc) return;  // strictly upper sub-tile
+    typename Pr::Acc acc = {};
+    const int i = lane & 15, q = lane >> 4;
+#pragma unroll 4
+    for (int k = 0; k < NP; k += 4)
+        acc = Pr::mma(pa[(k + q) * LDP + 16 * sr + i], pb[(k + q) * LDP + 16 * sc + i], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 32 * a + 16 * sr + Pr::row(v, lane), c = 32 * b + 16 * sc + (lane & 15);
+        if (r < d.n && c < d.n) S[(size_t)r * d.n + c] -= (double)acc[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2: pivot block factorization and inverted diagonal tiles.
+template <int NP, bool MIXED>
+__global__ __launch_bounds__(256) void k_tiled_potrf(Launch<FactorDesc> L) {
+    using Pr = Prec<MIXED>;
+    using F = typename Pr::F;
+    using Cfg = TiledCfg<NP>;
+    constexpr int LD = NP + 1;
+    constexpr int NB = 64;             // leading block
+    constexpr int M = (NP - NB) / kT;  // trailing 16-row strips
+    static_assert(NP - NB <= kWave && NP > NB, "trailing block fits one wavefront");
+    __shared__ double sS[NP * LD];
+    __shared__ double sInv[Cfg::NT16][kT * kLDI];
+    __shared__ double invd[NP];
+    __shared__ __align__(16) double colbuf[2][kWave];
+    __shared__ int fail;
+    FactorDesc P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
+    if (*P.info != kInfoOk) return;
+    const Node d = node_of(P, lvl, kk);
+    const int tid = threadIdx.x, w = tid / kWave;
+    const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i - 1) * d.nn : P.Ld + (size_t)d.pi * d.nn;
+    stage_lower<NP, 256>(sS, src, d.n, tid);
+    if (tid == 0) fail = 0;
+    __syncthreads();
+    if (w == 0) {
+        const bool ok = potrf_lookahead<NB, LD>(sS, invd, colbuf);
+        if (!ok && tid == 0) fail = 1;
+    }
+    __syncthreads();
+    if (fail) {
+        if (tid == 0) atomicMin(P.info, (unsigned long long)d.i);
+        return;
+    }
+    tile_inverse<LD, double>(sS, w * kT, invd, sInv[w]);
+    __syncthreads();
+    // trailing rows: A21 <- A21 L11^{-T}, strip by strip
+    for (int st = w; st < M; st += 4) {
+        const int r0 = NB + st * kT;
+#pragma unroll
+        for (int p = 0; p < NB / kT; ++p) {
+            d4 acc;
+            acc_load_lds<LD>(acc, sS, r0, p * kT);
+            for (int q = 0; q < p; ++q)
+                mma_tile<LD, LD, false, true, true>(acc, sS, r0, q * kT, sS, p * kT, q * kT, kT);
+            acc_store_lds<LD>(acc, sS, r0, p * kT);
+            d4 out = {0.0, 0.0, 0.0, 0.0};
+            mma_tile<LD, kLDI, false, true, false>(out, sS, r0, p * kT, sInv[p], 0, 0, kT);
+            acc_store_lds<LD>(out, sS, r0, p * kT);
+        }
+    }
+    __syncthreads();
+    // A22 -= A21 A21^T (lower tiles)
+    for (int t = w; t < M * (M + 1) / 2; t += 4) {
+        int ta, tb;
+        tri_tile(t, ta, tb);
+        d4 acc;
+        acc_load_lds<LD>(acc, sS, NB + ta * kT, NB + tb * kT);
+        mma_tile<LD, LD, false, true, true>(acc, sS, NB + ta * kT, 0, sS, NB + tb * kT, 0, NB);
+        acc_store_lds<LD>(acc, sS, NB + ta * kT, NB + tb * kT);
+    }
+    __syncthreads();
+    if (w == 0) {
+        const bool ok = potrf_lookahead<NP - NB, LD>(sS + NB * LD + NB, invd + NB, colbuf);
+        if (!ok && tid == 0) fail = 1;
+    }
+    __syncthreads();
+    if (fail) {
+        if (tid == 0) atomicMin(P.info, (unsigned long long)d.i);
+        return;
+    }
+    for (int t = NB / kT + w; t < Cfg::NT16; t += 4) tile_inverse<LD, double>(sS, t * kT, invd, sInv[t]);
+    __syncthreads();
+    // L (lower) and the inverted diagonal tiles
+    lds_store_as<NP, F, double>(Pr::Lf(P) + (size_t)d.pi * d.nn, sS, d.n, true, tid, 256);
+    F* dinv = (F*)P.Dinv + (size_t)d.pi * Cfg::NT16 * kT * kT;
+    for (int e = tid; e < Cfg::NT16 * kT * kT; e += 256) {
+        const int t = e / (kT * kT), r = (e / kT) % kT, c = e % kT;
+        dinv[e] = (F)sInv[t][r * kLDI + c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K3: triangular-solve strips (one wavefront each).  blockIdx.y < NT16:
+// rows [16y, 16y+16) of R; else columns [16(y-NT16), ...) of T.
+template <int NP, bool MIXED>
+__global__ __launch_bounds__(64) void k_tiled_trsm(Launch<FactorDesc> L) {
+    using Pr = Prec<MIXED>;
+    using F = typename Pr::F;
+    using Acc = typename Pr::Acc;
+    using Cfg = TiledCfg<NP>;
+    constexpr int LDX = NP + 1;  // R strip: [16][NP];  T strip: [NP][17] (stride kLDI)
+    __shared__ F sX[kT * LDX > NP * kLDI ? kT * LDX : NP * kLDI];
+    __shared__ F sLt[kT * kLDI];
+    __shared__ F sDi[kT * kLDI];
+    FactorDesc P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
+    if (*P.info != kInfoOk) return;
+    const Node d = node_of(P, lvl, kk);
+    const bool isR = (int)blockIdx.y < Cfg::NT16;
+    if (isR ? !d.has_r : !d.has_l) return;
+    const int t = isR ? blockIdx.y : blockIdx.y - Cfg::NT16;
+    const int lane = threadIdx.x, i = lane & 15, q4 = lane >> 4;
+    const int n = d.n;
+    const F* Lg = Pr::Lf(P) + (size_t)d.pi * d.nn;
+    const F* Dg = (const F*)P.Dinv + (size_t)d.pi * Cfg::NT16 * kT * kT;
+    F* dst = (isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn;
+    // stage the strip of the coupling
+    if (lvl == 0) {
+        const double* C = P.A_off + (size_t)(isR ? d.i - 1 : d.i - 2) * d.nn;
+        if (isR)
+            stage_panel<NP, kT, LDX, false, 64>(sX, C, n, kT * t, lane);
+        else
+            stage_panel<NP, kT, kLDI, true, 64>(sX, C, n, kT * t, lane);
+    } else {
+        if (isR)
+            stage_panel<NP, kT, LDX, false, 64>(sX, dst, n, kT * t, lane);
+        else
+            stage_panel<NP, kT, kLDI, true, 64>(sX, dst, n, kT * t, lane);
+    }
+    wave_lds_sync();
+    auto stage_tile = [&](F* s16, const F* g, int r0, int c0, bool unit_pad) {
+        for (int e = lane; e < kT * kT; e += 64) {
+            const int r = e / kT, c = e % kT, gr = r0 + r, gc = c0 + c;
+            F v = (unit_pad && gr == gc) ? F(1) : F(0);
+            if (gr < n && gc < n) v = g[(size_t)gr * n + gc];
+            s16[r * kLDI + c] = v;
+        }
+    };
+    for (int p = 0; p < Cfg::NT16; ++p) {
+        Acc acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = Pr::row(v, lane), c = lane & 15;
+            acc[v] = isR ? sX[r * LDX + kT * p + c] : sX[(kT * p + r) * kLDI + c];
+        }
+        for (int qq = 0; qq < p; ++qq) {
+            stage_tile(sLt, Lg, kT * p, kT * qq, false);  // L[p, qq]
+            wave_lds_sync();
+#pragma unroll
+            for (int k = 0; k < kT; k += 4) {
+                F a, b;
+                if (isR) {  // - X[:, qq] L[p, qq]^T
+                    a = sX[i * LDX + kT * qq + k + q4];
+                    b = sLt[i * kLDI + k + q4];
+                } else {    // - L[p, qq] X[qq, :]
+                    a = sLt[i * kLDI + k + q4];
+                    b = sX[(kT * qq + k + q4) * kLDI + i];
+                }
+                acc = Pr::mma(-a, b, acc);
+            }
+            wave_lds_sync();
+        }
+        // Y -> strip tile; then multiply by the inverted diagonal tile
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = Pr::row(v, lane), c = lane & 15;
+            if (isR)
+                sX[r * LDX + kT * p + c] = acc[v];
+            else
+                sX[(kT * p + r) * kLDI + c] = acc[v];
+        }
+        for (int e = lane; e < kT * kT; e += 64) sDi[(e / kT) * kLDI + e % kT] = Dg[(size_t)p * kT * kT + e];
+        wave_lds_sync();
+        Acc out = {};
+#pragma unroll
+        for (int k = 0; k < kT; k += 4) {
+            F a, b;
+            if (isR) {  // Y Dinv_p^T
+                a = sX[i * LDX + kT * p + k + q4];
+                b = sDi[i * kLDI + k + q4];
+            } else {    // Dinv_p Y
+                a = sDi[i * kLDI + k + q4];
+                b = sX[(kT * p + k + q4) * kLDI + i];
+            }
+            out = Pr::mma(a, b, out);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = Pr::row(v, lane), c = lane & 15;
+            if (isR)
+                sX[r * LDX + kT * p + c] = out[v];
+            else
+                sX[(kT * p + r) * kLDI + c] = out[v];
+        }
+        wave_lds_sync();
+    }
+    // write the strip back
+    if (isR) {
+        for (int e = lane; e < kT * NP; e += 64) {
+            const int r = e / NP, c = e % NP, gr = kT * t + r;
+            if (gr < n && c < n) dst[(size_t)gr * n + c] = sX[r * LDX + c];
+        }
+    } else {
+        for (int e = lane; e < NP * kT; e += 64) {
+            const int r = e / kT, c = e % kT, gc = kT * t + c;
+            if (r < n && gc < n) dst[(size_t)r * n + gc] = sX[r * kLDI + c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K4: blockIdx.y < NTRI32: lower tile of S_{i+s} -= R R^T; else fill tile
+// -R T (row-major over the W32 x W32 tiles).
+template <int NP, bool MIXED>
+__global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
+    using Pr = Prec<MIXED>;
+    using F = typename Pr::F;
+    using Cfg = TiledCfg<NP>;
+    constexpr int LDR = NP + 1;  // row panel [32][NP]
+    constexpr int LDP = 33;      // column panel [NP][32]
+    __shared__ F pa[32 * LDR];
+    __shared__ F pb[NP * LDP > 32 * LDR ? NP * LDP : 32 * LDR];
+    FactorDesc P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
+    if (*P.info != kInfoOk) return;
+    const Node d = node_of(P, lvl, kk);
+    const bool sep = (int)blockIdx.y < Cfg::NTRI32;
+    if (sep ? !d.has_r : !(d.has_r && d.has_l)) return;
+    int a, b;
+    if (sep) {
+        tri_tile(blockIdx.y, a, b);
+    } else {
+        a = (blockIdx.y - Cfg::NTRI32) / Cfg::W32;
+        b = (blockIdx.y - Cfg::NTRI32) % Cfg::W32;
+    }
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid & 63;
+    const int n = d.n;
+    const F* R = Pr::Rf(P) + (size_t)d.pi * d.nn;
+    const F* T = Pr::Tf(P) + (size_t)d.pi * d.nn;
+    stage_panel<NP, 32, LDR, false, 256>(pa, R, n, 32 * a, tid);
+    if (sep)
+        stage_panel<NP, 32, LDR, false, 256>(pb, R, n, 32 * b, tid);
+    else
+        stage_panel<NP, 32, LDP, true, 256>(pb, T, n, 32 * b, tid);
+    __syncthreads();
+    const int sr = w >> 1, sc = w & 1;
+    if (sep && a == b && sr < sc) return;
+    typename Pr::Acc acc = {};
+    const int i = lane & 15, q = lane >> 4;
+#pragma unroll 4
+    for (int k = 0; k < NP; k += 4) {
+        const F av = pa[(16 * sr + i) * LDR + k + q];
+        const F bv = sep ? pb[(16 * sc + i) * LDR + k + q] : pb[(k + q) * LDP + 16 * sc + i];
+        acc = Pr::mma(av, bv, acc);
+    }
+    if (sep) {
+        const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i + d.s - 1) * d.nn : P.Ld + (size_t)d.pr * d.nn;
+        double* S = P.Ld + (size_t)d.pr * d.nn;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 32 * a + 16 * sr + Pr::row(v, lane), c = 32 * b + 16 * sc + (lane & 15);
+            if (r < n && c < n) S[(size_t)r * n + c] = src[(size_t)r * n + c] - (double)acc[v];
+        }
+    } else {
+        const int64_t lft = d.i - d.s, rgt = d.i + d.s;
+        F* dst = (((lft >> (lvl + 1)) & 1) != 0) ? Pr::Rf(P) + (size_t)perm_pos(d.N, lvl + 1, lft) * d.nn
+                                                 : Pr::Tf(P) + (size_t)perm_pos(d.N, lvl + 1, rgt) * d.nn;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 32 * a + 16 * sr + Pr::row(v, lane), c = 32 * b + 16 * sc + (lane & 15);
+            if (r < n && c < n) dst[(size_t)r * n + c] = -acc[v];
+        }
+    }
+}
+
+template <int NP, bool MIXED>
+hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int level_hint, int64_t items, hipStream_t st) {
+    using Cfg = TiledCfg<NP>;
+    const unsigned g = (unsigned)items;
+    if (level_hint != 0)  // level 0 has no deferred updates
+        hipLaunchKernelGGL((k_tiled_syrk_deferred<NP, MIXED>), dim3(g, 2 * Cfg::NTRI32), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((k_tiled_potrf<NP, MIXED>), dim3(g), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((k_tiled_trsm<NP, MIXED>), dim3(g, 2 * Cfg::NT16), dim3(64), 0, st, p);
+    hipLaunchKernelGGL((k_tiled_update<NP, MIXED>), dim3(g, Cfg::NTRI32 + Cfg::W32 * Cfg::W32), dim3(256), 0, st,
+                       p);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, bool mixed, int level_hint, int64_t items,
+                               hipStream_t st) {
+    switch (np) {
+        case 96: return mixed ? launch_tiled_np<96, true>(p, level_hint, items, st)
+                              : launch_tiled_np<96, false>(p, level_hint, items, st);
+        case 128: return mixed ? launch_tiled_np<128, true>(p, level_hint, items, st)
+                               : launch_tiled_np<128, false>(p, level_hint, items, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace btc

@@ -39,6 +39,9 @@ struct btc_handle_s {
     float* R32 = nullptr;
     float* T32 = nullptr;
     unsigned long long* info = nullptr;
+    // large blocks (padded 96/128): inverted 16 x 16 diagonal tiles of each
+    // L_ii, produced and consumed within one factorization level step
+    void* Dinv = nullptr;
     // solve workspace, grown on demand (one allocation)
     void* ws = nullptr;
     int64_t ws_m = 0;
@@ -98,6 +101,7 @@ inline void free_all(btc_handle h) {
     dfree(h->Ld);
     dfree(h->Rb);
     dfree(h->Tb);
+    dfree(h->Dinv);
     dfree(h->S64);
     dfree(h->L32);
     dfree(h->R32);
@@ -144,10 +148,18 @@ inline void drain_profile(btc_handle h) {
     h->pending.clear();
 }
 
+// Inverted diagonal tiles of the tile-parallel factorization (padded block
+// sizes above 64 only): NP/16 tiles of 16 x 16 per node, in the factor's type.
+inline size_t dinv_bytes(int64_t N, int64_t n, int32_t prec) {
+    const int np = btc::padded_block((int)n);
+    if (np <= 64) return 0;
+    return (size_t)N * (size_t)(np / 16) * 256 * (is_mixed(prec) ? sizeof(float) : sizeof(double));
+}
+
 inline size_t factor_bytes(int64_t N, int64_t n, int32_t prec) {
     const size_t nn = (size_t)N * (size_t)n * (size_t)n;
-    if (is_mixed(prec)) return nn * (sizeof(double) + 3 * sizeof(float));
-    return 3 * nn * sizeof(double);
+    if (is_mixed(prec)) return nn * (sizeof(double) + 3 * sizeof(float)) + dinv_bytes(N, n, prec);
+    return 3 * nn * sizeof(double) + dinv_bytes(N, n, prec);
 }
 
 // Solve workspace: FP64 path: Y, U, V (FP64); mixed: r, y, u, v, d (FP32);
@@ -229,6 +241,7 @@ inline btc::FactorDesc factor_desc(btc_handle h, const double* A_diag, const dou
         d.Tb = h->Tb;
     }
     d.info = h->info;
+    d.Dinv = h->Dinv;
     d.N = h->N;
     d.n = (int32_t)h->n;
     return d;
@@ -239,10 +252,32 @@ inline int factor_np(btc_handle h) {
     return is_mixed(h->precision) ? btc::padded_block_mixed((int)h->n) : btc::padded_block((int)h->n);
 }
 
+// Factor kernel family of a handle: 0 VALU FP64 (np < 16), 1 MFMA FP64,
+// 2 mixed, 3 tile-parallel FP64 (np > 64), 4 tile-parallel mixed.
+inline int factor_kind(btc_handle h) {
+    const int np = factor_np(h);
+    const bool mixed = is_mixed(h->precision);
+    if (np > 64) return mixed ? 4 : 3;
+    if (mixed) return 2;
+    return np >= 16 ? 1 : 0;
+}
+
+// level_hint: the level of every item of the launch, or -1 when they differ.
+inline hipError_t launch_factor_kind(int kind, const btc::Launch<btc::FactorDesc>& L, int np, int level_hint,
+                                     int64_t items, hipStream_t st) {
+    switch (kind) {
+        case 0: return btc::launch_factor_valu(L, np, items, st);
+        case 1: return btc::launch_factor_mfma(L, np, items, st);
+        case 2: return btc::launch_factor_mixed(L, np, items, st);
+        case 3: return btc::launch_factor_tiled(L, np, false, level_hint, items, st);
+        case 4: return btc::launch_factor_tiled(L, np, true, level_hint, items, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 inline hipError_t launch_factor_any(btc_handle h, const btc::Launch<btc::FactorDesc>& L, int64_t items, hipStream_t st) {
     const int np = factor_np(h);
-    if (is_mixed(h->precision)) return btc::launch_factor_mixed(L, np, items, st);
-    return np >= 16 ? btc::launch_factor_mfma(L, np, items, st) : btc::launch_factor_valu(L, np, items, st);
+    return launch_factor_kind(factor_kind(h), L, np, L.level, items, st);
 }
 
 inline int launch_factor(btc_handle h, const double* A_diag, const double* A_off, hipStream_t st) {

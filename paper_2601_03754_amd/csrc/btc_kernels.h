@@ -57,6 +57,7 @@ struct FactorDesc {
     float* R32;
     float* T32;
     unsigned long long* info;  // ~0 = ok, else smallest failing 1-based block
+    void* Dinv;                // large blocks: inverted 16 x 16 diagonal tiles of L_ii (F), per node
     int64_t N;
     int32_t n;
     int32_t pad;
@@ -132,6 +133,10 @@ int padded_block_mixed(int n);
 hipError_t launch_factor_valu(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st);
 hipError_t launch_factor_mfma(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st);
 hipError_t launch_factor_mixed(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st);
+// Padded sizes 96 and 128: four tile-parallel launches per level (level_hint
+// 0 skips the deferred-update launch, which has nothing to do at level 0).
+hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, bool mixed, int level_hint, int64_t items,
+                               hipStream_t st);
 hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t items, bool backward, hipStream_t st);
 hipError_t launch_sweep(const Launch<SweepDesc<float>>& p, int np, int64_t items, bool backward, hipStream_t st);
 hipError_t launch_residual(const Launch<ResidualDesc>& p, int np, int64_t items, hipStream_t st);

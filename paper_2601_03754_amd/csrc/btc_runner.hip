@@ -32,7 +32,8 @@ __global__ void k_reset_infos(unsigned long long* const* __restrict__ ptrs, int 
 // One group = one launch.
 struct Group {
     int op;    // btc_op
-    int kind;  // FACTOR: 0 VALU f64, 1 MFMA f64, 2 mixed; sweeps: 0 double, 1 float
+    int kind;  // FACTOR: factor kernel family (factor_kind); sweeps: 0 double, 1 float
+    int level = -1;  // FACTOR: common level of the items, -1 if they differ
     int np;
     std::vector<char> descs;  // packed descriptors (all of one type)
     size_t desc_size = 0;
@@ -192,11 +193,12 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
                 h->failed_known = false;
             }
             const int np = factor_np(h);
-            const int kind = mixed ? 2 : (np >= 16 ? 1 : 0);
+            const int kind = factor_kind(h);
             Group& g = groups[std::make_tuple(s.op, kind, np)];
             g.op = s.op;
             g.kind = kind;
             g.np = np;
+            g.level = g.items.empty() ? s.level : (g.level == s.level ? s.level : -1);
             const int32_t inst = (int32_t)(g.descs.size() / sizeof(btc::FactorDesc));
             push_desc(g, factor_desc(h, h->A_diag, h->A_off));
             const int64_t nodes = level_nodes(h->N, s.level);
@@ -279,9 +281,7 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
         switch (g.op) {
             case BTC_OP_FACTOR: {
                 auto L = make_launch<btc::FactorDesc>(g, sl.dev);
-                e = g.kind == 2 ? btc::launch_factor_mixed(L, g.np, items, st)
-                                : g.kind == 1 ? btc::launch_factor_mfma(L, g.np, items, st)
-                                              : btc::launch_factor_valu(L, g.np, items, st);
+                e = launch_factor_kind(g.kind, L, g.np, g.level, items, st);
                 break;
             }
             case BTC_OP_FORWARD:

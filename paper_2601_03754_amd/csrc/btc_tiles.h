@@ -95,11 +95,10 @@ __device__ __forceinline__ void tri_tile(int k, int& a, int& b) {
 // rest of the column is broadcast through a double-buffered LDS column for
 // the trailing update.  1/sqrt of the pivot: hardware estimate refined by two
 // Newton steps.  Writes L (zero strict upper part) back and 1/L_jj to invd.
-template <int NP>
+template <int NP, int LD = NP + 1>
 __device__ __forceinline__ bool potrf_lookahead(double* __restrict__ A, double* __restrict__ invd,
                                                 double (*__restrict__ colbuf)[kWave]) {
     static_assert(NP <= kWave, "one lane per row");
-    constexpr int LD = NP + 1;
     const int lane = threadIdx.x & (kWave - 1);
     double a[NP];
 #pragma unroll

@@ -67,7 +67,7 @@ def test_footprint(lib):
     assert mixed == 16 * 64 * (8 + 3 * 4) + 8  # FP64 Schur complements + FP32 factor
     assert lib.btc_footprint_bytes(16, 8, lib.BTC_FP64, 4) > lib.btc_footprint_bytes(16, 8, lib.BTC_FP64, 1) > fp64
     assert lib.btc_footprint_bytes(0, 8, 0, 1) == 0
-    assert lib.btc_footprint_bytes(16, 65, 0, 1) == 0
+    assert lib.btc_footprint_bytes(16, 129, 0, 1) == 0
     assert lib.btc_footprint_bytes(16, 8, 7, 1) == 0
 
 
@@ -78,13 +78,13 @@ def test_argument_errors_before_device_work(lib):
     assert L.btc_factor(None, None, 4, 4, None, None, ctypes.byref(h)) == -1
     assert L.btc_factor(8, 8, 0, 4, None, None, ctypes.byref(h)) == -3
     assert L.btc_factor(8, 8, 4, 0, None, None, ctypes.byref(h)) == -4
-    assert L.btc_factor(8, 8, 4, 65, None, None, ctypes.byref(h)) == lib.BTC_ERR_UNSUPPORTED
+    assert L.btc_factor(8, 8, 4, 129, None, None, ctypes.byref(h)) == lib.BTC_ERR_UNSUPPORTED
     assert L.btc_factor(8, 8, 4, 4, None, None, None) == -7
     assert L.btc_solve(None, 8, 8, 1, None, None) == -1
     assert L.btc_status(None, None) == -1
     L.btc_destroy(None)
     assert L.btc_create(0, 4, None, ctypes.byref(h)) == -1
-    assert L.btc_create(4, 65, None, ctypes.byref(h)) == lib.BTC_ERR_UNSUPPORTED
+    assert L.btc_create(4, 129, None, ctypes.byref(h)) == lib.BTC_ERR_UNSUPPORTED
     assert L.btc_runner_run(None, 0, None) == -1
     assert L.btc_runner_create(None, None) == -2
     assert L.btc_runner_query(None) == -1
