@@ -1,24 +1,38 @@
 #!/usr/bin/env python3
 """Benchmark of the block-tridiagonal Cholesky hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload served|single]
 
-A step is one pass of the whole hot path over one synthetic instance that is
-already resident in HBM: a full refactorization (all levels of the
-nested-dissection elimination) followed by a solve (forward and backward
-level sweeps).  W untimed steps, then K timed steps bracketed by
-device synchronisation.  Prints ONE JSON line.
+Default workload ("served"): 256 clients, each with its own block-tridiagonal
+system (N log-uniform in [64, 4096], n uniform in {12..96}, diagonal shift 4,
+one right-hand side), served by the library's continuous-batching server.
+Every request is either a solve against the client's resident factor with a
+new right-hand side (70%) or a refactorization with new matrix values
+followed by a solve (30%).  The headline runs the server closed-loop at
+saturation: every client always has one request outstanding and submits its
+next one as soon as the previous one completes.  A step is 256 completed
+requests (one per client on average); W untimed steps, then K timed steps
+bracketed by device synchronisation.  The mixed-precision path (FP32 factor
+and sweeps, FP64 Schur complements, pivot factorizations, residual and
+iterative refinement to a 1e-10 relative residual) is the headline; the plain
+FP64 path runs the same trace beside it.  Latency (p50/p99) is measured per
+request from submission to the observed completion; the open-loop Poisson
+runs (--rates) report latency at fixed arrival rates from the scheduled
+arrival time.  Every input is drawn on the device before timing starts.
 
-The roofline object describes the dominant kernel (the level launch with the
-largest total time), timed live with HIP events recorded by the library on the
-launch stream; its algorithmic bytes and flops per launch are computed from
-the level schedule (see ``level_work``).  The CPU baseline runs the FP64
-oracle (test infrastructure) single-threaded on the same instance.
+Workload "single": one instance (N, n) refactored and solved every step.
+
+Roofline: the kernel group with the largest total time (found during the
+warm-up) is timed live during the timed region with HIP events that the
+library records on its launch stream; its algorithmic bytes/flops per launch
+come from btc_level_work.  The CPU baseline is the FP64 oracle (plain C, one
+thread) on a bounded sample of the same requests.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -31,203 +45,395 @@ sys.path.insert(0, ROOT)
 METRIC = "factor+solve/sec & p99 latency, served mixed-prec vs plain FP64 @1e-10 resid"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-FP64_RIDGE = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+FP32_PEAK_TFLOPS = 157.3
+OPS = {0: "factor", 1: "forward", 2: "backward", 3: "residual", 4: "refine_init", 5: "refine_test"}
+FACTOR_KIND = {0: "fp64 valu", 1: "fp64 mfma", 2: "mixed", 3: "fp64 tiled", 4: "mixed tiled"}
+SOLVE_FRAC = 0.7
+RELRES_TARGET = 1e-10
 
 
-def level_work(N: int, n: int, m: int = 1, mixed: bool = False):
-    """Algorithmic flops and HBM bytes of every level launch.
-
-    Factor, per node i at level l (stride s), with the block I/O the level step
-    of Algorithm 4 defines (each n x n block read or written once):
-      reads  S_i, C_{i+s,i} (if right), C_{i,i-s} (if left), T_{i+s/2} (if
-             deferred), S_{i+s} (if right), T_{i+3s/2} (if deferred)
-      writes L_ii, R_i, T_i, S_{i+s}, fill C_{i+s,i-s} (when present)
-      flops  potrf n^3/3, trsm n^3 each, syrk n^3 each, gemm 2n^3
-             (cost table of section "Computational Complexity").
-    Word sizes: 8 bytes for everything on the FP64 path; on the mixed path the
-    Schur complements S and the input blocks are FP64 (8 bytes) and the factor
-    blocks L, R, T and the fill couplings FP32 (4 bytes).
-    Solve, per node and sweep: reads L_ii, R_i, T_i (when present) plus the
-    n x m vectors it touches; flops n^2 m per triangular solve and 2n^2 m per
-    block product (Algorithm 6)."""
-    out = {"factor": [], "forward": [], "backward": []}
-    wS = 8.0
-    wF = 4.0 if mixed else 8.0
-    nn = n * n
-    L = int(np.floor(np.log2(N))) + 1
-    for l in range(L):
-        s = 1 << l
-        h = s >> 1
-        i = np.arange(s, N + 1, 2 * s, dtype=np.int64)
-        has_r = i + s <= N
-        has_l = i > s
-        d_self = (i + h <= N) & (l > 0)
-        d_sep = (i + 3 * h <= N) & has_r & (l > 0)
-        both = has_r & has_l
-        wC = 8.0 if l == 0 else wF  # level 0 reads the couplings from the FP64 input
-        rd = nn * (wS * (len(i) + has_r.sum()) + wC * (has_r.sum() + has_l.sum())
-                   + wF * (d_self.sum() + d_sep.sum()))
-        wr = nn * (wS * has_r.sum() + wF * (len(i) + has_r.sum() + has_l.sum() + both.sum()))
-        fl = n ** 3 * (len(i) / 3 + 2 * has_r.sum() + has_l.sum() + d_self.sum() + d_sep.sum()
-                       + 2 * both.sum())
-        out["factor"].append({"bytes": float(rd + wr), "flops": float(fl), "nodes": len(i)})
-        vec = wF * n * m
-        blocks = len(i) + has_r.sum() + has_l.sum()
-        pulls = len(i) * 2 * l  # at most 2 small vectors per lower level
-        fwd_b = blocks * nn * wF + vec * (len(i) + pulls) + vec * (len(i) + has_r.sum() + has_l.sum())
-        bwd_b = blocks * nn * wF + vec * (len(i) + has_r.sum() + has_l.sum()) + vec * len(i)
-        sfl = n * n * m * (len(i) + 2 * has_r.sum() + 2 * has_l.sum())
-        out["forward"].append({"bytes": float(fwd_b), "flops": float(sfl), "nodes": len(i)})
-        out["backward"].append({"bytes": float(bwd_b), "flops": float(sfl), "nodes": len(i)})
-    return out
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pr, budget_s: float):
-    """FP64 oracle (plain C, one thread) factor + solve on the same instance,
-    repeated while within the time budget (at least once)."""
-    import oracle
-    oracle.build()
-    t0 = time.perf_counter()
-    runs = 0
-    while True:
-        Ld, Rb, Tb, info = oracle.factor_nd(pr.D, pr.E)
-        oracle.solve_nd(Ld, Rb, Tb, pr.B)
-        runs += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or runs >= 50:
-            break
-        if el / runs * (runs + 1) > budget_s * 1.5:
-            break
-    return runs / el, runs, el
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else float("nan")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="fp64-single", choices=["fp64-single"])
-    ap.add_argument("--N", type=int, default=4096)
-    ap.add_argument("--n", type=int, default=64)
-    ap.add_argument("--nrhs", type=int, default=1)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_ir"])
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the method factors one block-tridiagonal system "
-              "per device here; multi-GPU runs are not part of this build", file=sys.stderr)
-        sys.exit(2)
-
+def relres_torch(D, E, X, B):
+    """max over columns of ||b - Psi x||_2 / ||b||_2 in FP64 with plain torch
+    ops (independent of the library): Psi has the lower triangles of D
+    mirrored on the diagonal and E[i-1] at block (i+1, i)."""
     import torch
-    import oracle
-    from paper_2601_03754_amd import btc, inputs
+    Dl = torch.tril(D) + torch.tril(D, -1).transpose(1, 2)
+    R = B - torch.bmm(Dl, X)
+    if E.shape[0]:
+        R[1:] -= torch.bmm(E, X[:-1])
+        R[:-1] -= torch.bmm(E.transpose(1, 2).contiguous(), X[1:])
+    num = torch.linalg.vector_norm(R, dim=(0, 1))
+    den = torch.linalg.vector_norm(B, dim=(0, 1))
+    return float((num / den).max())
 
+
+def roofline_entry(stat):
+    """Roofline object for one profiled kernel group."""
+    avg_ms = stat["ms"] / stat["launches"]
+    bpl = stat["bytes"] / stat["launches"]
+    fpl = stat["flops"] / stat["launches"]
+    t_hbm = bpl / (HBM_PEAK_GBS * 1e9)
+    # FP32 peak for the FP32 kernel families (mixed factor: its products run on
+    # FP32 matrix cores; FP32 sweeps), FP64 peak otherwise
+    fp32 = (stat["op"] == 0 and stat["kind"] in (2, 4)) or (stat["op"] in (1, 2) and stat["kind"] == 1)
+    fpeak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
+    t_alu = fpl / (fpeak * 1e12)
+    if t_hbm >= t_alu:
+        r = {"bound": "hbm", "achieved": bpl / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        r = {"bound": "alu", "achieved": fpl / (avg_ms * 1e-3) / 1e12, "peak": fpeak, "unit": "TFLOP/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = None
+    r["avg_launch_ms"] = avg_ms
+    r["launches"] = stat["launches"]
+    r["algorithmic_bytes_per_launch"] = bpl
+    r["algorithmic_flops_per_launch"] = fpl
+    kind = FACTOR_KIND.get(stat["kind"], str(stat["kind"])) if stat["op"] == 0 else \
+        ("fp32" if stat["kind"] == 1 else "fp64") if stat["op"] in (1, 2) else "fp64"
+    r["kernel"] = "%s %s np=%d" % (OPS[stat["op"]], kind, stat["np"])
+    return r
+
+
+# ---------------------------------------------------------------------------
+# served workload
+
+class Clients:
+    """Device-resident inputs of every client: two matrix versions (a
+    refactorization switches to the other one) and four right-hand sides."""
+
+    def __init__(self, shapes, seed=0):
+        import torch
+        from paper_2601_03754_amd import inputs
+        self.shapes = shapes
+        self.mats, self.rhs, self.X = [], [], []
+        for c, (N, n) in enumerate(shapes):
+            vers = []
+            for v in range(2):
+                D, E, B = inputs.block_tridiag_device(N, n, 4.0, seed=seed * 100003 + 2 * c + v, nrhs=4)
+                vers.append((D, E))
+                if v == 0:
+                    self.rhs.append([B[:, :, k:k + 1].contiguous() for k in range(4)])
+                del B
+            self.mats.append(vers)
+            self.X.append(torch.zeros((N, n, 1), dtype=torch.float64, device="cuda:0"))
+        torch.cuda.synchronize()
+
+
+class Served:
+    """One server (one precision) over the clients, with the bookkeeping of
+    the requests a run submits."""
+
+    def __init__(self, btc, clients, precision, seed):
+        self.btc = btc
+        self.cl = clients
+        self.srv = btc.Server(precision=precision, hbm_budget=1 << 46)
+        self.ids = [self.srv.add_client(N, n) for N, n in clients.shapes]
+        self.rng = np.random.default_rng(seed)
+        self.ver = [0] * len(self.ids)
+        self.rhs_k = [0] * len(self.ids)
+        self.first = [True] * len(self.ids)
+        self.last = {}  # client -> (version, rhs index) of its last submitted request
+
+    def submit(self, c, refactor=None):
+        if refactor is None:
+            refactor = self.first[c] or self.rng.random() >= SOLVE_FRAC
+        if refactor and not self.first[c]:
+            self.ver[c] ^= 1
+        self.first[c] = False
+        k = self.rhs_k[c] = (self.rhs_k[c] + 1) % 4
+        A = self.cl.mats[c][self.ver[c]] if refactor else None
+        t = self.srv.submit(self.ids[c], self.cl.rhs[c][k], self.cl.X[c], A=A)
+        self.last[c] = (self.ver[c], k)
+        return t
+
+    def closed_loop(self, requests):
+        """Every client keeps one request outstanding until `requests` have
+        been submitted; returns (completions, wall seconds)."""
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sub = 0
+        for c in range(len(self.ids)):
+            if sub < requests:
+                self.submit(c)
+                sub += 1
+        done = []
+        while len(done) < requests:
+            self.srv.step()
+            for d in self.srv.poll():
+                done.append(d)
+                if sub < requests:
+                    self.submit(d["client"])
+                    sub += 1
+        torch.cuda.synchronize()
+        return done, time.perf_counter() - t0
+
+    def open_loop(self, rate, requests):
+        """Poisson arrivals at `rate` per second over random clients;
+        latency from the scheduled arrival to the observed completion."""
+        import torch
+        rng = np.random.default_rng(int(rate))
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=requests))
+        who = rng.integers(0, len(self.ids), size=requests)
+        torch.cuda.synchronize()
+        t0m = time.monotonic()
+        sched = {}
+        k = 0
+        done = []
+        while len(done) < requests:
+            now = time.monotonic() - t0m
+            while k < requests and arr[k] <= now:
+                t = self.submit(int(who[k]))
+                sched[t] = t0m + arr[k]
+                k += 1
+            self.srv.step()
+            for d in self.srv.poll():
+                d["t_sched"] = sched.pop(d["ticket"])
+                done.append(d)
+        torch.cuda.synchronize()
+        wall = time.monotonic() - t0m
+        return done, wall
+
+    def verify(self):
+        """Relative residual of every client's last result (FP64, torch)."""
+        worst = 0.0
+        for c, (v, k) in self.last.items():
+            D, E = self.cl.mats[c][v]
+            worst = max(worst, relres_torch(D, E, self.cl.X[c], self.cl.rhs[c][k]))
+        return worst
+
+    def close(self):
+        self.srv.close()
+
+
+def lat_ms(done, key="t_submit", drop=0.05):
+    d = done[int(len(done) * drop):]
+    return [(x["t_done"] - x[key]) * 1e3 for x in d]
+
+
+def run_served(args, btc):
+    import torch
+    from paper_2601_03754_amd import inputs
+    shapes = inputs.served_clients(args.clients, seed=0)
+    log("generating inputs of %d clients on the device" % len(shapes))
+    cl = Clients(shapes)
+    per_step = len(shapes)
+    paths = {}
+    rates_out = []
+    roof = None
+    for name, prec in (("mixed", btc.BTC_FP32_IR), ("fp64", btc.BTC_FP64)):
+        sv = Served(btc, cl, prec, seed=1)
+        rh = sv.srv.runner_handle()
+        # warm-up: first requests factor every client; profile every group
+        btc.runner_profile(rh, -1, -1)
+        sv.closed_loop(per_step * max(1, args.warmup))
+        stats = btc.runner_profile_read(rh)
+        dom = stats[0]
+        # timed region: only the dominant group's family carries events
+        btc.runner_profile(rh, dom["op"], dom["kind"])
+        done, wall = sv.closed_loop(per_step * args.steps)
+        tstats = [s for s in btc.runner_profile_read(rh) if (s["op"], s["kind"], s["np"]) ==
+                  (dom["op"], dom["kind"], dom["np"])]
+        btc.runner_profile(rh, -2, -1)
+        lat = lat_ms(done)
+        relres = sv.verify()
+        ent = {"value": len(done) / wall, "ms_per_step": wall * 1e3 / args.steps,
+               "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "requests": len(done),
+               "refactor_share": float(np.mean([d["refactored"] for d in done])),
+               "max_relres_last": relres,
+               "warmup_kernel_ms": [{"kernel": roofline_entry(s)["kernel"],
+                                     "ms": round(s["ms"], 3), "launches": s["launches"]} for s in stats[:8]]}
+        if tstats:
+            ent["roofline"] = roofline_entry(tstats[0])
+        log("%s closed loop: %.0f req/s, p50 %.2f ms, p99 %.2f ms, relres %.2e"
+            % (name, ent["value"], ent["p50_ms"], ent["p99_ms"], relres))
+        for rate in args.rates:
+            nreq = int(min(args.rate_requests, max(200, rate * args.rate_seconds)))
+            d2, w2 = sv.open_loop(rate, nreq)
+            l2 = lat_ms(d2, key="t_sched")
+            rates_out.append({"path": name, "rate": rate, "requests": nreq, "achieved": nreq / w2,
+                              "p50_ms": pct(l2, 50), "p99_ms": pct(l2, 99)})
+            log("%s open loop %d/s: achieved %.0f/s p50 %.2f p99 %.2f ms"
+                % (name, rate, nreq / w2, rates_out[-1]["p50_ms"], rates_out[-1]["p99_ms"]))
+        sv.close()
+        paths[name] = ent
+        torch.cuda.synchronize()
+    return shapes, paths, rates_out
+
+
+def cpu_baseline_served(shapes, budget_s):
+    """The FP64 oracle (plain C, one thread) on requests of the same mix:
+    clients in order; refactor+solve for 30% of them, solve-only otherwise
+    (factor time not counted for those), until the time budget is used."""
+    import oracle
+    from paper_2601_03754_amd import inputs
+    oracle.build()
+    rng = np.random.default_rng(5)
+    t_work = 0.0
+    served = 0
+    used = []
+    t_start = time.perf_counter()
+    for c, (N, n) in enumerate(shapes):
+        if time.perf_counter() - t_start > budget_s:
+            break
+        pr = inputs.block_tridiag(N, n, c=4.0, seed=c, nrhs=1)
+        t0 = time.perf_counter()
+        Ld, Rb, Tb, info = oracle.factor_nd(pr.D, pr.E)
+        t1 = time.perf_counter()
+        oracle.solve_nd(Ld, Rb, Tb, pr.B)
+        t2 = time.perf_counter()
+        refactor = rng.random() >= SOLVE_FRAC
+        t_work += (t2 - t0) if refactor else (t2 - t1)
+        served += 1
+        used.append((N, n, bool(refactor)))
+    return served / t_work, served, t_work, used
+
+
+# ---------------------------------------------------------------------------
+# single-instance workload
+
+def run_single(args, btc):
+    import torch
+    from paper_2601_03754_amd import inputs
     N, n, m = args.N, args.n, args.nrhs
     seed = inputs.sweep_seed(N, n)
-    pr = inputs.block_tridiag(N, n, c=4.0, seed=seed, nrhs=m)
-    dev = torch.device("cuda:0")
-    D = torch.from_numpy(pr.D).to(dev)
-    E = torch.from_numpy(pr.E).to(dev)
-    B = torch.from_numpy(pr.B).to(dev)
+    D, E, B = inputs.block_tridiag_device(N, n, 4.0, seed=seed, nrhs=m)
     X = torch.empty_like(B)
-    stream = torch.cuda.current_stream()
     prec = btc.BTC_FP64 if args.precision == "fp64" else btc.BTC_FP32_IR
     f = btc.Factor(D, E, precision=prec)
     for _ in range(args.warmup):
         f.refactor(D, E)
         f.solve(B, X)
     torch.cuda.synchronize()
-    info = f.info
-    if info != 0:
-        raise RuntimeError("factorization broke down at block %d" % info)
-
-    # timed region: K steps bracketed by synchronisation, no instrumentation
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    if f.info != 0:
+        raise RuntimeError("factorization broke down at block %d" % f.info)
+    btc.btc_profile(f.handle, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
     for _ in range(args.steps):
         f.refactor(D, E)
         f.solve(B, X)
-    ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-
-    # live kernel timing: the same K steps again with HIP events recorded by the
-    # library around every level launch on its launch stream
-    btc.btc_profile(f.handle, True)
-    for _ in range(args.steps):
-        f.refactor(D, E)
-        f.solve(B, X)
-    torch.cuda.synchronize()
-    prof = {ph: btc.btc_profile_read(f.handle, k) for k, ph in enumerate(("factor", "forward", "backward", "refine"))}
+    prof = {ph: btc.btc_profile_read(f.handle, k) for k, ph in enumerate(("factor", "forward", "backward"))}
     btc.btc_profile(f.handle, False)
-
-    # accuracy of the last step, checked by the oracle's FP64 residual
-    relres = oracle.relres(pr.D, pr.E, X.cpu().numpy(), pr.B)
-    _, sinfo = f.solve(B, X, want_info=True)
-
-    ms_step = wall * 1e3 / args.steps
-    value = args.steps / wall
-
-    work = level_work(N, n, m, mixed=args.precision != "fp64")
+    relres = relres_torch(D, E, X, B)
     best = None
-    for ph in ("factor", "forward", "backward"):
+    for op, ph in enumerate(("factor", "forward", "backward")):
         ms, cnt = prof[ph]
         for l in range(len(ms)):
-            if cnt[l] > 0 and (best is None or ms[l] > best[0]):
-                best = (ms[l], ph, l, ms[l] / cnt[l])
-    _, ph, lvl, avg_ms = best
-    wk = work[ph][lvl]
-    ai = wk["flops"] / wk["bytes"]
-    if ai < FP64_RIDGE:
-        roof = {"bound": "hbm", "achieved": wk["bytes"] / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": wk["flops"] / (avg_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = "%s level %d (%d nodes)" % (ph, lvl, wk["nodes"])
-    roof["avg_launch_ms"] = avg_ms
+            if cnt[l] > 0 and (best is None or ms[l] > best["ms"]):
+                b, fl = btc.btc_level_work(op, prec, N, n, m, l)
+                best = {"op": op, "kind": 1 if prec else 0, "np": 0, "launches": int(cnt[l]), "ms": ms[l],
+                        "bytes": b * cnt[l], "flops": fl * cnt[l], "level": l}
+    roof = roofline_entry(best)
+    roof["kernel"] = "%s level %d" % (OPS[best["op"]], best["level"])
+    f.close()
+    return {"value": args.steps / wall, "ms_per_step": wall * 1e3 / args.steps, "relres": relres,
+            "roofline": roof, "seed": seed}
 
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="served", choices=["served", "single"])
+    ap.add_argument("--clients", type=int, default=256)
+    ap.add_argument("--rates", default="1000,10000,50000",
+                    help="open-loop Poisson arrival rates (req/s), comma separated; empty: none")
+    ap.add_argument("--rate-seconds", type=float, default=1.0)
+    ap.add_argument("--rate-requests", type=int, default=12000)
+    ap.add_argument("--N", type=int, default=4096)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_ir"])
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: every instance is factored and solved on a single device; "
+              "runs on more than one GPU are not part of this implementation", file=sys.stderr)
+        sys.exit(2)
+    args.rates = [int(x) for x in args.rates.split(",") if x.strip()]
+
+    import torch
+    from paper_2601_03754_amd import btc
+    btc.lib()
+    assert torch.cuda.is_available(), "a GPU is required"
+
+    if args.workload == "single":
+        r = run_single(args, btc)
+        cpu = None
+        if not args.no_cpu_baseline:
+            import oracle
+            from paper_2601_03754_amd import inputs
+            oracle.build()
+            pr = inputs.block_tridiag(args.N, args.n, c=4.0, seed=r["seed"], nrhs=args.nrhs)
+            t0 = time.perf_counter()
+            runs = 0
+            while time.perf_counter() - t0 < args.cpu_budget or runs == 0:
+                Ld, Rb, Tb, _ = oracle.factor_nd(pr.D, pr.E)
+                oracle.solve_nd(Ld, Rb, Tb, pr.B)
+                runs += 1
+            el = time.perf_counter() - t0
+            cpu = {"value": runs / el, "unit": "factor+solve/s", "cores": 1, "kind": "oracle",
+                   "sample": "%d factor+solve runs of the same instance in %.1f s" % (runs, el)}
+        line = {"metric": METRIC, "value": r["value"], "unit": "factor+solve/s", "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+                "config": {"workload": "single instance factor+solve, refactor every step", "N": args.N,
+                           "n": args.n, "nrhs": args.nrhs, "diag_shift": 4.0, "precision": args.precision},
+                "relres": r["relres"], "roofline": r["roofline"], "cpu_baseline": cpu}
+        print(json.dumps(line))
+        return
+
+    shapes, paths, rates = run_served(args, btc)
+    mixed, fp64 = paths["mixed"], paths["fp64"]
     cpu = None
     if not args.no_cpu_baseline:
-        rate, runs, el = cpu_baseline(pr, args.cpu_budget)
-        cpu = {"value": rate, "unit": "factor+solve/s", "cores": 1, "kind": "oracle",
-               "sample": "%d full factor+solve runs of the same instance (N=%d, n=%d, nrhs=%d) in %.1f s"
-                         % (runs, N, n, m, el)}
-
-    tot_fl = sum(w["flops"] for w in work["factor"]) + sum(w["flops"] for w in work["forward"]) \
-        + sum(w["flops"] for w in work["backward"])
+        rate, cnt, el, used = cpu_baseline_served(shapes, args.cpu_budget)
+        cpu = {"value": rate, "unit": "req/s", "cores": 1, "kind": "oracle",
+               "sample": "the first %d clients' systems (same shapes and mix; seeded host draws), one request "
+                         "each, FP64 oracle single-threaded, %.1f s of oracle time; solve-only requests count "
+                         "only the solve" % (cnt, el)}
     line = {
         "metric": METRIC,
-        "value": value,
-        "unit": "factor+solve/s",
+        "value": mixed["value"],
+        "unit": "req/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "plain FP64 factor+solve, single instance, refactor every step",
-                   "N": N, "n": n, "nrhs": m, "diag_shift": 4.0, "seed": seed,
-                   "precision": args.precision},
-        "refine": sinfo,
-        "relres": relres,
-        "gpu_event_ms_per_step": gpu_ms / args.steps,
-        "gflops_per_s": tot_fl / (ms_step * 1e-3) / 1e9,
-        "per_level_ms": {ph: [round(float(x) / args.steps, 5) for x in prof[ph][0]] for ph in prof},
-        "roofline": roof,
+        "config": {"workload": "served: 256 clients, N log-uniform [64, 4096], n uniform {12..96}, nrhs 1, "
+                               "70% solve on the resident factor / 30% refactor+solve, closed loop at "
+                               "saturation; mixed precision with FP64 refinement to 1e-10",
+                   "clients": len(shapes), "step_requests": len(shapes), "diag_shift": 4.0,
+                   "relres_target": RELRES_TARGET},
+        "p50_ms": mixed["p50_ms"],
+        "p99_ms": mixed["p99_ms"],
+        "max_relres_last": mixed["max_relres_last"],
+        "fp64_path": {k: fp64[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "max_relres_last")},
+        "speedup_vs_fp64": mixed["value"] / fp64["value"],
+        "open_loop": rates,
+        "paths": paths,
+        "roofline": mixed.get("roofline"),
         "cpu_baseline": cpu,
     }
-    f.close()
     print(json.dumps(line))
 
 

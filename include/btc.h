@@ -259,6 +259,56 @@ BTC_API int btc_runner_sync(btc_runner r);
 BTC_API void btc_runner_destroy(btc_runner r);
 
 /*
+ * Launch profiler of a runner.  While on, every launch of a selected group
+ * is bracketed by two HIP events recorded on the runner's stream, and its
+ * algorithmic work (btc_level_work summed over the steps of the launch) is
+ * added to the totals of its (op, kernel family, padded block size).
+ *   btc_runner_profile(r, op, kind): op -2 switches off, -1 selects every
+ *   group, >= 0 one btc_op; kind -1 any kernel family, else that family
+ *   (FACTOR: 0 FP64 VALU, 1 FP64 MFMA, 2 mixed, 3 FP64 tile-parallel,
+ *   4 mixed tile-parallel; sweeps: 0 FP64, 1 FP32).  Synchronises and
+ *   clears the totals.
+ *   btc_runner_profile_read(r, out, max, count): synchronises and writes up
+ *   to max totals (host array), largest time first, then clears them.
+ * A tile-parallel factor group is several kernels; its pair of events
+ * brackets all of them.
+ */
+typedef struct {
+    int32_t op;        /* btc_op */
+    int32_t kind;      /* kernel family, as above */
+    int32_t np;        /* padded block size of the kernel */
+    int32_t pad;
+    int64_t launches;
+    int64_t items;     /* nodes (sweeps, factor), block rows (residual) */
+    double ms;         /* summed event time */
+    double bytes;      /* algorithmic bytes (btc_level_work) */
+    double flops;      /* algorithmic flops (btc_level_work) */
+} btc_kernel_stat;
+
+BTC_API int btc_runner_profile(btc_runner r, int32_t op, int32_t kind);
+BTC_API int btc_runner_profile_read(btc_runner r, btc_kernel_stat *out, int32_t max, int32_t *count);
+
+/*
+ * btc_level_work -- algorithmic work of one step (host computation, no
+ * device access): HBM bytes and flops of level `level` of op FACTOR /
+ * FORWARD / BACKWARD, or of a whole RESIDUAL / REFINE_* step (level
+ * ignored), for a (N, n, nrhs) instance at the given precision.
+ *   Factor, per node i of level l (stride s): every n x n block the level
+ *   step of Algorithm 4 reads (S_i, S_{i+s}, the couplings, the deferred
+ *   T blocks of level l-1) or writes (L_ii, R_i, T_i, S_{i+s}, the fill)
+ *   counted once; flops n^3/3 (potrf) + n^3 per triangular solve and per
+ *   syrk + 2n^3 per fill (section "Computational Complexity").
+ *   Sweeps (Algorithm 6): the node's factor blocks once, its n x nrhs
+ *   vectors; flops n^2 nrhs per triangular solve, 2 n^2 nrhs per product.
+ *   Residual: 8 n^2 (2N-1) + 24 N n nrhs bytes, 2 n^2 nrhs (3N-2) flops.
+ * Word size 8 (FP64); BTC_FP32_IR: 4 for factor blocks, fills and sweep
+ * vectors, 8 for Schur complements, inputs and the residual.
+ * Returns 0, or -k for argument k out of range.
+ */
+BTC_API int btc_level_work(int32_t op, int32_t precision, int64_t N, int64_t n, int64_t nrhs, int32_t level,
+                           double *bytes, double *flops);
+
+/*
  * btc_factor_batched -- factor `count` independent instances (handles from
  * btc_create, host arrays of device pointers), walking their levels together.
  */
@@ -346,6 +396,10 @@ BTC_API int btc_server_stats(btc_server s, int64_t *queued, int64_t *in_flight, 
 
 /* The resident handle of a client (NULL if not resident); owned by the server. */
 BTC_API btc_handle btc_server_client_handle(btc_server s, int64_t client);
+
+/* The runner the server enqueues its steps on (owned by the server; for
+ * btc_runner_profile / btc_runner_profile_read). */
+BTC_API btc_runner btc_server_runner(btc_server s);
 
 BTC_API void btc_server_destroy(btc_server s);
 

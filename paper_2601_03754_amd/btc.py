@@ -53,6 +53,11 @@ class btc_server_options(ctypes.Structure):
                 ("max_active", i32), ("pad", i32)]
 
 
+class btc_kernel_stat(ctypes.Structure):
+    _fields_ = [("op", i32), ("kind", i32), ("np", i32), ("pad", i32), ("launches", i64), ("items", i64),
+                ("ms", dbl), ("bytes", dbl), ("flops", dbl)]
+
+
 class btc_server_completion(ctypes.Structure):
     _fields_ = [("ticket", i64), ("client", i64), ("t_submit", dbl), ("t_admit", dbl), ("t_done", dbl),
                 ("refactored", i32), ("pad", i32)]
@@ -129,6 +134,14 @@ def lib():
         L.btc_server_client_handle.argtypes = [vp, i64]
         L.btc_server_destroy.restype = None
         L.btc_server_destroy.argtypes = [vp]
+        L.btc_runner_profile.restype = ctypes.c_int
+        L.btc_runner_profile.argtypes = [vp, i32, i32]
+        L.btc_runner_profile_read.restype = ctypes.c_int
+        L.btc_runner_profile_read.argtypes = [vp, ctypes.POINTER(btc_kernel_stat), i32, ctypes.POINTER(i32)]
+        L.btc_level_work.restype = ctypes.c_int
+        L.btc_level_work.argtypes = [i32, i32, i64, i64, i64, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+        L.btc_server_runner.restype = vp
+        L.btc_server_runner.argtypes = [vp]
         L.btc_version.restype = ctypes.c_int
         L.btc_version.argtypes = []
         _lib = L
@@ -303,6 +316,13 @@ class Runner:
                                        _ptr_array([_dev(x, "X") for x in Xs]), nrhs),
                "btc_solve_batched")
 
+    def profile(self, op: int = -1, kind: int = -1) -> None:
+        """Switch the launch profiler on for (op, kind) (-1: any; op -2: off)."""
+        runner_profile(self.handle, op, kind)
+
+    def profile_read(self):
+        return runner_profile_read(self.handle)
+
     def close(self):
         if getattr(self, "handle", None):
             lib().btc_runner_destroy(self.handle)
@@ -313,6 +333,28 @@ class Runner:
             self.close()
         except Exception:
             pass
+
+
+def runner_profile(r: int, op: int = -1, kind: int = -1) -> None:
+    _check(lib().btc_runner_profile(r, op, kind), "btc_runner_profile")
+
+
+def runner_profile_read(r: int):
+    """Totals per (op, kind, np) since the profiler was switched on, largest
+    time first: dicts with launches, items, ms, bytes, flops."""
+    buf = (btc_kernel_stat * 256)()
+    cnt = i32()
+    _check(lib().btc_runner_profile_read(r, buf, 256, ctypes.byref(cnt)), "btc_runner_profile_read")
+    return [{"op": b.op, "kind": b.kind, "np": b.np, "launches": b.launches, "items": b.items, "ms": b.ms,
+             "bytes": b.bytes, "flops": b.flops} for b in buf[:cnt.value]]
+
+
+def btc_level_work(op: int, precision: int, N: int, n: int, nrhs: int, level: int):
+    """(bytes, flops) of one step as the library counts them (host only)."""
+    b, f = dbl(), dbl()
+    _check(lib().btc_level_work(op, precision, N, n, nrhs, level, ctypes.byref(b), ctypes.byref(f)),
+           "btc_level_work")
+    return b.value, f.value
 
 
 def step(h: int, op: int, level: int = 0, A_diag=None, A_off=None, B=None, X=None, nrhs: int = 0,
@@ -380,6 +422,10 @@ class Server:
 
     def client_handle(self, client: int) -> int:
         return lib().btc_server_client_handle(self.handle, client) or 0
+
+    def runner_handle(self) -> int:
+        """The server's step runner (for runner_profile / runner_profile_read)."""
+        return lib().btc_server_runner(self.handle) or 0
 
     def close(self):
         if getattr(self, "handle", None):

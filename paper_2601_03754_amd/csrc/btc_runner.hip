@@ -19,6 +19,7 @@
 #include "btc.h"
 #include "btc_handle.h"
 #include "btc_kernels.h"
+#include "btc_work.h"
 
 using namespace btc_host;
 
@@ -35,6 +36,8 @@ struct Group {
     int kind;  // FACTOR: factor kernel family (factor_kind); sweeps: 0 double, 1 float
     int level = -1;  // FACTOR: common level of the items, -1 if they differ
     int np;
+    bool prof = false;     // bracketed by timing events
+    Work work;             // algorithmic work of the launch (when profiled)
     std::vector<char> descs;  // packed descriptors (all of one type)
     size_t desc_size = 0;
     std::vector<btc::WorkItem> items;
@@ -56,7 +59,61 @@ struct btc_runner_s {
         bool pending = false;
     } slot[2];
     int cur = 0;
+    // launch profiler: op filter (-2 off, -1 every group), kind filter (-1 any)
+    int prof_op = -2, prof_kind = -1;
+    struct Pending {
+        std::tuple<int, int, int> key;
+        hipEvent_t a, b;
+        Work work;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::tuple<int, int, int>, btc_kernel_stat> totals;
 };
+
+namespace {
+
+bool prof_match(const btc_runner_s* r, int op, int kind) {
+    if (r->prof_op == -2) return false;
+    return (r->prof_op == -1 || r->prof_op == op) && (r->prof_kind == -1 || r->prof_kind == kind);
+}
+
+hipEvent_t take_event(btc_runner_s* r) {
+    if (!r->pool.empty()) {
+        hipEvent_t e = r->pool.back();
+        r->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Fold finished timing pairs into the totals (all of them when wait).
+void drain_prof(btc_runner_s* r, bool wait) {
+    size_t done = 0;
+    for (; done < r->pending.size(); ++done) {
+        auto& p = r->pending[done];
+        if (!wait && hipEventQuery(p.b) != hipSuccess) break;
+        if (wait) (void)hipEventSynchronize(p.b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, p.a, p.b);
+        btc_kernel_stat& t = r->totals[p.key];
+        t.op = std::get<0>(p.key);
+        t.kind = std::get<1>(p.key);
+        t.np = std::get<2>(p.key);
+        t.launches += 1;
+        t.items += p.work.items;
+        t.ms += ms;
+        t.bytes += p.work.bytes;
+        t.flops += p.work.flops;
+        r->pool.push_back(p.a);
+        r->pool.push_back(p.b);
+    }
+    r->pending.erase(r->pending.begin(), r->pending.begin() + done);
+}
+
+}  // namespace
 
 namespace {
 
@@ -128,6 +185,20 @@ int validate(const btc_step& s) {
 
 extern "C" {
 
+namespace {
+
+void add_work(const btc_runner_s* r, Group& g, const btc_step& s, bool mixed) {
+    if (!prof_match(r, g.op, g.kind)) return;
+    g.prof = true;
+    const btc_handle h = s.h;
+    const Work w = level_work(s.op, mixed, h->N, h->n, s.op == BTC_OP_FACTOR ? 0 : s.nrhs, s.level);
+    g.work.bytes += w.bytes;
+    g.work.flops += w.flops;
+    g.work.items += w.items;
+}
+
+}  // namespace
+
 BTC_API int btc_runner_create(void* stream, btc_runner* out) {
     if (!out) return -2;
     *out = nullptr;
@@ -147,6 +218,8 @@ BTC_API int btc_runner_create(void* stream, btc_runner* out) {
 BTC_API void btc_runner_destroy(btc_runner r) {
     if (!r) return;
     (void)hipStreamSynchronize(r->st);
+    drain_prof(r, true);
+    for (auto e : r->pool) (void)hipEventDestroy(e);
     for (auto& s : r->slot) {
         if (s.host) (void)hipHostFree(s.host);
         if (s.dev) (void)hipFree(s.dev);
@@ -201,6 +274,7 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
             g.level = g.items.empty() ? s.level : (g.level == s.level ? s.level : -1);
             const int32_t inst = (int32_t)(g.descs.size() / sizeof(btc::FactorDesc));
             push_desc(g, factor_desc(h, h->A_diag, h->A_off));
+            add_work(r, g, s, mixed);
             const int64_t nodes = level_nodes(h->N, s.level);
             for (int64_t q = 0; q < nodes; ++q) g.items.push_back({inst, s.level, q});
             continue;
@@ -220,6 +294,7 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
                 inst = (int32_t)(g.descs.size() / sizeof(btc::SweepDesc<double>));
                 push_desc(g, sweep_desc64(h, w, s.B, s.X, s.nrhs));
             }
+            add_work(r, g, s, mixed);
             const int64_t nodes = level_nodes(h->N, s.level);
             for (int64_t q = 0; q < nodes; ++q) g.items.push_back({inst, s.level, q});
         } else if (s.op == BTC_OP_RESIDUAL) {
@@ -229,6 +304,7 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
             g.np = np;
             const int32_t inst = (int32_t)(g.descs.size() / sizeof(btc::ResidualDesc));
             push_desc(g, residual_desc(h, w, s.B, s.X, s.nrhs, mixed));
+            add_work(r, g, s, mixed);
             for (int64_t q = 0; q < h->N; ++q) g.items.push_back({inst, 0, q});
         } else {
             Group& g = groups[std::make_tuple(s.op, 0, 0)];
@@ -239,6 +315,7 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
             const double tol = mixed ? h->tol : 0.0;
             const int steps_budget = mixed ? 1 + h->max_refine : 1;
             push_desc(g, ir_desc(h, w, s.nrhs, tol, steps_budget));
+            add_work(r, g, s, mixed);
             g.items.push_back({inst, 0, 0});
         }
     }
@@ -275,9 +352,20 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
         if (e != hipSuccess) return to_code(e);
     }
     // std::map orders groups by op: factor, forward, backward, residual, refine init, refine test
+    if (!r->pending.empty()) drain_prof(r, false);
     for (auto& kv : groups) {
         const Group& g = kv.second;
         const int64_t items = (int64_t)g.items.size();
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (g.prof) {
+            ea = take_event(r);
+            eb = ea ? take_event(r) : nullptr;
+            if (!eb) {
+                if (ea) r->pool.push_back(ea);
+                return BTC_ERR_HIP;
+            }
+            (void)hipEventRecord(ea, st);
+        }
         switch (g.op) {
             case BTC_OP_FACTOR: {
                 auto L = make_launch<btc::FactorDesc>(g, sl.dev);
@@ -303,8 +391,54 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
                 e = btc::launch_ir_check(make_launch<btc::IrDesc>(g, sl.dev), items, st);
                 break;
         }
+        if (g.prof) {
+            (void)hipEventRecord(eb, st);
+            r->pending.push_back({kv.first, ea, eb, g.work});
+        }
         if (e != hipSuccess) return to_code(e);
     }
+    return BTC_OK;
+}
+
+BTC_API int btc_runner_profile(btc_runner r, int32_t op, int32_t kind) {
+    if (!r) return -1;
+    if (op < -2 || op > BTC_OP_REFINE_TEST) return -2;
+    if (kind < -1) return -3;
+    (void)hipStreamSynchronize(r->st);
+    drain_prof(r, true);
+    r->totals.clear();
+    r->prof_op = op;
+    r->prof_kind = kind;
+    return BTC_OK;
+}
+
+BTC_API int btc_runner_profile_read(btc_runner r, btc_kernel_stat* out, int32_t max, int32_t* count) {
+    if (!r) return -1;
+    if (max < 0 || (max > 0 && !out)) return -2;
+    if (!count) return -4;
+    const hipError_t e = hipStreamSynchronize(r->st);
+    drain_prof(r, true);
+    std::vector<btc_kernel_stat> v;
+    for (auto& kv : r->totals) v.push_back(kv.second);
+    std::sort(v.begin(), v.end(), [](const btc_kernel_stat& a, const btc_kernel_stat& b) { return a.ms > b.ms; });
+    const int32_t c = (int32_t)std::min<size_t>(v.size(), (size_t)max);
+    for (int32_t k = 0; k < c; ++k) out[k] = v[k];
+    *count = c;
+    r->totals.clear();
+    return to_code(e);
+}
+
+BTC_API int btc_level_work(int32_t op, int32_t precision, int64_t N, int64_t n, int64_t nrhs, int32_t level,
+                           double* bytes, double* flops) {
+    if (op < BTC_OP_FACTOR || op > BTC_OP_REFINE_TEST) return -1;
+    if (precision != BTC_FP64 && !is_mixed(precision)) return -2;
+    if (N < 1) return -3;
+    if (n < 1) return -4;
+    if (nrhs < 0 || (op != BTC_OP_FACTOR && nrhs < 1)) return -5;
+    if ((op <= BTC_OP_BACKWARD) && (level < 0 || level >= num_levels(N))) return -6;
+    const Work w = level_work(op, is_mixed(precision), N, n, op == BTC_OP_FACTOR ? 0 : nrhs, level);
+    if (bytes) *bytes = w.bytes;
+    if (flops) *flops = w.flops;
     return BTC_OK;
 }
 

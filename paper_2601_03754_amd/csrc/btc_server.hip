@@ -424,3 +424,5 @@ BTC_API void btc_server_destroy(btc_server s) {
 }
 
 }  // extern "C"
+
+BTC_API btc_runner btc_server_runner(btc_server s) { return s ? s->runner : nullptr; }

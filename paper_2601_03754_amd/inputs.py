@@ -123,3 +123,31 @@ def batch_shapes(count: int = 512, seed: int = 0, N_range=(32, 2048),
     Ns = rng.integers(N_range[0], N_range[1] + 1, size=count)
     ns = rng.choice(np.asarray(n_choices), size=count)
     return [(int(a), int(b)) for a, b in zip(Ns, ns)]
+
+
+def served_clients(count: int = 256, seed: int = 0, N_range=(64, 4096), n_range=(12, 96)):
+    """(N, n) of the clients of the served workload: N = round(exp(U[ln N_lo,
+    ln N_hi])) (log-uniform), n ~ U{n_lo..n_hi}."""
+    rng = np.random.default_rng(seed)
+    lo, hi = math.log(N_range[0]), math.log(N_range[1])
+    Ns = np.rint(np.exp(rng.uniform(lo, hi, size=count))).astype(np.int64)
+    ns = rng.integers(n_range[0], n_range[1] + 1, size=count)
+    return [(int(a), int(b)) for a, b in zip(Ns, ns)]
+
+
+def block_tridiag_device(N: int, n: int, c: float = 4.0, seed: int = 0, nrhs: int = 1, device="cuda:0"):
+    """The same recipe drawn with torch's device generator (seeded; for
+    benchmark inputs too large to draw on the host): returns (D, E, B) FP64
+    tensors on `device`, D exactly symmetric (its lower triangle mirrored)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    G = torch.randn((N, n, n), generator=g, device=device, dtype=torch.float64)
+    D = torch.bmm(G, G.transpose(1, 2).contiguous()) / n
+    del G
+    low = torch.tril(D)
+    D = low + torch.tril(D, -1).transpose(1, 2) + c * torch.eye(n, device=device, dtype=torch.float64)
+    D = D.contiguous()
+    E = torch.randn((max(N - 1, 0), n, n), generator=g, device=device, dtype=torch.float64) / math.sqrt(n)
+    B = torch.randn((N, n, max(nrhs, 1)), generator=g, device=device, dtype=torch.float64)
+    return D, E, B

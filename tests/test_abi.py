@@ -94,3 +94,55 @@ def test_argument_errors_before_device_work(lib):
     L.btc_runner_destroy(None)
     assert "argument" in lib.btc_error_string(-3)
     assert "positive definite" in lib.btc_error_string(lib.BTC_ERR_NOT_SPD)
+
+
+# Off-diagonal factor blocks and fill blocks of the nested-dissection factor
+# (counted independently from the dense structure of the permuted factor).
+STRUCTURE = {16: (26, 11), 20: (33, 14), 64: (120, None), 256: (502, None), 1024: (2036, None),
+             4096: (8178, 4083), 16384: (32752, None)}
+
+
+@pytest.mark.parametrize("N", sorted(STRUCTURE))
+def test_level_work_flops_match_operation_counts(lib, N):
+    """Summed over the levels, the library's flop accounting equals the
+    operation counts of section "Computational Complexity": factor
+    n^3 (N/3 + 2 M_off + 2 F), both sweeps n^2 m (2N + 4 M_off)."""
+    n, m = 24, 3
+    L = int(np.floor(np.log2(N))) + 1
+    fac = sum(lib.btc_level_work(lib.BTC_OP_FACTOR, 0, N, n, 0, l)[1] for l in range(L))
+    fwd = sum(lib.btc_level_work(lib.BTC_OP_FORWARD, 0, N, n, m, l)[1] for l in range(L))
+    bwd = sum(lib.btc_level_work(lib.BTC_OP_BACKWARD, 0, N, n, m, l)[1] for l in range(L))
+    M_off, F = STRUCTURE[N]
+    if F is None:  # every fill couples the two neighbours of a node that has both
+        F = M_off - (N - 1)
+    assert fac == pytest.approx(n ** 3 * (N / 3 + 2 * M_off + 2 * F), rel=1e-12)
+    assert fwd + bwd == pytest.approx(n * n * m * (2 * N + 4 * M_off), rel=1e-12)
+
+
+def test_level_work_bytes(lib):
+    """Byte accounting: the residual reads every stored block of the matrix
+    once; mixed precision halves the factor-block words; level-0 factor of
+    N = 3: nodes 1 and 3, node 1 has a right neighbour, node 3 a left one."""
+    n, N, m = 8, 37, 2
+    b, f = lib.btc_level_work(lib.BTC_OP_RESIDUAL, 0, N, n, m, 0)
+    assert b == 8 * n * n * (2 * N - 1) + 24 * N * n * m
+    assert f == 2 * n * n * m * (3 * N - 2)
+    b64, _ = lib.btc_level_work(lib.BTC_OP_FACTOR, 0, 3, n, 0, 0)
+    # reads S_1, S_3, S_2 (node 1's right separator), C_21, C_32; writes L_11,
+    # L_33, R_1, T_3, S_2
+    assert b64 == 8 * n * n * (5 + 5)
+    b32, _ = lib.btc_level_work(lib.BTC_OP_FACTOR, 1, 3, n, 0, 0)
+    # FP64: S reads (3), coupling reads from the input (2), S_2 write; FP32: L, L, R, T
+    assert b32 == n * n * (8 * (3 + 2 + 1) + 4 * 4)
+
+
+def test_level_work_argument_errors(lib):
+    L = lib.lib()
+    import ctypes
+    b, f = ctypes.c_double(), ctypes.c_double()
+    assert L.btc_level_work(9, 0, 8, 4, 1, 0, ctypes.byref(b), ctypes.byref(f)) == -1
+    assert L.btc_level_work(0, 7, 8, 4, 1, 0, ctypes.byref(b), ctypes.byref(f)) == -2
+    assert L.btc_level_work(0, 0, 0, 4, 1, 0, ctypes.byref(b), ctypes.byref(f)) == -3
+    assert L.btc_level_work(1, 0, 8, 4, 0, 0, ctypes.byref(b), ctypes.byref(f)) == -5
+    assert L.btc_level_work(1, 0, 8, 4, 1, 4, ctypes.byref(b), ctypes.byref(f)) == -6
+    assert L.btc_runner_profile(None, -1, -1) == -1
