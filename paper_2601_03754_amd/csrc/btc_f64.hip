@@ -195,9 +195,6 @@ hipError_t launch_factor_valu(const Launch<FactorDesc>& p, int np, int64_t items
     const dim3 g((unsigned)items);
     switch (np) {
         case 8: hipLaunchKernelGGL((k_factor_level_f64<8, F64Cfg<8>::NT>), g, dim3(F64Cfg<8>::NT), 0, st, p); break;
-        case 16: hipLaunchKernelGGL((k_factor_level_f64<16, F64Cfg<16>::NT>), g, dim3(F64Cfg<16>::NT), 0, st, p); break;
-        case 32: hipLaunchKernelGGL((k_factor_level_f64<32, F64Cfg<32>::NT>), g, dim3(F64Cfg<32>::NT), 0, st, p); break;
-        case 64: hipLaunchKernelGGL((k_factor_level_f64<64, F64Cfg<64>::NT>), g, dim3(F64Cfg<64>::NT), 0, st, p); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

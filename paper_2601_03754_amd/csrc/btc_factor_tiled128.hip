@@ -1,0 +1,22 @@
+// Tile-parallel factorization level step, padded block size 128, and the
+// dispatcher over the padded sizes.
+#include "btc_tiled.h"
+
+namespace btc {
+
+hipError_t launch_factor_tiled128(const Launch<FactorDesc>& p, bool mixed, int level_hint, int64_t items,
+                                  hipStream_t st) {
+    return mixed ? launch_tiled_np<128, true>(p, level_hint, items, st)
+                 : launch_tiled_np<128, false>(p, level_hint, items, st);
+}
+
+hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, bool mixed, int level_hint, int64_t items,
+                               hipStream_t st) {
+    switch (np) {
+        case 96: return launch_factor_tiled96(p, mixed, level_hint, items, st);
+        case 128: return launch_factor_tiled128(p, mixed, level_hint, items, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace btc

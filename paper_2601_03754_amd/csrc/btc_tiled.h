@@ -17,6 +17,8 @@
 //       (lower tiles) and of the fill -R_i T_i
 // In mixed precision the Schur complements and K2 stay FP64 and the products
 // of K1, K3, K4 run on FP32 matrix cores (FP32 factor storage).
+#pragma once
+
 #include "btc_device.h"
 #include "btc_kernels.h"
 #include "btc_tiles.h"
@@ -474,15 +476,8 @@ hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int level_hint, int64_t 
 
 }  // namespace
 
-hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, bool mixed, int level_hint, int64_t items,
-                               hipStream_t st) {
-    switch (np) {
-        case 96: return mixed ? launch_tiled_np<96, true>(p, level_hint, items, st)
-                              : launch_tiled_np<96, false>(p, level_hint, items, st);
-        case 128: return mixed ? launch_tiled_np<128, true>(p, level_hint, items, st)
-                               : launch_tiled_np<128, false>(p, level_hint, items, st);
-        default: return hipErrorInvalidValue;
-    }
-}
+// Per padded size launchers (one translation unit each).
+hipError_t launch_factor_tiled96(const Launch<FactorDesc>& p, bool mixed, int level_hint, int64_t items, hipStream_t st);
+hipError_t launch_factor_tiled128(const Launch<FactorDesc>& p, bool mixed, int level_hint, int64_t items, hipStream_t st);
 
 }  // namespace btc
