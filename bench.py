@@ -249,8 +249,9 @@ def run_served(args, btc):
                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "requests": len(done),
                "refactor_share": float(np.mean([d["refactored"] for d in done])),
                "max_relres_last": relres,
-               "warmup_kernel_ms": [{"kernel": roofline_entry(s)["kernel"],
-                                     "ms": round(s["ms"], 3), "launches": s["launches"]} for s in stats[:8]]}
+               "warmup_kernel_ms": [{"kernel": roofline_entry(s)["kernel"], "ms": round(s["ms"], 3),
+                                     "launches": s["launches"],
+                                     "gbs": round(s["bytes"] / (s["ms"] * 1e-3) / 1e9, 1)} for s in stats[:10]]}
         if tstats:
             ent["roofline"] = roofline_entry(tstats[0])
         log("%s closed loop: %.0f req/s, p50 %.2f ms, p99 %.2f ms, relres %.2e"

@@ -307,12 +307,12 @@ inline hipError_t sweeps(btc_handle h, const btc::SweepDesc<T>& d, hipStream_t s
     const int np = btc::padded_block((int)h->n);
     for (int l = 0; l < h->levels; ++l) {
         L.level = l;
-        hipError_t e = timed(h, 1, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), false, st); });
+        hipError_t e = timed(h, 1, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), false, d.m, st); });
         if (e != hipSuccess) return e;
     }
     for (int l = h->levels - 1; l >= 0; --l) {
         L.level = l;
-        hipError_t e = timed(h, 2, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), true, st); });
+        hipError_t e = timed(h, 2, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), true, d.m, st); });
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -35,6 +35,7 @@ struct Group {
     int op;    // btc_op
     int kind;  // FACTOR: factor kernel family (factor_kind); sweeps: 0 double, 1 float
     int level = -1;  // FACTOR: common level of the items, -1 if they differ
+    int m_max = 1;   // sweeps / residual: largest number of right-hand sides
     int np;
     bool prof = false;     // bracketed by timing events
     Work work;             // algorithmic work of the launch (when profiled)
@@ -286,6 +287,7 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
             g.op = s.op;
             g.kind = mixed ? 1 : 0;
             g.np = np;
+            g.m_max = std::max<int>(g.m_max, (int)s.nrhs);
             int32_t inst;
             if (mixed) {
                 inst = (int32_t)(g.descs.size() / sizeof(btc::SweepDesc<float>));
@@ -302,6 +304,7 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
             g.op = s.op;
             g.kind = 0;
             g.np = np;
+            g.m_max = std::max<int>(g.m_max, (int)s.nrhs);
             const int32_t inst = (int32_t)(g.descs.size() / sizeof(btc::ResidualDesc));
             push_desc(g, residual_desc(h, w, s.B, s.X, s.nrhs, mixed));
             add_work(r, g, s, mixed);
@@ -376,13 +379,13 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
             case BTC_OP_BACKWARD: {
                 const bool bwd = g.op == BTC_OP_BACKWARD;
                 if (g.kind == 1)
-                    e = btc::launch_sweep(make_launch<btc::SweepDesc<float>>(g, sl.dev), g.np, items, bwd, st);
+                    e = btc::launch_sweep(make_launch<btc::SweepDesc<float>>(g, sl.dev), g.np, items, bwd, g.m_max, st);
                 else
-                    e = btc::launch_sweep(make_launch<btc::SweepDesc<double>>(g, sl.dev), g.np, items, bwd, st);
+                    e = btc::launch_sweep(make_launch<btc::SweepDesc<double>>(g, sl.dev), g.np, items, bwd, g.m_max, st);
                 break;
             }
             case BTC_OP_RESIDUAL:
-                e = btc::launch_residual(make_launch<btc::ResidualDesc>(g, sl.dev), g.np, items, st);
+                e = btc::launch_residual(make_launch<btc::ResidualDesc>(g, sl.dev), g.np, items, g.m_max, st);
                 break;
             case BTC_OP_REFINE_INIT:
                 e = btc::launch_ir_init(make_launch<btc::IrDesc>(g, sl.dev), items, st);

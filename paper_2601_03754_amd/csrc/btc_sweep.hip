@@ -1,0 +1,592 @@
+// Level sweeps of the solve (section "Cholesky Solve", Algorithm 6) and the
+// FP64 residual b - Psi x, streaming form: one wavefront per node (per block
+// row for the residual), every n x n block read from HBM once and coalesced.
+//
+// Lane r owns rows r and r + 64 of the node's vectors (columns of the
+// right-hand side are processed MC at a time, MC independent chains).  Every
+// block goes through LDS in slabs of 16 columns (each row contributes one
+// contiguous 16-element segment, written transposed) or 16 rows (contiguous),
+// laid out so that lane r reads slab[k][r] conflict-free whichever of
+// M[r][c] or M[c][r] the product needs.  Slabs are double-buffered and the
+// global loads of slab p+1 (NP/4 per lane) are in flight while slab p is
+// consumed, so the triangular solves' dependency chains overlap the block
+// traffic; with 64-thread workgroups and at most 16.5 KB per slab buffer
+// several nodes share each compute unit.
+//
+//   forward, node i of level l (stride s), levels ascending:
+//     y_i = L_ii^{-1} (b_i - sum of the u / v its descendants left for it)
+//         [column slabs of L_ii, column sweep, pivots broadcast by readlane]
+//     u_i = R_i y_i   [column slabs of R_i]   (pulled by node i+s)
+//     v_i = T_i^T y_i [row slabs of T_i]      (pulled by node i-s)
+//   backward, levels descending:
+//     x_i = L_ii^{-T} (y_i - R_i^T x_{i+s} - T_i x_{i-s})
+//         [R_i row slabs; T_i column slabs; L_ii row slabs consumed from the
+//          last row up]
+//   residual, block row i: r_i = b_i - D_i x_i - E_{i-1} x_{i-1} - E_i^T x_{i+1}
+//     [only the lower triangle of D_i is read: column slabs for D_i[r][c],
+//      c <= r, row slabs for D_i[c][r], c > r (the second pass mostly hits
+//      L2); E_{i-1} column slabs, E_i row slabs]; per-column partial squared
+//     norms of r_i and b_i.
+//     Work items of consecutive block rows are dispatched to the same XCD
+//     (shared couplings stay in that XCD's L2).
+// Instead of two nodes subtracting into the same y concurrently, each node
+// pulls its contributions in a fixed order: results are deterministic.
+#include "btc_device.h"
+#include "btc_kernels.h"
+
+namespace btc {
+namespace {
+
+constexpr unsigned long long kInfoOk = ~0ull;
+constexpr int kS = 16;  // slab width
+
+__device__ __forceinline__ double bcast(double v, int lane) { return readlane_d(v, lane); }
+__device__ __forceinline__ float bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+template <int NP>
+struct Geo {
+    static_assert(NP % kS == 0, "padded size is a multiple of the slab width");
+    static constexpr int RPL = (NP + kWave - 1) / kWave;  // rows per lane
+    static constexpr int LDB = kWave * RPL + 1;           // slab stride (elements), covers every lane row
+    static constexpr int PER = NP * kS / kWave;           // slab elements per lane
+};
+
+// Where the next slab comes from: column slab (elements M[r][c0+k], rows
+// r >= rmin) or row slab (elements M[r0+k][r], only r <= r0+k when tri).
+template <class S>
+struct SlabSrc {
+    const S* M;
+    int off;
+    int rmin;
+    bool rows;
+    bool tri;
+};
+
+template <int NP, class T>
+struct SlabRegs {
+    T v[Geo<NP>::PER];
+
+    template <class S>
+    __device__ __forceinline__ void fetch(const SlabSrc<S>& s, int n, int lane) {
+        if (!s.rows) {
+#pragma unroll
+            for (int u = 0; u < Geo<NP>::PER; ++u) {
+                const int e = lane + kWave * u, r = e / kS, c = s.off + e % kS;
+                T x = T(0);
+                if (r >= s.rmin && r < n && c < n) x = (T)s.M[(size_t)r * n + c];
+                v[u] = x;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < Geo<NP>::PER; ++u) {
+                const int e = lane + kWave * u, r = e % NP, rr = s.off + e / NP;
+                T x = T(0);
+                if (r < n && rr < n && (!s.tri || r <= rr)) x = (T)s.M[(size_t)rr * n + r];
+                v[u] = x;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void put(T* __restrict__ buf, bool rows, int lane) const {
+        if (!rows) {
+#pragma unroll
+            for (int u = 0; u < Geo<NP>::PER; ++u) {
+                const int e = lane + kWave * u;
+                buf[(e % kS) * Geo<NP>::LDB + e / kS] = v[u];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < Geo<NP>::PER; ++u) {
+                const int e = lane + kWave * u;
+                buf[(e / NP) * Geo<NP>::LDB + e % NP] = v[u];
+            }
+        }
+    }
+};
+
+// Value of vector row j (wave-uniform) of column c, held by lane j % 64.
+template <int RPL, int MC, class T>
+__device__ __forceinline__ T row_value(const T (&a)[RPL][MC], int j, int c) {
+    T x = a[0][c];
+#pragma unroll
+    for (int rr = 1; rr < RPL; ++rr)
+        if (j >= kWave * rr) x = a[rr][c];
+    return bcast(x, j & (kWave - 1));
+}
+
+template <class T>
+__device__ __forceinline__ bool skip_item(const SweepDesc<T>& P) {
+    if (*P.info != kInfoOk) return true;
+    if (P.skip && *P.skip) return true;
+    return false;
+}
+
+// A kernel's block traffic as a list of up to four segments of slabs, each
+// segment the slabs of one block in one orientation.  Kept as separate
+// scalars (selected by wave-uniform indices) so the plan lives in registers.
+template <class S>
+struct Seg {
+    const S* M;
+    int count;   // slabs (0: segment absent)
+    bool rows;   // row slabs (else column slabs)
+    bool desc;   // slabs from the last one to the first
+    bool tri;    // column slab p: rows >= 16p only; row slab: r <= row only
+};
+
+template <class S>
+struct Plan {
+    const S *m0, *m1, *m2, *m3;
+    int c0, c1, c2, c3;
+    unsigned rows, desc, tri;  // bit g: property of segment g
+    int total;
+    int slabs;                 // slabs per block (the same for every present segment)
+
+    __device__ __forceinline__ void set(int g, const Seg<S>& sg) {
+        if (g == 0) { m0 = sg.M; c0 = sg.count; }
+        if (g == 1) { m1 = sg.M; c1 = sg.count; }
+        if (g == 2) { m2 = sg.M; c2 = sg.count; }
+        if (g == 3) { m3 = sg.M; c3 = sg.count; }
+        const unsigned bit = 1u << g;
+        rows = sg.rows ? (rows | bit) : (rows & ~bit);
+        desc = sg.desc ? (desc | bit) : (desc & ~bit);
+        tri = sg.tri ? (tri | bit) : (tri & ~bit);
+        total = c0 + c1 + c2 + c3;
+        if (sg.count) slabs = sg.count;
+    }
+
+    __device__ __forceinline__ void clear() {
+        m0 = m1 = m2 = m3 = nullptr;
+        c0 = c1 = c2 = c3 = 0;
+        rows = desc = tri = 0u;
+        total = 0;
+        slabs = 0;
+    }
+
+    __device__ __forceinline__ bool is_rows(int g) const { return (rows >> g) & 1u; }
+
+    // segment index and slab index within it of global slab p
+    __device__ __forceinline__ int locate(int p, int& q) const {
+        q = p;
+        if (q < c0) return 0;
+        q -= c0;
+        if (q < c1) return 1;
+        q -= c1;
+        if (q < c2) return 2;
+        q -= c2;
+        return 3;
+    }
+
+    __device__ __forceinline__ SlabSrc<S> src(int p) const {
+        int q;
+        const int g = locate(p, q);
+        const S* M = g == 0 ? m0 : g == 1 ? m1 : g == 2 ? m2 : m3;
+        const bool r = (rows >> g) & 1u, d = (desc >> g) & 1u, t = (tri >> g) & 1u;
+        const int sl = d ? slabs - 1 - q : q;  // every present segment has `slabs` slabs
+        return {M, kS * sl, (!r && t) ? kS * sl : 0, r, r && t};
+    }
+};
+
+// target[r] += sgn * slab[k][r] * vec[off + k] over the 16 slab columns
+// (column slab: vec indexed by the block's column; row slab: by its row).
+// mask: 0 none, 1 only off+k <= r, 2 only r < off+k.
+template <int NP, int MC, class T>
+__device__ __forceinline__ void slab_axpy(T (&target)[Geo<NP>::RPL][MC], const T* __restrict__ b,
+                                          const T (&vec)[Geo<NP>::RPL][MC], int off, int n, T sgn, int mask,
+                                          int lane) {
+    constexpr int RPL = Geo<NP>::RPL, LDB = Geo<NP>::LDB;
+    for (int k = 0; k < kS; ++k) {
+        const int cc = off + k;
+        if (cc >= n) break;
+        T xc[MC];
+#pragma unroll
+        for (int c = 0; c < MC; ++c) xc[c] = sgn * row_value<RPL, MC, T>(vec, cc, c);
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+            const int r = lane + kWave * rr;
+            T a = b[k * LDB + r];
+            if (mask == 1 && cc > r) a = T(0);
+            if (mask == 2 && r >= cc) a = T(0);
+#pragma unroll
+            for (int c = 0; c < MC; ++c) target[rr][c] = fma(a, xc[c], target[rr][c]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <int NP, int MC, class T>
+__global__ __launch_bounds__(kWave) void k_fwd(Launch<SweepDesc<T>> L) {
+    using G = Geo<NP>;
+    constexpr int RPL = G::RPL, LDB = G::LDB;
+    __shared__ T buf[2][kS * LDB];
+    SweepDesc<T> P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
+    if (skip_item(P)) return;
+    const int lane = threadIdx.x;
+    const int64_t N = P.N;
+    const int n = P.n, m = P.m;
+    const size_t nn = (size_t)n * n, nm = (size_t)n * m;
+    const int64_t s = (int64_t)1 << lvl;
+    const int64_t i = (kk * 2 + 1) << lvl;
+    const bool has_r = i + s <= N, has_l = i > s;
+    const int64_t pi = perm_pos(N, lvl, i);
+    const int ns = (n + kS - 1) / kS;
+    // L_ii column slabs (lower part), R_i column slabs, T_i row slabs
+    Plan<T> pl;
+    pl.clear();
+    pl.set(0, {P.Ld + pi * nn, ns, false, false, true});
+    pl.set(1, {P.Rb + pi * nn, has_r ? ns : 0, false, false, false});
+    pl.set(2, {P.Tb + pi * nn, has_l ? ns : 0, true, false, false});
+
+    for (int q0 = 0; q0 < m; q0 += MC) {
+        T acc[RPL][MC], u[RPL][MC], v[RPL][MC];
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+            const int r = lane + kWave * rr;
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                const int q = q0 + c;
+                T a = T(0);
+                if (r < n && q < m) {
+                    const size_t bidx = ((size_t)(i - 1) * n + r) * m + q;
+                    a = P.B64 ? (T)P.B64[bidx] : P.B[bidx];
+                    for (int l2 = 0; l2 < lvl; ++l2) {
+                        const int64_t s2 = (int64_t)1 << l2;
+                        const size_t off = (size_t)r * m + q;
+                        a -= P.U[(size_t)perm_pos(N, l2, i - s2) * nm + off];
+                        if (i + s2 <= N) a -= P.V[(size_t)perm_pos(N, l2, i + s2) * nm + off];
+                    }
+                }
+                acc[rr][c] = a;
+                u[rr][c] = T(0);
+                v[rr][c] = T(0);
+            }
+        }
+        SlabRegs<NP, T> sr;
+        sr.fetch(pl.src(0), n, lane);
+        for (int p = 0; p < pl.total; ++p) {
+            T* b = buf[p & 1];
+            int q;
+            const int g = pl.locate(p, q);
+            sr.put(b, pl.is_rows(g), lane);
+            wave_lds_sync();
+            if (p + 1 < pl.total) sr.fetch(pl.src(p + 1), n, lane);
+            if (g == 0) {
+                // y = L^{-1} acc over columns j of this slab
+                for (int k = 0; k < kS; ++k) {
+                    const int j = kS * q + k;
+                    if (j >= n) break;
+                    const T inv = T(1) / b[k * LDB + j];
+                    T yj[MC];
+#pragma unroll
+                    for (int c = 0; c < MC; ++c) yj[c] = row_value<RPL, MC, T>(acc, j, c) * inv;
+#pragma unroll
+                    for (int rr = 0; rr < RPL; ++rr) {
+                        const int r = lane + kWave * rr;
+                        const T l = b[k * LDB + r];
+#pragma unroll
+                        for (int c = 0; c < MC; ++c) {
+                            if (r == j) acc[rr][c] = yj[c];
+                            else if (r > j) acc[rr][c] = fma(-l, yj[c], acc[rr][c]);
+                        }
+                    }
+                }
+            } else if (g == 1) {
+                slab_axpy<NP, MC, T>(u, b, acc, kS * q, n, T(1), 0, lane);  // u += R y
+            } else {
+                slab_axpy<NP, MC, T>(v, b, acc, kS * q, n, T(1), 0, lane);  // v += T^T y
+            }
+            wave_lds_sync();
+        }
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+            const int r = lane + kWave * rr;
+            if (r >= n) continue;
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                const int q = q0 + c;
+                if (q >= m) continue;
+                const size_t o = (size_t)pi * nm + (size_t)r * m + q;
+                P.Y[o] = acc[rr][c];
+                if (has_r) P.U[o] = u[rr][c];
+                if (has_l) P.V[o] = v[rr][c];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <int NP, int MC, class T>
+__global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
+    using G = Geo<NP>;
+    constexpr int RPL = G::RPL, LDB = G::LDB;
+    __shared__ T buf[2][kS * LDB];
+    SweepDesc<T> P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
+    if (skip_item(P)) return;
+    const int lane = threadIdx.x;
+    const int64_t N = P.N;
+    const int n = P.n, m = P.m;
+    const size_t nn = (size_t)n * n, nm = (size_t)n * m;
+    const int64_t s = (int64_t)1 << lvl;
+    const int64_t i = (kk * 2 + 1) << lvl;
+    const bool has_r = i + s <= N, has_l = i > s;
+    const int64_t pi = perm_pos(N, lvl, i);
+    const int ns = (n + kS - 1) / kS;
+    // R_i row slabs, T_i column slabs, L_ii row slabs from the last one up
+    Plan<T> pl;
+    pl.clear();
+    pl.set(0, {P.Rb + pi * nn, has_r ? ns : 0, true, false, false});
+    pl.set(1, {P.Tb + pi * nn, has_l ? ns : 0, false, false, false});
+    pl.set(2, {P.Ld + pi * nn, ns, true, true, true});
+
+    for (int q0 = 0; q0 < m; q0 += MC) {
+        T acc[RPL][MC], xr[RPL][MC], xl[RPL][MC];
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+            const int r = lane + kWave * rr;
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                const int q = q0 + c;
+                const bool ok = r < n && q < m;
+                acc[rr][c] = ok ? P.Y[(size_t)pi * nm + (size_t)r * m + q] : T(0);
+                xr[rr][c] = (ok && has_r) ? P.X[((size_t)(i + s - 1) * n + r) * m + q] : T(0);
+                xl[rr][c] = (ok && has_l) ? P.X[((size_t)(i - s - 1) * n + r) * m + q] : T(0);
+            }
+        }
+        SlabRegs<NP, T> sr;
+        sr.fetch(pl.src(0), n, lane);
+        for (int p = 0; p < pl.total; ++p) {
+            T* b = buf[p & 1];
+            int q;
+            const int g = pl.locate(p, q);
+            sr.put(b, pl.is_rows(g), lane);
+            wave_lds_sync();
+            if (p + 1 < pl.total) sr.fetch(pl.src(p + 1), n, lane);
+            if (g < 2) {
+                // acc -= R^T x_{i+s} (g = 0) or T x_{i-s} (g = 1); the vector is
+                // selected element by element so that both stay in registers
+                T xv[RPL][MC];
+#pragma unroll
+                for (int rr = 0; rr < RPL; ++rr)
+#pragma unroll
+                    for (int c = 0; c < MC; ++c) xv[rr][c] = g == 0 ? xr[rr][c] : xl[rr][c];
+                slab_axpy<NP, MC, T>(acc, b, xv, kS * q, n, T(-1), 0, lane);
+            } else {
+                // x = L^{-T} acc over rows j of this slab, last row first
+                const int sl = ns - 1 - q;
+                for (int k = kS - 1; k >= 0; --k) {
+                    const int j = kS * sl + k;
+                    if (j >= n) continue;
+                    const T inv = T(1) / b[k * LDB + j];
+                    T xj[MC];
+#pragma unroll
+                    for (int c = 0; c < MC; ++c) xj[c] = row_value<RPL, MC, T>(acc, j, c) * inv;
+#pragma unroll
+                    for (int rr = 0; rr < RPL; ++rr) {
+                        const int r = lane + kWave * rr;
+                        const T l = b[k * LDB + r];
+#pragma unroll
+                        for (int c = 0; c < MC; ++c) {
+                            if (r == j) acc[rr][c] = xj[c];
+                            else if (r < j) acc[rr][c] = fma(-l, xj[c], acc[rr][c]);
+                        }
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+            const int r = lane + kWave * rr;
+            if (r >= n) continue;
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                const int q = q0 + c;
+                if (q >= m) continue;
+                const size_t idx = ((size_t)(i - 1) * n + r) * m + q;
+                P.X[idx] = acc[rr][c];
+                if (P.X64) P.X64[idx] = P.first ? (double)acc[rr][c] : P.X64[idx] + (double)acc[rr][c];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Work item of block index b when consecutive items should share an XCD
+// (blocks are dispatched to the 8 XCDs round-robin).
+__device__ __forceinline__ unsigned xcd_local_block() {
+    constexpr unsigned kXcd = 8;
+    const unsigned g = gridDim.x, b = blockIdx.x;
+    const unsigned x = b % kXcd, per = g / kXcd, rem = g % kXcd;
+    return x * per + (x < rem ? x : rem) + b / kXcd;
+}
+
+template <int NP, int MC>
+__global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
+    using G = Geo<NP>;
+    constexpr int RPL = G::RPL, LDB = G::LDB;
+    __shared__ double buf[2][kS * LDB];
+    ResidualDesc P;
+    int64_t row0;
+    {
+        const unsigned b = xcd_local_block();
+        if (L.items) {
+            const WorkItem it = L.items[b];
+            P = L.descs[it.inst];
+            row0 = it.k;
+        } else {
+            P = L.single;
+            row0 = b;
+        }
+    }
+    if (P.state && P.state->done) return;
+    const int lane = threadIdx.x;
+    const int64_t N = P.N;
+    const int n = P.n, m = P.m;
+    const size_t nn = (size_t)n * n;
+    const int64_t i = row0 + 1;
+    const bool lft = i > 1, rgt = i < N;
+    const int ns = (n + kS - 1) / kS;
+    const double* Dg = P.A_diag + (size_t)(i - 1) * nn;
+    // D_i column slabs (lower part: D[r][c], c <= r), D_i row slabs (its
+    // transpose: D[c][r], c > r), E_{i-1} column slabs, E_i row slabs
+    Plan<double> pl;
+    pl.clear();
+    pl.set(0, {Dg, ns, false, false, true});
+    pl.set(1, {Dg, ns, true, false, true});
+    pl.set(2, {lft ? P.A_off + (size_t)(i - 2) * nn : nullptr, lft ? ns : 0, false, false, false});
+    pl.set(3, {rgt ? P.A_off + (size_t)(i - 1) * nn : nullptr, rgt ? ns : 0, true, false, false});
+
+    for (int q0 = 0; q0 < m; q0 += MC) {
+        double acc[RPL][MC], bb[RPL][MC], x0[RPL][MC], x1[RPL][MC], x2[RPL][MC];
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+            const int r = lane + kWave * rr;
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                const int q = q0 + c;
+                const bool ok = r < n && q < m;
+                bb[rr][c] = ok ? P.B[((size_t)(i - 1) * n + r) * m + q] : 0.0;
+                acc[rr][c] = bb[rr][c];
+                x0[rr][c] = (ok && lft) ? P.X[((size_t)(i - 2) * n + r) * m + q] : 0.0;
+                x1[rr][c] = ok ? P.X[((size_t)(i - 1) * n + r) * m + q] : 0.0;
+                x2[rr][c] = (ok && rgt) ? P.X[((size_t)i * n + r) * m + q] : 0.0;
+            }
+        }
+        SlabRegs<NP, double> sr;
+        sr.fetch(pl.src(0), n, lane);
+        for (int p = 0; p < pl.total; ++p) {
+            double* b = buf[p & 1];
+            int q;
+            const int g = pl.locate(p, q);
+            sr.put(b, pl.is_rows(g), lane);
+            wave_lds_sync();
+            if (p + 1 < pl.total) sr.fetch(pl.src(p + 1), n, lane);
+            if (g == 0)
+                slab_axpy<NP, MC, double>(acc, b, x1, kS * q, n, -1.0, 1, lane);
+            else if (g == 1)
+                slab_axpy<NP, MC, double>(acc, b, x1, kS * q, n, -1.0, 2, lane);
+            else if (g == 2)
+                slab_axpy<NP, MC, double>(acc, b, x0, kS * q, n, -1.0, 0, lane);
+            else
+                slab_axpy<NP, MC, double>(acc, b, x2, kS * q, n, -1.0, 0, lane);
+            wave_lds_sync();
+        }
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+            const int q = q0 + c;
+            double r2 = 0.0, b2 = 0.0;
+#pragma unroll
+            for (int rr = 0; rr < RPL; ++rr) {
+                const int r = lane + kWave * rr;
+                if (r < n && q < m) {
+                    if (P.R32) P.R32[((size_t)(i - 1) * n + r) * m + q] = (float)acc[rr][c];
+                    r2 = fma(acc[rr][c], acc[rr][c], r2);
+                    b2 = fma(bb[rr][c], bb[rr][c], b2);
+                }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                r2 += __shfl_xor(r2, off);
+                b2 += __shfl_xor(b2, off);
+            }
+            if (lane == 0 && q < m) {
+                P.part[((size_t)(i - 1) * m + q) * 2 + 0] = r2;
+                P.part[((size_t)(i - 1) * m + q) * 2 + 1] = b2;
+            }
+        }
+    }
+}
+
+template <int NP, class T>
+hipError_t launch_sweep_np(const Launch<SweepDesc<T>>& p, int64_t items, bool backward, int m_max, hipStream_t st) {
+    const dim3 g((unsigned)items), b(kWave);
+    if (m_max <= 1) {
+        if (backward)
+            hipLaunchKernelGGL((k_bwd<NP, 1, T>), g, b, 0, st, p);
+        else
+            hipLaunchKernelGGL((k_fwd<NP, 1, T>), g, b, 0, st, p);
+    } else {
+        if (backward)
+            hipLaunchKernelGGL((k_bwd<NP, 4, T>), g, b, 0, st, p);
+        else
+            hipLaunchKernelGGL((k_fwd<NP, 4, T>), g, b, 0, st, p);
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_sweep_t(const Launch<SweepDesc<T>>& p, int np, int64_t items, bool backward, int m_max,
+                          hipStream_t st) {
+    switch (np) {
+        case 8:
+        case 16: return launch_sweep_np<16, T>(p, items, backward, m_max, st);
+        case 32: return launch_sweep_np<32, T>(p, items, backward, m_max, st);
+        case 64: return launch_sweep_np<64, T>(p, items, backward, m_max, st);
+        case 96: return launch_sweep_np<96, T>(p, items, backward, m_max, st);
+        case 128: return launch_sweep_np<128, T>(p, items, backward, m_max, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int NP>
+hipError_t launch_res_np(const Launch<ResidualDesc>& p, int64_t items, int m_max, hipStream_t st) {
+    const dim3 g((unsigned)items), b(kWave);
+    if (m_max <= 1)
+        hipLaunchKernelGGL((k_res<NP, 1>), g, b, 0, st, p);
+    else
+        hipLaunchKernelGGL((k_res<NP, 4>), g, b, 0, st, p);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t items, bool backward, int m_max,
+                        hipStream_t st) {
+    return launch_sweep_t<double>(p, np, items, backward, m_max, st);
+}
+
+hipError_t launch_sweep(const Launch<SweepDesc<float>>& p, int np, int64_t items, bool backward, int m_max,
+                        hipStream_t st) {
+    return launch_sweep_t<float>(p, np, items, backward, m_max, st);
+}
+
+hipError_t launch_residual(const Launch<ResidualDesc>& p, int np, int64_t items, int m_max, hipStream_t st) {
+    switch (np) {
+        case 8:
+        case 16: return launch_res_np<16>(p, items, m_max, st);
+        case 32: return launch_res_np<32>(p, items, m_max, st);
+        case 64: return launch_res_np<64>(p, items, m_max, st);
+        case 96: return launch_res_np<96>(p, items, m_max, st);
+        case 128: return launch_res_np<128>(p, items, m_max, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace btc
