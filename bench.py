@@ -24,9 +24,13 @@ Workload "single": one instance (N, n) refactored and solved every step.
 
 Roofline: the kernel group with the largest total time (found during the
 warm-up) is timed live during the timed region with HIP events that the
-library records on its launch stream; its algorithmic bytes/flops per launch
-come from btc_level_work.  The CPU baseline is the FP64 oracle (plain C, one
-thread) on a bounded sample of the same requests.  Prints ONE JSON line.
+library records on the stream each launch runs on (independent groups of one
+server step run concurrently on up to four streams, so a timed launch may
+share the GPU); its algorithmic bytes/flops per launch come from
+btc_level_work.  "roofline_aggregate" divides the algorithmic bytes and flops
+of every kernel of the timed region by its wall time.  The CPU baseline is
+the FP64 oracle (plain C, one thread) on a bounded sample of the same
+requests.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -240,8 +244,8 @@ def run_served(args, btc):
         # timed region: only the dominant group's family carries events
         btc.runner_profile(rh, dom["op"], dom["kind"])
         done, wall = sv.closed_loop(per_step * args.steps)
-        tstats = [s for s in btc.runner_profile_read(rh) if (s["op"], s["kind"], s["np"]) ==
-                  (dom["op"], dom["kind"], dom["np"])]
+        allstats = btc.runner_profile_read(rh)
+        tstats = [s for s in allstats if (s["op"], s["kind"], s["np"]) == (dom["op"], dom["kind"], dom["np"])]
         btc.runner_profile(rh, -2, -1)
         lat = lat_ms(done)
         relres = sv.verify()
@@ -254,6 +258,11 @@ def run_served(args, btc):
                                      "gbs": round(s["bytes"] / (s["ms"] * 1e-3) / 1e9, 1)} for s in stats[:10]]}
         if tstats:
             ent["roofline"] = roofline_entry(tstats[0])
+        # every kernel of the timed region: algorithmic bytes / flops over its wall time
+        tb = sum(s["bytes"] for s in allstats)
+        tf = sum(s["flops"] for s in allstats)
+        ent["aggregate"] = {"bytes": tb, "flops": tf, "gbs": tb / wall / 1e9, "tflops": tf / wall / 1e12,
+                            "hbm_frac": tb / wall / 1e9 / HBM_PEAK_GBS}
         log("%s closed loop: %.0f req/s, p50 %.2f ms, p99 %.2f ms, relres %.2e"
             % (name, ent["value"], ent["p50_ms"], ent["p99_ms"], relres))
         for rate in args.rates:
@@ -433,6 +442,7 @@ def main():
         "open_loop": rates,
         "paths": paths,
         "roofline": mixed.get("roofline"),
+        "roofline_aggregate": mixed.get("aggregate"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

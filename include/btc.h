@@ -259,10 +259,14 @@ BTC_API int btc_runner_sync(btc_runner r);
 BTC_API void btc_runner_destroy(btc_runner r);
 
 /*
- * Launch profiler of a runner.  While on, every launch of a selected group
- * is bracketed by two HIP events recorded on the runner's stream, and its
- * algorithmic work (btc_level_work summed over the steps of the launch) is
- * added to the totals of its (op, kernel family, padded block size).
+ * Launch profiler of a runner.  While on, the algorithmic work of every
+ * launch (btc_level_work summed over the steps of the launch) is added to the
+ * totals of its (op, kernel family, padded block size), and every launch of a
+ * selected group is also bracketed by two HIP events recorded on the stream
+ * it runs on (ms stays 0 for groups not selected).  The independent groups of
+ * one btc_runner_run call run concurrently on the runner's stream and up to
+ * three side streams (created with the runner on the current device, default
+ * priority), so a timed launch may share the GPU with others.
  *   btc_runner_profile(r, op, kind): op -2 switches off, -1 selects every
  *   group, >= 0 one btc_op; kind -1 any kernel family, else that family
  *   (FACTOR: 0 FP64 VALU, 1 FP64 MFMA, 2 mixed, 3 FP64 tile-parallel,
@@ -280,7 +284,7 @@ typedef struct {
     int32_t pad;
     int64_t launches;
     int64_t items;     /* nodes (sweeps, factor), block rows (residual) */
-    double ms;         /* summed event time */
+    double ms;         /* summed event time (0 for groups not timed) */
     double bytes;      /* algorithmic bytes (btc_level_work) */
     double flops;      /* algorithmic flops (btc_level_work) */
 } btc_kernel_stat;

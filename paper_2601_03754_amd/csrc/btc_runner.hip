@@ -37,7 +37,9 @@ struct Group {
     int level = -1;  // FACTOR: common level of the items, -1 if they differ
     int m_max = 1;   // sweeps / residual: largest number of right-hand sides
     int np;
+    bool count = false;    // work accounted (profiler on)
     bool prof = false;     // bracketed by timing events
+    int lane = 0;          // 0: the runner's stream, k: side stream k-1
     Work work;             // algorithmic work of the launch (when profiled)
     std::vector<char> descs;  // packed descriptors (all of one type)
     size_t desc_size = 0;
@@ -60,6 +62,13 @@ struct btc_runner_s {
         bool pending = false;
     } slot[2];
     int cur = 0;
+    // Groups of one call are independent: they run concurrently on the main
+    // stream and up to kSide side streams (fork after the upload, join before
+    // the call returns, so later work on the main stream sees all of it).
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSide] = {};
     // launch profiler: op filter (-2 off, -1 every group), kind filter (-1 any)
     int prof_op = -2, prof_kind = -1;
     struct Pending {
@@ -112,6 +121,18 @@ void drain_prof(btc_runner_s* r, bool wait) {
         r->pool.push_back(p.b);
     }
     r->pending.erase(r->pending.begin(), r->pending.begin() + done);
+}
+
+// Work of a launch that the profiler counts but does not time.
+void add_untimed(btc_runner_s* r, const std::tuple<int, int, int>& key, const Work& w) {
+    btc_kernel_stat& t = r->totals[key];
+    t.op = std::get<0>(key);
+    t.kind = std::get<1>(key);
+    t.np = std::get<2>(key);
+    t.launches += 1;
+    t.items += w.items;
+    t.bytes += w.bytes;
+    t.flops += w.flops;
 }
 
 }  // namespace
@@ -189,8 +210,9 @@ extern "C" {
 namespace {
 
 void add_work(const btc_runner_s* r, Group& g, const btc_step& s, bool mixed) {
-    if (!prof_match(r, g.op, g.kind)) return;
-    g.prof = true;
+    if (r->prof_op == -2) return;
+    g.count = true;
+    g.prof = prof_match(r, g.op, g.kind);
     const btc_handle h = s.h;
     const Work w = level_work(s.op, mixed, h->N, h->n, s.op == BTC_OP_FACTOR ? 0 : s.nrhs, s.level);
     g.work.bytes += w.bytes;
@@ -206,11 +228,16 @@ BTC_API int btc_runner_create(void* stream, btc_runner* out) {
     btc_runner r = new (std::nothrow) btc_runner_s();
     if (!r) return BTC_ERR_OOM;
     r->st = (hipStream_t)stream;
-    for (auto& s : r->slot) {
-        if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
-            btc_runner_destroy(r);
-            return BTC_ERR_HIP;
-        }
+    bool ok = true;
+    for (auto& s : r->slot) ok = ok && hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&r->fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < btc_runner_s::kSide; ++k) {
+        ok = ok && hipStreamCreateWithFlags(&r->side[k], hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&r->join[k], hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) {
+        btc_runner_destroy(r);
+        return BTC_ERR_HIP;
     }
     *out = r;
     return BTC_OK;
@@ -221,11 +248,18 @@ BTC_API void btc_runner_destroy(btc_runner r) {
     (void)hipStreamSynchronize(r->st);
     drain_prof(r, true);
     for (auto e : r->pool) (void)hipEventDestroy(e);
+    for (int k = 0; k < btc_runner_s::kSide; ++k)
+        if (r->side[k]) (void)hipStreamSynchronize(r->side[k]);
     for (auto& s : r->slot) {
         if (s.host) (void)hipHostFree(s.host);
         if (s.dev) (void)hipFree(s.dev);
         if (s.ev) (void)hipEventDestroy(s.ev);
     }
+    for (int k = 0; k < btc_runner_s::kSide; ++k) {
+        if (r->side[k]) (void)hipStreamDestroy(r->side[k]);
+        if (r->join[k]) (void)hipEventDestroy(r->join[k]);
+    }
+    if (r->fork) (void)hipEventDestroy(r->fork);
     delete r;
 }
 
@@ -354,11 +388,44 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
         e = hipGetLastError();
         if (e != hipSuccess) return to_code(e);
     }
-    // std::map orders groups by op: factor, forward, backward, residual, refine init, refine test
     if (!r->pending.empty()) drain_prof(r, false);
+    // stream of every group: largest estimated work first, each onto the
+    // least loaded of the main and side streams
+    std::vector<std::pair<double, Group*>> order;
+    for (auto& kv : groups) {
+        Group& g = kv.second;
+        const double np = (double)std::max(g.np, 8);
+        const double w = (g.op == BTC_OP_FACTOR ? np : 1.0) * np * np * (double)g.items.size();
+        order.push_back({w, &g});
+    }
+    std::sort(order.begin(), order.end(), [](const std::pair<double, Group*>& a, const std::pair<double, Group*>& b) {
+        return a.first > b.first;
+    });
+    double load[1 + btc_runner_s::kSide] = {};
+    bool used[1 + btc_runner_s::kSide] = {};
+    for (auto& o : order) {
+        int best = 0;
+        for (int k = 1; k <= btc_runner_s::kSide; ++k)
+            if (load[k] < load[best]) best = k;
+        load[best] += o.first;
+        used[best] = true;
+        o.second->lane = best;
+    }
+    bool forked = false;
+    for (int k = 1; k <= btc_runner_s::kSide; ++k) {
+        if (!used[k]) continue;
+        if (!forked) {
+            e = hipEventRecord(r->fork, st);
+            if (e != hipSuccess) return to_code(e);
+            forked = true;
+        }
+        e = hipStreamWaitEvent(r->side[k - 1], r->fork, 0);
+        if (e != hipSuccess) return to_code(e);
+    }
     for (auto& kv : groups) {
         const Group& g = kv.second;
         const int64_t items = (int64_t)g.items.size();
+        hipStream_t gs = g.lane == 0 ? st : r->side[g.lane - 1];
         hipEvent_t ea = nullptr, eb = nullptr;
         if (g.prof) {
             ea = take_event(r);
@@ -367,37 +434,45 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
                 if (ea) r->pool.push_back(ea);
                 return BTC_ERR_HIP;
             }
-            (void)hipEventRecord(ea, st);
+            (void)hipEventRecord(ea, gs);
         }
         switch (g.op) {
             case BTC_OP_FACTOR: {
                 auto L = make_launch<btc::FactorDesc>(g, sl.dev);
-                e = launch_factor_kind(g.kind, L, g.np, g.level, items, st);
+                e = launch_factor_kind(g.kind, L, g.np, g.level, items, gs);
                 break;
             }
             case BTC_OP_FORWARD:
             case BTC_OP_BACKWARD: {
                 const bool bwd = g.op == BTC_OP_BACKWARD;
                 if (g.kind == 1)
-                    e = btc::launch_sweep(make_launch<btc::SweepDesc<float>>(g, sl.dev), g.np, items, bwd, g.m_max, st);
+                    e = btc::launch_sweep(make_launch<btc::SweepDesc<float>>(g, sl.dev), g.np, items, bwd, g.m_max, gs);
                 else
-                    e = btc::launch_sweep(make_launch<btc::SweepDesc<double>>(g, sl.dev), g.np, items, bwd, g.m_max, st);
+                    e = btc::launch_sweep(make_launch<btc::SweepDesc<double>>(g, sl.dev), g.np, items, bwd, g.m_max, gs);
                 break;
             }
             case BTC_OP_RESIDUAL:
-                e = btc::launch_residual(make_launch<btc::ResidualDesc>(g, sl.dev), g.np, items, g.m_max, st);
+                e = btc::launch_residual(make_launch<btc::ResidualDesc>(g, sl.dev), g.np, items, g.m_max, gs);
                 break;
             case BTC_OP_REFINE_INIT:
-                e = btc::launch_ir_init(make_launch<btc::IrDesc>(g, sl.dev), items, st);
+                e = btc::launch_ir_init(make_launch<btc::IrDesc>(g, sl.dev), items, gs);
                 break;
             default:
-                e = btc::launch_ir_check(make_launch<btc::IrDesc>(g, sl.dev), items, st);
+                e = btc::launch_ir_check(make_launch<btc::IrDesc>(g, sl.dev), items, gs);
                 break;
         }
         if (g.prof) {
-            (void)hipEventRecord(eb, st);
+            (void)hipEventRecord(eb, gs);
             r->pending.push_back({kv.first, ea, eb, g.work});
+        } else if (g.count) {
+            add_untimed(r, kv.first, g.work);
         }
+        if (e != hipSuccess) return to_code(e);
+    }
+    for (int k = 1; k <= btc_runner_s::kSide; ++k) {
+        if (!used[k]) continue;
+        e = hipEventRecord(r->join[k - 1], r->side[k - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, r->join[k - 1], 0);
         if (e != hipSuccess) return to_code(e);
     }
     return BTC_OK;
