@@ -8,9 +8,10 @@
 //   P1  stage S_i, S_{i+s} and the deferred T blocks in LDS
 //   P2  S_i -= T'^T T',  S_{i+s} -= T''^T T''       (deferred syrk, MFMA;
 //       lower-triangle tiles only, spread round-robin over the wavefronts)
-//   P3  wavefront 0: L_ii = chol(S_i) (pivot chain in registers); the other
-//       wavefronts stage the couplings C_{i+s,i}, C_{i,i-s}
-//   P4  every wavefront inverts one 16 x 16 diagonal tile of L_ii
+//   P3  the couplings C_{i+s,i}, C_{i,i-s} (loads issued before P2) go to
+//       LDS; L_ii = chol(S_i) blocked in 16-column panels by all wavefronts
+//       (wavefront 0 factors and inverts each diagonal tile, the panel and
+//       trailing updates run on the matrix cores)
 //   P5  R_i = C_{i+s,i} L_ii^{-T} and T_i = L_ii^{-1} C_{i,i-s} as a blocked
 //       triangular solve over the tiles: each step is a tile product with the
 //       already solved tiles followed by a product with an inverted diagonal
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(MfmaCfg<NP>::NT) void k_factor_level_mfma(Launch<Fa
     __shared__ double sB[NP * LD];         // T' -> C_{i+s,i} -> R_i
     __shared__ double sD[NP * LD];         // T'' -> C_{i,i-s} -> T_i
     __shared__ double sC[NP * LD];         // S_{i+s}
-    __shared__ double sInv[W][kT * kLDI];  // inverted diagonal tiles of L_ii
+    __shared__ double sInv[W][kT * kLDI];  // inverted diagonal tiles of L_ii (W = NP/16)
     __shared__ double invd[NP];
     __shared__ __align__(16) double colbuf[2][kWave];
     __shared__ int fail;
@@ -85,6 +86,16 @@ __global__ __launch_bounds__(MfmaCfg<NP>::NT) void k_factor_level_mfma(Launch<Fa
     if (tid == 0) fail = 0;
     __syncthreads();
 
+    // coupling loads go out now and land in LDS after P2 (their buffers hold
+    // the deferred T blocks until then)
+    const double* Cr = (lvl == 0) ? P.A_off + (size_t)(i - 1) * nn : P.Rb + (size_t)pi * nn;
+    const double* Cl = (lvl == 0) ? P.A_off + (size_t)(i - 2) * nn : P.Tb + (size_t)pi * nn;
+    Stage<NP, NT> cr, cl;
+    if (has_r) cr.fetch(Cr, n, false, 0.0, tid);
+    else cr.fetch(Cr, 0, false, 0.0, tid);
+    if (has_l) cl.fetch(Cl, n, false, 0.0, tid);
+    else cl.fetch(Cl, 0, false, 0.0, tid);
+
     // P2: deferred syrk updates (lower tiles, round-robin over wavefronts)
 #pragma unroll
     for (int t = 0; t < Cfg::TPW; ++t) {
@@ -108,38 +119,16 @@ __global__ __launch_bounds__(MfmaCfg<NP>::NT) void k_factor_level_mfma(Launch<Fa
     }
     __syncthreads();
 
-    // P3: potrf on wavefront 0 while the others stage the couplings
-    const double* Cr = (lvl == 0) ? P.A_off + (size_t)(i - 1) * nn : P.Rb + (size_t)pi * nn;
-    const double* Cl = (lvl == 0) ? P.A_off + (size_t)(i - 2) * nn : P.Tb + (size_t)pi * nn;
-    if constexpr (W > 1) {
-        if (w == 0) {
-            const bool ok = potrf_lookahead<NP>(sS, invd, colbuf);
-            if (!ok && tid == 0) fail = 1;
-        } else {
-            Stage<NP, NT - kWave> cr, cl;
-            if (has_r) cr.fetch(Cr, n, false, 0.0, tid - kWave);
-            if (has_l) cl.fetch(Cl, n, false, 0.0, tid - kWave);
-            if (has_r) cr.put(sB, tid - kWave);
-            if (has_l) cl.put(sD, tid - kWave);
-        }
-    } else {
-        Stage<NP, NT> cr, cl;
-        if (has_r) cr.fetch(Cr, n, false, 0.0, tid);
-        if (has_l) cl.fetch(Cl, n, false, 0.0, tid);
-        const bool ok = potrf_lookahead<NP>(sS, invd, colbuf);
-        if (!ok && tid == 0) fail = 1;
-        if (has_r) cr.put(sB, tid);
-        if (has_l) cl.put(sD, tid);
-    }
-    __syncthreads();
-    if (fail) {
+    // P3: stage the couplings (their loads were issued before P2), then the
+    // blocked Cholesky of S_i by all wavefronts: L_ii, 1/diag, inverted
+    // diagonal tiles
+    cr.put(sB, tid);
+    cl.put(sD, tid);
+    const bool ok = potrf_blocked<NP, LD, W>(sS, invd, sInv, colbuf, &fail);
+    if (!ok) {
         if (tid == 0) atomicMin(P.info, (unsigned long long)i);
         return;
     }
-
-    // P4: invert the diagonal tiles of L_ii (one per wavefront)
-    tile_inverse<LD>(sS, w * kT, invd, sInv[w]);
-    __syncthreads();
 
     // P5: blocked triangular solves; wavefront w owns tile-row w of R and
     // tile-column w of T

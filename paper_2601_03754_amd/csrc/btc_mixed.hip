@@ -52,6 +52,7 @@ __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(Launch<Fa
     __shared__ float fD[NP * LD];   // T'' -> C_{i,i-s} -> T_i
     __shared__ float fL[NP * LD];   // L_ii rounded to FP32
     __shared__ float fInv[W][kT * kLDI];
+    __shared__ double sInv[W][kT * kLDI];  // inverted diagonal tiles (FP64, W = NP/16)
     __shared__ double invd[NP];
     __shared__ __align__(16) double colbuf[2][kWave];
     __shared__ int fail;
@@ -94,6 +95,16 @@ __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(Launch<Fa
     if (tid == 0) fail = 0;
     __syncthreads();
 
+    // coupling loads (FP32) go out now and land in LDS after P2
+    Stage<NP, NT, float> cr, cl;
+    if (lvl == 0) {
+        cr.fetch(P.A_off + (size_t)(i - 1) * nn, has_r ? n : 0, false, 0.0, tid);
+        cl.fetch(P.A_off + (size_t)(i - 2) * nn, has_l ? n : 0, false, 0.0, tid);
+    } else {
+        cr.fetch(P.R32 + (size_t)pi * nn, has_r ? n : 0, false, 0.0, tid);
+        cl.fetch(P.T32 + (size_t)pi * nn, has_l ? n : 0, false, 0.0, tid);
+    }
+
     // P2: deferred syrk updates in FP32, subtracted into the FP64 blocks
 #pragma unroll
     for (int t = 0; t < Cfg::TPW; ++t) {
@@ -115,49 +126,22 @@ __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(Launch<Fa
     }
     __syncthreads();
 
-    // P3: FP64 potrf on wavefront 0 while the others stage the couplings in FP32
-    if constexpr (W > 1) {
-        if (w == 0) {
-            const bool ok = potrf_lookahead<NP>(sS, invd, colbuf);
-            if (!ok && tid == 0) fail = 1;
-        } else {
-            Stage<NP, NT - kWave, float> cr, cl;
-            if (lvl == 0) {
-                if (has_r) cr.fetch(P.A_off + (size_t)(i - 1) * nn, n, false, 0.0, tid - kWave);
-                if (has_l) cl.fetch(P.A_off + (size_t)(i - 2) * nn, n, false, 0.0, tid - kWave);
-            } else {
-                if (has_r) cr.fetch(P.R32 + (size_t)pi * nn, n, false, 0.0, tid - kWave);
-                if (has_l) cl.fetch(P.T32 + (size_t)pi * nn, n, false, 0.0, tid - kWave);
-            }
-            if (has_r) cr.put(fB, tid - kWave);
-            if (has_l) cl.put(fD, tid - kWave);
-        }
-    } else {
-        Stage<NP, NT, float> cr, cl;
-        if (lvl == 0) {
-            if (has_r) cr.fetch(P.A_off + (size_t)(i - 1) * nn, n, false, 0.0, tid);
-            if (has_l) cl.fetch(P.A_off + (size_t)(i - 2) * nn, n, false, 0.0, tid);
-        } else {
-            if (has_r) cr.fetch(P.R32 + (size_t)pi * nn, n, false, 0.0, tid);
-            if (has_l) cl.fetch(P.T32 + (size_t)pi * nn, n, false, 0.0, tid);
-        }
-        const bool ok = potrf_lookahead<NP>(sS, invd, colbuf);
-        if (!ok && tid == 0) fail = 1;
-        if (has_r) cr.put(fB, tid);
-        if (has_l) cl.put(fD, tid);
-    }
-    __syncthreads();
-    if (fail) {
+    // P3: couplings to LDS; blocked FP64 Cholesky of S_i by all wavefronts
+    cr.put(fB, tid);
+    cl.put(fD, tid);
+    const bool ok = potrf_blocked<NP, LD, W>(sS, invd, sInv, colbuf, &fail);
+    if (!ok) {
         if (tid == 0) atomicMin(P.info, (unsigned long long)i);
         return;
     }
 
-    // P4: L_ii rounded to FP32; inverted diagonal tiles (formed in FP64)
+    // P4: L_ii and the inverted diagonal tiles rounded to FP32
     for (int idx = tid; idx < NP * NP; idx += NT) {
         const int r = idx / NP, c = idx % NP;
         fL[r * LD + c] = (float)sS[r * LD + c];
     }
-    tile_inverse<LD, float>(sS, w * kT, invd, fInv[w]);
+    for (int idx = tid; idx < W * kT * kLDI; idx += NT) fInv[idx / (kT * kLDI)][idx % (kT * kLDI)] =
+        (float)sInv[idx / (kT * kLDI)][idx % (kT * kLDI)];
     __syncthreads();
 
     // P5: blocked FP32 triangular solves (wavefront w: tile-row w of R,

@@ -7,9 +7,9 @@
 //   K1  deferred syrk: S_i -= T'^T T' and S_{i+s} -= T''^T T'', one 256-thread
 //       workgroup per 32 x 32 lower tile (panels of T' staged in LDS)
 //   K2  one workgroup per node: the whole pivot block in LDS (FP64), blocked
-//       Cholesky (64-row leading factorization, matrix-core solve and update
-//       of the trailing rows, factorization of the trailing block), and the
-//       inverses of its 16 x 16 diagonal tiles, written to a per-node scratch
+//       Cholesky in 16-column panels (diagonal tiles factored and inverted by
+//       one wavefront, panel and trailing updates on the matrix cores), the
+//       inverted 16 x 16 diagonal tiles written to a per-node scratch
 //   K3  one wavefront per 16-row strip of R_i = C_{i+s,i} L_ii^{-T} and per
 //       16-column strip of T_i = L_ii^{-1} C_{i,i-s}: blocked substitution over
 //       the tiles with the inverted diagonal tiles (all products MFMA)
@@ -196,9 +196,6 @@ __global__ __launch_bounds__(256) void k_tiled_potrf(Launch<FactorDesc> L) {
     using F = typename Pr::F;
     using Cfg = TiledCfg<NP>;
     constexpr int LD = NP + 1;
-    constexpr int NB = 64;             // leading block
-    constexpr int M = (NP - NB) / kT;  // trailing 16-row strips
-    static_assert(NP - NB <= kWave && NP > NB, "trailing block fits one wavefront");
     __shared__ double sS[NP * LD];
     __shared__ double sInv[Cfg::NT16][kT * kLDI];
     __shared__ double invd[NP];
@@ -210,59 +207,16 @@ __global__ __launch_bounds__(256) void k_tiled_potrf(Launch<FactorDesc> L) {
     fetch_item(L, P, lvl, kk);
     if (*P.info != kInfoOk) return;
     const Node d = node_of(P, lvl, kk);
-    const int tid = threadIdx.x, w = tid / kWave;
+    const int tid = threadIdx.x;
     const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i - 1) * d.nn : P.Ld + (size_t)d.pi * d.nn;
     stage_lower<NP, 256>(sS, src, d.n, tid);
     if (tid == 0) fail = 0;
     __syncthreads();
-    if (w == 0) {
-        const bool ok = potrf_lookahead<NB, LD>(sS, invd, colbuf);
-        if (!ok && tid == 0) fail = 1;
-    }
-    __syncthreads();
-    if (fail) {
+    const bool ok = potrf_blocked<NP, LD, 4>(sS, invd, sInv, colbuf, &fail);
+    if (!ok) {
         if (tid == 0) atomicMin(P.info, (unsigned long long)d.i);
         return;
     }
-    tile_inverse<LD, double>(sS, w * kT, invd, sInv[w]);
-    __syncthreads();
-    // trailing rows: A21 <- A21 L11^{-T}, strip by strip
-    for (int st = w; st < M; st += 4) {
-        const int r0 = NB + st * kT;
-#pragma unroll
-        for (int p = 0; p < NB / kT; ++p) {
-            d4 acc;
-            acc_load_lds<LD>(acc, sS, r0, p * kT);
-            for (int q = 0; q < p; ++q)
-                mma_tile<LD, LD, false, true, true>(acc, sS, r0, q * kT, sS, p * kT, q * kT, kT);
-            acc_store_lds<LD>(acc, sS, r0, p * kT);
-            d4 out = {0.0, 0.0, 0.0, 0.0};
-            mma_tile<LD, kLDI, false, true, false>(out, sS, r0, p * kT, sInv[p], 0, 0, kT);
-            acc_store_lds<LD>(out, sS, r0, p * kT);
-        }
-    }
-    __syncthreads();
-    // A22 -= A21 A21^T (lower tiles)
-    for (int t = w; t < M * (M + 1) / 2; t += 4) {
-        int ta, tb;
-        tri_tile(t, ta, tb);
-        d4 acc;
-        acc_load_lds<LD>(acc, sS, NB + ta * kT, NB + tb * kT);
-        mma_tile<LD, LD, false, true, true>(acc, sS, NB + ta * kT, 0, sS, NB + tb * kT, 0, NB);
-        acc_store_lds<LD>(acc, sS, NB + ta * kT, NB + tb * kT);
-    }
-    __syncthreads();
-    if (w == 0) {
-        const bool ok = potrf_lookahead<NP - NB, LD>(sS + NB * LD + NB, invd + NB, colbuf);
-        if (!ok && tid == 0) fail = 1;
-    }
-    __syncthreads();
-    if (fail) {
-        if (tid == 0) atomicMin(P.info, (unsigned long long)d.i);
-        return;
-    }
-    for (int t = NB / kT + w; t < Cfg::NT16; t += 4) tile_inverse<LD, double>(sS, t * kT, invd, sInv[t]);
-    __syncthreads();
     // L (lower) and the inverted diagonal tiles
     lds_store_as<NP, F, double>(Pr::Lf(P) + (size_t)d.pi * d.nn, sS, d.n, true, tid, 256);
     F* dinv = (F*)P.Dinv + (size_t)d.pi * Cfg::NT16 * kT * kT;

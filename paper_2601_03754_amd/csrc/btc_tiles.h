@@ -36,14 +36,29 @@ __device__ __forceinline__ void mma_tile(d4& acc, const double* __restrict__ A, 
                                          const double* __restrict__ B, int cb, int kb, int K) {
     const int lane = threadIdx.x & 63;
     const int i = lane & 15, q = lane >> 4;
-#pragma unroll 4
-    for (int kk = 0; kk < K; kk += 4) {
-        const int k1 = ka + kk + q, k2 = kb + kk + q;
-        double a = TA ? A[k1 * LDA + ra + i] : A[(ra + i) * LDA + k1];
-        const double b = TB ? B[(cb + i) * LDB + k2] : B[k2 * LDB + cb + i];
-        if (NEG) a = -a;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    auto opa = [&](int kk) {
+        const int k1 = ka + kk + q;
+        const double a = TA ? A[k1 * LDA + ra + i] : A[(ra + i) * LDA + k1];
+        return NEG ? -a : a;
+    };
+    auto opb = [&](int kk) {
+        const int k2 = kb + kk + q;
+        return TB ? B[(cb + i) * LDB + k2] : B[k2 * LDB + cb + i];
+    };
+    if (K >= 16 && K % 8 == 0) {
+        // two independent accumulation chains (hides the matrix-core latency)
+        d4 acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+        for (int kk = 0; kk < K; kk += 8) {
+            const double a0 = opa(kk), b0 = opb(kk), a1 = opa(kk + 4), b1 = opb(kk + 4);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+        }
+        acc += acc1;
+        return;
     }
+#pragma unroll 4
+    for (int kk = 0; kk < K; kk += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(opa(kk), opb(kk), acc, 0, 0, 0);
 }
 
 template <int LD>
@@ -95,6 +110,47 @@ __device__ __forceinline__ void tri_tile(int k, int& a, int& b) {
 // rest of the column is broadcast through a double-buffered LDS column for
 // the trailing update.  1/sqrt of the pivot: hardware estimate refined by two
 // Newton steps.  Writes L (zero strict upper part) back and 1/L_jj to invd.
+// Cholesky of an NP x NP tile (NP <= 16) by one wavefront with lane r holding
+// row r: the multipliers of column j reach the other columns by readlane
+// broadcasts (no LDS round trip on the pivot chain).  Same contract as
+// potrf_lookahead.
+template <int NP, int LD = NP + 1>
+__device__ __forceinline__ bool potrf_small(double* __restrict__ A, double* __restrict__ invd) {
+    static_assert(NP <= 16, "small tiles only");
+    const int lane = threadIdx.x & (kWave - 1);
+    double a[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) a[c] = (lane < NP && c <= lane) ? A[lane * LD + c] : 0.0;
+    double myinv = 1.0;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const double piv = readlane_d(a[j], j);
+        ok = ok && (piv > 0.0);
+        double r = __builtin_amdgcn_rsq(piv);
+        double e = fma(-piv * r, r, 1.0);
+        r = fma(0.5 * r, e, r);
+        e = fma(-piv * r, r, 1.0);
+        r = fma(0.5 * r, e, r);
+        double l = a[j] * r;
+        l = (lane == j) ? piv * r : l;
+        l = (lane < j) ? 0.0 : l;
+        myinv = (lane == j) ? r : myinv;
+        a[j] = l;
+        double lc[NP];
+#pragma unroll
+        for (int c = j + 1; c < NP; ++c) lc[c] = readlane_d(l, c);
+#pragma unroll
+        for (int c = j + 1; c < NP; ++c) a[c] = fma(-l, lc[c], a[c]);
+    }
+    if (lane < NP) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c) A[lane * LD + c] = (c <= lane) ? a[c] : 0.0;
+        invd[lane] = myinv;
+    }
+    return ok;
+}
+
 template <int NP, int LD = NP + 1>
 __device__ __forceinline__ bool potrf_lookahead(double* __restrict__ A, double* __restrict__ invd,
                                                 double (*__restrict__ colbuf)[kWave]) {
@@ -165,6 +221,52 @@ __device__ __forceinline__ void tile_inverse(const double* __restrict__ L, int r
     }
 }
 
+
+// Blocked Cholesky of the lower triangle of an NP x NP LDS tile (row stride
+// LD) by all NW wavefronts of the workgroup (every thread must call it), in
+// 16-column panels: wavefront 0 factors the diagonal tile (potrf_small)
+// and inverts it; the tiles below it are multiplied by the inverse (L_tp =
+// A_tp L_pp^{-T}); the trailing lower tiles are updated, A_ab -= L_ap L_bp^T
+// (matrix cores, tiles spread over the wavefronts).  On return: L in the
+// lower triangle (strict upper part of each diagonal tile zeroed, tiles above
+// the diagonal untouched), 1/L_jj in invd, the inverted diagonal tiles in
+// inv[NP/16] (row stride kLDI).  *fail (LDS, 0 on entry) becomes 1 on a
+// non-positive or NaN pivot; the result is then false for every thread.
+template <int NP, int LD, int NW>
+__device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __restrict__ invd,
+                                              double (*__restrict__ inv)[kT * kLDI],
+                                              double (*__restrict__ colbuf)[kWave], int* fail) {
+    constexpr int NTL = NP / kT;
+    const int w = threadIdx.x / kWave;
+#pragma unroll 1
+    for (int p = 0; p < NTL; ++p) {
+        if (w == 0) {
+            const bool ok = potrf_small<kT, LD>(A + p * kT * LD + p * kT, invd + p * kT);
+            if (!ok && (threadIdx.x & 63) == 0) *fail = 1;
+            tile_inverse<LD, double>(A, p * kT, invd, inv[p]);
+        }
+        __syncthreads();
+        if (*fail) return false;
+        for (int t = p + 1 + w; t < NTL; t += NW) {
+            d4 out = {0.0, 0.0, 0.0, 0.0};
+            mma_tile<LD, kLDI, false, true, false>(out, A, t * kT, p * kT, inv[p], 0, 0, kT);
+            acc_store_lds<LD>(out, A, t * kT, p * kT);
+        }
+        __syncthreads();
+        const int m = NTL - 1 - p;
+        for (int k = w; k < m * (m + 1) / 2; k += NW) {
+            int ta, tb;
+            tri_tile(k, ta, tb);
+            const int a = p + 1 + ta, b = p + 1 + tb;
+            d4 acc;
+            acc_load_lds<LD>(acc, A, a * kT, b * kT);
+            mma_tile<LD, LD, false, true, true>(acc, A, a * kT, p * kT, A, b * kT, p * kT, kT);
+            acc_store_lds<LD>(acc, A, a * kT, b * kT);
+        }
+        __syncthreads();
+    }
+    return true;
+}
 
 // ---------------------------------------------------------------------------
 // FP32 tiles
