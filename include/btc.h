@@ -259,6 +259,53 @@ BTC_API int btc_runner_sync(btc_runner r);
 BTC_API void btc_runner_destroy(btc_runner r);
 
 /*
+ * Level schedules as HIP graphs.  btc_graph_begin(r) makes the runner record
+ * instead of run: every following btc_runner_run, btc_factor_batched and
+ * btc_solve_batched call on r is validated, its workspaces are allocated and
+ * its launches are planned, but nothing is enqueued.  btc_graph_end(r, &g)
+ * uploads the planned descriptors once (synchronising r's stream first) and
+ * captures all recorded launches (each call's independent groups on several
+ * streams) into an instantiated HIP graph; btc_graph_launch(g, stream)
+ * replays it with no host work per level.  A replay reads whatever the
+ * recorded A_diag / A_off / B arrays hold at that time and writes the recorded
+ * X arrays and factors: the repeated factor+solve of an MPC loop with new
+ * values in the same buffers.  The recorded handles must stay alive and keep
+ * their workspaces (a handle may not be given more right-hand sides than at
+ * recording while a graph of it exists; growing one inside a recording is
+ * refused with BTC_ERR_UNSUPPORTED).  Replays on one stream are ordered;
+ * replays of one graph must not run concurrently.
+ */
+typedef struct btc_graph_s *btc_graph;
+
+BTC_API int btc_graph_begin(btc_runner r);
+BTC_API int btc_graph_end(btc_runner r, btc_graph *out);
+BTC_API int btc_graph_launch(btc_graph g, void *stream);
+BTC_API void btc_graph_destroy(btc_graph g);
+
+/*
+ * Autotuned kernel variants (a process-wide table, default 0 everywhere),
+ * keyed by operation, precision, block size n (through its padded size) and
+ * level (bucket: level 0, levels >= 1):
+ *   BTC_OP_FACTOR, BTC_FP64, n 9..32: 0 matrix-core kernel, 1 vector-ALU
+ *     kernel (a different rounding order: results change at round-off level
+ *     when the choice changes)
+ *   BTC_OP_FORWARD / BACKWARD / RESIDUAL (nrhs > 1; level ignored): 0 four
+ *     right-hand-side columns per dependency-chain group, 1 one (identical
+ *     results)
+ * Other keys have the single variant 0 (btc_tune_set accepts only 0 there).
+ * btc_autotune times every variant of the handle's tunable families on the
+ * caller's matrix (reps timed repetitions after one warm-up each, per-level
+ * HIP events) and stores the fastest per key; it refactors the handle and
+ * overwrites X.  B and X are device arrays [N][n][nrhs], B != X.  Call it
+ * once at start-up: results computed before and after may differ at
+ * round-off level.  Returns 0 or -k for argument k.
+ */
+BTC_API int btc_tune_get(int32_t op, int32_t precision, int64_t n, int32_t level, int32_t *variant);
+BTC_API int btc_tune_set(int32_t op, int32_t precision, int64_t n, int32_t level, int32_t variant);
+BTC_API int btc_autotune(btc_handle h, const double *A_diag, const double *A_off, const double *B, double *X,
+                         int64_t nrhs, int32_t reps, void *stream);
+
+/*
  * Launch profiler of a runner.  While on, the algorithmic work of every
  * launch (btc_level_work summed over the steps of the launch) is added to the
  * totals of its (op, kernel family, padded block size), and every launch of a

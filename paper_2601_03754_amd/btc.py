@@ -140,6 +140,20 @@ def lib():
         L.btc_runner_profile_read.argtypes = [vp, ctypes.POINTER(btc_kernel_stat), i32, ctypes.POINTER(i32)]
         L.btc_level_work.restype = ctypes.c_int
         L.btc_level_work.argtypes = [i32, i32, i64, i64, i64, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+        L.btc_graph_begin.restype = ctypes.c_int
+        L.btc_graph_begin.argtypes = [vp]
+        L.btc_graph_end.restype = ctypes.c_int
+        L.btc_graph_end.argtypes = [vp, ctypes.POINTER(vp)]
+        L.btc_graph_launch.restype = ctypes.c_int
+        L.btc_graph_launch.argtypes = [vp, vp]
+        L.btc_graph_destroy.restype = None
+        L.btc_graph_destroy.argtypes = [vp]
+        L.btc_tune_get.restype = ctypes.c_int
+        L.btc_tune_get.argtypes = [i32, i32, i64, i32, ctypes.POINTER(i32)]
+        L.btc_tune_set.restype = ctypes.c_int
+        L.btc_tune_set.argtypes = [i32, i32, i64, i32, i32]
+        L.btc_autotune.restype = ctypes.c_int
+        L.btc_autotune.argtypes = [vp, vp, vp, vp, vp, i64, i32, vp]
         L.btc_server_runner.restype = vp
         L.btc_server_runner.argtypes = [vp]
         L.btc_version.restype = ctypes.c_int
@@ -316,6 +330,16 @@ class Runner:
                                        _ptr_array([_dev(x, "X") for x in Xs]), nrhs),
                "btc_solve_batched")
 
+    def graph_begin(self) -> None:
+        """Record the following runner calls instead of running them."""
+        _check(lib().btc_graph_begin(self.handle), "btc_graph_begin")
+
+    def graph_end(self) -> "Graph":
+        """Capture the recorded calls into a replayable HIP graph."""
+        g = vp()
+        _check(lib().btc_graph_end(self.handle, ctypes.byref(g)), "btc_graph_end")
+        return Graph(g.value)
+
     def profile(self, op: int = -1, kind: int = -1) -> None:
         """Switch the launch profiler on for (op, kind) (-1: any; op -2: off)."""
         runner_profile(self.handle, op, kind)
@@ -326,6 +350,27 @@ class Runner:
     def close(self):
         if getattr(self, "handle", None):
             lib().btc_runner_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """An instantiated level schedule (btc_graph_*)."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def launch(self, stream=None) -> None:
+        _check(lib().btc_graph_launch(self.handle, _stream(stream)), "btc_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().btc_graph_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -347,6 +392,25 @@ def runner_profile_read(r: int):
     _check(lib().btc_runner_profile_read(r, buf, 256, ctypes.byref(cnt)), "btc_runner_profile_read")
     return [{"op": b.op, "kind": b.kind, "np": b.np, "launches": b.launches, "items": b.items, "ms": b.ms,
              "bytes": b.bytes, "flops": b.flops} for b in buf[:cnt.value]]
+
+
+def btc_tune_get(op: int, precision: int, n: int, level: int) -> int:
+    v = i32()
+    _check(lib().btc_tune_get(op, precision, n, level, ctypes.byref(v)), "btc_tune_get")
+    return v.value
+
+
+def btc_tune_set(op: int, precision: int, n: int, level: int, variant: int) -> None:
+    _check(lib().btc_tune_set(op, precision, n, level, variant), "btc_tune_set")
+
+
+def btc_autotune(h: int, A_diag: torch.Tensor, A_off: torch.Tensor, B: torch.Tensor, X: torch.Tensor,
+                 reps: int = 3, stream=None) -> None:
+    """Time the kernel variants on this instance and keep the fastest."""
+    nrhs = B.shape[-1] if B.dim() == 3 else 1
+    po = _dev(A_off, "A_off") if A_off.numel() else 0
+    _check(lib().btc_autotune(h, _dev(A_diag, "A_diag"), po, _dev(B, "B"), _dev(X, "X"), nrhs, reps,
+                              _stream(stream)), "btc_autotune")
 
 
 def btc_level_work(op: int, precision: int, N: int, n: int, nrhs: int, level: int):

@@ -175,7 +175,8 @@ BTC_API int btc_solve(btc_handle h, const double* B, double* X, int64_t nrhs, vo
         btc::Launch<btc::ResidualDesc> R{};
         R.single = residual_desc(h, w, B, X, nrhs, false);
         e = btc::launch_ir_init(I, 1, st);
-        if (e == hipSuccess) e = btc::launch_residual(R, np, h->N, (int)nrhs, st);
+        if (e == hipSuccess)
+            e = timed(h, 3, 1, st, [&] { return btc::launch_residual(R, np, h->N, sweep_mc(BTC_OP_RESIDUAL, 0, np, nrhs), st); });
         if (e == hipSuccess) e = btc::launch_ir_check(I, 1, st);
         if (e != hipSuccess) return to_code(e);
     } else {
@@ -191,7 +192,8 @@ BTC_API int btc_solve(btc_handle h, const double* B, double* X, int64_t nrhs, vo
         if (e != hipSuccess) return to_code(e);
         for (int it = 0; it <= h->max_refine; ++it) {
             e = sweeps(h, sweep_desc32(h, w, B, X, nrhs, it == 0), st);
-            if (e == hipSuccess) e = timed(h, 3, 1, st, [&] { return btc::launch_residual(R, np, h->N, (int)nrhs, st); });
+            if (e == hipSuccess)
+                e = timed(h, 3, 1, st, [&] { return btc::launch_residual(R, np, h->N, sweep_mc(BTC_OP_RESIDUAL, 0, np, nrhs), st); });
             if (e == hipSuccess) e = timed(h, 3, 2, st, [&] { return btc::launch_ir_check(I, 1, st); });
             if (e != hipSuccess) return to_code(e);
         }

@@ -1,6 +1,7 @@
-// FP64 factorization level kernel on the vector ALUs (used for block sizes
-// n <= 8): one workgroup per block (node) of one level of the multi-stage
-// elimination tree.
+// FP64 factorization level kernel on the vector ALUs (block sizes n <= 8,
+// and n <= 32 where the autotuner prefers it to the matrix-core kernel): one
+// workgroup per block (node) of one level of the multi-stage elimination
+// tree.
 //
 // Factorization (section "Multi-Stage Permutation", Algorithm 4, the hybrid
 // left/right-looking form): at level l (stride s) node i
@@ -195,6 +196,8 @@ hipError_t launch_factor_valu(const Launch<FactorDesc>& p, int np, int64_t items
     const dim3 g((unsigned)items);
     switch (np) {
         case 8: hipLaunchKernelGGL((k_factor_level_f64<8, F64Cfg<8>::NT>), g, dim3(F64Cfg<8>::NT), 0, st, p); break;
+        case 16: hipLaunchKernelGGL((k_factor_level_f64<16, F64Cfg<16>::NT>), g, dim3(F64Cfg<16>::NT), 0, st, p); break;
+        case 32: hipLaunchKernelGGL((k_factor_level_f64<32, F64Cfg<32>::NT>), g, dim3(F64Cfg<32>::NT), 0, st, p); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

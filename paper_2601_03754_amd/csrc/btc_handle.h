@@ -252,14 +252,27 @@ inline int factor_np(btc_handle h) {
     return is_mixed(h->precision) ? btc::padded_block_mixed((int)h->n) : btc::padded_block((int)h->n);
 }
 
-// Factor kernel family of a handle: 0 VALU FP64 (np < 16), 1 MFMA FP64,
-// 2 mixed, 3 tile-parallel FP64 (np > 64), 4 tile-parallel mixed.
-inline int factor_kind(btc_handle h) {
+// Autotuned kernel variants (process-wide table, default 0).
+int tune_variant(int op, int kind, int np, int bucket);
+void tune_set(int op, int kind, int np, int bucket, int variant);
+
+// Factor kernel family of a handle at a level: 0 VALU FP64 (np < 16, or
+// np 16/32 where the autotuner chose it), 1 MFMA FP64, 2 mixed,
+// 3 tile-parallel FP64 (np > 64), 4 tile-parallel mixed.
+inline int factor_kind(btc_handle h, int level) {
     const int np = factor_np(h);
     const bool mixed = is_mixed(h->precision);
     if (np > 64) return mixed ? 4 : 3;
     if (mixed) return 2;
-    return np >= 16 ? 1 : 0;
+    if (np < 16) return 0;
+    if (np <= 32 && tune_variant(BTC_OP_FACTOR, 0, np, level > 0 ? 1 : 0) == 1) return 0;
+    return 1;
+}
+
+// Right-hand-side columns per dependency-chain group of a sweep or residual
+// launch (results do not depend on it).
+inline int sweep_mc(int op, int kind, int np, int64_t m) {
+    return (m <= 1 || tune_variant(op, kind, np, 0) == 1) ? 1 : 4;
 }
 
 // level_hint: the level of every item of the launch, or -1 when they differ.
@@ -277,7 +290,7 @@ inline hipError_t launch_factor_kind(int kind, const btc::Launch<btc::FactorDesc
 
 inline hipError_t launch_factor_any(btc_handle h, const btc::Launch<btc::FactorDesc>& L, int64_t items, hipStream_t st) {
     const int np = factor_np(h);
-    return launch_factor_kind(factor_kind(h), L, np, L.level, items, st);
+    return launch_factor_kind(factor_kind(h, L.level), L, np, L.level, items, st);
 }
 
 inline int launch_factor(btc_handle h, const double* A_diag, const double* A_off, hipStream_t st) {
@@ -307,12 +320,12 @@ inline hipError_t sweeps(btc_handle h, const btc::SweepDesc<T>& d, hipStream_t s
     const int np = btc::padded_block((int)h->n);
     for (int l = 0; l < h->levels; ++l) {
         L.level = l;
-        hipError_t e = timed(h, 1, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), false, d.m, st); });
+        hipError_t e = timed(h, 1, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), false, sweep_mc(BTC_OP_FORWARD, sizeof(T) == 4, np, d.m), st); });
         if (e != hipSuccess) return e;
     }
     for (int l = h->levels - 1; l >= 0; --l) {
         L.level = l;
-        hipError_t e = timed(h, 2, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), true, d.m, st); });
+        hipError_t e = timed(h, 2, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), true, sweep_mc(BTC_OP_BACKWARD, sizeof(T) == 4, np, d.m), st); });
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -137,12 +137,13 @@ hipError_t launch_factor_mixed(const Launch<FactorDesc>& p, int np, int64_t item
 // 0 skips the deferred-update launch, which has nothing to do at level 0).
 hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, bool mixed, int level_hint, int64_t items,
                                hipStream_t st);
-// m_max: the largest number of right-hand sides of any item of the launch.
-hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t items, bool backward, int m_max,
+// mc: right-hand-side columns per dependency-chain group (1 or 4; with 4,
+// instances with fewer columns mask the rest).
+hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t items, bool backward, int mc,
                         hipStream_t st);
-hipError_t launch_sweep(const Launch<SweepDesc<float>>& p, int np, int64_t items, bool backward, int m_max,
+hipError_t launch_sweep(const Launch<SweepDesc<float>>& p, int np, int64_t items, bool backward, int mc,
                         hipStream_t st);
-hipError_t launch_residual(const Launch<ResidualDesc>& p, int np, int64_t items, int m_max, hipStream_t st);
+hipError_t launch_residual(const Launch<ResidualDesc>& p, int np, int64_t items, int mc, hipStream_t st);
 hipError_t launch_ir_init(const Launch<IrDesc>& p, int64_t items, hipStream_t st);
 hipError_t launch_ir_check(const Launch<IrDesc>& p, int64_t items, hipStream_t st);
 

@@ -49,6 +49,14 @@ struct Group {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The groups of one runner call and the status words its level-0 factor
+// steps reset; offsets are into the device buffer the call is launched from.
+struct Call {
+    std::map<std::tuple<int, int, int>, Group> groups;
+    std::vector<unsigned long long*> resets;
+    size_t off_resets = 0;
+};
+
 }  // namespace
 
 struct btc_runner_s {
@@ -79,6 +87,17 @@ struct btc_runner_s {
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
     std::map<std::tuple<int, int, int>, btc_kernel_stat> totals;
+    // graph recording (btc_graph_begin .. btc_graph_end)
+    bool recording = false;
+    std::vector<Call> rec;
+    std::vector<btc_handle> rec_handles;
+};
+
+struct btc_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    char* dev = nullptr;
+    hipStream_t cap = nullptr;
 };
 
 namespace {
@@ -263,20 +282,21 @@ BTC_API void btc_runner_destroy(btc_runner r) {
     delete r;
 }
 
-BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
-    if (!r) return -1;
-    if (count < 0) return -2;
-    if (count > 0 && !steps) return -3;
-    if (count == 0) return BTC_OK;
-    hipStream_t st = r->st;
+namespace {
 
-    // workspaces first: growing one synchronises, before anything is queued
+// Validate the steps and grow the workspaces they need (growing one
+// synchronises, so this runs before anything of the call is queued).
+int prepare_steps(btc_runner r, int32_t count, const btc_step* steps, hipStream_t st) {
     for (int32_t k = 0; k < count; ++k) {
         const int rc = validate(steps[k]);
         if (rc != BTC_OK) return rc;
         btc_handle h = steps[k].h;
         if (steps[k].op != BTC_OP_FACTOR) {
             if (steps[k].nrhs > h->ws_m || !h->ws) {
+                // a recorded call already points into this workspace
+                if (r->recording && h->ws &&
+                    std::find(r->rec_handles.begin(), r->rec_handles.end(), h) != r->rec_handles.end())
+                    return BTC_ERR_UNSUPPORTED;
                 if (h->ws) (void)hipStreamSynchronize(st);
                 h->stream = st;
                 const int e = ensure_workspace(h, steps[k].nrhs);
@@ -285,8 +305,15 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
         }
     }
 
-    std::map<std::tuple<int, int, int>, Group> groups;
-    std::vector<unsigned long long*> resets;
+    if (r->recording)
+        for (int32_t k = 0; k < count; ++k) r->rec_handles.push_back(steps[k].h);
+    return BTC_OK;
+}
+
+// Group the steps of one call by (operation, kernel family, padded size).
+void build_call(btc_runner r, int32_t count, const btc_step* steps, hipStream_t st, Call& c) {
+    auto& groups = c.groups;
+    auto& resets = c.resets;
     for (int32_t k = 0; k < count; ++k) {
         const btc_step& s = steps[k];
         btc_handle h = s.h;
@@ -301,7 +328,7 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
                 h->failed_known = false;
             }
             const int np = factor_np(h);
-            const int kind = factor_kind(h);
+            const int kind = factor_kind(h, s.level);
             Group& g = groups[std::make_tuple(s.op, kind, np)];
             g.op = s.op;
             g.kind = kind;
@@ -357,38 +384,46 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
         }
     }
 
-    // pack: reset pointers, then descriptors and items of every group
-    size_t bytes = align256(resets.size() * sizeof(unsigned long long*));
-    for (auto& kv : groups) {
+}
+
+// Offsets of the call's reset list, descriptors and items from `base`;
+// returns the end.
+size_t layout_call(Call& c, size_t base) {
+    c.off_resets = base;
+    size_t bytes = align256(base + c.resets.size() * sizeof(unsigned long long*));
+    for (auto& kv : c.groups) {
         Group& g = kv.second;
         g.off_desc = bytes;
         bytes = align256(bytes + g.descs.size());
         g.off_items = bytes;
         bytes = align256(bytes + g.items.size() * sizeof(btc::WorkItem));
     }
-    btc_runner_s::Slot& sl = r->slot[r->cur];
-    int rc = slot_reserve(r, sl, bytes);
-    if (rc != BTC_OK) return rc;
-    if (!resets.empty()) memcpy(sl.host, resets.data(), resets.size() * sizeof(unsigned long long*));
-    for (auto& kv : groups) {
-        Group& g = kv.second;
-        memcpy(sl.host + g.off_desc, g.descs.data(), g.descs.size());
-        memcpy(sl.host + g.off_items, g.items.data(), g.items.size() * sizeof(btc::WorkItem));
-    }
-    hipError_t e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return to_code(e);
-    (void)hipEventRecord(sl.ev, st);
-    sl.pending = true;
-    r->cur ^= 1;
+    return bytes;
+}
 
+void write_call(const Call& c, char* host) {
+    if (!c.resets.empty()) memcpy(host + c.off_resets, c.resets.data(), c.resets.size() * sizeof(unsigned long long*));
+    for (auto& kv : c.groups) {
+        const Group& g = kv.second;
+        memcpy(host + g.off_desc, g.descs.data(), g.descs.size());
+        memcpy(host + g.off_items, g.items.data(), g.items.size() * sizeof(btc::WorkItem));
+    }
+}
+
+// Enqueue the call (its descriptors already in `dev`): status resets, then
+// every group, independent groups spread over the runner's streams.
+int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
+    hipError_t e = hipSuccess;
+    auto& groups = c.groups;
+    const auto& resets = c.resets;
     if (!resets.empty()) {
         const int n = (int)resets.size();
         hipLaunchKernelGGL(k_reset_infos, dim3((n + 255) / 256), dim3(256), 0, st,
-                           (unsigned long long* const*)sl.dev, n);
+                           (unsigned long long* const*)(dev + c.off_resets), n);
         e = hipGetLastError();
         if (e != hipSuccess) return to_code(e);
     }
-    if (!r->pending.empty()) drain_prof(r, false);
+    if (timing && !r->pending.empty()) drain_prof(r, false);
     // stream of every group: largest estimated work first, each onto the
     // least loaded of the main and side streams
     std::vector<std::pair<double, Group*>> order;
@@ -427,7 +462,7 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
         const int64_t items = (int64_t)g.items.size();
         hipStream_t gs = g.lane == 0 ? st : r->side[g.lane - 1];
         hipEvent_t ea = nullptr, eb = nullptr;
-        if (g.prof) {
+        if (g.prof && timing) {
             ea = take_event(r);
             eb = ea ? take_event(r) : nullptr;
             if (!eb) {
@@ -438,7 +473,7 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
         }
         switch (g.op) {
             case BTC_OP_FACTOR: {
-                auto L = make_launch<btc::FactorDesc>(g, sl.dev);
+                auto L = make_launch<btc::FactorDesc>(g, dev);
                 e = launch_factor_kind(g.kind, L, g.np, g.level, items, gs);
                 break;
             }
@@ -446,25 +481,25 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
             case BTC_OP_BACKWARD: {
                 const bool bwd = g.op == BTC_OP_BACKWARD;
                 if (g.kind == 1)
-                    e = btc::launch_sweep(make_launch<btc::SweepDesc<float>>(g, sl.dev), g.np, items, bwd, g.m_max, gs);
+                    e = btc::launch_sweep(make_launch<btc::SweepDesc<float>>(g, dev), g.np, items, bwd, sweep_mc(g.op, 1, g.np, g.m_max), gs);
                 else
-                    e = btc::launch_sweep(make_launch<btc::SweepDesc<double>>(g, sl.dev), g.np, items, bwd, g.m_max, gs);
+                    e = btc::launch_sweep(make_launch<btc::SweepDesc<double>>(g, dev), g.np, items, bwd, sweep_mc(g.op, 0, g.np, g.m_max), gs);
                 break;
             }
             case BTC_OP_RESIDUAL:
-                e = btc::launch_residual(make_launch<btc::ResidualDesc>(g, sl.dev), g.np, items, g.m_max, gs);
+                e = btc::launch_residual(make_launch<btc::ResidualDesc>(g, dev), g.np, items, sweep_mc(BTC_OP_RESIDUAL, 0, g.np, g.m_max), gs);
                 break;
             case BTC_OP_REFINE_INIT:
-                e = btc::launch_ir_init(make_launch<btc::IrDesc>(g, sl.dev), items, gs);
+                e = btc::launch_ir_init(make_launch<btc::IrDesc>(g, dev), items, gs);
                 break;
             default:
-                e = btc::launch_ir_check(make_launch<btc::IrDesc>(g, sl.dev), items, gs);
+                e = btc::launch_ir_check(make_launch<btc::IrDesc>(g, dev), items, gs);
                 break;
         }
-        if (g.prof) {
+        if (g.prof && timing) {
             (void)hipEventRecord(eb, gs);
             r->pending.push_back({kv.first, ea, eb, g.work});
-        } else if (g.count) {
+        } else if (g.count && timing) {
             add_untimed(r, kv.first, g.work);
         }
         if (e != hipSuccess) return to_code(e);
@@ -476,6 +511,108 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
         if (e != hipSuccess) return to_code(e);
     }
     return BTC_OK;
+}
+
+
+}  // namespace
+
+BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
+    if (!r) return -1;
+    if (count < 0) return -2;
+    if (count > 0 && !steps) return -3;
+    if (count == 0) return BTC_OK;
+    hipStream_t st = r->st;
+    int rc = prepare_steps(r, count, steps, st);
+    if (rc != BTC_OK) return rc;
+    Call c;
+    build_call(r, count, steps, st, c);
+    if (r->recording) {
+        r->rec.push_back(std::move(c));
+        return BTC_OK;
+    }
+    const size_t bytes = layout_call(c, 0);
+    btc_runner_s::Slot& sl = r->slot[r->cur];
+    rc = slot_reserve(r, sl, bytes);
+    if (rc != BTC_OK) return rc;
+    write_call(c, sl.host);
+    hipError_t e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return to_code(e);
+    (void)hipEventRecord(sl.ev, st);
+    sl.pending = true;
+    r->cur ^= 1;
+    return launch_call(r, c, sl.dev, st, true);
+}
+
+
+BTC_API int btc_graph_begin(btc_runner r) {
+    if (!r) return -1;
+    if (r->recording) return BTC_ERR_UNSUPPORTED;
+    r->recording = true;
+    r->rec.clear();
+    r->rec_handles.clear();
+    return BTC_OK;
+}
+
+BTC_API void btc_graph_destroy(btc_graph g) {
+    if (!g) return;
+    if (g->cap) (void)hipStreamSynchronize(g->cap);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->dev) (void)hipFree(g->dev);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    delete g;
+}
+
+BTC_API int btc_graph_end(btc_runner r, btc_graph* out) {
+    if (!r) return -1;
+    if (!out) return -2;
+    *out = nullptr;
+    if (!r->recording) return BTC_ERR_UNSUPPORTED;
+    r->recording = false;
+    std::vector<Call> calls;
+    calls.swap(r->rec);
+    r->rec_handles.clear();
+    btc_graph g = new (std::nothrow) btc_graph_s();
+    if (!g) return BTC_ERR_OOM;
+    size_t bytes = 0;
+    for (auto& c : calls) bytes = layout_call(c, bytes);
+    std::vector<char> host(std::max<size_t>(bytes, 256));
+    for (auto& c : calls) write_call(c, host.data());
+    // the recorded work of the runner's stream must be done before the
+    // descriptors are uploaded and the capture starts
+    hipError_t e = hipStreamSynchronize(r->st);
+    if (e == hipSuccess) e = hipMalloc(&g->dev, host.size());
+    if (e == hipSuccess) e = hipMemcpy(g->dev, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        btc_graph_destroy(g);
+        return to_code(e);
+    }
+    int rc = BTC_OK;
+    for (auto& c : calls) {
+        rc = launch_call(r, c, g->dev, g->cap, false);
+        if (rc != BTC_OK) break;
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(g->cap, &graph);
+    g->graph = graph;
+    if (rc == BTC_OK && e != hipSuccess) rc = to_code(e);
+    if (rc == BTC_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = to_code(e);
+    }
+    if (rc != BTC_OK) {
+        btc_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return BTC_OK;
+}
+
+BTC_API int btc_graph_launch(btc_graph g, void* stream) {
+    if (!g) return -1;
+    return to_code(hipGraphLaunch(g->exec, (hipStream_t)stream));
 }
 
 BTC_API int btc_runner_profile(btc_runner r, int32_t op, int32_t kind) {

@@ -525,9 +525,9 @@ __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
 }
 
 template <int NP, class T>
-hipError_t launch_sweep_np(const Launch<SweepDesc<T>>& p, int64_t items, bool backward, int m_max, hipStream_t st) {
+hipError_t launch_sweep_np(const Launch<SweepDesc<T>>& p, int64_t items, bool backward, int mc, hipStream_t st) {
     const dim3 g((unsigned)items), b(kWave);
-    if (m_max <= 1) {
+    if (mc <= 1) {
         if (backward)
             hipLaunchKernelGGL((k_bwd<NP, 1, T>), g, b, 0, st, p);
         else
@@ -542,23 +542,23 @@ hipError_t launch_sweep_np(const Launch<SweepDesc<T>>& p, int64_t items, bool ba
 }
 
 template <class T>
-hipError_t launch_sweep_t(const Launch<SweepDesc<T>>& p, int np, int64_t items, bool backward, int m_max,
+hipError_t launch_sweep_t(const Launch<SweepDesc<T>>& p, int np, int64_t items, bool backward, int mc,
                           hipStream_t st) {
     switch (np) {
         case 8:
-        case 16: return launch_sweep_np<16, T>(p, items, backward, m_max, st);
-        case 32: return launch_sweep_np<32, T>(p, items, backward, m_max, st);
-        case 64: return launch_sweep_np<64, T>(p, items, backward, m_max, st);
-        case 96: return launch_sweep_np<96, T>(p, items, backward, m_max, st);
-        case 128: return launch_sweep_np<128, T>(p, items, backward, m_max, st);
+        case 16: return launch_sweep_np<16, T>(p, items, backward, mc, st);
+        case 32: return launch_sweep_np<32, T>(p, items, backward, mc, st);
+        case 64: return launch_sweep_np<64, T>(p, items, backward, mc, st);
+        case 96: return launch_sweep_np<96, T>(p, items, backward, mc, st);
+        case 128: return launch_sweep_np<128, T>(p, items, backward, mc, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int NP>
-hipError_t launch_res_np(const Launch<ResidualDesc>& p, int64_t items, int m_max, hipStream_t st) {
+hipError_t launch_res_np(const Launch<ResidualDesc>& p, int64_t items, int mc, hipStream_t st) {
     const dim3 g((unsigned)items), b(kWave);
-    if (m_max <= 1)
+    if (mc <= 1)
         hipLaunchKernelGGL((k_res<NP, 1>), g, b, 0, st, p);
     else
         hipLaunchKernelGGL((k_res<NP, 4>), g, b, 0, st, p);
@@ -567,24 +567,24 @@ hipError_t launch_res_np(const Launch<ResidualDesc>& p, int64_t items, int m_max
 
 }  // namespace
 
-hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t items, bool backward, int m_max,
+hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t items, bool backward, int mc,
                         hipStream_t st) {
-    return launch_sweep_t<double>(p, np, items, backward, m_max, st);
+    return launch_sweep_t<double>(p, np, items, backward, mc, st);
 }
 
-hipError_t launch_sweep(const Launch<SweepDesc<float>>& p, int np, int64_t items, bool backward, int m_max,
+hipError_t launch_sweep(const Launch<SweepDesc<float>>& p, int np, int64_t items, bool backward, int mc,
                         hipStream_t st) {
-    return launch_sweep_t<float>(p, np, items, backward, m_max, st);
+    return launch_sweep_t<float>(p, np, items, backward, mc, st);
 }
 
-hipError_t launch_residual(const Launch<ResidualDesc>& p, int np, int64_t items, int m_max, hipStream_t st) {
+hipError_t launch_residual(const Launch<ResidualDesc>& p, int np, int64_t items, int mc, hipStream_t st) {
     switch (np) {
         case 8:
-        case 16: return launch_res_np<16>(p, items, m_max, st);
-        case 32: return launch_res_np<32>(p, items, m_max, st);
-        case 64: return launch_res_np<64>(p, items, m_max, st);
-        case 96: return launch_res_np<96>(p, items, m_max, st);
-        case 128: return launch_res_np<128>(p, items, m_max, st);
+        case 16: return launch_res_np<16>(p, items, mc, st);
+        case 32: return launch_res_np<32>(p, items, mc, st);
+        case 64: return launch_res_np<64>(p, items, mc, st);
+        case 96: return launch_res_np<96>(p, items, mc, st);
+        case 128: return launch_res_np<128>(p, items, mc, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,165 @@
+// Kernel variants chosen by the autotuner: a process-wide table keyed by
+// (operation, kernel family, padded block size, level bucket), and the tuner
+// that times the candidates on a caller's instance.
+//
+// Tunable choices:
+//   factor, FP64, padded size 16 or 32: 0 = matrix-core kernel, 1 = vector-ALU
+//     kernel (different rounding order; level bucket 0 = level 0, which has
+//     no deferred updates, 1 = the other levels)
+//   forward / backward sweep and residual, nrhs > 1: 0 = four right-hand-side
+//     columns per dependency chain group, 1 = one (bitwise identical results)
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "btc.h"
+#include "btc_handle.h"
+#include "btc_kernels.h"
+
+namespace btc_host {
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune;
+
+}  // namespace
+
+int tune_variant(int op, int kind, int np, int bucket) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(op, kind, np, bucket));
+    return it == g_tune.end() ? 0 : it->second;
+}
+
+void tune_set(int op, int kind, int np, int bucket, int variant) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(op, kind, np, bucket)] = variant;
+}
+
+}  // namespace btc_host
+
+using namespace btc_host;
+
+namespace {
+
+// (kind, padded size) of a tunable family for a handle, or false.
+bool tunable(int op, int32_t prec, int64_t n, int& kind, int& np, int& variants) {
+    const bool mixed = is_mixed(prec);
+    np = btc::padded_block((int)n);
+    if (op == BTC_OP_FACTOR) {
+        kind = 0;
+        variants = 2;
+        return !mixed && (np == 16 || np == 32);
+    }
+    if (op == BTC_OP_FORWARD || op == BTC_OP_BACKWARD) {
+        kind = mixed ? 1 : 0;
+        variants = 2;
+        return true;
+    }
+    if (op == BTC_OP_RESIDUAL) {
+        kind = 0;
+        variants = 2;
+        return true;
+    }
+    return false;
+}
+
+// Level bucket of a key: the factor distinguishes level 0 from the others;
+// the sweeps and the residual ignore the level.
+int bucket_of(int op, int level) { return (op == BTC_OP_FACTOR && level > 0) ? 1 : 0; }
+
+}  // namespace
+
+extern "C" {
+
+BTC_API int btc_tune_get(int32_t op, int32_t precision, int64_t n, int32_t level, int32_t* variant) {
+    if (op < BTC_OP_FACTOR || op > BTC_OP_REFINE_TEST) return -1;
+    if (precision != BTC_FP64 && !is_mixed(precision)) return -2;
+    if (n < 1 || n > BTC_MAX_BLOCK) return -3;
+    if (level < 0) return -4;
+    if (!variant) return -5;
+    int kind, np, nv;
+    *variant = tunable(op, precision, n, kind, np, nv) ? tune_variant(op, kind, np, bucket_of(op, level)) : 0;
+    return BTC_OK;
+}
+
+BTC_API int btc_tune_set(int32_t op, int32_t precision, int64_t n, int32_t level, int32_t variant) {
+    if (op < BTC_OP_FACTOR || op > BTC_OP_REFINE_TEST) return -1;
+    if (precision != BTC_FP64 && !is_mixed(precision)) return -2;
+    if (n < 1 || n > BTC_MAX_BLOCK) return -3;
+    if (level < 0) return -4;
+    int kind, np, nv;
+    if (!tunable(op, precision, n, kind, np, nv)) return variant == 0 ? BTC_OK : BTC_ERR_UNSUPPORTED;
+    if (variant < 0 || variant >= nv) return -5;
+    tune_set(op, kind, np, bucket_of(op, level), variant);
+    return BTC_OK;
+}
+
+BTC_API int btc_autotune(btc_handle h, const double* A_diag, const double* A_off, const double* B, double* X,
+                         int64_t nrhs, int32_t reps, void* stream) {
+    if (!h) return -1;
+    if (!A_diag || (h->N > 1 && !A_off)) return -2;
+    if (!B || !X || B == X) return -4;
+    if (nrhs < 1) return -6;
+    if (reps < 1) return -7;
+    int kind, np, nv;
+    // factor: per level bucket, the variant with the least summed level time
+    if (tunable(BTC_OP_FACTOR, h->precision, h->n, kind, np, nv)) {
+        double best[2] = {1e300, 1e300};
+        int pick[2] = {0, 0};
+        for (int v = 0; v < nv; ++v) {
+            tune_set(BTC_OP_FACTOR, kind, np, 0, v);
+            tune_set(BTC_OP_FACTOR, kind, np, 1, v);
+            int rc = btc_refactor(h, A_diag, A_off, stream);  // warm-up
+            if (rc == BTC_OK) rc = btc_profile(h, 1);
+            for (int k = 0; k < reps && rc == BTC_OK; ++k) rc = btc_refactor(h, A_diag, A_off, stream);
+            double ms[64] = {};
+            if (rc == BTC_OK) rc = btc_profile_read(h, 0, ms, nullptr, 64) < 0 ? BTC_ERR_HIP : BTC_OK;
+            btc_profile(h, 0);
+            if (rc != BTC_OK) return rc;
+            const double t[2] = {ms[0], [&] { double a = 0; for (int l = 1; l < h->levels; ++l) a += ms[l]; return a; }()};
+            for (int b = 0; b < 2; ++b)
+                if (t[b] < best[b]) {
+                    best[b] = t[b];
+                    pick[b] = v;
+                }
+        }
+        tune_set(BTC_OP_FACTOR, kind, np, 0, pick[0]);
+        tune_set(BTC_OP_FACTOR, kind, np, 1, pick[1]);
+    }
+    int rc = btc_refactor(h, A_diag, A_off, stream);
+    if (rc != BTC_OK) return rc;
+    // sweeps and residual: only with several right-hand sides
+    if (nrhs > 1) {
+        const int ops[3] = {BTC_OP_FORWARD, BTC_OP_BACKWARD, BTC_OP_RESIDUAL};
+        double tot[3][2] = {};
+        for (int v = 0; v < 2; ++v) {
+            for (int op : ops) {
+                tunable(op, h->precision, h->n, kind, np, nv);
+                tune_set(op, kind, np, 0, v);
+            }
+            btc_solve_info info;
+            rc = btc_solve(h, B, X, nrhs, stream, nullptr);  // warm-up
+            if (rc == BTC_OK) rc = btc_profile(h, 1);
+            for (int k = 0; k < reps && rc == BTC_OK; ++k) rc = btc_solve(h, B, X, nrhs, stream, &info);
+            double ms[3][64] = {};
+            for (int ph = 0; ph < 3 && rc == BTC_OK; ++ph)
+                if (btc_profile_read(h, ph == 2 ? 3 : ph + 1, ms[ph], nullptr, 64) < 0) rc = BTC_ERR_HIP;
+            btc_profile(h, 0);
+            if (rc != BTC_OK) return rc;
+            for (int ph = 0; ph < 3; ++ph)
+                for (int l = 0; l < 64; ++l)
+                    if (ph < 2 || l == 1) tot[ph][v] += ms[ph][l];  // refinement phase entry 1: residual
+        }
+        for (int k = 0; k < 3; ++k) {
+            tunable(ops[k], h->precision, h->n, kind, np, nv);
+            // the FP64 path forms a residual only when asked for it: keep the default
+            const int v = (k == 2 && tot[2][0] == 0.0 && tot[2][1] == 0.0) ? 0 : (tot[k][1] < tot[k][0] ? 1 : 0);
+            tune_set(ops[k], kind, np, 0, v);
+        }
+    }
+    return BTC_OK;
+}
+
+}  // extern "C"

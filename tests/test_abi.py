@@ -146,3 +146,38 @@ def test_level_work_argument_errors(lib):
     assert L.btc_level_work(1, 0, 8, 4, 0, 0, ctypes.byref(b), ctypes.byref(f)) == -5
     assert L.btc_level_work(1, 0, 8, 4, 1, 4, ctypes.byref(b), ctypes.byref(f)) == -6
     assert L.btc_runner_profile(None, -1, -1) == -1
+
+
+def test_graph_argument_errors(lib):
+    L = lib.lib()
+    assert L.btc_graph_begin(None) == -1
+    assert L.btc_graph_end(None, None) == -1
+    assert L.btc_graph_launch(None, None) == -1
+    L.btc_graph_destroy(None)
+
+
+def test_tune_table_host_only(lib):
+    """The variant table is host state: defaults, set/get round trip, keys
+    without a choice accept only variant 0, argument errors."""
+    F, FW, R = lib.BTC_OP_FACTOR, lib.BTC_OP_FORWARD, lib.BTC_OP_RESIDUAL
+    assert lib.btc_tune_get(F, 0, 24, 0) == 0
+    lib.btc_tune_set(F, 0, 24, 3, 1)           # n 24 -> padded 32, levels >= 1
+    assert lib.btc_tune_get(F, 0, 20, 5) == 1  # same padded size and bucket
+    assert lib.btc_tune_get(F, 0, 24, 0) == 0  # level 0 bucket untouched
+    lib.btc_tune_set(F, 0, 24, 3, 0)
+    assert lib.btc_tune_get(F, 0, 24, 3) == 0
+    lib.btc_tune_set(FW, 1, 64, 0, 1)
+    assert lib.btc_tune_get(FW, 1, 50, 7) == 1
+    lib.btc_tune_set(FW, 1, 64, 0, 0)
+    lib.btc_tune_set(F, 1, 24, 0, 0)           # mixed factor: single variant
+    with pytest.raises(lib.BtcError) as ei:
+        lib.btc_tune_set(F, 1, 24, 0, 1)
+    assert ei.value.code == lib.BTC_ERR_UNSUPPORTED
+    L = lib.lib()
+    v = ctypes.c_int32()
+    assert L.btc_tune_get(9, 0, 8, 0, ctypes.byref(v)) == -1
+    assert L.btc_tune_get(0, 5, 8, 0, ctypes.byref(v)) == -2
+    assert L.btc_tune_get(0, 0, 200, 0, ctypes.byref(v)) == -3
+    assert L.btc_tune_get(0, 0, 8, -1, ctypes.byref(v)) == -4
+    assert L.btc_tune_set(R, 0, 8, 0, 2) == -5
+    assert L.btc_autotune(None, None, None, None, None, 1, 1, None) == -1

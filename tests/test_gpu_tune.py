@@ -1,0 +1,100 @@
+"""Autotuned kernel variants through the C ABI: every variant of every
+tunable family meets the oracle's accuracy, the column-grouping variants of
+the sweeps and residual give bit-identical results, batched runs follow the
+table exactly as single-instance runs do, and btc_autotune picks variants
+that keep all of this true."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2601_03754_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def btc():
+    from paper_2601_03754_amd import btc as b
+    b.lib()
+    yield b
+    for op in (0, 1, 2, 3):
+        for n in (16, 32, 64):
+            for lvl in (0, 1):
+                b.btc_tune_set(op, 0, n, lvl, 0)
+                if op:
+                    b.btc_tune_set(op, 1, n, lvl, 0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def run(btc, p, precision=0):
+    f = btc.Factor(dev(p.D), dev(p.E), precision=precision)
+    X = f.solve(dev(p.B)).cpu().numpy()
+    blocks = f.export()
+    f.close()
+    return X, blocks
+
+
+@pytest.mark.parametrize("n", [12, 24, 32])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_factor_variants_match_oracle(btc, n, variant):
+    p = inputs.block_tridiag(77, n, seed=400 + n, nrhs=2)
+    btc.btc_tune_set(0, 0, n, 0, variant)
+    btc.btc_tune_set(0, 0, n, 1, variant)
+    X, blocks = run(btc, p)
+    btc.btc_tune_set(0, 0, n, 0, 0)
+    btc.btc_tune_set(0, 0, n, 1, 0)
+    Ld, Rb, Tb, info = oracle.factor_nd(p.D, p.E)
+    scale = max(np.abs(Ld).max(), 1.0)
+    for g, o in zip(blocks, (Ld, Rb, Tb)):
+        assert np.abs(g - o).max() <= 1e-12 * scale
+    assert oracle.relres(p.D, p.E, X, p.B) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_column_grouping_is_bitwise_neutral(btc, precision):
+    p = inputs.block_tridiag(65, 40, seed=5, nrhs=3)
+    outs = []
+    for v in (0, 1):
+        for op in (1, 2, 3):
+            btc.btc_tune_set(op, precision, 40, 0, v)
+        outs.append(run(btc, p, precision)[0])
+    for op in (1, 2, 3):
+        btc.btc_tune_set(op, precision, 40, 0, 0)
+    assert np.array_equal(outs[0], outs[1])
+    assert oracle.relres(p.D, p.E, outs[0], p.B) <= (1e-12 if precision == 0 else 1e-10)
+
+
+def test_batched_follows_table_like_single(btc):
+    btc.btc_tune_set(0, 0, 30, 1, 1)  # VALU kernel above level 0 for padded 32
+    prs = [inputs.block_tridiag(N, 30, seed=N, nrhs=1) for N in (9, 40, 100)]
+    r = btc.Runner()
+    hs = [btc.btc_create(p.N, p.n, 0) for p in prs]
+    Xs = [torch.empty_like(dev(p.B)) for p in prs]
+    r.factor_batched(hs, [dev(p.D) for p in prs], [dev(p.E) for p in prs])
+    r.solve_batched(hs, [dev(p.B) for p in prs], Xs, 1)
+    r.sync()
+    for k, p in enumerate(prs):
+        Xsng, _ = run(btc, p)
+        assert np.array_equal(Xs[k].cpu().numpy(), Xsng)
+        btc.btc_destroy(hs[k])
+    r.close()
+    btc.btc_tune_set(0, 0, 30, 1, 0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autotune_keeps_results_correct(btc, precision):
+    p = inputs.block_tridiag(300, 28, seed=8, nrhs=4)
+    D, E, B = dev(p.D), dev(p.E), dev(p.B)
+    X = torch.empty_like(B)
+    h = btc.btc_create(p.N, p.n, precision)
+    btc.btc_autotune(h, D, E, B, X, reps=2)
+    torch.cuda.synchronize()
+    for op, lvl in ((0, 0), (0, 1), (1, 0), (2, 0), (3, 0)):
+        assert btc.btc_tune_get(op, precision, 28, lvl) in (0, 1)
+    btc.btc_destroy(h)
+    X2, _ = run(btc, p, precision)
+    assert oracle.relres(p.D, p.E, X2, p.B) <= (1e-12 if precision == 0 else 1e-10)
