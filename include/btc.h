@@ -61,6 +61,7 @@ typedef struct btc_handle_s *btc_handle; /* opaque; owned by the library */
 
 /* Defaults of the refinement options (used when the field is 0). */
 #define BTC_DEFAULT_MAX_REFINE 4
+#define BTC_DEFAULT_MAX_REFINE_BF16 30
 #define BTC_DEFAULT_TOL 1e-10
 
 /*
@@ -77,10 +78,15 @@ typedef struct btc_handle_s *btc_handle; /* opaque; owned by the library */
  *                The handle keeps pointers to A_diag and A_off for the
  *                residual, so they must stay valid and unchanged while the
  *                handle is used for solves.
+ *   BTC_BF16_IR  as BTC_FP32_IR, but the Schur and fill products (syrk,
+ *                gemm) take BF16 operands (round to nearest even) with FP32
+ *                accumulation; more refinement steps are needed (default cap
+ *                BTC_DEFAULT_MAX_REFINE_BF16).
  */
 typedef enum {
     BTC_FP64 = 0,
-    BTC_FP32_IR = 1
+    BTC_FP32_IR = 1,
+    BTC_BF16_IR = 2
 } btc_precision;
 
 typedef struct {

@@ -21,6 +21,7 @@ _lib = None
 
 BTC_FP64 = 0
 BTC_FP32_IR = 1
+BTC_BF16_IR = 2
 BTC_OK = 0
 BTC_ERR_HIP = -100
 BTC_ERR_OOM = -101

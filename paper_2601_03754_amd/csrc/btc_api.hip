@@ -67,7 +67,8 @@ BTC_API int btc_create(int64_t N, int64_t n, const btc_options* opt, btc_handle*
     h->N = N;
     h->n = n;
     h->precision = prec;
-    h->max_refine = (opt && opt->max_refine > 0) ? opt->max_refine : BTC_DEFAULT_MAX_REFINE;
+    h->max_refine = (opt && opt->max_refine > 0) ? opt->max_refine
+                                                  : (is_bf16(prec) ? BTC_DEFAULT_MAX_REFINE_BF16 : BTC_DEFAULT_MAX_REFINE);
     h->tol = (opt && opt->tol > 0.0) ? opt->tol : BTC_DEFAULT_TOL;
     h->levels = num_levels(N);
     (void)hipGetDevice(&h->device);

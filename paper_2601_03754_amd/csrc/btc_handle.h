@@ -64,7 +64,8 @@ struct btc_handle_s {
 
 namespace btc_host {
 
-inline bool is_mixed(int32_t p) { return p == BTC_FP32_IR; }
+inline bool is_mixed(int32_t p) { return p == BTC_FP32_IR || p == BTC_BF16_IR; }
+inline bool is_bf16(int32_t p) { return p == BTC_BF16_IR; }
 
 inline int num_levels(int64_t N) {
     int L = 0;
@@ -258,12 +259,13 @@ void tune_set(int op, int kind, int np, int bucket, int variant);
 
 // Factor kernel family of a handle at a level: 0 VALU FP64 (np < 16, or
 // np 16/32 where the autotuner chose it), 1 MFMA FP64, 2 mixed,
-// 3 tile-parallel FP64 (np > 64), 4 tile-parallel mixed.
+// 3 tile-parallel FP64 (np > 64), 4 tile-parallel mixed, 5 mixed with BF16
+// products, 6 tile-parallel mixed with BF16 products.
 inline int factor_kind(btc_handle h, int level) {
     const int np = factor_np(h);
     const bool mixed = is_mixed(h->precision);
-    if (np > 64) return mixed ? 4 : 3;
-    if (mixed) return 2;
+    if (np > 64) return mixed ? (is_bf16(h->precision) ? 6 : 4) : 3;
+    if (mixed) return is_bf16(h->precision) ? 5 : 2;
     if (np < 16) return 0;
     if (np <= 32 && tune_variant(BTC_OP_FACTOR, 0, np, level > 0 ? 1 : 0) == 1) return 0;
     return 1;
@@ -281,9 +283,11 @@ inline hipError_t launch_factor_kind(int kind, const btc::Launch<btc::FactorDesc
     switch (kind) {
         case 0: return btc::launch_factor_valu(L, np, items, st);
         case 1: return btc::launch_factor_mfma(L, np, items, st);
-        case 2: return btc::launch_factor_mixed(L, np, items, st);
-        case 3: return btc::launch_factor_tiled(L, np, false, level_hint, items, st);
-        case 4: return btc::launch_factor_tiled(L, np, true, level_hint, items, st);
+        case 2: return btc::launch_factor_mixed(L, np, false, items, st);
+        case 3: return btc::launch_factor_tiled(L, np, 0, level_hint, items, st);
+        case 4: return btc::launch_factor_tiled(L, np, 1, level_hint, items, st);
+        case 5: return btc::launch_factor_mixed(L, np, true, items, st);
+        case 6: return btc::launch_factor_tiled(L, np, 2, level_hint, items, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -132,10 +132,12 @@ int padded_block_mixed(int n);
 
 hipError_t launch_factor_valu(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st);
 hipError_t launch_factor_mfma(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st);
-hipError_t launch_factor_mixed(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st);
+// bf16: Schur / fill products with BF16 operands (FP32 accumulation)
+hipError_t launch_factor_mixed(const Launch<FactorDesc>& p, int np, bool bf16, int64_t items, hipStream_t st);
 // Padded sizes 96 and 128: four tile-parallel launches per level (level_hint
 // 0 skips the deferred-update launch, which has nothing to do at level 0).
-hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, bool mixed, int level_hint, int64_t items,
+// mode: 0 FP64, 1 mixed, 2 mixed with BF16 Schur / fill products.
+hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, int mode, int level_hint, int64_t items,
                                hipStream_t st);
 // mc: right-hand-side columns per dependency-chain group (1 or 4; with 4,
 // instances with fewer columns mask the rest).

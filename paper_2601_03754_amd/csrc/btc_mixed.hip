@@ -8,7 +8,10 @@
 //     and the fill-in couplings;
 //   * the triangular solves and the Schur/fill products run on FP32 matrix
 //     cores (v_mfma_f32_16x16x4f32, FP32 accumulation); each FP32 Schur
-//     product is subtracted into the FP64 block it updates.
+//     product is subtracted into the FP64 block it updates;
+//   * BF16 variant: the Schur/fill products (syrk, gemm) take BF16 operands
+//     rounded to nearest even (v_mfma_f32_16x16x32_bf16, FP32 accumulation);
+//     the triangular solves stay FP32.
 // The accuracy lost to FP32 is won back by FP64 iterative refinement of the
 // solution (residual computed in FP64 from the original blocks).
 #include "btc_device.h"
@@ -42,7 +45,7 @@ __device__ __forceinline__ void tile64_store_global_acc32(const double* __restri
     }
 }
 
-template <int NP>
+template <int NP, bool BF16>
 __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(Launch<FactorDesc> L) {
     using Cfg = MixCfg<NP>;
     constexpr int W = Cfg::W, NT = Cfg::NT, LD = NP + 1;
@@ -114,12 +117,12 @@ __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(Launch<Fa
             tri_tile(k, ta, tb);
             if (def_self) {
                 f4 acc = {0.f, 0.f, 0.f, 0.f};
-                mma_tile32<LD, LD, true, false, false>(acc, fB, ta * kT, 0, fB, tb * kT, 0, NP);
+                mma_prod<BF16, LD, LD, true, false, false>(acc, fB, ta * kT, 0, fB, tb * kT, 0, NP);
                 acc32_sub_from_lds64<LD>(acc, sS, ta * kT, tb * kT);
             }
             if (def_sep) {
                 f4 acc = {0.f, 0.f, 0.f, 0.f};
-                mma_tile32<LD, LD, true, false, false>(acc, fD, ta * kT, 0, fD, tb * kT, 0, NP);
+                mma_prod<BF16, LD, LD, true, false, false>(acc, fD, ta * kT, 0, fD, tb * kT, 0, NP);
                 acc32_sub_from_lds64<LD>(acc, sC, ta * kT, tb * kT);
             }
         }
@@ -185,7 +188,7 @@ __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(Launch<Fa
                 int ta, tb;
                 tri_tile(k, ta, tb);
                 f4 acc = {0.f, 0.f, 0.f, 0.f};
-                mma_tile32<LD, LD, false, true, false>(acc, fB, ta * kT, 0, fB, tb * kT, 0, NP);
+                mma_prod<BF16, LD, LD, false, true, false>(acc, fB, ta * kT, 0, fB, tb * kT, 0, NP);
                 acc32_sub_from_lds64<LD>(acc, sC, ta * kT, tb * kT);
                 tile64_store_global_acc32<LD>(sC, P.Ld + (size_t)pr * nn, n, ta * kT, tb * kT);
             }
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(Launch<Fa
 #pragma unroll
         for (int t = 0; t < W; ++t) {
             f4 acc = {0.f, 0.f, 0.f, 0.f};
-            mma_tile32<LD, LD, false, false, true>(acc, fB, w * kT, 0, fD, t * kT, 0, NP);
+            mma_prod<BF16, LD, LD, false, false, true>(acc, fB, w * kT, 0, fD, t * kT, 0, NP);
             acc32_store_global(acc, dst, n, w * kT, t * kT);
         }
     }
@@ -215,12 +218,21 @@ int padded_block_mixed(int n) {
     return (np != 0 && np < 16) ? 16 : np;
 }
 
-hipError_t launch_factor_mixed(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st) {
+hipError_t launch_factor_mixed(const Launch<FactorDesc>& p, int np, bool bf16, int64_t items, hipStream_t st) {
     const dim3 g((unsigned)items);
     switch (np) {
-        case 16: hipLaunchKernelGGL(k_factor_level_mixed<16>, g, dim3(MixCfg<16>::NT), 0, st, p); break;
-        case 32: hipLaunchKernelGGL(k_factor_level_mixed<32>, g, dim3(MixCfg<32>::NT), 0, st, p); break;
-        case 64: hipLaunchKernelGGL(k_factor_level_mixed<64>, g, dim3(MixCfg<64>::NT), 0, st, p); break;
+        case 16:
+            if (bf16) hipLaunchKernelGGL((k_factor_level_mixed<16, true>), g, dim3(MixCfg<16>::NT), 0, st, p);
+            else hipLaunchKernelGGL((k_factor_level_mixed<16, false>), g, dim3(MixCfg<16>::NT), 0, st, p);
+            break;
+        case 32:
+            if (bf16) hipLaunchKernelGGL((k_factor_level_mixed<32, true>), g, dim3(MixCfg<32>::NT), 0, st, p);
+            else hipLaunchKernelGGL((k_factor_level_mixed<32, false>), g, dim3(MixCfg<32>::NT), 0, st, p);
+            break;
+        case 64:
+            if (bf16) hipLaunchKernelGGL((k_factor_level_mixed<64, true>), g, dim3(MixCfg<64>::NT), 0, st, p);
+            else hipLaunchKernelGGL((k_factor_level_mixed<64, false>), g, dim3(MixCfg<64>::NT), 0, st, p);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

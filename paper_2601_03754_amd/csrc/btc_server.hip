@@ -260,7 +260,8 @@ BTC_API int btc_server_create(const btc_server_options* opt, void* stream, btc_s
     btc_server s = new (std::nothrow) btc_server_s();
     if (!s) return BTC_ERR_OOM;
     s->opt = *opt;
-    if (s->opt.max_refine == 0) s->opt.max_refine = BTC_DEFAULT_MAX_REFINE;
+    if (s->opt.max_refine == 0)
+        s->opt.max_refine = is_bf16(s->opt.precision) ? BTC_DEFAULT_MAX_REFINE_BF16 : BTC_DEFAULT_MAX_REFINE;
     if (s->opt.tol == 0.0) s->opt.tol = BTC_DEFAULT_TOL;
     if (s->opt.max_active == 0) s->opt.max_active = 1 << 20;
     s->st = (hipStream_t)stream;

@@ -16,7 +16,9 @@
 //   K4  one 256-thread workgroup per 32 x 32 tile of S_{i+s} -= R_i R_i^T
 //       (lower tiles) and of the fill -R_i T_i
 // In mixed precision the Schur complements and K2 stay FP64 and the products
-// of K1, K3, K4 run on FP32 matrix cores (FP32 factor storage).
+// of K1, K3, K4 run on FP32 matrix cores (FP32 factor storage); the BF16
+// variant rounds the operands of the K1 and K4 products to BF16 (FP32
+// accumulation).
 #pragma once
 
 #include "btc_device.h"
@@ -149,7 +151,7 @@ __device__ __forceinline__ void stage_lower(double* __restrict__ dst, const doub
 
 // ---------------------------------------------------------------------------
 // K1: deferred syrk.  blockIdx.y < NTRI32: tile of S_i; else tile of S_{i+s}.
-template <int NP, bool MIXED>
+template <int NP, bool MIXED, bool BF16>
 __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> L) {
     using Pr = Prec<MIXED>;
     using F = typename Pr::F;
@@ -178,9 +180,14 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
     if (a == b && sr < sc) return;  // strictly upper sub-tile
     typename Pr::Acc acc = {};
     const int i = lane & 15, q = lane >> 4;
+    if constexpr (BF16) {
+        // (T^T T) tile with BF16 operands: A[r][k] = T[k][r], B[k][c] = T[k][c]
+        mma_tile_bf16<LDP, LDP, true, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
+    } else {
 #pragma unroll 4
-    for (int k = 0; k < NP; k += 4)
-        acc = Pr::mma(pa[(k + q) * LDP + 16 * sr + i], pb[(k + q) * LDP + 16 * sc + i], acc);
+        for (int k = 0; k < NP; k += 4)
+            acc = Pr::mma(pa[(k + q) * LDP + 16 * sr + i], pb[(k + q) * LDP + 16 * sc + i], acc);
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int r = 32 * a + 16 * sr + Pr::row(v, lane), c = 32 * b + 16 * sc + (lane & 15);
@@ -351,7 +358,7 @@ __global__ __launch_bounds__(64) void k_tiled_trsm(Launch<FactorDesc> L) {
 // ---------------------------------------------------------------------------
 // K4: blockIdx.y < NTRI32: lower tile of S_{i+s} -= R R^T; else fill tile
 // -R T (row-major over the W32 x W32 tiles).
-template <int NP, bool MIXED>
+template <int NP, bool MIXED, bool BF16>
 __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     using Pr = Prec<MIXED>;
     using F = typename Pr::F;
@@ -389,11 +396,19 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     if (sep && a == b && sr < sc) return;
     typename Pr::Acc acc = {};
     const int i = lane & 15, q = lane >> 4;
+    if constexpr (BF16) {
+        // R R^T (B[k][c] = R[c][k]) or R T (B[k][c] = T[k][c]) with BF16 operands
+        if (sep)
+            mma_tile_bf16<LDR, LDR, false, true, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
+        else
+            mma_tile_bf16<LDR, LDP, false, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
+    } else {
 #pragma unroll 4
-    for (int k = 0; k < NP; k += 4) {
-        const F av = pa[(16 * sr + i) * LDR + k + q];
-        const F bv = sep ? pb[(16 * sc + i) * LDR + k + q] : pb[(k + q) * LDP + 16 * sc + i];
-        acc = Pr::mma(av, bv, acc);
+        for (int k = 0; k < NP; k += 4) {
+            const F av = pa[(16 * sr + i) * LDR + k + q];
+            const F bv = sep ? pb[(16 * sc + i) * LDR + k + q] : pb[(k + q) * LDP + 16 * sc + i];
+            acc = Pr::mma(av, bv, acc);
+        }
     }
     if (sep) {
         const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i + d.s - 1) * d.nn : P.Ld + (size_t)d.pr * d.nn;
@@ -415,23 +430,24 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     }
 }
 
-template <int NP, bool MIXED>
+template <int NP, bool MIXED, bool BF16>
 hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int level_hint, int64_t items, hipStream_t st) {
     using Cfg = TiledCfg<NP>;
     const unsigned g = (unsigned)items;
     if (level_hint != 0)  // level 0 has no deferred updates
-        hipLaunchKernelGGL((k_tiled_syrk_deferred<NP, MIXED>), dim3(g, 2 * Cfg::NTRI32), dim3(256), 0, st, p);
+        hipLaunchKernelGGL((k_tiled_syrk_deferred<NP, MIXED, BF16>), dim3(g, 2 * Cfg::NTRI32), dim3(256), 0, st, p);
     hipLaunchKernelGGL((k_tiled_potrf<NP, MIXED>), dim3(g), dim3(256), 0, st, p);
     hipLaunchKernelGGL((k_tiled_trsm<NP, MIXED>), dim3(g, 2 * Cfg::NT16), dim3(64), 0, st, p);
-    hipLaunchKernelGGL((k_tiled_update<NP, MIXED>), dim3(g, Cfg::NTRI32 + Cfg::W32 * Cfg::W32), dim3(256), 0, st,
-                       p);
+    hipLaunchKernelGGL((k_tiled_update<NP, MIXED, BF16>), dim3(g, Cfg::NTRI32 + Cfg::W32 * Cfg::W32), dim3(256), 0,
+                       st, p);
     return hipGetLastError();
 }
 
 }  // namespace
 
 // Per padded size launchers (one translation unit each).
-hipError_t launch_factor_tiled96(const Launch<FactorDesc>& p, bool mixed, int level_hint, int64_t items, hipStream_t st);
-hipError_t launch_factor_tiled128(const Launch<FactorDesc>& p, bool mixed, int level_hint, int64_t items, hipStream_t st);
+// mode: 0 FP64, 1 mixed (FP32 products), 2 mixed with BF16 Schur / fill products
+hipError_t launch_factor_tiled96(const Launch<FactorDesc>& p, int mode, int level_hint, int64_t items, hipStream_t st);
+hipError_t launch_factor_tiled128(const Launch<FactorDesc>& p, int mode, int level_hint, int64_t items, hipStream_t st);
 
 }  // namespace btc

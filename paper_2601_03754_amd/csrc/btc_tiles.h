@@ -17,6 +17,7 @@ namespace btc {
 namespace tiles {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -287,6 +288,43 @@ __device__ __forceinline__ void mma_tile32(f4& acc, const float* __restrict__ A,
         if (NEG) a = -a;
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
     }
+}
+
+// acc += (NEG ? -1 : 1) * sum_{kk<K} opA[ra+i][ka+kk] * opB[kb+kk][cb+j] with the
+// operands rounded to BF16 (round to nearest even) and FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)+e] and
+// B[8(l/16)+e][l%16], e < 8; accumulator layout as the FP32 tiles).  K is
+// padded with zeros to a multiple of 32.
+template <int LDA, int LDB, bool TA, bool TB, bool NEG>
+__device__ __forceinline__ void mma_tile_bf16(f4& acc, const float* __restrict__ A, int ra, int ka,
+                                              const float* __restrict__ B, int cb, int kb, int K) {
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 15, q = lane >> 4;
+    for (int kk = 0; kk < K; kk += 32) {
+        bf8 a, b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = kk + 8 * q + e;
+            float av = 0.f, bv = 0.f;
+            if (k < K) {
+                av = TA ? A[(ka + k) * LDA + ra + i] : A[(ra + i) * LDA + ka + k];
+                bv = TB ? B[(cb + i) * LDB + kb + k] : B[(kb + k) * LDB + cb + i];
+            }
+            a[e] = (__bf16)(NEG ? -av : av);
+            b[e] = (__bf16)bv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+}
+
+// Schur / fill product of the mixed kernels: FP32 or BF16 operands.
+template <bool BF16, int LDA, int LDB, bool TA, bool TB, bool NEG>
+__device__ __forceinline__ void mma_prod(f4& acc, const float* __restrict__ A, int ra, int ka,
+                                         const float* __restrict__ B, int cb, int kb, int K) {
+    if constexpr (BF16)
+        mma_tile_bf16<LDA, LDB, TA, TB, NEG>(acc, A, ra, ka, B, cb, kb, K);
+    else
+        mma_tile32<LDA, LDB, TA, TB, NEG>(acc, A, ra, ka, B, cb, kb, K);
 }
 
 template <int LD>

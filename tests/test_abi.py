@@ -181,3 +181,9 @@ def test_tune_table_host_only(lib):
     assert L.btc_tune_get(0, 0, 8, -1, ctypes.byref(v)) == -4
     assert L.btc_tune_set(R, 0, 8, 0, 2) == -5
     assert L.btc_autotune(None, None, None, None, None, 1, 1, None) == -1
+
+
+def test_bf16_footprint_matches_mixed(lib):
+    for n in (8, 40, 100):
+        assert lib.btc_footprint_bytes(33, n, lib.BTC_BF16_IR, 2) == lib.btc_footprint_bytes(33, n, lib.BTC_FP32_IR, 2)
+    assert lib.btc_footprint_bytes(33, 8, 3, 2) == 0
