@@ -84,8 +84,6 @@ BTC_API int btc_create(int64_t N, int64_t n, const btc_options* opt, btc_handle*
         if (e == hipSuccess) e = hipMalloc(&h->Rb, nn * sizeof(double));
         if (e == hipSuccess) e = hipMalloc(&h->Tb, nn * sizeof(double));
     }
-    const size_t dinv = dinv_bytes(N, n, prec);
-    if (e == hipSuccess && dinv > 0) e = hipMalloc(&h->Dinv, dinv);
     if (e != hipSuccess) {
         free_all(h);
         delete h;

@@ -39,9 +39,6 @@ struct btc_handle_s {
     float* R32 = nullptr;
     float* T32 = nullptr;
     unsigned long long* info = nullptr;
-    // large blocks (padded 96/128): inverted 16 x 16 diagonal tiles of each
-    // L_ii, produced and consumed within one factorization level step
-    void* Dinv = nullptr;
     // solve workspace, grown on demand (one allocation)
     void* ws = nullptr;
     int64_t ws_m = 0;
@@ -102,7 +99,6 @@ inline void free_all(btc_handle h) {
     dfree(h->Ld);
     dfree(h->Rb);
     dfree(h->Tb);
-    dfree(h->Dinv);
     dfree(h->S64);
     dfree(h->L32);
     dfree(h->R32);
@@ -149,18 +145,10 @@ inline void drain_profile(btc_handle h) {
     h->pending.clear();
 }
 
-// Inverted diagonal tiles of the tile-parallel factorization (padded block
-// sizes above 64 only): NP/16 tiles of 16 x 16 per node, in the factor's type.
-inline size_t dinv_bytes(int64_t N, int64_t n, int32_t prec) {
-    const int np = btc::padded_block((int)n);
-    if (np <= 64) return 0;
-    return (size_t)N * (size_t)(np / 16) * 256 * (is_mixed(prec) ? sizeof(float) : sizeof(double));
-}
-
 inline size_t factor_bytes(int64_t N, int64_t n, int32_t prec) {
     const size_t nn = (size_t)N * (size_t)n * (size_t)n;
-    if (is_mixed(prec)) return nn * (sizeof(double) + 3 * sizeof(float)) + dinv_bytes(N, n, prec);
-    return 3 * nn * sizeof(double) + dinv_bytes(N, n, prec);
+    if (is_mixed(prec)) return nn * (sizeof(double) + 3 * sizeof(float));
+    return 3 * nn * sizeof(double);
 }
 
 // Solve workspace: FP64 path: Y, U, V (FP64); mixed: r, y, u, v, d (FP32);
@@ -242,7 +230,6 @@ inline btc::FactorDesc factor_desc(btc_handle h, const double* A_diag, const dou
         d.Tb = h->Tb;
     }
     d.info = h->info;
-    d.Dinv = h->Dinv;
     d.N = h->N;
     d.n = (int32_t)h->n;
     return d;

@@ -57,7 +57,6 @@ struct FactorDesc {
     float* R32;
     float* T32;
     unsigned long long* info;  // ~0 = ok, else smallest failing 1-based block
-    void* Dinv;                // large blocks: inverted 16 x 16 diagonal tiles of L_ii (F), per node
     int64_t N;
     int32_t n;
     int32_t pad;

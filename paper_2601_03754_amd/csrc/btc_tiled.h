@@ -2,17 +2,16 @@
 // and 128), FP64 or mixed precision.
 //
 // A node whose four n x n blocks no longer fit in LDS together is split over
-// several workgroups and four launches per level (the same per-node algebra
-// as the single-kernel paths, Algorithm 4):
+// three launches per level (the same per-node algebra as the single-kernel
+// paths, Algorithm 4):
 //   K1  deferred syrk: S_i -= T'^T T' and S_{i+s} -= T''^T T'', one 256-thread
 //       workgroup per 32 x 32 lower tile (panels of T' staged in LDS)
 //   K2  one workgroup per node: the whole pivot block in LDS (FP64), blocked
 //       Cholesky in 16-column panels (diagonal tiles factored and inverted by
-//       one wavefront, panel and trailing updates on the matrix cores), the
-//       inverted 16 x 16 diagonal tiles written to a per-node scratch
-//   K3  one wavefront per 16-row strip of R_i = C_{i+s,i} L_ii^{-T} and per
-//       16-column strip of T_i = L_ii^{-1} C_{i,i-s}: blocked substitution over
-//       the tiles with the inverted diagonal tiles (all products MFMA)
+//       one wavefront, panel and trailing updates on the matrix cores), then
+//       R_i = C_{i+s,i} L_ii^{-T} and T_i = L_ii^{-1} C_{i,i-s} strip by strip
+//       (one 16-row or 16-column strip per wavefront at a time, blocked
+//       substitution with the inverted diagonal tiles, all products MFMA)
 //   K4  one 256-thread workgroup per 32 x 32 tile of S_{i+s} -= R_i R_i^T
 //       (lower tiles) and of the fill -R_i T_i
 // In mixed precision the Schur complements and K2 stay FP64 and the products
@@ -196,15 +195,26 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
 }
 
 // ---------------------------------------------------------------------------
-// K2: pivot block factorization and inverted diagonal tiles.
+// K2: pivot block factorization and the two triangular solves, one
+// workgroup (four wavefronts) per node.  S_i is staged in LDS and factored
+// by the blocked Cholesky (which also leaves the inverted 16 x 16 diagonal
+// tiles in LDS); L_ii is stored; then every wavefront solves 16-row strips
+// of R_i = C_{i+s,i} L_ii^{-T} and 16-column strips of T_i = L_ii^{-1} C_{i,i-s}
+// tile by tile: X_p = (C_p - sum_{q<p} X_q L_pq^T) Dinv_p^T for R (the
+// transposed products for T), the solved tiles held in registers and passed
+// to the matrix cores through a one-tile LDS scratch per wavefront, the
+// coupling tiles read straight from HBM into the accumulator layout.
 template <int NP, bool MIXED>
-__global__ __launch_bounds__(256) void k_tiled_potrf(Launch<FactorDesc> L) {
+__global__ __launch_bounds__(256) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
     using Pr = Prec<MIXED>;
     using F = typename Pr::F;
+    using Acc = typename Pr::Acc;
     using Cfg = TiledCfg<NP>;
     constexpr int LD = NP + 1;
+    constexpr int NT16 = Cfg::NT16;
     __shared__ double sS[NP * LD];
-    __shared__ double sInv[Cfg::NT16][kT * kLDI];
+    __shared__ double sInv[NT16][kT * kLDI];
+    __shared__ F sTile[4][kT * kLDI];
     __shared__ double invd[NP];
     __shared__ __align__(16) double colbuf[2][kWave];
     __shared__ int fail;
@@ -214,9 +224,10 @@ __global__ __launch_bounds__(256) void k_tiled_potrf(Launch<FactorDesc> L) {
     fetch_item(L, P, lvl, kk);
     if (*P.info != kInfoOk) return;
     const Node d = node_of(P, lvl, kk);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid & 63;
+    const int n = d.n;
     const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i - 1) * d.nn : P.Ld + (size_t)d.pi * d.nn;
-    stage_lower<NP, 256>(sS, src, d.n, tid);
+    stage_lower<NP, 256>(sS, src, n, tid);
     if (tid == 0) fail = 0;
     __syncthreads();
     const bool ok = potrf_blocked<NP, LD, 4>(sS, invd, sInv, colbuf, &fail);
@@ -224,133 +235,75 @@ __global__ __launch_bounds__(256) void k_tiled_potrf(Launch<FactorDesc> L) {
         if (tid == 0) atomicMin(P.info, (unsigned long long)d.i);
         return;
     }
-    // L (lower) and the inverted diagonal tiles
-    lds_store_as<NP, F, double>(Pr::Lf(P) + (size_t)d.pi * d.nn, sS, d.n, true, tid, 256);
-    F* dinv = (F*)P.Dinv + (size_t)d.pi * Cfg::NT16 * kT * kT;
-    for (int e = tid; e < Cfg::NT16 * kT * kT; e += 256) {
-        const int t = e / (kT * kT), r = (e / kT) % kT, c = e % kT;
-        dinv[e] = (F)sInv[t][r * kLDI + c];
-    }
-}
+    lds_store_as<NP, F, double>(Pr::Lf(P) + (size_t)d.pi * d.nn, sS, n, true, tid, 256);
 
-// ---------------------------------------------------------------------------
-// K3: triangular-solve strips (one wavefront each).  blockIdx.y < NT16:
-// rows [16y, 16y+16) of R; else columns [16(y-NT16), ...) of T.
-template <int NP, bool MIXED>
-__global__ __launch_bounds__(64) void k_tiled_trsm(Launch<FactorDesc> L) {
-    using Pr = Prec<MIXED>;
-    using F = typename Pr::F;
-    using Acc = typename Pr::Acc;
-    using Cfg = TiledCfg<NP>;
-    constexpr int LDX = NP + 1;  // R strip: [16][NP];  T strip: [NP][17] (stride kLDI)
-    __shared__ F sX[kT * LDX > NP * kLDI ? kT * LDX : NP * kLDI];
-    __shared__ F sLt[kT * kLDI];
-    __shared__ F sDi[kT * kLDI];
-    FactorDesc P;
-    int lvl;
-    int64_t kk;
-    fetch_item(L, P, lvl, kk);
-    if (*P.info != kInfoOk) return;
-    const Node d = node_of(P, lvl, kk);
-    const bool isR = (int)blockIdx.y < Cfg::NT16;
-    if (isR ? !d.has_r : !d.has_l) return;
-    const int t = isR ? blockIdx.y : blockIdx.y - Cfg::NT16;
-    const int lane = threadIdx.x, i = lane & 15, q4 = lane >> 4;
-    const int n = d.n;
-    const F* Lg = Pr::Lf(P) + (size_t)d.pi * d.nn;
-    const F* Dg = (const F*)P.Dinv + (size_t)d.pi * Cfg::NT16 * kT * kT;
-    F* dst = (isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn;
-    // stage the strip of the coupling
-    if (lvl == 0) {
-        const double* C = P.A_off + (size_t)(isR ? d.i - 1 : d.i - 2) * d.nn;
-        if (isR)
-            stage_panel<NP, kT, LDX, false, 64>(sX, C, n, kT * t, lane);
-        else
-            stage_panel<NP, kT, kLDI, true, 64>(sX, C, n, kT * t, lane);
-    } else {
-        if (isR)
-            stage_panel<NP, kT, LDX, false, 64>(sX, dst, n, kT * t, lane);
-        else
-            stage_panel<NP, kT, kLDI, true, 64>(sX, dst, n, kT * t, lane);
-    }
-    wave_lds_sync();
-    auto stage_tile = [&](F* s16, const F* g, int r0, int c0, bool unit_pad) {
-        for (int e = lane; e < kT * kT; e += 64) {
-            const int r = e / kT, c = e % kT, gr = r0 + r, gc = c0 + c;
-            F v = (unit_pad && gr == gc) ? F(1) : F(0);
-            if (gr < n && gc < n) v = g[(size_t)gr * n + gc];
-            s16[r * kLDI + c] = v;
-        }
-    };
-    for (int p = 0; p < Cfg::NT16; ++p) {
-        Acc acc;
+    const int i = lane & 15, q4 = lane >> 4;
+    F* tile = sTile[w];
+    auto put = [&](const Acc& x) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = Pr::row(v, lane), c = lane & 15;
-            acc[v] = isR ? sX[r * LDX + kT * p + c] : sX[(kT * p + r) * kLDI + c];
-        }
-        for (int qq = 0; qq < p; ++qq) {
-            stage_tile(sLt, Lg, kT * p, kT * qq, false);  // L[p, qq]
-            wave_lds_sync();
+        for (int v = 0; v < 4; ++v) tile[Pr::row(v, lane) * kLDI + i] = x[v];
+        wave_lds_sync();
+    };
+    for (int sidx = w; sidx < 2 * NT16; sidx += 4) {
+        const bool isR = sidx < NT16;
+        const int t = isR ? sidx : sidx - NT16;
+        if (isR ? !d.has_r : !d.has_l) continue;
+        F* dst = (isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn;
+        const double* C64 = (lvl == 0) ? P.A_off + (size_t)(isR ? d.i - 1 : d.i - 2) * d.nn : nullptr;
+        const F* Cf = dst;  // levels above 0: the incoming coupling sits in the output slot
+        Acc X[NT16];
+#pragma unroll
+        for (int p = 0; p < NT16; ++p) {
+            Acc acc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = Pr::row(v, lane);
+                const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
+                F x = F(0);
+                if (gr < n && gc < n) x = C64 ? (F)C64[(size_t)gr * n + gc] : Cf[(size_t)gr * n + gc];
+                acc[v] = x;
+            }
+#pragma unroll
+            for (int qq = 0; qq < p; ++qq) {
+                put(X[qq]);
+#pragma unroll
+                for (int k = 0; k < kT; k += 4) {
+                    F a, b;
+                    const F l = (F)sS[(kT * p + i) * LD + kT * qq + k + q4];  // L[16p+i][16qq+k+q4]
+                    if (isR) {  // - X_qq L_p,qq^T
+                        a = tile[i * kLDI + k + q4];
+                        b = l;
+                    } else {    // - L_p,qq X_qq
+                        a = l;
+                        b = tile[(k + q4) * kLDI + i];
+                    }
+                    acc = Pr::mma(-a, b, acc);
+                }
+                wave_lds_sync();
+            }
+            put(acc);
+            Acc out = {};
 #pragma unroll
             for (int k = 0; k < kT; k += 4) {
+                const F dv = (F)sInv[p][i * kLDI + k + q4];  // Dinv_p[i][k+q4]
                 F a, b;
-                if (isR) {  // - X[:, qq] L[p, qq]^T
-                    a = sX[i * LDX + kT * qq + k + q4];
-                    b = sLt[i * kLDI + k + q4];
-                } else {    // - L[p, qq] X[qq, :]
-                    a = sLt[i * kLDI + k + q4];
-                    b = sX[(kT * qq + k + q4) * kLDI + i];
+                if (isR) {  // Y Dinv_p^T
+                    a = tile[i * kLDI + k + q4];
+                    b = dv;
+                } else {    // Dinv_p Y
+                    a = dv;
+                    b = tile[(k + q4) * kLDI + i];
                 }
-                acc = Pr::mma(-a, b, acc);
+                out = Pr::mma(a, b, out);
             }
             wave_lds_sync();
-        }
-        // Y -> strip tile; then multiply by the inverted diagonal tile
+            X[p] = out;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = Pr::row(v, lane), c = lane & 15;
-            if (isR)
-                sX[r * LDX + kT * p + c] = acc[v];
-            else
-                sX[(kT * p + r) * kLDI + c] = acc[v];
-        }
-        for (int e = lane; e < kT * kT; e += 64) sDi[(e / kT) * kLDI + e % kT] = Dg[(size_t)p * kT * kT + e];
-        wave_lds_sync();
-        Acc out = {};
-#pragma unroll
-        for (int k = 0; k < kT; k += 4) {
-            F a, b;
-            if (isR) {  // Y Dinv_p^T
-                a = sX[i * LDX + kT * p + k + q4];
-                b = sDi[i * kLDI + k + q4];
-            } else {    // Dinv_p Y
-                a = sDi[i * kLDI + k + q4];
-                b = sX[(kT * p + k + q4) * kLDI + i];
+            for (int v = 0; v < 4; ++v) {
+                const int rr = Pr::row(v, lane);
+                const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
+                if (gr < n && gc < n) dst[(size_t)gr * n + gc] = out[v];
             }
-            out = Pr::mma(a, b, out);
-        }
-        wave_lds_sync();
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = Pr::row(v, lane), c = lane & 15;
-            if (isR)
-                sX[r * LDX + kT * p + c] = out[v];
-            else
-                sX[(kT * p + r) * kLDI + c] = out[v];
-        }
-        wave_lds_sync();
-    }
-    // write the strip back
-    if (isR) {
-        for (int e = lane; e < kT * NP; e += 64) {
-            const int r = e / NP, c = e % NP, gr = kT * t + r;
-            if (gr < n && c < n) dst[(size_t)gr * n + c] = sX[r * LDX + c];
-        }
-    } else {
-        for (int e = lane; e < NP * kT; e += 64) {
-            const int r = e / kT, c = e % kT, gc = kT * t + c;
-            if (r < n && gc < n) dst[(size_t)r * n + gc] = sX[r * kLDI + c];
         }
     }
 }
@@ -436,8 +389,7 @@ hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int level_hint, int64_t 
     const unsigned g = (unsigned)items;
     if (level_hint != 0)  // level 0 has no deferred updates
         hipLaunchKernelGGL((k_tiled_syrk_deferred<NP, MIXED, BF16>), dim3(g, 2 * Cfg::NTRI32), dim3(256), 0, st, p);
-    hipLaunchKernelGGL((k_tiled_potrf<NP, MIXED>), dim3(g), dim3(256), 0, st, p);
-    hipLaunchKernelGGL((k_tiled_trsm<NP, MIXED>), dim3(g, 2 * Cfg::NT16), dim3(64), 0, st, p);
+    hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED>), dim3(g), dim3(256), 0, st, p);
     hipLaunchKernelGGL((k_tiled_update<NP, MIXED, BF16>), dim3(g, Cfg::NTRI32 + Cfg::W32 * Cfg::W32), dim3(256), 0,
                        st, p);
     return hipGetLastError();
