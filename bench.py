@@ -51,7 +51,9 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 OPS = {0: "factor", 1: "forward", 2: "backward", 3: "residual", 4: "refine_init", 5: "refine_test"}
-FACTOR_KIND = {0: "fp64 valu", 1: "fp64 mfma", 2: "mixed", 3: "fp64 tiled", 4: "mixed tiled"}
+FACTOR_KIND = {0: "fp64 valu", 1: "fp64 mfma", 2: "mixed", 3: "fp64 tiled", 4: "mixed tiled", 5: "mixed bf16",
+               6: "mixed bf16 tiled"}
+TILED_PART = {1: "k_tiled_syrk_deferred", 2: "k_tiled_potrf_trsm", 3: "k_tiled_update"}
 SOLVE_FRAC = 0.7
 RELRES_TARGET = 1e-10
 
@@ -103,6 +105,8 @@ def roofline_entry(stat):
     kind = FACTOR_KIND.get(stat["kind"], str(stat["kind"])) if stat["op"] == 0 else \
         ("fp32" if stat["kind"] == 1 else "fp64") if stat["op"] in (1, 2) else "fp64"
     r["kernel"] = "%s %s np=%d" % (OPS[stat["op"]], kind, stat["np"])
+    if stat.get("part"):
+        r["kernel"] += " " + TILED_PART[stat["part"]]
     return r
 
 
@@ -245,7 +249,8 @@ def run_served(args, btc):
         btc.runner_profile(rh, dom["op"], dom["kind"])
         done, wall = sv.closed_loop(per_step * args.steps)
         allstats = btc.runner_profile_read(rh)
-        tstats = [s for s in allstats if (s["op"], s["kind"], s["np"]) == (dom["op"], dom["kind"], dom["np"])]
+        tstats = [s for s in allstats
+                  if (s["op"], s["kind"], s["np"], s["part"]) == (dom["op"], dom["kind"], dom["np"], dom["part"])]
         btc.runner_profile(rh, -2, -1)
         lat = lat_ms(done)
         relres = sv.verify()

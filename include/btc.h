@@ -289,12 +289,14 @@ BTC_API int btc_graph_launch(btc_graph g, void *stream);
 BTC_API void btc_graph_destroy(btc_graph g);
 
 /*
- * Autotuned kernel variants (a process-wide table, default 0 everywhere),
+ * Autotuned kernel variants (a process-wide table; until set, variant 1 for
+ * the factor at n 33..64 and 0 everywhere else),
  * keyed by operation, precision, block size n (through its padded size) and
  * level (bucket: level 0, levels >= 1):
  *   BTC_OP_FACTOR, BTC_FP64, n 9..32: 0 matrix-core kernel, 1 vector-ALU
- *     kernel (a different rounding order: results change at round-off level
- *     when the choice changes)
+ *     kernel; any precision, n 33..64: 0 one workgroup per node, 1 the
+ *     tile-parallel level step (different rounding orders: results change at
+ *     round-off level when the choice changes)
  *   BTC_OP_FORWARD / BACKWARD / RESIDUAL (nrhs > 1; level ignored): 0 four
  *     right-hand-side columns per dependency-chain group, 1 one (identical
  *     results)
@@ -327,14 +329,16 @@ BTC_API int btc_autotune(btc_handle h, const double *A_diag, const double *A_off
  *   clears the totals.
  *   btc_runner_profile_read(r, out, max, count): synchronises and writes up
  *   to max totals (host array), largest time first, then clears them.
- * A tile-parallel factor group is several kernels; its pair of events
- * brackets all of them.
+ * A timed tile-parallel factor group is timed kernel by kernel (part 1..3,
+ * each with its own algorithmic work: the kernels pass S and the factor
+ * blocks through HBM between them).
  */
 typedef struct {
     int32_t op;        /* btc_op */
     int32_t kind;      /* kernel family, as above */
     int32_t np;        /* padded block size of the kernel */
-    int32_t pad;
+    int32_t part;      /* tile-parallel factor, timed: 1 deferred syrk, 2 pivot factorization and
+                          triangular solves, 3 separator / fill products; else 0 (whole launch) */
     int64_t launches;
     int64_t items;     /* nodes (sweeps, factor), block rows (residual) */
     double ms;         /* summed event time (0 for groups not timed) */

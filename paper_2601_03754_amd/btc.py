@@ -55,7 +55,7 @@ class btc_server_options(ctypes.Structure):
 
 
 class btc_kernel_stat(ctypes.Structure):
-    _fields_ = [("op", i32), ("kind", i32), ("np", i32), ("pad", i32), ("launches", i64), ("items", i64),
+    _fields_ = [("op", i32), ("kind", i32), ("np", i32), ("part", i32), ("launches", i64), ("items", i64),
                 ("ms", dbl), ("bytes", dbl), ("flops", dbl)]
 
 
@@ -391,7 +391,8 @@ def runner_profile_read(r: int):
     buf = (btc_kernel_stat * 256)()
     cnt = i32()
     _check(lib().btc_runner_profile_read(r, buf, 256, ctypes.byref(cnt)), "btc_runner_profile_read")
-    return [{"op": b.op, "kind": b.kind, "np": b.np, "launches": b.launches, "items": b.items, "ms": b.ms,
+    return [{"op": b.op, "kind": b.kind, "np": b.np, "part": b.part, "launches": b.launches, "items": b.items,
+             "ms": b.ms,
              "bytes": b.bytes, "flops": b.flops} for b in buf[:cnt.value]]
 
 

@@ -246,15 +246,20 @@ void tune_set(int op, int kind, int np, int bucket, int variant);
 
 // Factor kernel family of a handle at a level: 0 VALU FP64 (np < 16, or
 // np 16/32 where the autotuner chose it), 1 MFMA FP64, 2 mixed,
-// 3 tile-parallel FP64 (np > 64), 4 tile-parallel mixed, 5 mixed with BF16
-// products, 6 tile-parallel mixed with BF16 products.
+// 3 tile-parallel FP64 (np > 64, or np 64 where the autotuner chose it),
+// 4 tile-parallel mixed, 5 mixed with BF16 products, 6 tile-parallel mixed
+// with BF16 products.
 inline int factor_kind(btc_handle h, int level) {
     const int np = factor_np(h);
     const bool mixed = is_mixed(h->precision);
-    if (np > 64) return mixed ? (is_bf16(h->precision) ? 6 : 4) : 3;
+    const int tiled = mixed ? (is_bf16(h->precision) ? 6 : 4) : 3;
+    if (np > 64) return tiled;
+    const int bucket = level > 0 ? 1 : 0;
+    if (np == 64 && tune_variant(BTC_OP_FACTOR, mixed ? (is_bf16(h->precision) ? 2 : 1) : 0, np, bucket) == 1)
+        return tiled;
     if (mixed) return is_bf16(h->precision) ? 5 : 2;
     if (np < 16) return 0;
-    if (np <= 32 && tune_variant(BTC_OP_FACTOR, 0, np, level > 0 ? 1 : 0) == 1) return 0;
+    if (np <= 32 && tune_variant(BTC_OP_FACTOR, 0, np, bucket) == 1) return 0;
     return 1;
 }
 
@@ -264,17 +269,18 @@ inline int sweep_mc(int op, int kind, int np, int64_t m) {
     return (m <= 1 || tune_variant(op, kind, np, 0) == 1) ? 1 : 4;
 }
 
-// level_hint: the level of every item of the launch, or -1 when they differ.
+// level_hint: the level of every item of the launch, or -1 when they differ;
+// part: tile-parallel families only, 0 the whole step or one of its kernels.
 inline hipError_t launch_factor_kind(int kind, const btc::Launch<btc::FactorDesc>& L, int np, int level_hint,
-                                     int64_t items, hipStream_t st) {
+                                     int64_t items, hipStream_t st, int part = 0) {
     switch (kind) {
         case 0: return btc::launch_factor_valu(L, np, items, st);
         case 1: return btc::launch_factor_mfma(L, np, items, st);
         case 2: return btc::launch_factor_mixed(L, np, false, items, st);
-        case 3: return btc::launch_factor_tiled(L, np, 0, level_hint, items, st);
-        case 4: return btc::launch_factor_tiled(L, np, 1, level_hint, items, st);
+        case 3: return btc::launch_factor_tiled(L, np, 0, part, level_hint, items, st);
+        case 4: return btc::launch_factor_tiled(L, np, 1, part, level_hint, items, st);
         case 5: return btc::launch_factor_mixed(L, np, true, items, st);
-        case 6: return btc::launch_factor_tiled(L, np, 2, level_hint, items, st);
+        case 6: return btc::launch_factor_tiled(L, np, 2, part, level_hint, items, st);
         default: return hipErrorInvalidValue;
     }
 }

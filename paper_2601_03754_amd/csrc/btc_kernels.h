@@ -135,9 +135,10 @@ hipError_t launch_factor_mfma(const Launch<FactorDesc>& p, int np, int64_t items
 hipError_t launch_factor_mixed(const Launch<FactorDesc>& p, int np, bool bf16, int64_t items, hipStream_t st);
 // Padded sizes 96 and 128: four tile-parallel launches per level (level_hint
 // 0 skips the deferred-update launch, which has nothing to do at level 0).
-// mode: 0 FP64, 1 mixed, 2 mixed with BF16 Schur / fill products.
-hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, int mode, int level_hint, int64_t items,
-                               hipStream_t st);
+// mode: 0 FP64, 1 mixed, 2 mixed with BF16 Schur / fill products; part 0 the
+// whole level step, 1..3 one of its three kernels (in that order).
+hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, int mode, int part, int level_hint,
+                               int64_t items, hipStream_t st);
 // mc: right-hand-side columns per dependency-chain group (1 or 4; with 4,
 // instances with fewer columns mask the rest).
 hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t items, bool backward, int mc,

@@ -41,6 +41,7 @@ struct Group {
     bool prof = false;     // bracketed by timing events
     int lane = 0;          // 0: the runner's stream, k: side stream k-1
     Work work;             // algorithmic work of the launch (when profiled)
+    Work part[4];          // tile-parallel factor: work of each of its kernels (1..3)
     std::vector<char> descs;  // packed descriptors (all of one type)
     size_t desc_size = 0;
     std::vector<btc::WorkItem> items;
@@ -80,13 +81,13 @@ struct btc_runner_s {
     // launch profiler: op filter (-2 off, -1 every group), kind filter (-1 any)
     int prof_op = -2, prof_kind = -1;
     struct Pending {
-        std::tuple<int, int, int> key;
+        std::tuple<int, int, int, int> key;  // op, kind, np, part
         hipEvent_t a, b;
         Work work;
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
-    std::map<std::tuple<int, int, int>, btc_kernel_stat> totals;
+    std::map<std::tuple<int, int, int, int>, btc_kernel_stat> totals;
     // graph recording (btc_graph_begin .. btc_graph_end)
     bool recording = false;
     std::vector<Call> rec;
@@ -131,6 +132,7 @@ void drain_prof(btc_runner_s* r, bool wait) {
         t.op = std::get<0>(p.key);
         t.kind = std::get<1>(p.key);
         t.np = std::get<2>(p.key);
+        t.part = std::get<3>(p.key);
         t.launches += 1;
         t.items += p.work.items;
         t.ms += ms;
@@ -143,11 +145,12 @@ void drain_prof(btc_runner_s* r, bool wait) {
 }
 
 // Work of a launch that the profiler counts but does not time.
-void add_untimed(btc_runner_s* r, const std::tuple<int, int, int>& key, const Work& w) {
+void add_untimed(btc_runner_s* r, const std::tuple<int, int, int, int>& key, const Work& w) {
     btc_kernel_stat& t = r->totals[key];
     t.op = std::get<0>(key);
     t.kind = std::get<1>(key);
     t.np = std::get<2>(key);
+    t.part = std::get<3>(key);
     t.launches += 1;
     t.items += w.items;
     t.bytes += w.bytes;
@@ -228,6 +231,12 @@ extern "C" {
 
 namespace {
 
+bool tiled_kind(int kind) { return kind == 3 || kind == 4 || kind == 6; }
+
+std::tuple<int, int, int, int> key4(const std::tuple<int, int, int>& k, int part) {
+    return std::make_tuple(std::get<0>(k), std::get<1>(k), std::get<2>(k), part);
+}
+
 void add_work(const btc_runner_s* r, Group& g, const btc_step& s, bool mixed) {
     if (r->prof_op == -2) return;
     g.count = true;
@@ -237,6 +246,13 @@ void add_work(const btc_runner_s* r, Group& g, const btc_step& s, bool mixed) {
     g.work.bytes += w.bytes;
     g.work.flops += w.flops;
     g.work.items += w.items;
+    if (s.op == BTC_OP_FACTOR && tiled_kind(g.kind))
+        for (int k = 1; k <= 3; ++k) {
+            const Work pw = tiled_part_work(k, mixed, h->N, h->n, s.level);
+            g.part[k].bytes += pw.bytes;
+            g.part[k].flops += pw.flops;
+            g.part[k].items += pw.items;
+        }
 }
 
 }  // namespace
@@ -462,7 +478,8 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
         const int64_t items = (int64_t)g.items.size();
         hipStream_t gs = g.lane == 0 ? st : r->side[g.lane - 1];
         hipEvent_t ea = nullptr, eb = nullptr;
-        if (g.prof && timing) {
+        const bool split = g.prof && timing && g.op == BTC_OP_FACTOR && tiled_kind(g.kind);
+        if (g.prof && timing && !split) {
             ea = take_event(r);
             eb = ea ? take_event(r) : nullptr;
             if (!eb) {
@@ -474,7 +491,23 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
         switch (g.op) {
             case BTC_OP_FACTOR: {
                 auto L = make_launch<btc::FactorDesc>(g, dev);
-                e = launch_factor_kind(g.kind, L, g.np, g.level, items, gs);
+                if (!split) {
+                    e = launch_factor_kind(g.kind, L, g.np, g.level, items, gs);
+                    break;
+                }
+                // one timing pair per kernel of the tile-parallel step
+                for (int part = 1; part <= 3 && e == hipSuccess; ++part) {
+                    hipEvent_t pa = take_event(r);
+                    hipEvent_t pb = pa ? take_event(r) : nullptr;
+                    if (!pb) {
+                        if (pa) r->pool.push_back(pa);
+                        return BTC_ERR_HIP;
+                    }
+                    (void)hipEventRecord(pa, gs);
+                    e = launch_factor_kind(g.kind, L, g.np, g.level, items, gs, part);
+                    (void)hipEventRecord(pb, gs);
+                    r->pending.push_back({std::make_tuple(g.op, g.kind, g.np, part), pa, pb, g.part[part]});
+                }
                 break;
             }
             case BTC_OP_FORWARD:
@@ -496,11 +529,11 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
                 e = btc::launch_ir_check(make_launch<btc::IrDesc>(g, dev), items, gs);
                 break;
         }
-        if (g.prof && timing) {
+        if (g.prof && timing && !split) {
             (void)hipEventRecord(eb, gs);
-            r->pending.push_back({kv.first, ea, eb, g.work});
-        } else if (g.count && timing) {
-            add_untimed(r, kv.first, g.work);
+            r->pending.push_back({key4(kv.first, 0), ea, eb, g.work});
+        } else if (g.count && timing && !split) {
+            add_untimed(r, key4(kv.first, 0), g.work);
         }
         if (e != hipSuccess) return to_code(e);
     }

@@ -383,15 +383,18 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     }
 }
 
+// part 0: the whole level step; 1, 2, 3: only K1, K2, K4 (for per-kernel
+// timing; launched in that order they make up the step)
 template <int NP, bool MIXED, bool BF16>
-hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int level_hint, int64_t items, hipStream_t st) {
+hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int part, int level_hint, int64_t items, hipStream_t st) {
     using Cfg = TiledCfg<NP>;
     const unsigned g = (unsigned)items;
-    if (level_hint != 0)  // level 0 has no deferred updates
+    if ((part == 0 || part == 1) && level_hint != 0)  // level 0 has no deferred updates
         hipLaunchKernelGGL((k_tiled_syrk_deferred<NP, MIXED, BF16>), dim3(g, 2 * Cfg::NTRI32), dim3(256), 0, st, p);
-    hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED>), dim3(g), dim3(256), 0, st, p);
-    hipLaunchKernelGGL((k_tiled_update<NP, MIXED, BF16>), dim3(g, Cfg::NTRI32 + Cfg::W32 * Cfg::W32), dim3(256), 0,
-                       st, p);
+    if (part == 0 || part == 2) hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED>), dim3(g), dim3(256), 0, st, p);
+    if (part == 0 || part == 3)
+        hipLaunchKernelGGL((k_tiled_update<NP, MIXED, BF16>), dim3(g, Cfg::NTRI32 + Cfg::W32 * Cfg::W32), dim3(256),
+                           0, st, p);
     return hipGetLastError();
 }
 
@@ -399,7 +402,11 @@ hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int level_hint, int64_t 
 
 // Per padded size launchers (one translation unit each).
 // mode: 0 FP64, 1 mixed (FP32 products), 2 mixed with BF16 Schur / fill products
-hipError_t launch_factor_tiled96(const Launch<FactorDesc>& p, int mode, int level_hint, int64_t items, hipStream_t st);
-hipError_t launch_factor_tiled128(const Launch<FactorDesc>& p, int mode, int level_hint, int64_t items, hipStream_t st);
+hipError_t launch_factor_tiled64(const Launch<FactorDesc>& p, int mode, int part, int level_hint, int64_t items,
+                                 hipStream_t st);
+hipError_t launch_factor_tiled96(const Launch<FactorDesc>& p, int mode, int part, int level_hint, int64_t items,
+                                 hipStream_t st);
+hipError_t launch_factor_tiled128(const Launch<FactorDesc>& p, int mode, int part, int level_hint, int64_t items,
+                                  hipStream_t st);
 
 }  // namespace btc

@@ -4,8 +4,9 @@
 //
 // Tunable choices:
 //   factor, FP64, padded size 16 or 32: 0 = matrix-core kernel, 1 = vector-ALU
-//     kernel (different rounding order; level bucket 0 = level 0, which has
-//     no deferred updates, 1 = the other levels)
+//     kernel; padded size 64, every precision: 0 = one workgroup per node,
+//     1 = the tile-parallel step (different rounding orders; level bucket 0 =
+//     level 0, which has no deferred updates, 1 = the other levels)
 //   forward / backward sweep and residual, nrhs > 1: 0 = four right-hand-side
 //     columns per dependency chain group, 1 = one (bitwise identical results)
 #include <hip/hip_runtime.h>
@@ -26,10 +27,15 @@ std::map<std::tuple<int, int, int, int>, int> g_tune;
 
 }  // namespace
 
+// Variant of a key nobody has set: measured on MI355X, the tile-parallel
+// step beats the one-workgroup-per-node kernel at padded size 64 (it needs
+// less LDS per workgroup, so several nodes share a compute unit); 0 elsewhere.
+int default_variant(int op, int np) { return (op == BTC_OP_FACTOR && np == 64) ? 1 : 0; }
+
 int tune_variant(int op, int kind, int np, int bucket) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(std::make_tuple(op, kind, np, bucket));
-    return it == g_tune.end() ? 0 : it->second;
+    return it == g_tune.end() ? default_variant(op, np) : it->second;
 }
 
 void tune_set(int op, int kind, int np, int bucket, int variant) {
@@ -48,9 +54,9 @@ bool tunable(int op, int32_t prec, int64_t n, int& kind, int& np, int& variants)
     const bool mixed = is_mixed(prec);
     np = btc::padded_block((int)n);
     if (op == BTC_OP_FACTOR) {
-        kind = 0;
+        kind = mixed ? (prec == BTC_BF16_IR ? 2 : 1) : 0;
         variants = 2;
-        return !mixed && (np == 16 || np == 32);
+        return np == 64 || (!mixed && (np == 16 || np == 32));
     }
     if (op == BTC_OP_FORWARD || op == BTC_OP_BACKWARD) {
         kind = mixed ? 1 : 0;

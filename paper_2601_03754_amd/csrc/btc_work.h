@@ -84,4 +84,35 @@ inline Work level_work(int op, bool mixed, int64_t N, int64_t n, int64_t m, int 
     return w;
 }
 
+// Work of one launch of the tile-parallel factorization (padded sizes above
+// 64) split by kernel: part 1 the deferred syrk (reads T_{i+h}, T_{i+3h},
+// reads and writes the S blocks it updates), part 2 the pivot factorization
+// with both triangular solves (reads S_i and the couplings, writes L_ii, R_i,
+// T_i), part 3 the separator and fill products (reads R_i, T_i and S_{i+s},
+// writes S_{i+s} and the fill).  The parts pass S and the factor blocks
+// through HBM between them, so their sum exceeds the level step's count.
+inline Work tiled_part_work(int part, bool mixed, int64_t N, int64_t n, int level) {
+    Work w;
+    const double nn = (double)n * (double)n, n3 = nn * (double)n;
+    const double wS = 8.0, wF = mixed ? 4.0 : 8.0, wC = level == 0 ? 8.0 : wF;
+    const int64_t s = (int64_t)1 << level, h = s >> 1;
+    if (level < 0 || level > 62 || s > N) return w;
+    for (int64_t i = s; i <= N; i += 2 * s) {
+        const bool hr = i + s <= N, hl = i > s, both = hr && hl;
+        const int def = (level > 0 && i + h <= N) + (level > 0 && hr && i + 3 * h <= N);
+        ++w.items;
+        if (part == 1) {
+            w.bytes += nn * (wF + 2.0 * wS) * def;
+            w.flops += n3 * def;
+        } else if (part == 2) {
+            w.bytes += nn * (wS + wC * (hr + hl) + wF * (1 + hr + hl));
+            w.flops += n3 * (1.0 / 3.0 + hr + hl);
+        } else {
+            w.bytes += nn * (wF * (hr + both) + 2.0 * wS * hr + wF * both);
+            w.flops += n3 * (hr + 2.0 * both);
+        }
+    }
+    return w;
+}
+
 }  // namespace btc_host

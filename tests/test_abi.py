@@ -161,6 +161,8 @@ def test_tune_table_host_only(lib):
     without a choice accept only variant 0, argument errors."""
     F, FW, R = lib.BTC_OP_FACTOR, lib.BTC_OP_FORWARD, lib.BTC_OP_RESIDUAL
     assert lib.btc_tune_get(F, 0, 24, 0) == 0
+    assert lib.btc_tune_get(F, 1, 50, 0) == 1  # tile-parallel step by default at padded 64
+    assert lib.btc_tune_get(F, 0, 64, 4) == 1
     lib.btc_tune_set(F, 0, 24, 3, 1)           # n 24 -> padded 32, levels >= 1
     assert lib.btc_tune_get(F, 0, 20, 5) == 1  # same padded size and bucket
     assert lib.btc_tune_get(F, 0, 24, 0) == 0  # level 0 bucket untouched

@@ -21,9 +21,11 @@ def btc():
     for op in (0, 1, 2, 3):
         for n in (16, 32, 64):
             for lvl in (0, 1):
-                b.btc_tune_set(op, 0, n, lvl, 0)
-                if op:
-                    b.btc_tune_set(op, 1, n, lvl, 0)
+                for prec in (0, 1, 2):
+                    try:
+                        b.btc_tune_set(op, prec, n, lvl, 1 if (op == 0 and n == 64) else 0)
+                    except b.BtcError:
+                        pass
 
 
 def dev(a):
@@ -52,6 +54,32 @@ def test_factor_variants_match_oracle(btc, n, variant):
     for g, o in zip(blocks, (Ld, Rb, Tb)):
         assert np.abs(g - o).max() <= 1e-12 * scale
     assert oracle.relres(p.D, p.E, X, p.B) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("n", [40, 64])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_factor_variants_at_64(btc, precision, n, variant):
+    """Padded size 64 through the one-workgroup-per-node kernel (variant 0)
+    or the tile-parallel level step (variant 1, the default) at every level:
+    oracle accuracy for FP64, refinement target for mixed."""
+    p = inputs.block_tridiag(150, n, seed=600 + n, nrhs=2)
+    btc.btc_tune_set(0, precision, n, 0, variant)
+    btc.btc_tune_set(0, precision, n, 1, variant)
+    f = btc.Factor(dev(p.D), dev(p.E), precision=precision)
+    X, info = f.solve(dev(p.B), want_info=True)
+    X = X.cpu().numpy()
+    blocks = f.export()
+    f.close()
+    btc.btc_tune_set(0, precision, n, 0, 1)
+    btc.btc_tune_set(0, precision, n, 1, 1)
+    Ld, Rb, Tb, _ = oracle.factor_nd(p.D, p.E)
+    scale = max(np.abs(Ld).max(), 1.0)
+    ftol = {0: 1e-12, 1: 1e-4, 2: 3e-2}[precision]
+    for g, o in zip(blocks, (Ld, Rb, Tb)):
+        assert np.abs(g - o).max() <= ftol * scale
+    assert oracle.relres(p.D, p.E, X, p.B) <= (1e-12 if precision == 0 else 1e-10)
+    assert info["converged"]
 
 
 @pytest.mark.parametrize("precision", [0, 1])
