@@ -361,7 +361,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="served", choices=["served", "single"])
+    ap.add_argument("--workload", default="served", choices=["served", "single", "copy"])
     ap.add_argument("--clients", type=int, default=256)
     ap.add_argument("--rates", default="1000,10000,50000",
                     help="open-loop Poisson arrival rates (req/s), comma separated; empty: none")
@@ -384,6 +384,28 @@ def main():
     from paper_2601_03754_amd import btc
     btc.lib()
     assert torch.cuda.is_available(), "a GPU is required"
+
+    if args.workload == "copy":
+        # plain device copy of a known size: the reference for scaling HBM
+        # traffic counters (FETCH_SIZE / WRITE_SIZE per dispatch)
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        print(json.dumps({"metric": "device copy bandwidth (read + write)", "value": 2 * nbytes * args.steps / wall / 1e9,
+                          "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "copy of a 1 GiB FP64 buffer", "bytes_read_per_step": nbytes,
+                                     "bytes_written_per_step": nbytes}}))
+        return
 
     if args.workload == "single":
         r = run_single(args, btc)

@@ -7,11 +7,11 @@
 // block goes through LDS in slabs of 16 columns (each row contributes one
 // contiguous 16-element segment, written transposed) or 16 rows (contiguous),
 // laid out so that lane r reads slab[k][r] conflict-free whichever of
-// M[r][c] or M[c][r] the product needs.  Slabs are double-buffered and the
-// global loads of slab p+1 (NP/4 per lane) are in flight while slab p is
-// consumed, so the triangular solves' dependency chains overlap the block
-// traffic; with 64-thread workgroups and at most 16.5 KB per slab buffer
-// several nodes share each compute unit.
+// M[r][c] or M[c][r] the product needs.  The global loads of slab p+1 (NP/4
+// per lane, held in registers) are in flight while slab p is consumed from
+// LDS, so the triangular solves' dependency chains overlap the block
+// traffic; with one wavefront per workgroup and one slab buffer (at most
+// 16.5 KB), many nodes share each compute unit.
 //
 //   forward, node i of level l (stride s), levels ascending:
 //     y_i = L_ii^{-1} (b_i - sum of the u / v its descendants left for it)
@@ -219,7 +219,7 @@ template <int NP, int MC, class T>
 __global__ __launch_bounds__(kWave) void k_fwd(Launch<SweepDesc<T>> L) {
     using G = Geo<NP>;
     constexpr int RPL = G::RPL, LDB = G::LDB;
-    __shared__ T buf[2][kS * LDB];
+    __shared__ T buf[kS * LDB];
     SweepDesc<T> P;
     int lvl;
     int64_t kk;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kWave) void k_fwd(Launch<SweepDesc<T>> L) {
         SlabRegs<NP, T> sr;
         sr.fetch(pl.src(0), n, lane);
         for (int p = 0; p < pl.total; ++p) {
-            T* b = buf[p & 1];
+            T* b = buf;
             int q;
             const int g = pl.locate(p, q);
             sr.put(b, pl.is_rows(g), lane);
@@ -323,7 +323,7 @@ template <int NP, int MC, class T>
 __global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
     using G = Geo<NP>;
     constexpr int RPL = G::RPL, LDB = G::LDB;
-    __shared__ T buf[2][kS * LDB];
+    __shared__ T buf[kS * LDB];
     SweepDesc<T> P;
     int lvl;
     int64_t kk;
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
         SlabRegs<NP, T> sr;
         sr.fetch(pl.src(0), n, lane);
         for (int p = 0; p < pl.total; ++p) {
-            T* b = buf[p & 1];
+            T* b = buf;
             int q;
             const int g = pl.locate(p, q);
             sr.put(b, pl.is_rows(g), lane);
@@ -431,7 +431,7 @@ template <int NP, int MC>
 __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
     using G = Geo<NP>;
     constexpr int RPL = G::RPL, LDB = G::LDB;
-    __shared__ double buf[2][kS * LDB];
+    __shared__ double buf[kS * LDB];
     ResidualDesc P;
     int64_t row0;
     {
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
         SlabRegs<NP, double> sr;
         sr.fetch(pl.src(0), n, lane);
         for (int p = 0; p < pl.total; ++p) {
-            double* b = buf[p & 1];
+            double* b = buf;
             int q;
             const int g = pl.locate(p, q);
             sr.put(b, pl.is_rows(g), lane);
