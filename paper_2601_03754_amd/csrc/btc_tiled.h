@@ -6,7 +6,8 @@
 // paths, Algorithm 4):
 //   K1  deferred syrk: S_i -= T'^T T' and S_{i+s} -= T''^T T'', one 256-thread
 //       workgroup per 32 x 32 lower tile (panels of T' staged in LDS)
-//   K2  one workgroup per node: the whole pivot block in LDS (FP64), blocked
+//   K2  one workgroup (8 wavefronts; 4 at padded size 128) per node: the
+//       whole pivot block in LDS (FP64), blocked
 //       Cholesky in 16-column panels (diagonal tiles factored and inverted by
 //       one wavefront, panel and trailing updates on the matrix cores), then
 //       R_i = C_{i+s,i} L_ii^{-T} and T_i = L_ii^{-1} C_{i,i-s} strip by strip
@@ -204,17 +205,23 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
 // transposed products for T), the solved tiles held in registers and passed
 // to the matrix cores through a one-tile LDS scratch per wavefront, the
 // coupling tiles read straight from HBM into the accumulator layout.
+// Wavefronts of K2: eight while the LDS allows it (more strips solved at
+// once), four at padded size 128.
+template <int NP>
+constexpr int k2_waves() { return NP <= 96 ? 8 : 4; }
+
 template <int NP, bool MIXED>
-__global__ __launch_bounds__(256) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
+__global__ __launch_bounds__(k2_waves<NP>() * kWave) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
     using Pr = Prec<MIXED>;
     using F = typename Pr::F;
     using Acc = typename Pr::Acc;
     using Cfg = TiledCfg<NP>;
     constexpr int LD = NP + 1;
     constexpr int NT16 = Cfg::NT16;
+    constexpr int NW = k2_waves<NP>();
     __shared__ double sS[NP * LD];
     __shared__ double sInv[NT16][kT * kLDI];
-    __shared__ F sTile[4][kT * kLDI];
+    __shared__ F sTile[NW][kT * kLDI];
     __shared__ double invd[NP];
     __shared__ __align__(16) double colbuf[2][kWave];
     __shared__ int fail;
@@ -227,15 +234,15 @@ __global__ __launch_bounds__(256) void k_tiled_potrf_trsm(Launch<FactorDesc> L) 
     const int tid = threadIdx.x, w = tid / kWave, lane = tid & 63;
     const int n = d.n;
     const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i - 1) * d.nn : P.Ld + (size_t)d.pi * d.nn;
-    stage_lower<NP, 256>(sS, src, n, tid);
+    stage_lower<NP, NW * kWave>(sS, src, n, tid);
     if (tid == 0) fail = 0;
     __syncthreads();
-    const bool ok = potrf_blocked<NP, LD, 4>(sS, invd, sInv, colbuf, &fail);
+    const bool ok = potrf_blocked<NP, LD, NW>(sS, invd, sInv, colbuf, &fail);
     if (!ok) {
         if (tid == 0) atomicMin(P.info, (unsigned long long)d.i);
         return;
     }
-    lds_store_as<NP, F, double>(Pr::Lf(P) + (size_t)d.pi * d.nn, sS, n, true, tid, 256);
+    lds_store_as<NP, F, double>(Pr::Lf(P) + (size_t)d.pi * d.nn, sS, n, true, tid, NW * kWave);
 
     const int i = lane & 15, q4 = lane >> 4;
     F* tile = sTile[w];
@@ -244,7 +251,7 @@ __global__ __launch_bounds__(256) void k_tiled_potrf_trsm(Launch<FactorDesc> L) 
         for (int v = 0; v < 4; ++v) tile[Pr::row(v, lane) * kLDI + i] = x[v];
         wave_lds_sync();
     };
-    for (int sidx = w; sidx < 2 * NT16; sidx += 4) {
+    for (int sidx = w; sidx < 2 * NT16; sidx += NW) {
         const bool isR = sidx < NT16;
         const int t = isR ? sidx : sidx - NT16;
         if (isR ? !d.has_r : !d.has_l) continue;
@@ -391,7 +398,8 @@ hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int part, int level_hint
     const unsigned g = (unsigned)items;
     if ((part == 0 || part == 1) && level_hint != 0)  // level 0 has no deferred updates
         hipLaunchKernelGGL((k_tiled_syrk_deferred<NP, MIXED, BF16>), dim3(g, 2 * Cfg::NTRI32), dim3(256), 0, st, p);
-    if (part == 0 || part == 2) hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED>), dim3(g), dim3(256), 0, st, p);
+    if (part == 0 || part == 2)
+        hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED>), dim3(g), dim3(k2_waves<NP>() * kWave), 0, st, p);
     if (part == 0 || part == 3)
         hipLaunchKernelGGL((k_tiled_update<NP, MIXED, BF16>), dim3(g, Cfg::NTRI32 + Cfg::W32 * Cfg::W32), dim3(256),
                            0, st, p);

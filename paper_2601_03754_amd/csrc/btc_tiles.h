@@ -122,27 +122,39 @@ __device__ __forceinline__ bool potrf_small(double* __restrict__ A, double* __re
     double a[NP];
 #pragma unroll
     for (int c = 0; c < NP; ++c) a[c] = (lane < NP && c <= lane) ? A[lane * LD + c] : 0.0;
+    // 1/sqrt(p): hardware estimate refined by two Newton steps
+    auto rsqrt_refined = [](double p) {
+        double r = __builtin_amdgcn_rsq(p);
+        double e = fma(-p * r, r, 1.0);
+        r = fma(0.5 * r, e, r);
+        e = fma(-p * r, r, 1.0);
+        return fma(0.5 * r, e, r);
+    };
+    double piv = readlane_d(a[0], 0);
+    double r = rsqrt_refined(piv);
     double myinv = 1.0;
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-        const double piv = readlane_d(a[j], j);
         ok = ok && (piv > 0.0);
-        double r = __builtin_amdgcn_rsq(piv);
-        double e = fma(-piv * r, r, 1.0);
-        r = fma(0.5 * r, e, r);
-        e = fma(-piv * r, r, 1.0);
-        r = fma(0.5 * r, e, r);
         double l = a[j] * r;
         l = (lane == j) ? piv * r : l;
         l = (lane < j) ? 0.0 : l;
         myinv = (lane == j) ? r : myinv;
         a[j] = l;
-        double lc[NP];
+        if (j + 1 < NP) {
+            // the next pivot first: its reciprocal square root overlaps the
+            // rest of this column's update
+            a[j + 1] = fma(-l, readlane_d(l, j + 1), a[j + 1]);
+            piv = readlane_d(a[j + 1], j + 1);
+            const double rn = rsqrt_refined(piv);
+            double lc[NP];
 #pragma unroll
-        for (int c = j + 1; c < NP; ++c) lc[c] = readlane_d(l, c);
+            for (int c = j + 2; c < NP; ++c) lc[c] = readlane_d(l, c);
 #pragma unroll
-        for (int c = j + 1; c < NP; ++c) a[c] = fma(-l, lc[c], a[c]);
+            for (int c = j + 2; c < NP; ++c) a[c] = fma(-l, lc[c], a[c]);
+            r = rn;
+        }
     }
     if (lane < NP) {
 #pragma unroll
@@ -225,33 +237,48 @@ __device__ __forceinline__ void tile_inverse(const double* __restrict__ L, int r
 
 // Blocked Cholesky of the lower triangle of an NP x NP LDS tile (row stride
 // LD) by all NW wavefronts of the workgroup (every thread must call it), in
-// 16-column panels: wavefront 0 factors the diagonal tile (potrf_small)
-// and inverts it; the tiles below it are multiplied by the inverse (L_tp =
-// A_tp L_pp^{-T}); the trailing lower tiles are updated, A_ab -= L_ap L_bp^T
-// (matrix cores, tiles spread over the wavefronts).  On return: L in the
-// lower triangle (strict upper part of each diagonal tile zeroed, tiles above
-// the diagonal untouched), 1/L_jj in invd, the inverted diagonal tiles in
-// inv[NP/16] (row stride kLDI).  *fail (LDS, 0 on entry) becomes 1 on a
-// non-positive or NaN pivot; the result is then false for every thread.
+// 16-column panels: wavefront 0 factors the diagonal tile (potrf_small); the
+// rows below it are solved against it by substitution, one row per thread
+// (L_tp = A_tp L_pp^{-T}); the trailing lower tiles are updated, A_ab -=
+// L_ap L_bp^T (matrix cores, tiles spread over the wavefronts).  The 16 x 16
+// diagonal tiles are inverted at the end, off the pivot chain, spread over
+// the wavefronts.  On return: L in the lower triangle (strict upper part of
+// each diagonal tile zeroed, tiles above the diagonal untouched), 1/L_jj in
+// invd, the inverted diagonal tiles in inv[NP/16] (row stride kLDI).  *fail
+// (LDS, 0 on entry) becomes 1 on a non-positive or NaN pivot; the result is
+// then false for every thread.
 template <int NP, int LD, int NW>
 __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __restrict__ invd,
                                               double (*__restrict__ inv)[kT * kLDI],
                                               double (*__restrict__ colbuf)[kWave], int* fail) {
     constexpr int NTL = NP / kT;
-    const int w = threadIdx.x / kWave;
+    const int tid = threadIdx.x;
+    const int w = tid / kWave;
 #pragma unroll 1
     for (int p = 0; p < NTL; ++p) {
+        const int c0 = p * kT;
         if (w == 0) {
-            const bool ok = potrf_small<kT, LD>(A + p * kT * LD + p * kT, invd + p * kT);
-            if (!ok && (threadIdx.x & 63) == 0) *fail = 1;
-            tile_inverse<LD, double>(A, p * kT, invd, inv[p]);
+            const bool ok = potrf_small<kT, LD>(A + c0 * LD + c0, invd + c0);
+            if (!ok && (tid & 63) == 0) *fail = 1;
         }
         __syncthreads();
         if (*fail) return false;
-        for (int t = p + 1 + w; t < NTL; t += NW) {
-            d4 out = {0.0, 0.0, 0.0, 0.0};
-            mma_tile<LD, kLDI, false, true, false>(out, A, t * kT, p * kT, inv[p], 0, 0, kT);
-            acc_store_lds<LD>(out, A, t * kT, p * kT);
+        // rows below the diagonal tile: x L_pp^T = a, forward substitution
+        const int rows = NP - c0 - kT;
+        for (int t = tid; t < rows; t += NW * kWave) {
+            double* row = A + (c0 + kT + t) * LD + c0;
+            double x[kT];
+#pragma unroll
+            for (int c = 0; c < kT; ++c) x[c] = row[c];
+#pragma unroll
+            for (int c = 0; c < kT; ++c) {
+                double acc = x[c];
+#pragma unroll
+                for (int k = 0; k < c; ++k) acc = fma(-x[k], A[(c0 + c) * LD + c0 + k], acc);
+                x[c] = acc * invd[c0 + c];
+            }
+#pragma unroll
+            for (int c = 0; c < kT; ++c) row[c] = x[c];
         }
         __syncthreads();
         const int m = NTL - 1 - p;
@@ -261,11 +288,13 @@ __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __
             const int a = p + 1 + ta, b = p + 1 + tb;
             d4 acc;
             acc_load_lds<LD>(acc, A, a * kT, b * kT);
-            mma_tile<LD, LD, false, true, true>(acc, A, a * kT, p * kT, A, b * kT, p * kT, kT);
+            mma_tile<LD, LD, false, true, true>(acc, A, a * kT, c0, A, b * kT, c0, kT);
             acc_store_lds<LD>(acc, A, a * kT, b * kT);
         }
         __syncthreads();
     }
+    for (int t = w; t < NTL; t += NW) tile_inverse<LD, double>(A, t * kT, invd, inv[t]);
+    __syncthreads();
     return true;
 }
 
