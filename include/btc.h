@@ -248,8 +248,10 @@ BTC_API int btc_runner_create(void *stream, btc_runner *out);
 
 /*
  * btc_runner_run -- enqueue `count` steps (host array).  Steps of one call
- * must not depend on each other (at most one step per handle per call);
- * calls are executed in order.  Returns once the work is enqueued; -3 for an
+ * must not depend on each other: at most one step per handle per call, except
+ * that FACTOR level l+1 and FORWARD level l of one handle may share a call
+ * (the sweep reads only level-l factor blocks, the factor step writes only
+ * blocks of higher levels); calls are executed in order.  Returns once the work is enqueued; -3 for an
  * invalid step (unknown op, level out of range, missing pointers, a sweep or
  * residual on a handle never factored).
  */
@@ -403,7 +405,9 @@ BTC_API int btc_refine_info(btc_handle h, btc_solve_info *info);
  * btc_server_step call admits queued requests and enqueues the next level
  * step of every request in flight as one runner call, so requests at
  * different levels and phases share launches and new requests join at the
- * next step.  Admission is in arrival order, one request in flight per
+ * next step.  A refactor+solve request runs its first forward sweep
+ * interlaced with the factorization (forward level l in the tick of factor
+ * level l+1; section "Fused and Blocked Kernels").  Admission is in arrival order, one request in flight per
  * client (so a client's requests complete in order), within an HBM budget on
  * the resident factors + workspaces: idle clients are evicted least recently
  * used first, and a later "solve" of an evicted client is run as

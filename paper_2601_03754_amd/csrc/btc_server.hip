@@ -69,6 +69,7 @@ struct Req {
     double t_submit = 0.0;
     double t_admit = 0.0;
     std::vector<btc_step> plan;
+    std::vector<uint8_t> joint;  // joint[k]: plan step k runs in the same tick as step k+1
     size_t pc = 0;
     bool refactored = false;
     bool retired = false;
@@ -150,6 +151,12 @@ int admit_client(btc_server s, Client& c, int64_t nrhs) {
     return BTC_OK;
 }
 
+// The steps of a request, in order, grouped into ticks.  A refactor+solve
+// request interlaces the factorization with the first forward sweep (the
+// paper's interlaced factor and forward substitution, section "Fused and
+// Blocked Kernels"): forward level l only reads factor blocks of level l,
+// final once factor level l has run, so it shares a tick with factor level
+// l+1, which writes only blocks of higher levels.
 void build_plan(btc_server s, Req* r, Client& c) {
     btc_handle h = c.h;
     const int L = h->levels;
@@ -158,47 +165,67 @@ void build_plan(btc_server s, Req* r, Client& c) {
         c.A_diag = r->A_diag;
         c.A_off = r->A_off;
     }
+    auto push = [&](const btc_step& t, bool joint) {
+        r->plan.push_back(t);
+        r->joint.push_back(joint ? 1 : 0);
+    };
+    btc_step f{};
+    f.h = h;
+    f.op = BTC_OP_FACTOR;
+    f.A_diag = c.A_diag;
+    f.A_off = c.A_off;
     btc_step t{};
-    t.h = h;
-    if (factor) {
-        r->refactored = true;
-        for (int l = 0; l < L; ++l) {
-            t.op = BTC_OP_FACTOR;
-            t.level = l;
-            t.A_diag = c.A_diag;
-            t.A_off = c.A_off;
-            r->plan.push_back(t);
-        }
-    }
-    t = btc_step{};
     t.h = h;
     t.B = r->B;
     t.X = r->X;
     t.nrhs = r->nrhs;
     const bool mixed = is_mixed(h->precision);
     const int rounds = mixed ? 1 + h->max_refine : 1;
-    if (mixed) {
-        t.op = BTC_OP_REFINE_INIT;
-        r->plan.push_back(t);
-    }
+    if (factor) r->refactored = true;
     for (int k = 0; k < rounds; ++k) {
         t.first = (k == 0) ? 1 : 0;
-        for (int l = 0; l < L; ++l) {
-            t.op = BTC_OP_FORWARD;
-            t.level = l;
-            r->plan.push_back(t);
+        if (k == 0 && factor) {
+            // tick 0: factor level 0 (+ refinement set-up); tick l: factor level
+            // l + forward level l-1; tick L: forward level L-1
+            f.level = 0;
+            push(f, mixed);
+            if (mixed) {
+                t.op = BTC_OP_REFINE_INIT;
+                t.level = 0;
+                push(t, false);
+            }
+            for (int l = 1; l <= L; ++l) {
+                if (l < L) {
+                    f.level = l;
+                    push(f, true);
+                }
+                t.op = BTC_OP_FORWARD;
+                t.level = l - 1;
+                push(t, false);
+            }
+        } else {
+            if (k == 0 && mixed) {
+                t.op = BTC_OP_REFINE_INIT;
+                t.level = 0;
+                push(t, false);
+            }
+            for (int l = 0; l < L; ++l) {
+                t.op = BTC_OP_FORWARD;
+                t.level = l;
+                push(t, false);
+            }
         }
         for (int l = L - 1; l >= 0; --l) {
             t.op = BTC_OP_BACKWARD;
             t.level = l;
-            r->plan.push_back(t);
+            push(t, false);
         }
         if (mixed) {
             t.level = 0;
             t.op = BTC_OP_RESIDUAL;
-            r->plan.push_back(t);
+            push(t, false);
             t.op = BTC_OP_REFINE_TEST;
-            r->plan.push_back(t);
+            push(t, false);
         }
     }
 }
@@ -354,11 +381,15 @@ BTC_API int btc_server_step(btc_server s) {
     for (Req* r : s->active) {
         if (r->retired || r->pc >= r->plan.size()) continue;  // done, or waiting for its last tick
         r->last_tick = t.id;
-        const btc_step& st = r->plan[r->pc++];
-        s->scratch.push_back(st);
-        if (st.op == BTC_OP_REFINE_TEST && r->pc < r->plan.size()) {
-            t.polls.push_back({r, s->flag_next});
-            s->flag_next = (s->flag_next + 1) % s->flag_cap;
+        bool more = true;
+        while (more && r->pc < r->plan.size()) {
+            more = r->joint[r->pc] != 0;
+            const btc_step& st = r->plan[r->pc++];
+            s->scratch.push_back(st);
+            if (st.op == BTC_OP_REFINE_TEST && r->pc < r->plan.size()) {
+                t.polls.push_back({r, s->flag_next});
+                s->flag_next = (s->flag_next + 1) % s->flag_cap;
+            }
         }
         if (r->pc == r->plan.size()) t.finishing.push_back(r);
     }
