@@ -214,6 +214,38 @@ __device__ __forceinline__ void slab_axpy(T (&target)[Geo<NP>::RPL][MC], const T
     }
 }
 
+// Slabs in flight beyond the one being consumed.  Measured on MI355X: a
+// second one buys little per-node latency and costs occupancy (registers),
+// so one.
+template <int NP, class T>
+constexpr int slab_depth() { return 1; }
+
+// Walk the slabs of a plan through the LDS buffer: slab p is consumed by
+// body(p, segment, slab index in segment, buffer) while the loads of the next
+// DEPTH slabs are in flight (register buffers indexed by unrolled constants).
+template <int NP, class T, int DEPTH, class S, class Body>
+__device__ __forceinline__ void run_slabs(const Plan<S>& pl, int n, int lane, T* __restrict__ buf, Body&& body) {
+    SlabRegs<NP, T> r[DEPTH];
+#pragma unroll
+    for (int u = 0; u < DEPTH; ++u)
+        if (u < pl.total) r[u].fetch(pl.src(u), n, lane);
+    for (int p = 0; p < pl.total; p += DEPTH) {
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u) {
+            const int q = p + u;
+            if (q < pl.total) {
+                int qs;
+                const int g = pl.locate(q, qs);
+                r[u].put(buf, pl.is_rows(g), lane);
+                wave_lds_sync();
+                if (q + DEPTH < pl.total) r[u].fetch(pl.src(q + DEPTH), n, lane);
+                body(g, qs, buf);
+                wave_lds_sync();
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 template <int NP, int MC, class T>
 __global__ __launch_bounds__(kWave) void k_fwd(Launch<SweepDesc<T>> L) {
@@ -265,15 +297,7 @@ __global__ __launch_bounds__(kWave) void k_fwd(Launch<SweepDesc<T>> L) {
                 v[rr][c] = T(0);
             }
         }
-        SlabRegs<NP, T> sr;
-        sr.fetch(pl.src(0), n, lane);
-        for (int p = 0; p < pl.total; ++p) {
-            T* b = buf;
-            int q;
-            const int g = pl.locate(p, q);
-            sr.put(b, pl.is_rows(g), lane);
-            wave_lds_sync();
-            if (p + 1 < pl.total) sr.fetch(pl.src(p + 1), n, lane);
+        run_slabs<NP, T, slab_depth<NP, T>()>(pl, n, lane, buf, [&](int g, int q, const T* b) {
             if (g == 0) {
                 // y = L^{-1} acc over columns j of this slab
                 for (int k = 0; k < kS; ++k) {
@@ -299,8 +323,7 @@ __global__ __launch_bounds__(kWave) void k_fwd(Launch<SweepDesc<T>> L) {
             } else {
                 slab_axpy<NP, MC, T>(v, b, acc, kS * q, n, T(1), 0, lane);  // v += T^T y
             }
-            wave_lds_sync();
-        }
+        });
 #pragma unroll
         for (int rr = 0; rr < RPL; ++rr) {
             const int r = lane + kWave * rr;
@@ -359,15 +382,7 @@ __global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
                 xl[rr][c] = (ok && has_l) ? P.X[((size_t)(i - s - 1) * n + r) * m + q] : T(0);
             }
         }
-        SlabRegs<NP, T> sr;
-        sr.fetch(pl.src(0), n, lane);
-        for (int p = 0; p < pl.total; ++p) {
-            T* b = buf;
-            int q;
-            const int g = pl.locate(p, q);
-            sr.put(b, pl.is_rows(g), lane);
-            wave_lds_sync();
-            if (p + 1 < pl.total) sr.fetch(pl.src(p + 1), n, lane);
+        run_slabs<NP, T, slab_depth<NP, T>()>(pl, n, lane, buf, [&](int g, int q, const T* b) {
             if (g < 2) {
                 // acc -= R^T x_{i+s} (g = 0) or T x_{i-s} (g = 1); the vector is
                 // selected element by element so that both stay in registers
@@ -399,8 +414,7 @@ __global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
                     }
                 }
             }
-            wave_lds_sync();
-        }
+        });
 #pragma unroll
         for (int rr = 0; rr < RPL; ++rr) {
             const int r = lane + kWave * rr;
@@ -479,15 +493,7 @@ __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
                 x2[rr][c] = (ok && rgt) ? P.X[((size_t)i * n + r) * m + q] : 0.0;
             }
         }
-        SlabRegs<NP, double> sr;
-        sr.fetch(pl.src(0), n, lane);
-        for (int p = 0; p < pl.total; ++p) {
-            double* b = buf;
-            int q;
-            const int g = pl.locate(p, q);
-            sr.put(b, pl.is_rows(g), lane);
-            wave_lds_sync();
-            if (p + 1 < pl.total) sr.fetch(pl.src(p + 1), n, lane);
+        run_slabs<NP, double, slab_depth<NP, double>()>(pl, n, lane, buf, [&](int g, int q, const double* b) {
             if (g == 0)
                 slab_axpy<NP, MC, double>(acc, b, x1, kS * q, n, -1.0, 1, lane);
             else if (g == 1)
@@ -496,8 +502,7 @@ __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
                 slab_axpy<NP, MC, double>(acc, b, x0, kS * q, n, -1.0, 0, lane);
             else
                 slab_axpy<NP, MC, double>(acc, b, x2, kS * q, n, -1.0, 0, lane);
-            wave_lds_sync();
-        }
+        });
 #pragma unroll
         for (int c = 0; c < MC; ++c) {
             const int q = q0 + c;
