@@ -174,15 +174,22 @@ class Served:
                 self.submit(c)
                 sub += 1
         done = []
+        t_step = 0.0
+        ticks = 0
         while len(done) < requests:
+            ts = time.perf_counter()
             self.srv.step()
+            t_step += time.perf_counter() - ts
+            ticks += 1
             for d in self.srv.poll():
                 done.append(d)
                 if sub < requests:
                     self.submit(d["client"])
                     sub += 1
         torch.cuda.synchronize()
-        return done, time.perf_counter() - t0
+        wall = time.perf_counter() - t0
+        self.last_loop = {"ticks": ticks, "host_step_s": t_step, "wall_s": wall}
+        return done, wall
 
     def open_loop(self, rate, requests):
         """Poisson arrivals at `rate` per second over random clients;
@@ -253,10 +260,12 @@ def run_served(args, btc):
                   if (s["op"], s["kind"], s["np"], s["part"]) == (dom["op"], dom["kind"], dom["np"], dom["part"])]
         btc.runner_profile(rh, -2, -1)
         lat = lat_ms(done)
+        loop = dict(sv.last_loop)
         relres = sv.verify()
         ent = {"value": len(done) / wall, "ms_per_step": wall * 1e3 / args.steps,
                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "requests": len(done),
                "refactor_share": float(np.mean([d["refactored"] for d in done])),
+               "server_ticks": loop["ticks"], "host_step_frac": loop["host_step_s"] / loop["wall_s"],
                "max_relres_last": relres,
                "warmup_kernel_ms": [{"kernel": roofline_entry(s)["kernel"], "ms": round(s["ms"], 3),
                                      "launches": s["launches"],
@@ -268,8 +277,9 @@ def run_served(args, btc):
         tf = sum(s["flops"] for s in allstats)
         ent["aggregate"] = {"bytes": tb, "flops": tf, "gbs": tb / wall / 1e9, "tflops": tf / wall / 1e12,
                             "hbm_frac": tb / wall / 1e9 / HBM_PEAK_GBS}
-        log("%s closed loop: %.0f req/s, p50 %.2f ms, p99 %.2f ms, relres %.2e"
-            % (name, ent["value"], ent["p50_ms"], ent["p99_ms"], relres))
+        log("%s closed loop: %.0f req/s, p50 %.2f ms, p99 %.2f ms, relres %.2e, %d ticks, host step %.0f%%"
+            % (name, ent["value"], ent["p50_ms"], ent["p99_ms"], relres, loop["ticks"],
+               100 * ent["host_step_frac"]))
         for rate in args.rates:
             nreq = int(min(args.rate_requests, max(200, rate * args.rate_seconds)))
             d2, w2 = sv.open_loop(rate, nreq)
