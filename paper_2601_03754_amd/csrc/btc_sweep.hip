@@ -45,13 +45,37 @@ __device__ __forceinline__ float bcast(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+constexpr int gcd_i(int a, int b) { return b == 0 ? a : gcd_i(b, a % b); }
+
 template <int NP>
 struct Geo {
     static_assert(NP % kS == 0, "padded size is a multiple of the slab width");
     static constexpr int RPL = (NP + kWave - 1) / kWave;  // rows per lane
-    static constexpr int LDB = kWave * RPL + 1;           // slab stride (elements), covers every lane row
+    static constexpr int LDB = NP + 1;                    // slab stride (elements)
+    // lanes past the last row (r >= NP) read past the end of the last slab
+    // row: the buffer is long enough for them (their values are never used)
+    static constexpr int BUF = kS * LDB + kWave * RPL - NP;
     static constexpr int PER = NP * kS / kWave;           // slab elements per lane
+    // row slab element u of a lane: pattern u % RP (row, column) of the first
+    // RP elements, moved down by (u / RP) * RK rows
+    static constexpr int RP = NP / gcd_i(NP, kWave);
+    static constexpr int RK = kWave / gcd_i(NP, kWave);
 };
+
+// Buffer-resource loads of one n x n block: every offset is range checked
+// against the block's size, so an offset at or past it reads 0 and touches
+// no memory (used for rows and columns beyond n and for skipped parts).
+constexpr int kOob = 0x40000000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void* p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ void buf_ld(double& x, __amdgpu_buffer_rsrc_t r, int off) {
+    x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_ld(float& x, __amdgpu_buffer_rsrc_t r, int off) {
+    x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
 
 // Where the next slab comes from: column slab (elements M[r][c0+k], rows
 // r >= rmin) or row slab (elements M[r0+k][r], only r <= r0+k when tri).
@@ -68,24 +92,39 @@ template <int NP, class T>
 struct SlabRegs {
     T v[Geo<NP>::PER];
 
+    // Column slab: lane (q, k) = (lane / 16, lane % 16) reads rows q + 4u
+    // of column off + k, every offset a lane constant plus 4un.  Row slab:
+    // lanes read along the rows (pattern offsets of Geo).  Both skip what the
+    // triangular blocks do not use (column slab: the rows above rmin, a
+    // whole element index at a time; row slab: columns past the slab's last
+    // row).
     template <class S>
     __device__ __forceinline__ void fetch(const SlabSrc<S>& s, int n, int lane) {
+        using G = Geo<NP>;
+        const __amdgpu_buffer_rsrc_t rs = block_rsrc(s.M, n * n * (int)sizeof(S));
         if (!s.rows) {
+            const int k = lane & (kS - 1), q = lane >> 4;
+            const int c = s.off + k;
+            const int base = c < n ? (q * n + c) * (int)sizeof(S) : kOob;
+            const int step = 4 * n * (int)sizeof(S);
 #pragma unroll
-            for (int u = 0; u < Geo<NP>::PER; ++u) {
-                const int e = lane + kWave * u, r = e / kS, c = s.off + e % kS;
-                T x = T(0);
-                if (r >= s.rmin && r < n && c < n) x = (T)s.M[(size_t)r * n + c];
-                v[u] = x;
+            for (int u = 0; u < G::PER; ++u) {
+                if (4 * u < s.rmin)
+                    v[u] = T(0);
+                else
+                    buf_ld(v[u], rs, base + u * step);
             }
         } else {
+            int base[G::RP];
 #pragma unroll
-            for (int u = 0; u < Geo<NP>::PER; ++u) {
-                const int e = lane + kWave * u, r = e % NP, rr = s.off + e / NP;
-                T x = T(0);
-                if (r < n && rr < n && (!s.tri || r <= rr)) x = (T)s.M[(size_t)rr * n + r];
-                v[u] = x;
+            for (int j = 0; j < G::RP; ++j) {
+                const int e = lane + kWave * j, r = e % NP, k = e / NP;
+                const bool ok = r < n && (!s.tri || r < s.off + kS);
+                base[j] = ok ? ((s.off + k) * n + r) * (int)sizeof(S) : kOob;
             }
+            const int step = G::RK * n * (int)sizeof(S);
+#pragma unroll
+            for (int u = 0; u < G::PER; ++u) buf_ld(v[u], rs, base[u % G::RP] + (u / G::RP) * step);
         }
     }
 
@@ -251,7 +290,7 @@ template <int NP, int MC, class T>
 __global__ __launch_bounds__(kWave) void k_fwd(Launch<SweepDesc<T>> L) {
     using G = Geo<NP>;
     constexpr int RPL = G::RPL, LDB = G::LDB;
-    __shared__ T buf[kS * LDB];
+    __shared__ T buf[G::BUF];
     SweepDesc<T> P;
     int lvl;
     int64_t kk;
@@ -346,7 +385,7 @@ template <int NP, int MC, class T>
 __global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
     using G = Geo<NP>;
     constexpr int RPL = G::RPL, LDB = G::LDB;
-    __shared__ T buf[kS * LDB];
+    __shared__ T buf[G::BUF];
     SweepDesc<T> P;
     int lvl;
     int64_t kk;
@@ -445,7 +484,7 @@ template <int NP, int MC>
 __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
     using G = Geo<NP>;
     constexpr int RPL = G::RPL, LDB = G::LDB;
-    __shared__ double buf[kS * LDB];
+    __shared__ double buf[G::BUF];
     ResidualDesc P;
     int64_t row0;
     {
