@@ -149,6 +149,42 @@ __device__ __forceinline__ void stage_lower(double* __restrict__ dst, const doub
     }
 }
 
+// The same into the packed lower-tile layout (whole diagonal tiles: their
+// strict upper part 0).
+template <int NP, int NT>
+__device__ __forceinline__ void stage_lower_packed(double* __restrict__ dst, const double* __restrict__ src, int n,
+                                                   int t) {
+    constexpr int CH = 8;
+    for (int base = 0; base < NP * NP; base += NT * CH) {
+        double v[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = base + t + NT * u, r = e / NP, c = e % NP;
+            double x = (r == c) ? 1.0 : 0.0;
+            if (e < NP * NP && r < n && c <= r) x = src[(size_t)r * n + c];
+            v[u] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = base + t + NT * u, r = e / NP, c = e % NP;
+            if (e < NP * NP && c / kT <= r / kT) PackedLds::tile(dst, r / kT, c / kT)[(r % kT) * kLDI + c % kT] = v[u];
+        }
+    }
+}
+
+// Leading n x n part of a packed lower-tile LDS block to global memory as
+// type D (strict upper triangle written as 0).
+template <int NP, class D>
+__device__ __forceinline__ void store_lower_packed(D* __restrict__ dst, const double* __restrict__ src, int n, int t,
+                                                   int nt) {
+    for (int idx = t; idx < NP * NP; idx += nt) {
+        const int r = idx / NP, c = idx % NP;
+        if (r < n && c < n)
+            dst[(size_t)r * n + c] =
+                (D)(c <= r ? PackedLds::tile(src, r / kT, c / kT)[(r % kT) * kLDI + c % kT] : 0.0);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K1: deferred syrk.  blockIdx.y < NTRI32: tile of S_i; else tile of S_{i+s}.
 template <int NP, bool MIXED, bool BF16>
@@ -204,22 +240,30 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
 // tile by tile: X_p = (C_p - sum_{q<p} X_q L_pq^T) Dinv_p^T for R (the
 // transposed products for T), the solved tiles held in registers and passed
 // to the matrix cores through a one-tile LDS scratch per wavefront, the
-// coupling tiles read straight from HBM into the accumulator layout.
+// coupling tiles read straight from HBM into the accumulator layout (issued
+// before the pivot factorization, which hides their latency).
 // Wavefronts of K2: eight while the LDS allows it (more strips solved at
 // once), four at padded size 128.
 template <int NP>
 constexpr int k2_waves() { return NP <= 96 ? 8 : 4; }
+// Workgroups of K2 per compute unit the LDS allows (the register budget is
+// held to it: the second launch bound counts wavefronts per SIMD) and strips per wavefront whose coupling tiles are prefetched.
+template <int NP>
+constexpr int k2_blocks() { return NP <= 96 ? 2 : 1; }
+template <int NP, bool MIXED>
+constexpr int k2_prefetch() {
+    return NP >= 96 ? 0 : MIXED ? (2 * (NP / 16) + k2_waves<NP>() - 1) / k2_waves<NP>() : 0;
+}
 
 template <int NP, bool MIXED>
-__global__ __launch_bounds__(k2_waves<NP>() * kWave) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
+__global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<NP>() / 4) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
     using Pr = Prec<MIXED>;
     using F = typename Pr::F;
     using Acc = typename Pr::Acc;
     using Cfg = TiledCfg<NP>;
-    constexpr int LD = NP + 1;
     constexpr int NT16 = Cfg::NT16;
     constexpr int NW = k2_waves<NP>();
-    __shared__ double sS[NP * LD];
+    __shared__ double sS[packed_lds_elems<NP>()];  // lower tiles of S_i, then of L_ii
     __shared__ double sInv[NT16][kT * kLDI];
     __shared__ F sTile[NW][kT * kLDI];
     __shared__ double invd[NP];
@@ -234,41 +278,71 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave) void k_tiled_potrf_trsm(Lau
     const int tid = threadIdx.x, w = tid / kWave, lane = tid & 63;
     const int n = d.n;
     const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i - 1) * d.nn : P.Ld + (size_t)d.pi * d.nn;
-    stage_lower<NP, NW * kWave>(sS, src, n, tid);
+    const int i = lane & 15, q4 = lane >> 4;
+    // This wavefront's strips (w and w + NW), their coupling tiles loaded
+    // into registers before the pivot factorization so that the loads
+    // complete behind it.
+    constexpr int NS = (2 * NT16 + NW - 1) / NW, PF = k2_prefetch<NP, MIXED>();
+    Acc C[PF > 0 ? PF : 1][NT16];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+        const int sidx = w + j * NW;
+        const bool isR = sidx < NT16;
+        const int t = isR ? sidx : sidx - NT16;
+        const bool live = sidx < 2 * NT16 && (isR ? d.has_r : d.has_l);
+        const double* C64 = (lvl == 0) ? P.A_off + (size_t)(isR ? d.i - 1 : d.i - 2) * d.nn : nullptr;
+        const F* Cf = (isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn;  // levels above 0: the output slot
+#pragma unroll
+        for (int p = 0; p < NT16; ++p)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = Pr::row(v, lane);
+                const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
+                F x = F(0);
+                if (live && gr < n && gc < n) x = C64 ? (F)C64[(size_t)gr * n + gc] : Cf[(size_t)gr * n + gc];
+                C[j][p][v] = x;
+            }
+    }
+    stage_lower_packed<NP, NW * kWave>(sS, src, n, tid);
     if (tid == 0) fail = 0;
     __syncthreads();
-    const bool ok = potrf_blocked<NP, LD, NW>(sS, invd, sInv, colbuf, &fail);
+    const bool ok = potrf_blocked<NP, kLDI, NW, PackedLds>(sS, invd, sInv, colbuf, &fail);
     if (!ok) {
         if (tid == 0) atomicMin(P.info, (unsigned long long)d.i);
         return;
     }
-    lds_store_as<NP, F, double>(Pr::Lf(P) + (size_t)d.pi * d.nn, sS, n, true, tid, NW * kWave);
+    store_lower_packed<NP, F>(Pr::Lf(P) + (size_t)d.pi * d.nn, sS, n, tid, NW * kWave);
 
-    const int i = lane & 15, q4 = lane >> 4;
     F* tile = sTile[w];
     auto put = [&](const Acc& x) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) tile[Pr::row(v, lane) * kLDI + i] = x[v];
         wave_lds_sync();
     };
-    for (int sidx = w; sidx < 2 * NT16; sidx += NW) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const int sidx = w + j * NW;
+        if (sidx >= 2 * NT16) break;
         const bool isR = sidx < NT16;
         const int t = isR ? sidx : sidx - NT16;
         if (isR ? !d.has_r : !d.has_l) continue;
         F* dst = (isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn;
         const double* C64 = (lvl == 0) ? P.A_off + (size_t)(isR ? d.i - 1 : d.i - 2) * d.nn : nullptr;
-        const F* Cf = dst;  // levels above 0: the incoming coupling sits in the output slot
         Acc X[NT16];
 #pragma unroll
         for (int p = 0; p < NT16; ++p) {
             Acc acc;
+            if (j < PF) {
+                acc = C[j < PF ? j : 0][p];
+            } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int rr = Pr::row(v, lane);
-                const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
-                F x = F(0);
-                if (gr < n && gc < n) x = C64 ? (F)C64[(size_t)gr * n + gc] : Cf[(size_t)gr * n + gc];
-                acc[v] = x;
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = Pr::row(v, lane);
+                    const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
+                    F x = F(0);
+                    if (gr < n && gc < n) x = C64 ? (F)C64[(size_t)gr * n + gc] : dst[(size_t)gr * n + gc];
+                    acc[v] = x;
+                }
             }
 #pragma unroll
             for (int qq = 0; qq < p; ++qq) {
@@ -276,7 +350,7 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave) void k_tiled_potrf_trsm(Lau
 #pragma unroll
                 for (int k = 0; k < kT; k += 4) {
                     F a, b;
-                    const F l = (F)sS[(kT * p + i) * LD + kT * qq + k + q4];  // L[16p+i][16qq+k+q4]
+                    const F l = (F)PackedLds::tile(sS, p, qq)[i * kLDI + k + q4];  // L[16p+i][16qq+k+q4]
                     if (isR) {  // - X_qq L_p,qq^T
                         a = tile[i * kLDI + k + q4];
                         b = l;

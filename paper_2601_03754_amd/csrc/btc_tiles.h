@@ -97,6 +97,26 @@ __device__ __forceinline__ void acc_store_global(const d4& acc, double* __restri
     }
 }
 
+// LDS layouts of the lower triangle of an NP x NP block, addressed by
+// 16 x 16 tiles; tile (a, b) has row stride LDT.
+// Row-major square layout, row stride LD.
+template <int LD>
+struct SquareLds {
+    static constexpr int LDT = LD;
+    template <class T>
+    __device__ static T* tile(T* A, int a, int b) { return A + (kT * a) * LD + kT * b; }
+};
+// Lower tiles only (about half the LDS): tile (a, b), b <= a, at position
+// a(a+1)/2 + b, rows of kLDI elements (conflict-free 16 x 4 operand reads).
+struct PackedLds {
+    static constexpr int LDT = kLDI;
+    static constexpr int kTile = kT * kLDI;
+    template <class T>
+    __device__ static T* tile(T* A, int a, int b) { return A + (a * (a + 1) / 2 + b) * kTile; }
+};
+template <int NP>
+constexpr int packed_lds_elems() { return (NP / kT) * (NP / kT + 1) / 2 * PackedLds::kTile; }
+
 // k-th lower-triangle tile (a, b), b <= a, in row-major order of the triangle.
 __device__ __forceinline__ void tri_tile(int k, int& a, int& b) {
     a = 0;
@@ -247,18 +267,20 @@ __device__ __forceinline__ void tile_inverse(const double* __restrict__ L, int r
 // invd, the inverted diagonal tiles in inv[NP/16] (row stride kLDI).  *fail
 // (LDS, 0 on entry) becomes 1 on a non-positive or NaN pivot; the result is
 // then false for every thread.
-template <int NP, int LD, int NW>
+template <int NP, int LD, int NW, class Lay = SquareLds<LD>>
 __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __restrict__ invd,
                                               double (*__restrict__ inv)[kT * kLDI],
                                               double (*__restrict__ colbuf)[kWave], int* fail) {
     constexpr int NTL = NP / kT;
+    constexpr int LT = Lay::LDT;
     const int tid = threadIdx.x;
     const int w = tid / kWave;
 #pragma unroll 1
     for (int p = 0; p < NTL; ++p) {
         const int c0 = p * kT;
+        double* D = Lay::tile(A, p, p);
         if (w == 0) {
-            const bool ok = potrf_small<kT, LD>(A + c0 * LD + c0, invd + c0);
+            const bool ok = potrf_small<kT, LT>(D, invd + c0);
             if (!ok && (tid & 63) == 0) *fail = 1;
         }
         __syncthreads();
@@ -266,7 +288,7 @@ __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __
         // rows below the diagonal tile: x L_pp^T = a, forward substitution
         const int rows = NP - c0 - kT;
         for (int t = tid; t < rows; t += NW * kWave) {
-            double* row = A + (c0 + kT + t) * LD + c0;
+            double* row = Lay::tile(A, p + 1 + t / kT, p) + (t % kT) * LT;
             double x[kT];
 #pragma unroll
             for (int c = 0; c < kT; ++c) x[c] = row[c];
@@ -274,7 +296,7 @@ __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __
             for (int c = 0; c < kT; ++c) {
                 double acc = x[c];
 #pragma unroll
-                for (int k = 0; k < c; ++k) acc = fma(-x[k], A[(c0 + c) * LD + c0 + k], acc);
+                for (int k = 0; k < c; ++k) acc = fma(-x[k], D[c * LT + k], acc);
                 x[c] = acc * invd[c0 + c];
             }
 #pragma unroll
@@ -286,14 +308,15 @@ __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __
             int ta, tb;
             tri_tile(k, ta, tb);
             const int a = p + 1 + ta, b = p + 1 + tb;
+            double* Tab = Lay::tile(A, a, b);
             d4 acc;
-            acc_load_lds<LD>(acc, A, a * kT, b * kT);
-            mma_tile<LD, LD, false, true, true>(acc, A, a * kT, c0, A, b * kT, c0, kT);
-            acc_store_lds<LD>(acc, A, a * kT, b * kT);
+            acc_load_lds<LT>(acc, Tab, 0, 0);
+            mma_tile<LT, LT, false, true, true>(acc, Lay::tile(A, a, p), 0, 0, Lay::tile(A, b, p), 0, 0, kT);
+            acc_store_lds<LT>(acc, Tab, 0, 0);
         }
         __syncthreads();
     }
-    for (int t = w; t < NTL; t += NW) tile_inverse<LD, double>(A, t * kT, invd, inv[t]);
+    for (int t = w; t < NTL; t += NW) tile_inverse<LT, double>(Lay::tile(A, t, t), 0, invd + t * kT, inv[t]);
     __syncthreads();
     return true;
 }
