@@ -3,11 +3,11 @@
 
 namespace btc {
 
-hipError_t launch_factor_tiled96(const Launch<FactorDesc>& p, int mode, int part, int level_hint, int64_t items,
+hipError_t launch_factor_tiled96(const Launch<FactorDesc>& p, int mode, int part, bool deferred, int64_t items,
                                   hipStream_t st) {
-    if (mode == 2) return launch_tiled_np<96, true, true>(p, part, level_hint, items, st);
-    if (mode == 1) return launch_tiled_np<96, true, false>(p, part, level_hint, items, st);
-    return launch_tiled_np<96, false, false>(p, part, level_hint, items, st);
+    if (mode == 2) return launch_tiled_np<96, true, true>(p, part, deferred, items, st);
+    if (mode == 1) return launch_tiled_np<96, true, false>(p, part, deferred, items, st);
+    return launch_tiled_np<96, false, false>(p, part, deferred, items, st);
 }
 
 }  // namespace btc

@@ -215,8 +215,11 @@ inline int ensure_workspace(btc_handle h, int64_t m) {
     return BTC_OK;
 }
 
-inline btc::FactorDesc factor_desc(btc_handle h, const double* A_diag, const double* A_off) {
+inline int32_t factor_flags(btc_handle h, int level);
+
+inline btc::FactorDesc factor_desc(btc_handle h, const double* A_diag, const double* A_off, int level) {
     btc::FactorDesc d{};
+    d.flags = factor_flags(h, level);
     d.A_diag = A_diag;
     d.A_off = A_off;
     if (is_mixed(h->precision)) {
@@ -263,31 +266,46 @@ inline int factor_kind(btc_handle h, int level) {
     return 1;
 }
 
+inline bool tiled_kind(int kind) { return kind == 3 || kind == 4 || kind == 6; }
+
+// FactorDesc flags of a handle's level step: a level whose step and the
+// next level's step are both tile-parallel applies the right neighbours'
+// T^T T eagerly (its separators then receive both contributions in one
+// pass), and the next level has no deferred updates.
+inline int32_t factor_flags(btc_handle h, int level) {
+    auto eager = [h](int l) {
+        return l >= 0 && l + 1 < h->levels && tiled_kind(factor_kind(h, l)) && tiled_kind(factor_kind(h, l + 1));
+    };
+    return (eager(level) ? btc::kFactorEagerT : 0) | (eager(level - 1) ? btc::kFactorDeferredDone : 0);
+}
+
 // Right-hand-side columns per dependency-chain group of a sweep or residual
 // launch (results do not depend on it).
 inline int sweep_mc(int op, int kind, int np, int64_t m) {
     return (m <= 1 || tune_variant(op, kind, np, 0) == 1) ? 1 : 4;
 }
 
-// level_hint: the level of every item of the launch, or -1 when they differ;
-// part: tile-parallel families only, 0 the whole step or one of its kernels.
-inline hipError_t launch_factor_kind(int kind, const btc::Launch<btc::FactorDesc>& L, int np, int level_hint,
+// deferred: some item of the launch has deferred updates to apply (tile-
+// parallel families: otherwise that kernel is not launched); part: tile-
+// parallel families only, 0 the whole step or one of its kernels.
+inline hipError_t launch_factor_kind(int kind, const btc::Launch<btc::FactorDesc>& L, int np, bool deferred,
                                      int64_t items, hipStream_t st, int part = 0) {
     switch (kind) {
         case 0: return btc::launch_factor_valu(L, np, items, st);
         case 1: return btc::launch_factor_mfma(L, np, items, st);
         case 2: return btc::launch_factor_mixed(L, np, false, items, st);
-        case 3: return btc::launch_factor_tiled(L, np, 0, part, level_hint, items, st);
-        case 4: return btc::launch_factor_tiled(L, np, 1, part, level_hint, items, st);
+        case 3: return btc::launch_factor_tiled(L, np, 0, part, deferred, items, st);
+        case 4: return btc::launch_factor_tiled(L, np, 1, part, deferred, items, st);
         case 5: return btc::launch_factor_mixed(L, np, true, items, st);
-        case 6: return btc::launch_factor_tiled(L, np, 2, part, level_hint, items, st);
+        case 6: return btc::launch_factor_tiled(L, np, 2, part, deferred, items, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 inline hipError_t launch_factor_any(btc_handle h, const btc::Launch<btc::FactorDesc>& L, int64_t items, hipStream_t st) {
     const int np = factor_np(h);
-    return launch_factor_kind(factor_kind(h, L.level), L, np, L.level, items, st);
+    const bool deferred = L.level > 0 && !(L.single.flags & btc::kFactorDeferredDone);
+    return launch_factor_kind(factor_kind(h, L.level), L, np, deferred, items, st);
 }
 
 inline int launch_factor(btc_handle h, const double* A_diag, const double* A_off, hipStream_t st) {
@@ -295,8 +313,8 @@ inline int launch_factor(btc_handle h, const double* A_diag, const double* A_off
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return to_code(e);
     btc::Launch<btc::FactorDesc> L{};
-    L.single = factor_desc(h, A_diag, A_off);
     for (int l = 0; l < h->levels; ++l) {
+        L.single = factor_desc(h, A_diag, A_off, l);
         L.level = l;
         const int64_t nodes = level_nodes(h->N, l);
         e = timed(h, 0, l, st, [&] { return launch_factor_any(h, L, nodes, st); });

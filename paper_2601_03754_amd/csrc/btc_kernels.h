@@ -59,7 +59,7 @@ struct FactorDesc {
     unsigned long long* info;  // ~0 = ok, else smallest failing 1-based block
     int64_t N;
     int32_t n;
-    int32_t pad;
+    int32_t flags;  // kFactorEagerT | kFactorDeferredDone
 };
 
 // Sweeps of one instance; T is the storage type of the factor and vectors.
@@ -125,6 +125,14 @@ struct IrDesc {
     int32_t pad;
 };
 
+// FactorDesc.flags (tile-parallel families).  Eager: the Schur update of a
+// node's right separator S_{i+s} also subtracts T'^T T' of the node's right
+// neighbour at the same level (T' = T_{i+2s}, the separator's other
+// contribution), so no update of a later level is deferred.  Deferred done:
+// the previous level ran eagerly, this level has no deferred updates.
+constexpr int32_t kFactorEagerT = 1;
+constexpr int32_t kFactorDeferredDone = 2;
+
 // Padded compute tile for block size n (0 when unsupported).
 int padded_block(int n);
 int padded_block_mixed(int n);
@@ -133,11 +141,12 @@ hipError_t launch_factor_valu(const Launch<FactorDesc>& p, int np, int64_t items
 hipError_t launch_factor_mfma(const Launch<FactorDesc>& p, int np, int64_t items, hipStream_t st);
 // bf16: Schur / fill products with BF16 operands (FP32 accumulation)
 hipError_t launch_factor_mixed(const Launch<FactorDesc>& p, int np, bool bf16, int64_t items, hipStream_t st);
-// Padded sizes 96 and 128: four tile-parallel launches per level (level_hint
-// 0 skips the deferred-update launch, which has nothing to do at level 0).
+// Padded sizes 64 to 128: three tile-parallel launches per level (deferred
+// false skips the deferred-update launch: level 0, or every item's previous
+// level ran eagerly).
 // mode: 0 FP64, 1 mixed, 2 mixed with BF16 Schur / fill products; part 0 the
 // whole level step, 1..3 one of its three kernels (in that order).
-hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, int mode, int part, int level_hint,
+hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, int mode, int part, bool deferred,
                                int64_t items, hipStream_t st);
 // mc: right-hand-side columns per dependency-chain group (1 or 4; with 4,
 // instances with fewer columns mask the rest).

@@ -34,7 +34,7 @@ __global__ void k_reset_infos(unsigned long long* const* __restrict__ ptrs, int 
 struct Group {
     int op;    // btc_op
     int kind;  // FACTOR: factor kernel family (factor_kind); sweeps: 0 double, 1 float
-    int level = -1;  // FACTOR: common level of the items, -1 if they differ
+    bool deferred = false;  // FACTOR: some item has deferred updates to apply
     int m_max = 1;   // sweeps / residual: largest number of right-hand sides
     int np;
     bool count = false;    // work accounted (profiler on)
@@ -231,8 +231,6 @@ extern "C" {
 
 namespace {
 
-bool tiled_kind(int kind) { return kind == 3 || kind == 4 || kind == 6; }
-
 std::tuple<int, int, int, int> key4(const std::tuple<int, int, int>& k, int part) {
     return std::make_tuple(std::get<0>(k), std::get<1>(k), std::get<2>(k), part);
 }
@@ -248,7 +246,7 @@ void add_work(const btc_runner_s* r, Group& g, const btc_step& s, bool mixed) {
     g.work.items += w.items;
     if (s.op == BTC_OP_FACTOR && tiled_kind(g.kind))
         for (int k = 1; k <= 3; ++k) {
-            const Work pw = tiled_part_work(k, mixed, h->N, h->n, s.level);
+            const Work pw = tiled_part_work(k, mixed, h->N, h->n, s.level, factor_flags(h, s.level));
             g.part[k].bytes += pw.bytes;
             g.part[k].flops += pw.flops;
             g.part[k].items += pw.items;
@@ -349,9 +347,10 @@ void build_call(btc_runner r, int32_t count, const btc_step* steps, hipStream_t 
             g.op = s.op;
             g.kind = kind;
             g.np = np;
-            g.level = g.items.empty() ? s.level : (g.level == s.level ? s.level : -1);
+            const btc::FactorDesc fd = factor_desc(h, h->A_diag, h->A_off, s.level);
+            g.deferred = g.deferred || (s.level > 0 && !(fd.flags & btc::kFactorDeferredDone));
             const int32_t inst = (int32_t)(g.descs.size() / sizeof(btc::FactorDesc));
-            push_desc(g, factor_desc(h, h->A_diag, h->A_off));
+            push_desc(g, fd);
             add_work(r, g, s, mixed);
             const int64_t nodes = level_nodes(h->N, s.level);
             for (int64_t q = 0; q < nodes; ++q) g.items.push_back({inst, s.level, q});
@@ -492,11 +491,11 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
             case BTC_OP_FACTOR: {
                 auto L = make_launch<btc::FactorDesc>(g, dev);
                 if (!split) {
-                    e = launch_factor_kind(g.kind, L, g.np, g.level, items, gs);
+                    e = launch_factor_kind(g.kind, L, g.np, g.deferred, items, gs);
                     break;
                 }
                 // one timing pair per kernel of the tile-parallel step
-                for (int part = 1; part <= 3 && e == hipSuccess; ++part) {
+                for (int part = g.deferred ? 1 : 2; part <= 3 && e == hipSuccess; ++part) {
                     hipEvent_t pa = take_event(r);
                     hipEvent_t pb = pa ? take_event(r) : nullptr;
                     if (!pb) {
@@ -504,7 +503,7 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
                         return BTC_ERR_HIP;
                     }
                     (void)hipEventRecord(pa, gs);
-                    e = launch_factor_kind(g.kind, L, g.np, g.level, items, gs, part);
+                    e = launch_factor_kind(g.kind, L, g.np, g.deferred, items, gs, part);
                     (void)hipEventRecord(pb, gs);
                     r->pending.push_back({std::make_tuple(g.op, g.kind, g.np, part), pa, pb, g.part[part]});
                 }

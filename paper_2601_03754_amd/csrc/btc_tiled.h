@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
     int lvl;
     int64_t kk;
     fetch_item(L, P, lvl, kk);
-    if (*P.info != kInfoOk) return;
+    if (*P.info != kInfoOk || (P.flags & kFactorDeferredDone)) return;
     const Node d = node_of(P, lvl, kk);
     const bool self = (int)blockIdx.y < Cfg::NTRI32;
     if (self ? !d.def_self : !d.def_sep) return;
@@ -390,8 +390,9 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
 }
 
 // ---------------------------------------------------------------------------
-// K4: blockIdx.y < NTRI32: lower tile of S_{i+s} -= R R^T; else fill tile
-// -R T (row-major over the W32 x W32 tiles).
+// K4: blockIdx.y < NTRI32: lower tile of S_{i+s} -= R R^T (eagerly also
+// - T'^T T' with T' = T_{i+2s}, the separator's other contribution); else
+// fill tile -R T (row-major over the W32 x W32 tiles).
 template <int NP, bool MIXED, bool BF16>
 __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     using Pr = Prec<MIXED>;
@@ -399,8 +400,9 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     using Cfg = TiledCfg<NP>;
     constexpr int LDR = NP + 1;  // row panel [32][NP]
     constexpr int LDP = 33;      // column panel [NP][32]
-    __shared__ F pa[32 * LDR];
-    __shared__ F pb[NP * LDP > 32 * LDR ? NP * LDP : 32 * LDR];
+    constexpr int PSZ = NP * LDP > 32 * LDR ? NP * LDP : 32 * LDR;
+    __shared__ F pa[PSZ];
+    __shared__ F pb[PSZ];
     FactorDesc P;
     int lvl;
     int64_t kk;
@@ -427,23 +429,43 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
         stage_panel<NP, 32, LDP, true, 256>(pb, T, n, 32 * b, tid);
     __syncthreads();
     const int sr = w >> 1, sc = w & 1;
-    if (sep && a == b && sr < sc) return;
+    const bool idle = sep && a == b && sr < sc;  // strictly upper sub-tile
     typename Pr::Acc acc = {};
     const int i = lane & 15, q = lane >> 4;
-    if constexpr (BF16) {
-        // R R^T (B[k][c] = R[c][k]) or R T (B[k][c] = T[k][c]) with BF16 operands
-        if (sep)
-            mma_tile_bf16<LDR, LDR, false, true, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
-        else
-            mma_tile_bf16<LDR, LDP, false, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
-    } else {
+    if (!idle) {
+        if constexpr (BF16) {
+            // R R^T (B[k][c] = R[c][k]) or R T (B[k][c] = T[k][c]) with BF16 operands
+            if (sep)
+                mma_tile_bf16<LDR, LDR, false, true, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
+            else
+                mma_tile_bf16<LDR, LDP, false, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
+        } else {
 #pragma unroll 4
-        for (int k = 0; k < NP; k += 4) {
-            const F av = pa[(16 * sr + i) * LDR + k + q];
-            const F bv = sep ? pb[(16 * sc + i) * LDR + k + q] : pb[(k + q) * LDP + 16 * sc + i];
-            acc = Pr::mma(av, bv, acc);
+            for (int k = 0; k < NP; k += 4) {
+                const F av = pa[(16 * sr + i) * LDR + k + q];
+                const F bv = sep ? pb[(16 * sc + i) * LDR + k + q] : pb[(k + q) * LDP + 16 * sc + i];
+                acc = Pr::mma(av, bv, acc);
+            }
         }
     }
+    if (sep && (P.flags & kFactorEagerT) && d.i + 2 * d.s <= d.N) {
+        // the right neighbour's T'^T T' (A[r][k] = T'[k][r], B[k][c] = T'[k][c])
+        const F* T2 = Pr::Tf(P) + (size_t)perm_pos(d.N, lvl, d.i + 2 * d.s) * d.nn;
+        __syncthreads();
+        stage_panel<NP, 32, LDP, true, 256>(pa, T2, n, 32 * a, tid);
+        stage_panel<NP, 32, LDP, true, 256>(pb, T2, n, 32 * b, tid);
+        __syncthreads();
+        if (!idle) {
+            if constexpr (BF16) {
+                mma_tile_bf16<LDP, LDP, true, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
+            } else {
+#pragma unroll 4
+                for (int k = 0; k < NP; k += 4)
+                    acc = Pr::mma(pa[(k + q) * LDP + 16 * sr + i], pb[(k + q) * LDP + 16 * sc + i], acc);
+            }
+        }
+    }
+    if (idle) return;
     if (sep) {
         const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i + d.s - 1) * d.nn : P.Ld + (size_t)d.pr * d.nn;
         double* S = P.Ld + (size_t)d.pr * d.nn;
@@ -467,10 +489,10 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
 // part 0: the whole level step; 1, 2, 3: only K1, K2, K4 (for per-kernel
 // timing; launched in that order they make up the step)
 template <int NP, bool MIXED, bool BF16>
-hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int part, int level_hint, int64_t items, hipStream_t st) {
+hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int part, bool deferred, int64_t items, hipStream_t st) {
     using Cfg = TiledCfg<NP>;
     const unsigned g = (unsigned)items;
-    if ((part == 0 || part == 1) && level_hint != 0)  // level 0 has no deferred updates
+    if ((part == 0 || part == 1) && deferred)
         hipLaunchKernelGGL((k_tiled_syrk_deferred<NP, MIXED, BF16>), dim3(g, 2 * Cfg::NTRI32), dim3(256), 0, st, p);
     if (part == 0 || part == 2)
         hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED>), dim3(g), dim3(k2_waves<NP>() * kWave), 0, st, p);
@@ -484,11 +506,11 @@ hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int part, int level_hint
 
 // Per padded size launchers (one translation unit each).
 // mode: 0 FP64, 1 mixed (FP32 products), 2 mixed with BF16 Schur / fill products
-hipError_t launch_factor_tiled64(const Launch<FactorDesc>& p, int mode, int part, int level_hint, int64_t items,
+hipError_t launch_factor_tiled64(const Launch<FactorDesc>& p, int mode, int part, bool deferred, int64_t items,
                                  hipStream_t st);
-hipError_t launch_factor_tiled96(const Launch<FactorDesc>& p, int mode, int part, int level_hint, int64_t items,
+hipError_t launch_factor_tiled96(const Launch<FactorDesc>& p, int mode, int part, bool deferred, int64_t items,
                                  hipStream_t st);
-hipError_t launch_factor_tiled128(const Launch<FactorDesc>& p, int mode, int part, int level_hint, int64_t items,
+hipError_t launch_factor_tiled128(const Launch<FactorDesc>& p, int mode, int part, bool deferred, int64_t items,
                                   hipStream_t st);
 
 }  // namespace btc

@@ -84,22 +84,26 @@ inline Work level_work(int op, bool mixed, int64_t N, int64_t n, int64_t m, int 
     return w;
 }
 
-// Work of one launch of the tile-parallel factorization (padded sizes above
-// 64) split by kernel: part 1 the deferred syrk (reads T_{i+h}, T_{i+3h},
-// reads and writes the S blocks it updates), part 2 the pivot factorization
-// with both triangular solves (reads S_i and the couplings, writes L_ii, R_i,
-// T_i), part 3 the separator and fill products (reads R_i, T_i and S_{i+s},
-// writes S_{i+s} and the fill).  The parts pass S and the factor blocks
-// through HBM between them, so their sum exceeds the level step's count.
-inline Work tiled_part_work(int part, bool mixed, int64_t N, int64_t n, int level) {
+// Work of one launch of the tile-parallel factorization (padded sizes 64 and
+// above) split by kernel: part 1 the deferred syrk (reads T_{i+h}, T_{i+3h},
+// reads and writes the S blocks it updates; nothing when the previous level
+// ran eagerly), part 2 the pivot factorization with both triangular solves
+// (reads S_i and the couplings, writes L_ii, R_i, T_i), part 3 the separator
+// and fill products (reads R_i, T_i and S_{i+s}, writes S_{i+s} and the fill;
+// eagerly also reads the right neighbour's T_{i+2s} and applies its syrk).
+// The parts pass S and the factor blocks through HBM between them, so their
+// sum exceeds the level step's count.  flags: the FactorDesc flags.
+inline Work tiled_part_work(int part, bool mixed, int64_t N, int64_t n, int level, int flags) {
     Work w;
     const double nn = (double)n * (double)n, n3 = nn * (double)n;
     const double wS = 8.0, wF = mixed ? 4.0 : 8.0, wC = level == 0 ? 8.0 : wF;
     const int64_t s = (int64_t)1 << level, h = s >> 1;
     if (level < 0 || level > 62 || s > N) return w;
+    const bool eager = (flags & 1) != 0, done = (flags & 2) != 0;
     for (int64_t i = s; i <= N; i += 2 * s) {
         const bool hr = i + s <= N, hl = i > s, both = hr && hl;
-        const int def = (level > 0 && i + h <= N) + (level > 0 && hr && i + 3 * h <= N);
+        const int def = done ? 0 : (level > 0 && i + h <= N) + (level > 0 && hr && i + 3 * h <= N);
+        const int nb = eager && hr && i + 2 * s <= N;  // right neighbour's T^T T
         ++w.items;
         if (part == 1) {
             w.bytes += nn * (wF + 2.0 * wS) * def;
@@ -108,8 +112,8 @@ inline Work tiled_part_work(int part, bool mixed, int64_t N, int64_t n, int leve
             w.bytes += nn * (wS + wC * (hr + hl) + wF * (1 + hr + hl));
             w.flops += n3 * (1.0 / 3.0 + hr + hl);
         } else {
-            w.bytes += nn * (wF * (hr + both) + 2.0 * wS * hr + wF * both);
-            w.flops += n3 * (hr + 2.0 * both);
+            w.bytes += nn * (wF * (hr + both + nb) + 2.0 * wS * hr + wF * both);
+            w.flops += n3 * (hr + 2.0 * both + nb);
         }
     }
     return w;
