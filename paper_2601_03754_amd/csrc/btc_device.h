@@ -36,6 +36,40 @@ __host__ __device__ __forceinline__ int level_of(int64_t i) {
     return __builtin_ctzll((unsigned long long)i);
 }
 
+// Buffer-resource access to one block of at most 1 GiB: every offset is
+// range checked against the block's size, so a load at or past the end reads
+// 0 and a store there is dropped, without touching memory.  Masking by
+// offset (kOob) keeps masked loads and stores free of branches and out of
+// the flat address space (whose waits also cover LDS traffic).
+constexpr int kOob = 0x40000000;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void* p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ void buf_ld(double& x, __amdgpu_buffer_rsrc_t r, int off) {
+    x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_ld(float& x, __amdgpu_buffer_rsrc_t r, int off) {
+    x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(double x, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(float x, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, off, 0, 0);
+}
+// Element (r, c) of an n x n row-major block of S: byte offset, or kOob
+// when not `ok`.
+template <class S>
+__device__ __forceinline__ int elem_off(int r, int c, int n, bool ok) {
+    return ok ? (r * n + c) * (int)sizeof(S) : kOob;
+}
+template <class S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t nn_rsrc(const S* p, int n) {
+    return block_rsrc(p, n * n * (int)sizeof(S));
+}
+
 // Broadcast a double from lane `lane` (wave-uniform) to the whole wavefront.
 __device__ __forceinline__ double readlane_d(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);

@@ -31,17 +31,33 @@ struct Launch {
 };
 
 template <class D>
-__device__ __forceinline__ void fetch_item(const Launch<D>& P, D& d, int& level, int64_t& k) {
+__device__ __forceinline__ void fetch_item_at(const Launch<D>& P, int64_t idx, D& d, int& level, int64_t& k) {
     if (P.items) {
-        const WorkItem it = P.items[blockIdx.x];
+        const WorkItem it = P.items[idx];
         d = P.descs[it.inst];
         level = it.level;
         k = it.k;
     } else {
         d = P.single;
         level = P.level;
-        k = blockIdx.x;
+        k = idx;
     }
+}
+
+template <class D>
+__device__ __forceinline__ void fetch_item(const Launch<D>& P, D& d, int& level, int64_t& k) {
+    fetch_item_at(P, blockIdx.x, d, level, k);
+}
+
+// Renumbering of a one-dimensional grid under which consecutive numbers
+// run on the same XCD at about the same time (blocks are dispatched to the
+// 8 XCDs round-robin, each XCD with its own L2): work that shares data
+// should take consecutive numbers.
+__device__ __forceinline__ unsigned xcd_local_block() {
+    constexpr unsigned kXcd = 8;
+    const unsigned g = gridDim.x, b = blockIdx.x;
+    const unsigned x = b % kXcd, per = g / kXcd, rem = g % kXcd;
+    return x * per + (x < rem ? x : rem) + b / kXcd;
 }
 
 // Factorization of one instance.  FP64 path: S_i then L_ii in Ld, couplings

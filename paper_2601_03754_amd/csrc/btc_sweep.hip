@@ -62,20 +62,8 @@ struct Geo {
     static constexpr int RK = kWave / gcd_i(NP, kWave);
 };
 
-// Buffer-resource loads of one n x n block: every offset is range checked
-// against the block's size, so an offset at or past it reads 0 and touches
-// no memory (used for rows and columns beyond n and for skipped parts).
-constexpr int kOob = 0x40000000;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void* p, int bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
-}
-__device__ __forceinline__ void buf_ld(double& x, __amdgpu_buffer_rsrc_t r, int off) {
-    x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ __forceinline__ void buf_ld(float& x, __amdgpu_buffer_rsrc_t r, int off) {
-    x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
+// Slab loads go through buffer resources (block_rsrc): rows and columns
+// beyond n and the skipped parts are masked by offset.
 
 // Where the next slab comes from: column slab (elements M[r][c0+k], rows
 // r >= rmin) or row slab (elements M[r0+k][r], only r <= r0+k when tri).
@@ -471,15 +459,8 @@ __global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
 }
 
 // ---------------------------------------------------------------------------
-// Work item of block index b when consecutive items should share an XCD
-// (blocks are dispatched to the 8 XCDs round-robin).
-__device__ __forceinline__ unsigned xcd_local_block() {
-    constexpr unsigned kXcd = 8;
-    const unsigned g = gridDim.x, b = blockIdx.x;
-    const unsigned x = b % kXcd, per = g / kXcd, rem = g % kXcd;
-    return x * per + (x < rem ? x : rem) + b / kXcd;
-}
-
+// Residual: work items of consecutive block rows share an XCD
+// (xcd_local_block), so the couplings two rows share stay in one L2.
 template <int NP, int MC>
 __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
     using G = Geo<NP>;

@@ -91,102 +91,82 @@ __device__ __forceinline__ Node node_of(const FactorDesc& P, int lvl, int64_t kk
 
 // Stage rows [r0, r0+R) (all NP columns) of an n x n block into LDS as
 // dst[r][k] (row stride LDD), zero padded; or, when COLS, columns [c0, c0+R)
-// (all NP rows) as dst[k][c] (row stride LDD).  NT threads; loads are issued
-// eight at a time per thread before the LDS writes, so they overlap.
+// (all NP rows) as dst[k][c] (row stride LDD).  NT threads; every load of a
+// thread is issued before its LDS writes (buffer loads masked by offset: no
+// branches), so they overlap.
 template <int NP, int R, int LDD, bool COLS, int NT, class S, class F>
 __device__ __forceinline__ void stage_panel(F* __restrict__ dst, const S* __restrict__ src, int n, int r0, int t) {
-    constexpr int TOTAL = NP * R;
-    constexpr int CH = 8;
-    for (int base = 0; base < TOTAL; base += NT * CH) {
-        F v[CH];
+    constexpr int TOTAL = NP * R, CNT = TOTAL / NT;
+    static_assert(CNT * NT == TOTAL, "threads divide the panel");
+    const __amdgpu_buffer_rsrc_t rs = nn_rsrc(src, n);
+    F v[CNT];
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int e = base + t + NT * u;
-            F x = F(0);
-            if (e < TOTAL) {
-                if (COLS) {
-                    const int k = e / R, gc = r0 + e % R;
-                    if (k < n && gc < n) x = (F)src[(size_t)k * n + gc];
-                } else {
-                    const int gr = r0 + e / NP, k = e % NP;
-                    if (gr < n && k < n) x = (F)src[(size_t)gr * n + k];
-                }
-            }
-            v[u] = x;
+    for (int u = 0; u < CNT; ++u) {
+        const int e = t + NT * u;
+        S x;
+        if (COLS) {
+            const int k = e / R, gc = r0 + e % R;
+            buf_ld(x, rs, elem_off<S>(k, gc, n, k < n && gc < n));
+        } else {
+            const int gr = r0 + e / NP, k = e % NP;
+            buf_ld(x, rs, elem_off<S>(gr, k, n, gr < n && k < n));
         }
+        v[u] = (F)x;
+    }
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int e = base + t + NT * u;
-            if (e < TOTAL) {
-                if (COLS)
-                    dst[(e / R) * LDD + e % R] = v[u];
-                else
-                    dst[(e / NP) * LDD + e % NP] = v[u];
-            }
-        }
+    for (int u = 0; u < CNT; ++u) {
+        const int e = t + NT * u;
+        if (COLS)
+            dst[(e / R) * LDD + e % R] = v[u];
+        else
+            dst[(e / NP) * LDD + e % NP] = v[u];
     }
 }
 
-// Whole lower triangle of an n x n FP64 block into an NP x NP LDS tile
-// (identity padding), loads batched as in stage_panel.
-template <int NP, int NT>
-__device__ __forceinline__ void stage_lower(double* __restrict__ dst, const double* __restrict__ src, int n, int t) {
-    constexpr int CH = 8;
-    for (int base = 0; base < NP * NP; base += NT * CH) {
-        double v[CH];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int e = base + t + NT * u, r = e / NP, c = e % NP;
-            double x = (r == c) ? 1.0 : 0.0;
-            if (e < NP * NP && r < n && c <= r) x = src[(size_t)r * n + c];
-            v[u] = x;
-        }
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int e = base + t + NT * u;
-            if (e < NP * NP) dst[(e / NP) * (NP + 1) + e % NP] = v[u];
-        }
-    }
-}
-
-// The same into the packed lower-tile layout (whole diagonal tiles: their
-// strict upper part 0).
+// Whole lower triangle of an n x n FP64 block into the packed lower-tile
+// LDS layout (whole diagonal tiles: their strict upper part 0; identity
+// padding beyond n); loads by buffer resource, masked by offset.
 template <int NP, int NT>
 __device__ __forceinline__ void stage_lower_packed(double* __restrict__ dst, const double* __restrict__ src, int n,
                                                    int t) {
-    constexpr int CH = 8;
-    for (int base = 0; base < NP * NP; base += NT * CH) {
+    constexpr int TOTAL = NP * NP, PER = TOTAL / NT, CH = PER <= 24 ? PER : 16;
+    static_assert(PER * NT == TOTAL && PER % CH == 0, "threads divide the block");
+    const __amdgpu_buffer_rsrc_t rs = nn_rsrc(src, n);
+#pragma unroll 1
+    for (int base = 0; base < TOTAL; base += NT * CH) {
         double v[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int e = base + t + NT * u, r = e / NP, c = e % NP;
-            double x = (r == c) ? 1.0 : 0.0;
-            if (e < NP * NP && r < n && c <= r) x = src[(size_t)r * n + c];
-            v[u] = x;
+            double x;
+            buf_ld(x, rs, elem_off<double>(r, c, n, r < n && c <= r));
+            v[u] = (r == c && r >= n) ? 1.0 : x;
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int e = base + t + NT * u, r = e / NP, c = e % NP;
-            if (e < NP * NP && c / kT <= r / kT) PackedLds::tile(dst, r / kT, c / kT)[(r % kT) * kLDI + c % kT] = v[u];
+            if (c / kT <= r / kT) PackedLds::tile(dst, r / kT, c / kT)[(r % kT) * kLDI + c % kT] = v[u];
         }
     }
 }
 
 // Leading n x n part of a packed lower-tile LDS block to global memory as
-// type D (strict upper triangle written as 0).
+// type D (strict upper triangle written as 0); buffer stores, the part
+// beyond n dropped by offset.
 template <int NP, class D>
 __device__ __forceinline__ void store_lower_packed(D* __restrict__ dst, const double* __restrict__ src, int n, int t,
                                                    int nt) {
+    const __amdgpu_buffer_rsrc_t rs = nn_rsrc(dst, n);
     for (int idx = t; idx < NP * NP; idx += nt) {
         const int r = idx / NP, c = idx % NP;
-        if (r < n && c < n)
-            dst[(size_t)r * n + c] =
-                (D)(c <= r ? PackedLds::tile(src, r / kT, c / kT)[(r % kT) * kLDI + c % kT] : 0.0);
+        const double x = c <= r ? PackedLds::tile(src, r / kT, c / kT)[(r % kT) * kLDI + c % kT] : 0.0;
+        buf_st((D)x, rs, elem_off<D>(r, c, n, r < n && c < n));
     }
 }
 
 // ---------------------------------------------------------------------------
-// K1: deferred syrk.  blockIdx.y < NTRI32: tile of S_i; else tile of S_{i+s}.
+// K1: deferred syrk.  Tile number ty < NTRI32 of a node: tile of S_i; else
+// tile of S_{i+s}.
 template <int NP, bool MIXED, bool BF16>
 __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> L) {
     using Pr = Prec<MIXED>;
@@ -198,13 +178,15 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
     FactorDesc P;
     int lvl;
     int64_t kk;
-    fetch_item(L, P, lvl, kk);
+    // the tiles of one node take consecutive numbers on one XCD (shared panels)
+    const unsigned blk = xcd_local_block(), ty = blk % (2 * Cfg::NTRI32);
+    fetch_item_at(L, blk / (2 * Cfg::NTRI32), P, lvl, kk);
     if (*P.info != kInfoOk || (P.flags & kFactorDeferredDone)) return;
     const Node d = node_of(P, lvl, kk);
-    const bool self = (int)blockIdx.y < Cfg::NTRI32;
+    const bool self = (int)ty < Cfg::NTRI32;
     if (self ? !d.def_self : !d.def_sep) return;
     int a, b;
-    tri_tile(self ? blockIdx.y : blockIdx.y - Cfg::NTRI32, a, b);
+    tri_tile(self ? ty : ty - Cfg::NTRI32, a, b);
     const int64_t src_node = self ? d.i + d.h : d.i + 3 * d.h;
     const F* Tsrc = Pr::Tf(P) + (size_t)perm_pos(d.N, lvl - 1, src_node) * d.nn;
     double* S = P.Ld + (size_t)(self ? d.pi : d.pr) * d.nn;
@@ -224,10 +206,14 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
         for (int k = 0; k < NP; k += 4)
             acc = Pr::mma(pa[(k + q) * LDP + 16 * sr + i], pb[(k + q) * LDP + 16 * sc + i], acc);
     }
+    const __amdgpu_buffer_rsrc_t rs = nn_rsrc(S, d.n);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int r = 32 * a + 16 * sr + Pr::row(v, lane), c = 32 * b + 16 * sc + (lane & 15);
-        if (r < d.n && c < d.n) S[(size_t)r * d.n + c] -= (double)acc[v];
+        const int off = elem_off<double>(r, c, d.n, r < d.n && c < d.n);
+        double x;
+        buf_ld(x, rs, off);
+        buf_st(x - (double)acc[v], rs, off);
     }
 }
 
@@ -279,6 +265,32 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
     const int n = d.n;
     const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i - 1) * d.nn : P.Ld + (size_t)d.pi * d.nn;
     const int i = lane & 15, q4 = lane >> 4;
+    // Tile p of strip t of the coupling C_{i+s,i} (isR: R strips are 16-row
+    // strips) or C_{i,i-s} (16-column strips), in the accumulator layout:
+    // level 0 reads the input couplings (FP64), higher levels the coupling
+    // left in the output slot by the previous level.
+    auto load_coupling = [&](bool isR, int t, int p, bool live) {
+        Acc acc;
+        const int64_t cblk = isR ? d.i - 1 : d.i - 2;
+        const __amdgpu_buffer_rsrc_t r64 = nn_rsrc(P.A_off + (size_t)(lvl == 0 && live ? cblk : 0) * d.nn, n);
+        const __amdgpu_buffer_rsrc_t rf = nn_rsrc((isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn, n);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = Pr::row(v, lane);
+            const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
+            const bool ok = live && gr < n && gc < n;
+            if (lvl == 0) {
+                double x;
+                buf_ld(x, r64, elem_off<double>(gr, gc, n, ok));
+                acc[v] = (F)x;
+            } else {
+                F x;
+                buf_ld(x, rf, elem_off<F>(gr, gc, n, ok));
+                acc[v] = x;
+            }
+        }
+        return acc;
+    };
     // This wavefront's strips (w and w + NW), their coupling tiles loaded
     // into registers before the pivot factorization so that the loads
     // complete behind it.
@@ -290,18 +302,8 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
         const bool isR = sidx < NT16;
         const int t = isR ? sidx : sidx - NT16;
         const bool live = sidx < 2 * NT16 && (isR ? d.has_r : d.has_l);
-        const double* C64 = (lvl == 0) ? P.A_off + (size_t)(isR ? d.i - 1 : d.i - 2) * d.nn : nullptr;
-        const F* Cf = (isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn;  // levels above 0: the output slot
 #pragma unroll
-        for (int p = 0; p < NT16; ++p)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int rr = Pr::row(v, lane);
-                const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
-                F x = F(0);
-                if (live && gr < n && gc < n) x = C64 ? (F)C64[(size_t)gr * n + gc] : Cf[(size_t)gr * n + gc];
-                C[j][p][v] = x;
-            }
+        for (int p = 0; p < NT16; ++p) C[j][p] = load_coupling(isR, t, p, live);
     }
     stage_lower_packed<NP, NW * kWave>(sS, src, n, tid);
     if (tid == 0) fail = 0;
@@ -326,24 +328,15 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
         const bool isR = sidx < NT16;
         const int t = isR ? sidx : sidx - NT16;
         if (isR ? !d.has_r : !d.has_l) continue;
-        F* dst = (isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn;
-        const double* C64 = (lvl == 0) ? P.A_off + (size_t)(isR ? d.i - 1 : d.i - 2) * d.nn : nullptr;
+        const __amdgpu_buffer_rsrc_t rdst = nn_rsrc((isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn, n);
         Acc X[NT16];
 #pragma unroll
         for (int p = 0; p < NT16; ++p) {
             Acc acc;
-            if (j < PF) {
+            if (j < PF)
                 acc = C[j < PF ? j : 0][p];
-            } else {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int rr = Pr::row(v, lane);
-                    const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
-                    F x = F(0);
-                    if (gr < n && gc < n) x = C64 ? (F)C64[(size_t)gr * n + gc] : dst[(size_t)gr * n + gc];
-                    acc[v] = x;
-                }
-            }
+            else
+                acc = load_coupling(isR, t, p, true);
 #pragma unroll
             for (int qq = 0; qq < p; ++qq) {
                 put(X[qq]);
@@ -383,14 +376,14 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
             for (int v = 0; v < 4; ++v) {
                 const int rr = Pr::row(v, lane);
                 const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
-                if (gr < n && gc < n) dst[(size_t)gr * n + gc] = out[v];
+                buf_st(out[v], rdst, elem_off<F>(gr, gc, n, gr < n && gc < n));
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// K4: blockIdx.y < NTRI32: lower tile of S_{i+s} -= R R^T (eagerly also
+// K4: tile number ty < NTRI32 of a node: lower tile of S_{i+s} -= R R^T (eagerly also
 // - T'^T T' with T' = T_{i+2s}, the separator's other contribution); else
 // fill tile -R T (row-major over the W32 x W32 tiles).
 template <int NP, bool MIXED, bool BF16>
@@ -406,17 +399,20 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     FactorDesc P;
     int lvl;
     int64_t kk;
-    fetch_item(L, P, lvl, kk);
+    // the tiles of one node take consecutive numbers on one XCD (shared panels)
+    constexpr int NTILE = Cfg::NTRI32 + Cfg::W32 * Cfg::W32;
+    const unsigned blk = xcd_local_block(), ty = blk % NTILE;
+    fetch_item_at(L, blk / NTILE, P, lvl, kk);
     if (*P.info != kInfoOk) return;
     const Node d = node_of(P, lvl, kk);
-    const bool sep = (int)blockIdx.y < Cfg::NTRI32;
+    const bool sep = (int)ty < Cfg::NTRI32;
     if (sep ? !d.has_r : !(d.has_r && d.has_l)) return;
     int a, b;
     if (sep) {
-        tri_tile(blockIdx.y, a, b);
+        tri_tile(ty, a, b);
     } else {
-        a = (blockIdx.y - Cfg::NTRI32) / Cfg::W32;
-        b = (blockIdx.y - Cfg::NTRI32) % Cfg::W32;
+        a = (ty - Cfg::NTRI32) / Cfg::W32;
+        b = (ty - Cfg::NTRI32) % Cfg::W32;
     }
     const int tid = threadIdx.x, w = tid / kWave, lane = tid & 63;
     const int n = d.n;
@@ -468,20 +464,24 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     if (idle) return;
     if (sep) {
         const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i + d.s - 1) * d.nn : P.Ld + (size_t)d.pr * d.nn;
-        double* S = P.Ld + (size_t)d.pr * d.nn;
+        const __amdgpu_buffer_rsrc_t rsrc = nn_rsrc(src, n), rs = nn_rsrc(P.Ld + (size_t)d.pr * d.nn, n);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = 32 * a + 16 * sr + Pr::row(v, lane), c = 32 * b + 16 * sc + (lane & 15);
-            if (r < n && c < n) S[(size_t)r * n + c] = src[(size_t)r * n + c] - (double)acc[v];
+            const int off = elem_off<double>(r, c, n, r < n && c < n);
+            double x;
+            buf_ld(x, rsrc, off);
+            buf_st(x - (double)acc[v], rs, off);
         }
     } else {
         const int64_t lft = d.i - d.s, rgt = d.i + d.s;
         F* dst = (((lft >> (lvl + 1)) & 1) != 0) ? Pr::Rf(P) + (size_t)perm_pos(d.N, lvl + 1, lft) * d.nn
                                                  : Pr::Tf(P) + (size_t)perm_pos(d.N, lvl + 1, rgt) * d.nn;
+        const __amdgpu_buffer_rsrc_t rd = nn_rsrc(dst, n);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = 32 * a + 16 * sr + Pr::row(v, lane), c = 32 * b + 16 * sc + (lane & 15);
-            if (r < n && c < n) dst[(size_t)r * n + c] = -acc[v];
+            buf_st(-acc[v], rd, elem_off<F>(r, c, n, r < n && c < n));
         }
     }
 }
@@ -493,11 +493,11 @@ hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int part, bool deferred,
     using Cfg = TiledCfg<NP>;
     const unsigned g = (unsigned)items;
     if ((part == 0 || part == 1) && deferred)
-        hipLaunchKernelGGL((k_tiled_syrk_deferred<NP, MIXED, BF16>), dim3(g, 2 * Cfg::NTRI32), dim3(256), 0, st, p);
+        hipLaunchKernelGGL((k_tiled_syrk_deferred<NP, MIXED, BF16>), dim3(g * 2 * Cfg::NTRI32), dim3(256), 0, st, p);
     if (part == 0 || part == 2)
         hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED>), dim3(g), dim3(k2_waves<NP>() * kWave), 0, st, p);
     if (part == 0 || part == 3)
-        hipLaunchKernelGGL((k_tiled_update<NP, MIXED, BF16>), dim3(g, Cfg::NTRI32 + Cfg::W32 * Cfg::W32), dim3(256),
+        hipLaunchKernelGGL((k_tiled_update<NP, MIXED, BF16>), dim3(g * (Cfg::NTRI32 + Cfg::W32 * Cfg::W32)), dim3(256),
                            0, st, p);
     return hipGetLastError();
 }
