@@ -202,9 +202,13 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
         // (T^T T) tile with BF16 operands: A[r][k] = T[k][r], B[k][c] = T[k][c]
         mma_tile_bf16<LDP, LDP, true, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
     } else {
+        typename Pr::Acc acc1 = {};
 #pragma unroll 4
-        for (int k = 0; k < NP; k += 4)
+        for (int k = 0; k < NP; k += 8) {
             acc = Pr::mma(pa[(k + q) * LDP + 16 * sr + i], pb[(k + q) * LDP + 16 * sc + i], acc);
+            acc1 = Pr::mma(pa[(k + 4 + q) * LDP + 16 * sr + i], pb[(k + 4 + q) * LDP + 16 * sc + i], acc1);
+        }
+        acc += acc1;
     }
     const __amdgpu_buffer_rsrc_t rs = nn_rsrc(S, d.n);
 #pragma unroll
@@ -436,12 +440,17 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
             else
                 mma_tile_bf16<LDR, LDP, false, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
         } else {
+            // two independent accumulation chains (hide the matrix-core latency)
+            typename Pr::Acc acc1 = {};
 #pragma unroll 4
-            for (int k = 0; k < NP; k += 4) {
-                const F av = pa[(16 * sr + i) * LDR + k + q];
-                const F bv = sep ? pb[(16 * sc + i) * LDR + k + q] : pb[(k + q) * LDP + 16 * sc + i];
-                acc = Pr::mma(av, bv, acc);
+            for (int k = 0; k < NP; k += 8) {
+                const F a0 = pa[(16 * sr + i) * LDR + k + q], a1 = pa[(16 * sr + i) * LDR + k + 4 + q];
+                const F b0 = sep ? pb[(16 * sc + i) * LDR + k + q] : pb[(k + q) * LDP + 16 * sc + i];
+                const F b1 = sep ? pb[(16 * sc + i) * LDR + k + 4 + q] : pb[(k + 4 + q) * LDP + 16 * sc + i];
+                acc = Pr::mma(a0, b0, acc);
+                acc1 = Pr::mma(a1, b1, acc1);
             }
+            acc += acc1;
         }
     }
     if (sep && (P.flags & kFactorEagerT) && d.i + 2 * d.s <= d.N) {
@@ -455,9 +464,13 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
             if constexpr (BF16) {
                 mma_tile_bf16<LDP, LDP, true, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
             } else {
+                typename Pr::Acc acc1 = {};
 #pragma unroll 4
-                for (int k = 0; k < NP; k += 4)
+                for (int k = 0; k < NP; k += 8) {
                     acc = Pr::mma(pa[(k + q) * LDP + 16 * sr + i], pb[(k + q) * LDP + 16 * sc + i], acc);
+                    acc1 = Pr::mma(pa[(k + 4 + q) * LDP + 16 * sr + i], pb[(k + 4 + q) * LDP + 16 * sc + i], acc1);
+                }
+                acc += acc1;
             }
         }
     }
