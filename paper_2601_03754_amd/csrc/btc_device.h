@@ -70,6 +70,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t nn_rsrc(const S* p, int n) {
     return block_rsrc(p, n * n * (int)sizeof(S));
 }
 
+// Index of the calling wavefront in its workgroup, as a wave-uniform
+// (scalar) value: work selected by it then keeps its addresses and buffer
+// resources in scalar registers.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave); }
+
 // Broadcast a double from lane `lane` (wave-uniform) to the whole wavefront.
 __device__ __forceinline__ double readlane_d(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);

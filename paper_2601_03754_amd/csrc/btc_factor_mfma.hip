@@ -56,7 +56,7 @@ __global__ __launch_bounds__(MfmaCfg<NP>::NT) void k_factor_level_mfma(Launch<Fa
     if (*P.info != kInfoOk) return;  // an earlier level broke down
 
     const int tid = threadIdx.x;
-    const int w = tid / kWave;
+    const int w = wave_id();
     const int64_t N = P.N;
     const int n = P.n;
     const size_t nn = (size_t)n * n;

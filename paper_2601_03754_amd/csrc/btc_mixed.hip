@@ -67,7 +67,7 @@ __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(Launch<Fa
     if (*P.info != kInfoOk) return;
 
     const int tid = threadIdx.x;
-    const int w = tid / kWave;
+    const int w = wave_id();
     const int64_t N = P.N;
     const int n = P.n;
     const size_t nn = (size_t)n * n;

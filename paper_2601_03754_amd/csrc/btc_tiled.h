@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
     const int64_t src_node = self ? d.i + d.h : d.i + 3 * d.h;
     const F* Tsrc = Pr::Tf(P) + (size_t)perm_pos(d.N, lvl - 1, src_node) * d.nn;
     double* S = P.Ld + (size_t)(self ? d.pi : d.pr) * d.nn;
-    const int tid = threadIdx.x, w = tid / kWave, lane = tid & 63;
+    const int tid = threadIdx.x, w = wave_id(), lane = tid & 63;
     stage_panel<NP, 32, LDP, true, 256>(pa, Tsrc, d.n, 32 * a, tid);
     stage_panel<NP, 32, LDP, true, 256>(pb, Tsrc, d.n, 32 * b, tid);
     __syncthreads();
@@ -230,20 +230,16 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
 // tile by tile: X_p = (C_p - sum_{q<p} X_q L_pq^T) Dinv_p^T for R (the
 // transposed products for T), the solved tiles held in registers and passed
 // to the matrix cores through a one-tile LDS scratch per wavefront, the
-// coupling tiles read straight from HBM into the accumulator layout (issued
-// before the pivot factorization, which hides their latency).
+// coupling tiles read straight from HBM into the accumulator layout, two
+// tiles ahead of their use.
 // Wavefronts of K2: eight while the LDS allows it (more strips solved at
 // once), four at padded size 128.
 template <int NP>
 constexpr int k2_waves() { return NP <= 96 ? 8 : 4; }
 // Workgroups of K2 per compute unit the LDS allows (the register budget is
-// held to it: the second launch bound counts wavefronts per SIMD) and strips per wavefront whose coupling tiles are prefetched.
+// held to it: the second launch bound counts wavefronts per SIMD).
 template <int NP>
 constexpr int k2_blocks() { return NP <= 96 ? 2 : 1; }
-template <int NP, bool MIXED>
-constexpr int k2_prefetch() {
-    return NP >= 96 ? 0 : MIXED ? (2 * (NP / 16) + k2_waves<NP>() - 1) / k2_waves<NP>() : 0;
-}
 
 template <int NP, bool MIXED>
 __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<NP>() / 4) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
@@ -265,7 +261,7 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
     fetch_item(L, P, lvl, kk);
     if (*P.info != kInfoOk) return;
     const Node d = node_of(P, lvl, kk);
-    const int tid = threadIdx.x, w = tid / kWave, lane = tid & 63;
+    const int tid = threadIdx.x, w = wave_id(), lane = tid & 63;
     const int n = d.n;
     const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i - 1) * d.nn : P.Ld + (size_t)d.pi * d.nn;
     const int i = lane & 15, q4 = lane >> 4;
@@ -295,20 +291,7 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
         }
         return acc;
     };
-    // This wavefront's strips (w and w + NW), their coupling tiles loaded
-    // into registers before the pivot factorization so that the loads
-    // complete behind it.
-    constexpr int NS = (2 * NT16 + NW - 1) / NW, PF = k2_prefetch<NP, MIXED>();
-    Acc C[PF > 0 ? PF : 1][NT16];
-#pragma unroll
-    for (int j = 0; j < PF; ++j) {
-        const int sidx = w + j * NW;
-        const bool isR = sidx < NT16;
-        const int t = isR ? sidx : sidx - NT16;
-        const bool live = sidx < 2 * NT16 && (isR ? d.has_r : d.has_l);
-#pragma unroll
-        for (int p = 0; p < NT16; ++p) C[j][p] = load_coupling(isR, t, p, live);
-    }
+    constexpr int NS = (2 * NT16 + NW - 1) / NW;  // strips per wavefront (w, w + NW, ...)
     stage_lower_packed<NP, NW * kWave>(sS, src, n, tid);
     if (tid == 0) fail = 0;
     __syncthreads();
@@ -334,13 +317,16 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
         if (isR ? !d.has_r : !d.has_l) continue;
         const __amdgpu_buffer_rsrc_t rdst = nn_rsrc((isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn, n);
         Acc X[NT16];
+        // the couplings of the next two tiles are in flight while this one
+        // is solved (the solved tiles are stored after the strip, so no
+        // store sits between a load and its wait)
+        Acc nx0 = load_coupling(isR, t, 0, true), nx1 = {};
+        if (NT16 > 1) nx1 = load_coupling(isR, t, 1, true);
 #pragma unroll
         for (int p = 0; p < NT16; ++p) {
-            Acc acc;
-            if (j < PF)
-                acc = C[j < PF ? j : 0][p];
-            else
-                acc = load_coupling(isR, t, p, true);
+            Acc acc = nx0;
+            nx0 = nx1;
+            if (p + 2 < NT16) nx1 = load_coupling(isR, t, p + 2, true);
 #pragma unroll
             for (int qq = 0; qq < p; ++qq) {
                 put(X[qq]);
@@ -376,13 +362,15 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
             }
             wave_lds_sync();
             X[p] = out;
+        }
+#pragma unroll
+        for (int p = 0; p < NT16; ++p)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int rr = Pr::row(v, lane);
                 const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
-                buf_st(out[v], rdst, elem_off<F>(gr, gc, n, gr < n && gc < n));
+                buf_st(X[p][v], rdst, elem_off<F>(gr, gc, n, gr < n && gc < n));
             }
-        }
     }
 }
 
@@ -418,7 +406,7 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
         a = (ty - Cfg::NTRI32) / Cfg::W32;
         b = (ty - Cfg::NTRI32) % Cfg::W32;
     }
-    const int tid = threadIdx.x, w = tid / kWave, lane = tid & 63;
+    const int tid = threadIdx.x, w = wave_id(), lane = tid & 63;
     const int n = d.n;
     const F* R = Pr::Rf(P) + (size_t)d.pi * d.nn;
     const F* T = Pr::Tf(P) + (size_t)d.pi * d.nn;

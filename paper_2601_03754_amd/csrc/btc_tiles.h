@@ -274,7 +274,7 @@ __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __
     constexpr int NTL = NP / kT;
     constexpr int LT = Lay::LDT;
     const int tid = threadIdx.x;
-    const int w = tid / kWave;
+    const int w = wave_id();
 #pragma unroll 1
     for (int p = 0; p < NTL; ++p) {
         const int c0 = p * kT;
