@@ -15,8 +15,9 @@
 //       substitution with the inverted diagonal tiles, all products MFMA)
 //   K4  one 256-thread workgroup per 32 x 32 tile of S_{i+s} -= R_i R_i^T
 //       (lower tiles) and of the fill -R_i T_i
-// In mixed precision the Schur complements and K2 stay FP64 and the products
-// of K1, K3, K4 run on FP32 matrix cores (FP32 factor storage); the BF16
+// In mixed precision the Schur complements and K2 stay FP64 (its solves too;
+// R_i and T_i are rounded to FP32 when stored) and the products of K1 and K4
+// run on FP32 matrix cores (FP32 factor storage); the BF16
 // variant rounds the operands of the K1 and K4 products to BF16 (FP32
 // accumulation).
 #pragma once
@@ -243,15 +244,16 @@ constexpr int k2_blocks() { return NP <= 96 ? 2 : 1; }
 
 template <int NP, bool MIXED>
 __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<NP>() / 4) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
-    using Pr = Prec<MIXED>;
+    using Pr = Prec<MIXED>;  // storage of the factor blocks
+    using Pm = Prec<false>;  // the solves run in FP64 (latency bound: no gain from FP32)
     using F = typename Pr::F;
-    using Acc = typename Pr::Acc;
+    using Acc = typename Pm::Acc;
     using Cfg = TiledCfg<NP>;
     constexpr int NT16 = Cfg::NT16;
     constexpr int NW = k2_waves<NP>();
     __shared__ double sS[packed_lds_elems<NP>()];  // lower tiles of S_i, then of L_ii
     __shared__ double sInv[NT16][kT * kLDI];
-    __shared__ F sTile[NW][kT * kLDI];
+    __shared__ double sTile[NW][kT * kLDI];
     __shared__ double invd[NP];
     __shared__ __align__(16) double colbuf[2][kWave];
     __shared__ int fail;
@@ -276,13 +278,13 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
         const __amdgpu_buffer_rsrc_t rf = nn_rsrc((isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn, n);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int rr = Pr::row(v, lane);
+            const int rr = Pm::row(v, lane);
             const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
             const bool ok = live && gr < n && gc < n;
             if (lvl == 0) {
                 double x;
                 buf_ld(x, r64, elem_off<double>(gr, gc, n, ok));
-                acc[v] = (F)x;
+                acc[v] = x;
             } else {
                 F x;
                 buf_ld(x, rf, elem_off<F>(gr, gc, n, ok));
@@ -302,10 +304,10 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
     }
     store_lower_packed<NP, F>(Pr::Lf(P) + (size_t)d.pi * d.nn, sS, n, tid, NW * kWave);
 
-    F* tile = sTile[w];
+    double* tile = sTile[w];
     auto put = [&](const Acc& x) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) tile[Pr::row(v, lane) * kLDI + i] = x[v];
+        for (int v = 0; v < 4; ++v) tile[Pm::row(v, lane) * kLDI + i] = x[v];
         wave_lds_sync();
     };
 #pragma unroll
@@ -332,8 +334,8 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
                 put(X[qq]);
 #pragma unroll
                 for (int k = 0; k < kT; k += 4) {
-                    F a, b;
-                    const F l = (F)PackedLds::tile(sS, p, qq)[i * kLDI + k + q4];  // L[16p+i][16qq+k+q4]
+                    double a, b;
+                    const double l = PackedLds::tile(sS, p, qq)[i * kLDI + k + q4];  // L[16p+i][16qq+k+q4]
                     if (isR) {  // - X_qq L_p,qq^T
                         a = tile[i * kLDI + k + q4];
                         b = l;
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
                         a = l;
                         b = tile[(k + q4) * kLDI + i];
                     }
-                    acc = Pr::mma(-a, b, acc);
+                    acc = Pm::mma(-a, b, acc);
                 }
                 wave_lds_sync();
             }
@@ -349,8 +351,8 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
             Acc out = {};
 #pragma unroll
             for (int k = 0; k < kT; k += 4) {
-                const F dv = (F)sInv[p][i * kLDI + k + q4];  // Dinv_p[i][k+q4]
-                F a, b;
+                const double dv = sInv[p][i * kLDI + k + q4];  // Dinv_p[i][k+q4]
+                double a, b;
                 if (isR) {  // Y Dinv_p^T
                     a = tile[i * kLDI + k + q4];
                     b = dv;
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
                     a = dv;
                     b = tile[(k + q4) * kLDI + i];
                 }
-                out = Pr::mma(a, b, out);
+                out = Pm::mma(a, b, out);
             }
             wave_lds_sync();
             X[p] = out;
@@ -367,9 +369,9 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
         for (int p = 0; p < NT16; ++p)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int rr = Pr::row(v, lane);
+                const int rr = Pm::row(v, lane);
                 const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
-                buf_st(X[p][v], rdst, elem_off<F>(gr, gc, n, gr < n && gc < n));
+                buf_st((F)X[p][v], rdst, elem_off<F>(gr, gc, n, gr < n && gc < n));
             }
     }
 }
