@@ -260,7 +260,9 @@ __device__ __forceinline__ void tile_inverse(const double* __restrict__ L, int r
 // 16-column panels: wavefront 0 factors the diagonal tile (potrf_small); the
 // rows below it are solved against it by substitution, one row per thread
 // (L_tp = A_tp L_pp^{-T}); the trailing lower tiles are updated, A_ab -=
-// L_ap L_bp^T (matrix cores, tiles spread over the wavefronts).  The 16 x 16
+// L_ap L_bp^T (matrix cores, tiles spread over the wavefronts), wavefront 0
+// taking the next diagonal tile and factoring it right away (look-ahead:
+// the pivot chain does not wait for the rest of the trailing update).  The 16 x 16
 // diagonal tiles are inverted at the end, off the pivot chain, spread over
 // the wavefronts.  On return: L in the lower triangle (strict upper part of
 // each diagonal tile zeroed, tiles above the diagonal untouched), 1/L_jj in
@@ -273,19 +275,21 @@ __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __
                                               double (*__restrict__ colbuf)[kWave], int* fail) {
     constexpr int NTL = NP / kT;
     constexpr int LT = Lay::LDT;
+    static_assert(NW >= 2 || NTL == 1, "the look-ahead needs a second wavefront");
     const int tid = threadIdx.x;
     const int w = wave_id();
+    if (w == 0) {
+        const bool ok = potrf_small<kT, LT>(Lay::tile(A, 0, 0), invd);
+        if (!ok && (tid & 63) == 0) *fail = 1;
+    }
+    __syncthreads();
+    if (*fail) return false;
 #pragma unroll 1
     for (int p = 0; p < NTL; ++p) {
         const int c0 = p * kT;
-        double* D = Lay::tile(A, p, p);
-        if (w == 0) {
-            const bool ok = potrf_small<kT, LT>(D, invd + c0);
-            if (!ok && (tid & 63) == 0) *fail = 1;
-        }
-        __syncthreads();
-        if (*fail) return false;
+        const double* D = Lay::tile(A, p, p);
         // rows below the diagonal tile: x L_pp^T = a, forward substitution
+        // by columns (each finished x_c updates the later ones independently)
         const int rows = NP - c0 - kT;
         for (int t = tid; t < rows; t += NW * kWave) {
             double* row = Lay::tile(A, p + 1 + t / kT, p) + (t % kT) * LT;
@@ -294,17 +298,20 @@ __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __
             for (int c = 0; c < kT; ++c) x[c] = row[c];
 #pragma unroll
             for (int c = 0; c < kT; ++c) {
-                double acc = x[c];
+                x[c] *= invd[c0 + c];
 #pragma unroll
-                for (int k = 0; k < c; ++k) acc = fma(-x[k], D[c * LT + k], acc);
-                x[c] = acc * invd[c0 + c];
+                for (int k = c + 1; k < kT; ++k) x[k] = fma(-x[c], D[k * LT + c], x[k]);
             }
 #pragma unroll
             for (int c = 0; c < kT; ++c) row[c] = x[c];
         }
         __syncthreads();
         const int m = NTL - 1 - p;
-        for (int k = w; k < m * (m + 1) / 2; k += NW) {
+        if (m == 0) break;
+        // trailing update A_ab -= L_ap L_bp^T.  Look-ahead: wavefront 0
+        // updates the next diagonal tile and factors it at once, while the
+        // others update the rest of the trailing tiles.
+        auto update = [&](int k) {
             int ta, tb;
             tri_tile(k, ta, tb);
             const int a = p + 1 + ta, b = p + 1 + tb;
@@ -313,8 +320,17 @@ __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __
             acc_load_lds<LT>(acc, Tab, 0, 0);
             mma_tile<LT, LT, false, true, true>(acc, Lay::tile(A, a, p), 0, 0, Lay::tile(A, b, p), 0, 0, kT);
             acc_store_lds<LT>(acc, Tab, 0, 0);
+        };
+        if (w == 0) {
+            update(0);
+            wave_lds_sync();
+            const bool ok = potrf_small<kT, LT>(Lay::tile(A, p + 1, p + 1), invd + c0 + kT);
+            if (!ok && (tid & 63) == 0) *fail = 1;
+        } else {
+            for (int k = w; k < m * (m + 1) / 2; k += NW - 1) update(k);
         }
         __syncthreads();
+        if (*fail) return false;
     }
     for (int t = w; t < NTL; t += NW) tile_inverse<LT, double>(Lay::tile(A, t, t), 0, invd + t * kT, inv[t]);
     __syncthreads();
