@@ -363,9 +363,20 @@ def run_single(args, btc):
                         "bytes": b * cnt[l], "flops": fl * cnt[l], "level": l}
     roof = roofline_entry(best)
     roof["kernel"] = "%s level %d" % (OPS[best["op"]], best["level"])
+    # per level step: microseconds per launch and algorithmic GB/s
+    levels = {}
+    for op, ph in enumerate(("factor", "forward", "backward")):
+        ms, cnt = prof[ph]
+        row = []
+        for l in range(len(ms)):
+            if cnt[l] > 0:
+                b, _ = btc.btc_level_work(op, prec, N, n, m, l)
+                us = ms[l] / cnt[l] * 1e3
+                row.append([l, round(us, 1), round(b / (us * 1e-6) / 1e9, 1)])
+        levels[ph] = row
     f.close()
     return {"value": args.steps / wall, "ms_per_step": wall * 1e3 / args.steps, "relres": relres,
-            "roofline": roof, "seed": seed}
+            "roofline": roof, "seed": seed, "levels": levels}
 
 
 def main():
@@ -442,7 +453,8 @@ def main():
                 "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
                 "config": {"workload": "single instance factor+solve, refactor every step", "N": args.N,
                            "n": args.n, "nrhs": args.nrhs, "diag_shift": 4.0, "precision": args.precision},
-                "relres": r["relres"], "roofline": r["roofline"], "cpu_baseline": cpu}
+                "relres": r["relres"], "roofline": r["roofline"], "cpu_baseline": cpu,
+                "levels_us_gbs": r["levels"]}
         print(json.dumps(line))
         return
 
