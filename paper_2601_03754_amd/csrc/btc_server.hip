@@ -20,10 +20,10 @@
 //     run as "refactor + solve" with the client's last matrix.
 // Completion: each tick records an event; a request completes when the event
 // of the tick holding its last step has fired.  A mixed-precision request
-// whose refinement has converged is retired early: the convergence flag of
-// every test step is copied back asynchronously and read when its tick's
-// event fires; the steps still queued for that request would only have
-// returned at once.
+// whose refinement has converged is retired early: the convergence flags of
+// a tick's test steps are written into pinned host memory by one small
+// kernel after them and read when the tick's event fires; the steps still
+// queued for that request would only have returned at once.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -42,6 +42,22 @@
 using namespace btc_host;
 
 namespace {
+
+// Copy of refinement flags (device) into the pinned ring (host memory the
+// device writes through its mapped address).
+constexpr int kGather = 128;
+struct FlagGather {
+    const int32_t* src[kGather];
+    int32_t dst[kGather];
+    int32_t count;
+    int32_t* flags;
+};
+
+__global__ void k_gather_flags(FlagGather a) {
+    const int t = threadIdx.x;
+    if (t < a.count) a.flags[a.dst[t]] = *a.src[t];
+    __threadfence_system();
+}
 
 double now_s() {
     using namespace std::chrono;
@@ -94,7 +110,8 @@ struct btc_server_s {
     std::vector<Req*> active;
     std::deque<Tick> ticks;
     std::vector<hipEvent_t> ev_pool;
-    int32_t* flags = nullptr;  // pinned ring of refinement flags
+    int32_t* flags = nullptr;      // pinned ring of refinement flags (host view)
+    int32_t* flags_dev = nullptr;  // the same memory as the device sees it
     int flag_cap = 0, flag_next = 0;
     size_t resident = 0;
     uint64_t clock = 0;
@@ -295,8 +312,10 @@ BTC_API int btc_server_create(const btc_server_options* opt, void* stream, btc_s
     int rc = btc_runner_create(stream, &s->runner);
     if (rc == BTC_OK) {
         s->flag_cap = 1 << 16;
-        if (hipHostMalloc((void**)&s->flags, sizeof(int32_t) * s->flag_cap, hipHostMallocDefault) != hipSuccess)
+        if (hipHostMalloc((void**)&s->flags, sizeof(int32_t) * s->flag_cap, hipHostMallocMapped) != hipSuccess)
             rc = BTC_ERR_OOM;
+        else if (hipHostGetDevicePointer((void**)&s->flags_dev, s->flags, 0) != hipSuccess)
+            rc = BTC_ERR_HIP;
     }
     if (rc != BTC_OK) {
         btc_server_destroy(s);
@@ -396,12 +415,21 @@ BTC_API int btc_server_step(btc_server s) {
     if (s->scratch.empty()) return (int)(s->pending.size() + s->active.size());
     int rc = btc_runner_run(s->runner, (int32_t)s->scratch.size(), s->scratch.data());
     if (rc != BTC_OK) return rc;
-    for (auto& p : t.polls) {
+    // the convergence flags of this tick's tests, copied into the pinned
+    // ring by one small kernel (not one copy command per test)
+    FlagGather ga{};
+    ga.flags = s->flags_dev;
+    for (size_t k = 0; k < t.polls.size(); ++k) {
+        const auto& p = t.polls[k];
         const Workspace w = carve(p.first->plan[0].h, p.first->plan[0].h->ws_m);
         s->flags[p.second] = 0;
-        if (hipMemcpyAsync(&s->flags[p.second], &w.ir->done, sizeof(int32_t), hipMemcpyDeviceToHost, s->st) !=
-            hipSuccess)
-            return BTC_ERR_HIP;
+        ga.src[ga.count] = &w.ir->done;
+        ga.dst[ga.count] = p.second;
+        if (++ga.count == kGather || k + 1 == t.polls.size()) {
+            hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(kGather), 0, s->st, ga);
+            if (hipGetLastError() != hipSuccess) return BTC_ERR_HIP;
+            ga.count = 0;
+        }
     }
     if (!s->ev_pool.empty()) {
         t.ev = s->ev_pool.back();
