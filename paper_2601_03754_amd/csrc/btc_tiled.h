@@ -90,38 +90,46 @@ __device__ __forceinline__ Node node_of(const FactorDesc& P, int lvl, int64_t kk
     return d;
 }
 
-// Stage rows [r0, r0+R) (all NP columns) of an n x n block into LDS as
-// dst[r][k] (row stride LDD), zero padded; or, when COLS, columns [c0, c0+R)
-// (all NP rows) as dst[k][c] (row stride LDD).  NT threads; every load of a
-// thread is issued before its LDS writes (buffer loads masked by offset: no
-// branches), so they overlap.
+// Rows [r0, r0+R) (all NP columns) of an n x n block, or when cols its
+// columns [r0, r0+R) (all NP rows), zero padded: the share of thread t of
+// NT in registers (buffer loads masked by offset, all issued together), then
+// written to LDS as dst[r][k] or, for columns, dst[k][c] (row stride ldd).
+template <int NP, int R, int NT, class F>
+struct PanelRegs {
+    static constexpr int TOTAL = NP * R, CNT = TOTAL / NT;
+    static_assert(CNT * NT == TOTAL, "threads divide the panel");
+    F v[CNT];
+
+    template <class S>
+    __device__ __forceinline__ void load(const S* __restrict__ src, int n, int r0, bool cols, int t) {
+        const __amdgpu_buffer_rsrc_t rs = nn_rsrc(src, n);
+#pragma unroll
+        for (int u = 0; u < CNT; ++u) {
+            const int e = t + NT * u;
+            const int rr = cols ? e / R : r0 + e / NP, cc = cols ? r0 + e % R : e % NP;
+            S x;
+            buf_ld(x, rs, elem_off<S>(rr, cc, n, rr < n && cc < n));
+            v[u] = (F)x;
+        }
+    }
+
+    __device__ __forceinline__ void put(F* __restrict__ dst, int ldd, bool cols, int t) const {
+#pragma unroll
+        for (int u = 0; u < CNT; ++u) {
+            const int e = t + NT * u;
+            if (cols)
+                dst[(e / R) * ldd + e % R] = v[u];
+            else
+                dst[(e / NP) * ldd + e % NP] = v[u];
+        }
+    }
+};
+
 template <int NP, int R, int LDD, bool COLS, int NT, class S, class F>
 __device__ __forceinline__ void stage_panel(F* __restrict__ dst, const S* __restrict__ src, int n, int r0, int t) {
-    constexpr int TOTAL = NP * R, CNT = TOTAL / NT;
-    static_assert(CNT * NT == TOTAL, "threads divide the panel");
-    const __amdgpu_buffer_rsrc_t rs = nn_rsrc(src, n);
-    F v[CNT];
-#pragma unroll
-    for (int u = 0; u < CNT; ++u) {
-        const int e = t + NT * u;
-        S x;
-        if (COLS) {
-            const int k = e / R, gc = r0 + e % R;
-            buf_ld(x, rs, elem_off<S>(k, gc, n, k < n && gc < n));
-        } else {
-            const int gr = r0 + e / NP, k = e % NP;
-            buf_ld(x, rs, elem_off<S>(gr, k, n, gr < n && k < n));
-        }
-        v[u] = (F)x;
-    }
-#pragma unroll
-    for (int u = 0; u < CNT; ++u) {
-        const int e = t + NT * u;
-        if (COLS)
-            dst[(e / R) * LDD + e % R] = v[u];
-        else
-            dst[(e / NP) * LDD + e % NP] = v[u];
-    }
+    PanelRegs<NP, R, NT, F> g;
+    g.load(src, n, r0, COLS, t);
+    g.put(dst, LDD, COLS, t);
 }
 
 // Whole lower triangle of an n x n FP64 block into the packed lower-tile
@@ -192,8 +200,13 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
     const F* Tsrc = Pr::Tf(P) + (size_t)perm_pos(d.N, lvl - 1, src_node) * d.nn;
     double* S = P.Ld + (size_t)(self ? d.pi : d.pr) * d.nn;
     const int tid = threadIdx.x, w = wave_id(), lane = tid & 63;
-    stage_panel<NP, 32, LDP, true, 256>(pa, Tsrc, d.n, 32 * a, tid);
-    stage_panel<NP, 32, LDP, true, 256>(pb, Tsrc, d.n, 32 * b, tid);
+    {
+        PanelRegs<NP, 32, 256, F> ga, gb;
+        ga.load(Tsrc, d.n, 32 * a, true, tid);
+        gb.load(Tsrc, d.n, 32 * b, true, tid);
+        ga.put(pa, LDP, true, tid);
+        gb.put(pb, LDP, true, tid);
+    }
     __syncthreads();
     const int sr = w >> 1, sc = w & 1;
     if (a == b && sr < sc) return;  // strictly upper sub-tile
@@ -412,14 +425,36 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     const int n = d.n;
     const F* R = Pr::Rf(P) + (size_t)d.pi * d.nn;
     const F* T = Pr::Tf(P) + (size_t)d.pi * d.nn;
-    stage_panel<NP, 32, LDR, false, 256>(pa, R, n, 32 * a, tid);
-    if (sep)
-        stage_panel<NP, 32, LDR, false, 256>(pb, R, n, 32 * b, tid);
-    else
-        stage_panel<NP, 32, LDP, true, 256>(pb, T, n, 32 * b, tid);
-    __syncthreads();
     const int sr = w >> 1, sc = w & 1;
     const bool idle = sep && a == b && sr < sc;  // strictly upper sub-tile
+    const bool eager = sep && (P.flags & kFactorEagerT) && d.i + 2 * d.s <= d.N;
+    // every global read up front: both panels of the first product and the
+    // Schur complement entries this thread updates
+    {
+        PanelRegs<NP, 32, 256, F> g1, g2;
+        g1.load(R, n, 32 * a, false, tid);
+        g2.load(sep ? R : T, n, 32 * b, !sep, tid);
+        g1.put(pa, LDR, false, tid);
+        g2.put(pb, sep ? LDR : LDP, !sep, tid);
+    }
+    double sv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (sep) {
+        const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i + d.s - 1) * d.nn : P.Ld + (size_t)d.pr * d.nn;
+        const __amdgpu_buffer_rsrc_t rsrc = nn_rsrc(src, n);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 32 * a + 16 * sr + Pr::row(v, lane), c = 32 * b + 16 * sc + (lane & 15);
+            buf_ld(sv[v], rsrc, elem_off<double>(r, c, n, !idle && r < n && c < n));
+        }
+    }
+    // the second product's panels (the right neighbour's T') load during the first
+    PanelRegs<NP, 32, 256, F> g3, g4;
+    const F* T2 = Pr::Tf(P) + (size_t)(eager ? perm_pos(d.N, lvl, d.i + 2 * d.s) : d.pi) * d.nn;
+    if (eager) {
+        g3.load(T2, n, 32 * a, true, tid);
+        g4.load(T2, n, 32 * b, true, tid);
+    }
+    __syncthreads();
     typename Pr::Acc acc = {};
     const int i = lane & 15, q = lane >> 4;
     if (!idle) {
@@ -443,12 +478,11 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
             acc += acc1;
         }
     }
-    if (sep && (P.flags & kFactorEagerT) && d.i + 2 * d.s <= d.N) {
+    if (eager) {
         // the right neighbour's T'^T T' (A[r][k] = T'[k][r], B[k][c] = T'[k][c])
-        const F* T2 = Pr::Tf(P) + (size_t)perm_pos(d.N, lvl, d.i + 2 * d.s) * d.nn;
         __syncthreads();
-        stage_panel<NP, 32, LDP, true, 256>(pa, T2, n, 32 * a, tid);
-        stage_panel<NP, 32, LDP, true, 256>(pb, T2, n, 32 * b, tid);
+        g3.put(pa, LDP, true, tid);
+        g4.put(pb, LDP, true, tid);
         __syncthreads();
         if (!idle) {
             if constexpr (BF16) {
@@ -466,15 +500,11 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     }
     if (idle) return;
     if (sep) {
-        const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i + d.s - 1) * d.nn : P.Ld + (size_t)d.pr * d.nn;
-        const __amdgpu_buffer_rsrc_t rsrc = nn_rsrc(src, n), rs = nn_rsrc(P.Ld + (size_t)d.pr * d.nn, n);
+        const __amdgpu_buffer_rsrc_t rs = nn_rsrc(P.Ld + (size_t)d.pr * d.nn, n);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = 32 * a + 16 * sr + Pr::row(v, lane), c = 32 * b + 16 * sc + (lane & 15);
-            const int off = elem_off<double>(r, c, n, r < n && c < n);
-            double x;
-            buf_ld(x, rsrc, off);
-            buf_st(x - (double)acc[v], rs, off);
+            buf_st(sv[v] - (double)acc[v], rs, elem_off<double>(r, c, n, r < n && c < n));
         }
     } else {
         const int64_t lft = d.i - d.s, rgt = d.i + d.s;
