@@ -12,7 +12,8 @@
 //       one wavefront, panel and trailing updates on the matrix cores), then
 //       R_i = C_{i+s,i} L_ii^{-T} and T_i = L_ii^{-1} C_{i,i-s} strip by strip
 //       (one 16-row or 16-column strip per wavefront at a time, blocked
-//       substitution with the inverted diagonal tiles, all products MFMA)
+//       substitution with the inverted diagonal tiles, all products MFMA,
+//       the solved tiles kept in registers as the products' B operand)
 //   K4  one 256-thread workgroup per 32 x 32 tile of S_{i+s} -= R_i R_i^T
 //       (lower tiles) and of the fill -R_i T_i
 // In mixed precision the Schur complements and K2 stay FP64 (its solves too;
@@ -253,10 +254,10 @@ constexpr int k2_waves() { return NP <= 96 ? 8 : 4; }
 // Workgroups of K2 per compute unit the LDS allows (the register budget is
 // held to it: the second launch bound counts wavefronts per SIMD).
 template <int NP>
-constexpr int k2_blocks() { return NP <= 96 ? 2 : 1; }
+constexpr int k2_blocks() { return NP <= 64 ? 3 : NP <= 96 ? 2 : 1; }
 
 template <int NP, bool MIXED>
-__global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<NP>() / 4) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
+__global__ __launch_bounds__(k2_waves<NP>() * kWave, (k2_blocks<NP>() * k2_waves<NP>() + 3) / 4) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
     using Pr = Prec<MIXED>;  // storage of the factor blocks
     using Pm = Prec<false>;  // the solves run in FP64 (latency bound: no gain from FP32)
     using F = typename Pr::F;
@@ -264,9 +265,9 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
     using Cfg = TiledCfg<NP>;
     constexpr int NT16 = Cfg::NT16;
     constexpr int NW = k2_waves<NP>();
-    __shared__ double sS[packed_lds_elems<NP>()];  // lower tiles of S_i, then of L_ii
-    __shared__ double sInv[NT16][kT * kLDI];
-    __shared__ double sTile[NW][kT * kLDI];
+    // lower tiles of S_i, then of L_ii, the strict upper part of each
+    // diagonal tile holding its inverse (transposed)
+    __shared__ double sS[packed_lds_elems<NP>()];
     __shared__ double invd[NP];
     __shared__ __align__(16) double colbuf[2][kWave];
     __shared__ int fail;
@@ -280,10 +281,20 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
     const int n = d.n;
     const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i - 1) * d.nn : P.Ld + (size_t)d.pi * d.nn;
     const int i = lane & 15, q4 = lane >> 4;
-    // Tile p of strip t of the coupling C_{i+s,i} (isR: R strips are 16-row
-    // strips) or C_{i,i-s} (16-column strips), in the accumulator layout:
-    // level 0 reads the input couplings (FP64), higher levels the coupling
-    // left in the output slot by the previous level.
+    // Every strip is solved as X = L^{-1} C': T strips (16 columns of T_i)
+    // with C' = C_{i,i-s}, R strips transposed (R_i^T = L_ii^{-1}
+    // C_{i+s,i}^T, 16 rows of R_i).  Tile p of strip t in the accumulator
+    // layout: lane (c, q), register v, holds element (16p + 4v+q, 16t + c) of
+    // C' or X, i.e. entry (gr, gc) below of the coupling or of R_i / T_i.
+    // That layout is also the B operand of the next products, so the solved
+    // tiles feed the matrix cores straight from registers.
+    auto gpos = [&](bool isR, int t, int p, int v, int& gr, int& gc) {
+        const int rr = Pm::row(v, lane);
+        gr = isR ? kT * t + i : kT * p + rr;
+        gc = isR ? kT * p + rr : kT * t + i;
+    };
+    // the coupling tile: level 0 reads the input couplings (FP64), higher
+    // levels the coupling left in the output slot by the previous level
     auto load_coupling = [&](bool isR, int t, int p, bool live) {
         Acc acc;
         const int64_t cblk = isR ? d.i - 1 : d.i - 2;
@@ -291,8 +302,8 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
         const __amdgpu_buffer_rsrc_t rf = nn_rsrc((isR ? Pr::Rf(P) : Pr::Tf(P)) + (size_t)d.pi * d.nn, n);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int rr = Pm::row(v, lane);
-            const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
+            int gr, gc;
+            gpos(isR, t, p, v, gr, gc);
             const bool ok = live && gr < n && gc < n;
             if (lvl == 0) {
                 double x;
@@ -310,19 +321,13 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
     stage_lower_packed<NP, NW * kWave>(sS, src, n, tid);
     if (tid == 0) fail = 0;
     __syncthreads();
-    const bool ok = potrf_blocked<NP, kLDI, NW, PackedLds>(sS, invd, sInv, colbuf, &fail);
+    const bool ok = potrf_blocked<NP, kLDI, NW, PackedLds, 2>(sS, invd, nullptr, colbuf, &fail);
     if (!ok) {
         if (tid == 0) atomicMin(P.info, (unsigned long long)d.i);
         return;
     }
     store_lower_packed<NP, F>(Pr::Lf(P) + (size_t)d.pi * d.nn, sS, n, tid, NW * kWave);
 
-    double* tile = sTile[w];
-    auto put = [&](const Acc& x) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) tile[Pm::row(v, lane) * kLDI + i] = x[v];
-        wave_lds_sync();
-    };
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         const int sidx = w + j * NW;
@@ -342,48 +347,31 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, k2_blocks<NP>() * k2_waves<
             Acc acc = nx0;
             nx0 = nx1;
             if (p + 2 < NT16) nx1 = load_coupling(isR, t, p + 2, true);
+            // acc -= L_p,qq X_qq (A from LDS, B = X_qq's registers)
 #pragma unroll
             for (int qq = 0; qq < p; ++qq) {
-                put(X[qq]);
+                const double* Lt = PackedLds::tile(sS, p, qq);
 #pragma unroll
-                for (int k = 0; k < kT; k += 4) {
-                    double a, b;
-                    const double l = PackedLds::tile(sS, p, qq)[i * kLDI + k + q4];  // L[16p+i][16qq+k+q4]
-                    if (isR) {  // - X_qq L_p,qq^T
-                        a = tile[i * kLDI + k + q4];
-                        b = l;
-                    } else {    // - L_p,qq X_qq
-                        a = l;
-                        b = tile[(k + q4) * kLDI + i];
-                    }
-                    acc = Pm::mma(-a, b, acc);
-                }
-                wave_lds_sync();
+                for (int v = 0; v < 4; ++v) acc = Pm::mma(-Lt[i * kLDI + 4 * v + q4], X[qq][v], acc);
             }
-            put(acc);
+            // X_p = Dinv_p acc
             Acc out = {};
+            // Dinv_p[i][k]: k < i in the diagonal tile's upper part (transposed), k = i in invd
+            const double* Dt = PackedLds::tile(sS, p, p);
 #pragma unroll
-            for (int k = 0; k < kT; k += 4) {
-                const double dv = sInv[p][i * kLDI + k + q4];  // Dinv_p[i][k+q4]
-                double a, b;
-                if (isR) {  // Y Dinv_p^T
-                    a = tile[i * kLDI + k + q4];
-                    b = dv;
-                } else {    // Dinv_p Y
-                    a = dv;
-                    b = tile[(k + q4) * kLDI + i];
-                }
-                out = Pm::mma(a, b, out);
+            for (int v = 0; v < 4; ++v) {
+                const int k = 4 * v + q4;
+                const double dv = k < i ? Dt[k * kLDI + i] : (k == i ? invd[kT * p + i] : 0.0);
+                out = Pm::mma(dv, acc[v], out);
             }
-            wave_lds_sync();
             X[p] = out;
         }
 #pragma unroll
         for (int p = 0; p < NT16; ++p)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int rr = Pm::row(v, lane);
-                const int gr = isR ? kT * t + rr : kT * p + rr, gc = isR ? kT * p + i : kT * t + i;
+                int gr, gc;
+                gpos(isR, t, p, v, gr, gc);
                 buf_st((F)X[p][v], rdst, elem_off<F>(gr, gc, n, gr < n && gc < n));
             }
     }

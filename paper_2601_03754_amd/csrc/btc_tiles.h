@@ -255,6 +255,33 @@ __device__ __forceinline__ void tile_inverse(const double* __restrict__ L, int r
 }
 
 
+// Inverse of the 16 x 16 lower-triangular tile T (row stride LD) by one
+// wavefront, written transposed into the tile's strict upper triangle: the
+// strict lower part of the inverse at T[c][j] for c < j (its diagonal is
+// invd).  Lane c (< 16) forward-substitutes e_c; the reads (lower part) and
+// the writes (upper part) never touch the same element.
+template <int LD>
+__device__ __forceinline__ void tile_inverse_upper(double* T, const double* __restrict__ invd) {
+    static_assert(LD > kT, "the tile rows need a padding column");
+    const int lane = threadIdx.x & 63;
+    const int c = lane & 15;
+    double x[kT];
+#pragma unroll
+    for (int j = 0; j < kT; ++j) x[j] = (j == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < kT; ++j) {
+        x[j] *= invd[j];
+#pragma unroll
+        for (int k = j + 1; k < kT; ++k) x[k] = fma(-T[k * LD + j], x[j], x[k]);
+    }
+    if (lane < kT) {
+        // entries on or below the diagonal go to the row's padding column
+        // (index kT; LD > kT), so every store is unconditional
+#pragma unroll
+        for (int j = 1; j < kT; ++j) T[c * LD + (j > c ? j : kT)] = x[j];
+    }
+}
+
 // Blocked Cholesky of the lower triangle of an NP x NP LDS tile (row stride
 // LD) by all NW wavefronts of the workgroup (every thread must call it), in
 // 16-column panels: wavefront 0 factors the diagonal tile (potrf_small); the
@@ -269,7 +296,9 @@ __device__ __forceinline__ void tile_inverse(const double* __restrict__ L, int r
 // invd, the inverted diagonal tiles in inv[NP/16] (row stride kLDI).  *fail
 // (LDS, 0 on entry) becomes 1 on a non-positive or NaN pivot; the result is
 // then false for every thread.
-template <int NP, int LD, int NW, class Lay = SquareLds<LD>>
+// INV: where the inverted diagonal tiles go: 1 the array inv (row stride
+// kLDI), 2 transposed into the strict upper part of each diagonal tile.
+template <int NP, int LD, int NW, class Lay = SquareLds<LD>, int INV = 1>
 __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __restrict__ invd,
                                               double (*__restrict__ inv)[kT * kLDI],
                                               double (*__restrict__ colbuf)[kWave], int* fail) {
@@ -332,10 +361,15 @@ __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __
         __syncthreads();
         if (*fail) return false;
     }
-    for (int t = w; t < NTL; t += NW) tile_inverse<LT, double>(Lay::tile(A, t, t), 0, invd + t * kT, inv[t]);
+    if (INV == 1)
+        for (int t = w; t < NTL; t += NW) tile_inverse<LT, double>(Lay::tile(A, t, t), 0, invd + t * kT, inv[t]);
+    else
+        for (int t = w; t < NTL; t += NW) tile_inverse_upper<LT>(Lay::tile(A, t, t), invd + t * kT);
     __syncthreads();
     return true;
 }
+
+
 
 // ---------------------------------------------------------------------------
 // FP32 tiles
