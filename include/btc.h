@@ -251,7 +251,9 @@ BTC_API int btc_runner_create(void *stream, btc_runner *out);
  * must not depend on each other: at most one step per handle per call, except
  * that FACTOR level l+1 and FORWARD level l of one handle may share a call
  * (the sweep reads only level-l factor blocks, the factor step writes only
- * blocks of higher levels); calls are executed in order.  Returns once the work is enqueued; -3 for an
+ * blocks of higher levels), and so may a RESIDUAL and the REFINE_TEST that
+ * reads it (REFINE_TEST steps run after every other step of their call);
+ * calls are executed in order.  Returns once the work is enqueued; -3 for an
  * invalid step (unknown op, level out of range, missing pointers, a sweep or
  * residual on a handle never factored).
  */

@@ -441,9 +441,16 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
     if (timing && !r->pending.empty()) drain_prof(r, false);
     // stream of every group: largest estimated work first, each onto the
     // least loaded of the main and side streams
+    // (convergence tests run after every other group of the call, on the
+    // runner's stream once the side streams have joined: a call may hold a
+    // residual step and the test that reads it)
     std::vector<std::pair<double, Group*>> order;
     for (auto& kv : groups) {
         Group& g = kv.second;
+        if (g.op == BTC_OP_REFINE_TEST) {
+            g.lane = 0;
+            continue;
+        }
         const double np = (double)std::max(g.np, 8);
         const double w = (g.op == BTC_OP_FACTOR ? np : 1.0) * np * np * (double)g.items.size();
         order.push_back({w, &g});
@@ -472,8 +479,7 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
         e = hipStreamWaitEvent(r->side[k - 1], r->fork, 0);
         if (e != hipSuccess) return to_code(e);
     }
-    for (auto& kv : groups) {
-        const Group& g = kv.second;
+    auto launch_group = [&](const std::tuple<int, int, int>& key, const Group& g) -> int {
         const int64_t items = (int64_t)g.items.size();
         hipStream_t gs = g.lane == 0 ? st : r->side[g.lane - 1];
         hipEvent_t ea = nullptr, eb = nullptr;
@@ -530,17 +536,27 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
         }
         if (g.prof && timing && !split) {
             (void)hipEventRecord(eb, gs);
-            r->pending.push_back({key4(kv.first, 0), ea, eb, g.work});
+            r->pending.push_back({key4(key, 0), ea, eb, g.work});
         } else if (g.count && timing && !split) {
-            add_untimed(r, key4(kv.first, 0), g.work);
+            add_untimed(r, key4(key, 0), g.work);
         }
-        if (e != hipSuccess) return to_code(e);
+        return e != hipSuccess ? to_code(e) : BTC_OK;
+    };
+    for (auto& kv : groups) {
+        if (kv.second.op == BTC_OP_REFINE_TEST) continue;
+        const int rc = launch_group(kv.first, kv.second);
+        if (rc != BTC_OK) return rc;
     }
     for (int k = 1; k <= btc_runner_s::kSide; ++k) {
         if (!used[k]) continue;
         e = hipEventRecord(r->join[k - 1], r->side[k - 1]);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, r->join[k - 1], 0);
         if (e != hipSuccess) return to_code(e);
+    }
+    for (auto& kv : groups) {
+        if (kv.second.op != BTC_OP_REFINE_TEST) continue;
+        const int rc = launch_group(kv.first, kv.second);
+        if (rc != BTC_OK) return rc;
     }
     return BTC_OK;
 }

@@ -238,9 +238,11 @@ void build_plan(btc_server s, Req* r, Client& c) {
             push(t, false);
         }
         if (mixed) {
+            // the residual and its convergence test share a tick (the runner
+            // runs tests after the other steps of a call)
             t.level = 0;
             t.op = BTC_OP_RESIDUAL;
-            push(t, false);
+            push(t, true);
             t.op = BTC_OP_REFINE_TEST;
             push(t, false);
         }
