@@ -82,6 +82,34 @@ def test_factor_variants_at_64(btc, precision, n, variant):
     assert info["converged"]
 
 
+@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("v0,v1", [(1, 0), (0, 1)])
+def test_factor_families_mixed_across_levels(btc, precision, v0, v1):
+    """Padded size 64 with the tile-parallel step at level 0 only, or above
+    level 0 only: the separator updates deferred or applied eagerly follow
+    the kernel family of each level (no update lost or applied twice)."""
+    n = 56
+    p = inputs.block_tridiag(200, n, seed=700 + v0, nrhs=2)
+    btc.btc_tune_set(0, precision, n, 0, v0)
+    btc.btc_tune_set(0, precision, n, 1, v1)
+    try:
+        f = btc.Factor(dev(p.D), dev(p.E), precision=precision)
+        X, info = f.solve(dev(p.B), want_info=True)
+        X = X.cpu().numpy()
+        blocks = f.export()
+        f.close()
+    finally:
+        btc.btc_tune_set(0, precision, n, 0, 1)
+        btc.btc_tune_set(0, precision, n, 1, 1)
+    Ld, Rb, Tb, _ = oracle.factor_nd(p.D, p.E)
+    scale = max(np.abs(Ld).max(), 1.0)
+    ftol = {0: 1e-12, 1: 1e-4, 2: 3e-2}[precision]
+    for g, o in zip(blocks, (Ld, Rb, Tb)):
+        assert np.abs(g - o).max() <= ftol * scale
+    assert oracle.relres(p.D, p.E, X, p.B) <= (1e-12 if precision == 0 else 1e-10)
+    assert info["converged"]
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_column_grouping_is_bitwise_neutral(btc, precision):
     p = inputs.block_tridiag(65, 40, seed=5, nrhs=3)
