@@ -133,13 +133,17 @@ __device__ __forceinline__ void stage_panel(F* __restrict__ dst, const S* __rest
     g.put(dst, LDD, COLS, t);
 }
 
+// Loads in flight per thread and round when staging PER elements: the
+// largest divisor of PER not above 24.
+constexpr int load_chunk(int per, int c = 24) { return per % c == 0 ? c : load_chunk(per, c - 1); }
+
 // Whole lower triangle of an n x n FP64 block into the packed lower-tile
 // LDS layout (whole diagonal tiles: their strict upper part 0; identity
 // padding beyond n); loads by buffer resource, masked by offset.
 template <int NP, int NT>
 __device__ __forceinline__ void stage_lower_packed(double* __restrict__ dst, const double* __restrict__ src, int n,
                                                    int t) {
-    constexpr int TOTAL = NP * NP, PER = TOTAL / NT, CH = PER <= 24 ? PER : 16;
+    constexpr int TOTAL = NP * NP, PER = TOTAL / NT, CH = load_chunk(PER);
     static_assert(PER * NT == TOTAL && PER % CH == 0, "threads divide the block");
     const __amdgpu_buffer_rsrc_t rs = nn_rsrc(src, n);
 #pragma unroll 1
@@ -247,14 +251,15 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
 // to the matrix cores through a one-tile LDS scratch per wavefront, the
 // coupling tiles read straight from HBM into the accumulator layout, two
 // tiles ahead of their use.
-// Wavefronts of K2: eight while the LDS allows it (more strips solved at
-// once), four at padded size 128.
+// Wavefronts of K2 and workgroups per compute unit (measured: at padded size
+// 64 five nodes of four wavefronts per CU beat three of eight; at 96 two of
+// eight beat three of four, whose strips take three rounds).
 template <int NP>
-constexpr int k2_waves() { return NP <= 96 ? 8 : 4; }
-// Workgroups of K2 per compute unit the LDS allows (the register budget is
-// held to it: the second launch bound counts wavefronts per SIMD).
+constexpr int k2_waves() { return NP == 96 ? 8 : 4; }
+// The register budget is held to the workgroups per CU (the second launch
+// bound counts wavefronts per SIMD).
 template <int NP>
-constexpr int k2_blocks() { return NP <= 64 ? 3 : NP <= 96 ? 2 : 1; }
+constexpr int k2_blocks() { return NP <= 64 ? 5 : NP <= 96 ? 2 : 1; }
 
 template <int NP, bool MIXED>
 __global__ __launch_bounds__(k2_waves<NP>() * kWave, (k2_blocks<NP>() * k2_waves<NP>() + 3) / 4) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
