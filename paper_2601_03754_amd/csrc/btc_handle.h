@@ -152,10 +152,11 @@ inline size_t factor_bytes(int64_t N, int64_t n, int32_t prec) {
 }
 
 // Solve workspace: FP64 path: Y, U, V (FP64); mixed: r, y, u, v, d (FP32);
-// both: partial norms (FP64, N x m x 2) and the refinement state.
+// both: partial norms (FP64, N x m x 2), the residual's two FP64 scratch
+// vectors and the refinement state.
 inline size_t workspace_bytes(int64_t N, int64_t n, int32_t prec, int64_t m) {
     const size_t v = (size_t)N * (size_t)n * (size_t)m;
-    const size_t tail = 2 * (size_t)N * (size_t)m * sizeof(double) + 256 + 256 + 256;
+    const size_t tail = 2 * (size_t)N * (size_t)m * sizeof(double) + 2 * v * sizeof(double) + 4 * 256;
     if (is_mixed(prec)) return 5 * v * sizeof(float) + tail;
     return 3 * v * sizeof(double) + tail;
 }
@@ -164,6 +165,7 @@ struct Workspace {
     double *Y = nullptr, *U = nullptr, *V = nullptr;                              // FP64 path
     float *r = nullptr, *y = nullptr, *u = nullptr, *v = nullptr, *d = nullptr;  // mixed
     double* part = nullptr;
+    double *rp = nullptr, *rq = nullptr;  // residual scratch
     btc::IrState* ir = nullptr;
 };
 
@@ -194,6 +196,11 @@ inline Workspace carve(btc_handle h, int64_t m) {
     p = align(p);
     w.part = (double*)p;
     p += 2 * (size_t)h->N * (size_t)m * sizeof(double);
+    p = align(p);
+    w.rp = (double*)p;
+    p += v * sizeof(double);
+    w.rq = (double*)p;
+    p += v * sizeof(double);
     p = align(p);
     w.ir = (btc::IrState*)p;
     return w;
@@ -394,6 +401,8 @@ inline btc::ResidualDesc residual_desc(btc_handle h, const Workspace& w, const d
     r.X = X;
     r.R32 = to_fp32 ? w.r : nullptr;
     r.part = w.part;
+    r.P = w.rp;
+    r.Q = w.rq;
     r.state = w.ir;
     r.N = h->N;
     r.n = (int32_t)h->n;

@@ -121,6 +121,8 @@ struct ResidualDesc {
     const double* X;           // [N][n][m] FP64 iterate
     float* R32;                // optional: residual rounded to FP32
     double* part;              // [N][m][2] squared column norms of r_i and b_i per block row
+    double* P;                 // [N][n][m] scratch: b_i - D_i x_i - E_i^T x_{i+1}
+    double* Q;                 // [N][n][m] scratch: row i holds E_{i-1} x_{i-1} (i >= 2)
     const IrState* state;      // optional: skip when state->done
     int64_t N;
     int32_t n;
@@ -170,6 +172,7 @@ hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t item
                         hipStream_t st);
 hipError_t launch_sweep(const Launch<SweepDesc<float>>& p, int np, int64_t items, bool backward, int mc,
                         hipStream_t st);
+// Two launches over the same items (every block row of each instance).
 hipError_t launch_residual(const Launch<ResidualDesc>& p, int np, int64_t items, int mc, hipStream_t st);
 hipError_t launch_ir_init(const Launch<IrDesc>& p, int64_t items, hipStream_t st);
 hipError_t launch_ir_check(const Launch<IrDesc>& p, int64_t items, hipStream_t st);

@@ -23,12 +23,10 @@
 //         [R_i row slabs; T_i column slabs; L_ii row slabs consumed from the
 //          last row up]
 //   residual, block row i: r_i = b_i - D_i x_i - E_{i-1} x_{i-1} - E_i^T x_{i+1}
-//     [only the lower triangle of D_i is read: column slabs for D_i[r][c],
-//      c <= r, row slabs for D_i[c][r], c > r (the second pass mostly hits
-//      L2); E_{i-1} column slabs, E_i row slabs]; per-column partial squared
-//     norms of r_i and b_i.
-//     Work items of consecutive block rows are dispatched to the same XCD
-//     (shared couplings stay in that XCD's L2).
+//     [row slabs of the lower triangle of D_i and of E_i, each element used
+//      for its own row and, through a wavefront sum, for its transpose's;
+//      E_i x_i is left for row i+1]; then per-column partial squared norms
+//     of r_i and b_i.
 // Instead of two nodes subtracting into the same y concurrently, each node
 // pulls its contributions in a fixed order: results are deterministic.
 #include "btc_device.h"
@@ -459,12 +457,50 @@ __global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
 }
 
 // ---------------------------------------------------------------------------
-// Residual: work items of consecutive block rows share an XCD
-// (xcd_local_block), so the couplings two rows share stay in one L2.
+// Residual in two kernels, every block read from HBM once.  The wavefront of
+// block row i streams the lower triangle of D_i and the coupling E_i (block
+// (i+1, i)) as row slabs and uses each element M[c][r] twice: as M^T[r][c]
+// (lane r, the vector's row c broadcast) and as M[c][r] (lane r's product
+// with the lane's own vector row, summed over the wavefront into row c):
+//   P_i     = b_i - D_i x_i - E_i^T x_{i+1}
+//   Q_{i+1} = E_i x_i
+// The second kernel forms r_i = P_i - Q_i, its FP32 copy and the per-column
+// partial squared norms of r_i and b_i.  Work items of consecutive block rows
+// share an XCD (xcd_local_block).
+
+
+
+constexpr int ilog2_c(int v) { return v <= 1 ? 0 : 1 + ilog2_c(v / 2); }
+
+// Sum over the wavefront of KB values per lane: afterwards lane l holds the
+// total of value l >> (6 - log2 KB).  Each halving step keeps half of the
+// lane's values and adds the other half of its partner's, so KB values cost
+// KB - 1 exchanges plus the last 6 - log2 KB.
+template <int KB>
+__device__ __forceinline__ double wave_sum_rows(double (&v)[KB], int lane) {
+#pragma unroll
+    for (int w = KB / 2, h = kWave / 2; w >= 1; w /= 2, h /= 2) {
+        const bool up = (lane & h) != 0;
+#pragma unroll
+        for (int j = 0; j < w; ++j) {
+            const double send = up ? v[j] : v[j + w];
+            const double keep = up ? v[j + w] : v[j];
+            v[j] = keep + __shfl_xor(send, h);
+        }
+    }
+    double s = v[0];
+#pragma unroll
+    for (int h = kWave >> (ilog2_c(KB) + 1); h >= 1; h /= 2) s += __shfl_xor(s, h);
+    return s;
+}
+
 template <int NP, int MC>
 __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
     using G = Geo<NP>;
     constexpr int RPL = G::RPL, LDB = G::LDB;
+    constexpr int KB = 4 / MC;              // slab rows per wavefront sum (4 sums live)
+    constexpr int SH = 6 - ilog2_c(KB);     // lane l holds the sum of row l >> SH
+    static_assert(KB >= 1 && kS % KB == 0, "chunks divide the slab");
     __shared__ double buf[G::BUF];
     ResidualDesc P;
     int64_t row0;
@@ -485,20 +521,20 @@ __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
     const int n = P.n, m = P.m;
     const size_t nn = (size_t)n * n;
     const int64_t i = row0 + 1;
-    const bool lft = i > 1, rgt = i < N;
+    const bool rgt = i < N;
     const int ns = (n + kS - 1) / kS;
-    const double* Dg = P.A_diag + (size_t)(i - 1) * nn;
-    // D_i column slabs (lower part: D[r][c], c <= r), D_i row slabs (its
-    // transpose: D[c][r], c > r), E_{i-1} column slabs, E_i row slabs
+    // D_i row slabs (the lower triangle: slab rows c, columns r <= last row
+    // of the slab), E_i row slabs
     Plan<double> pl;
     pl.clear();
-    pl.set(0, {Dg, ns, false, false, true});
-    pl.set(1, {Dg, ns, true, false, true});
-    pl.set(2, {lft ? P.A_off + (size_t)(i - 2) * nn : nullptr, lft ? ns : 0, false, false, false});
-    pl.set(3, {rgt ? P.A_off + (size_t)(i - 1) * nn : nullptr, rgt ? ns : 0, true, false, false});
+    pl.set(0, {P.A_diag + (size_t)(i - 1) * nn, ns, true, false, true});
+    pl.set(1, {rgt ? P.A_off + (size_t)(i - 1) * nn : nullptr, rgt ? ns : 0, true, false, false});
 
     for (int q0 = 0; q0 < m; q0 += MC) {
-        double acc[RPL][MC], bb[RPL][MC], x0[RPL][MC], x1[RPL][MC], x2[RPL][MC];
+        // acc: b_i minus the broadcast products; dl: (D_i x_i) over the lower
+        // triangle; qa: E_i x_i.  dl and qa take one wavefront sum per row,
+        // so the result does not depend on how rows are chunked (MC).
+        double acc[RPL][MC], dl[RPL][MC], qa[RPL][MC], x1[RPL][MC], x2[RPL][MC];
 #pragma unroll
         for (int rr = 0; rr < RPL; ++rr) {
             const int r = lane + kWave * rr;
@@ -506,45 +542,114 @@ __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
             for (int c = 0; c < MC; ++c) {
                 const int q = q0 + c;
                 const bool ok = r < n && q < m;
-                bb[rr][c] = ok ? P.B[((size_t)(i - 1) * n + r) * m + q] : 0.0;
-                acc[rr][c] = bb[rr][c];
-                x0[rr][c] = (ok && lft) ? P.X[((size_t)(i - 2) * n + r) * m + q] : 0.0;
+                acc[rr][c] = ok ? P.B[((size_t)(i - 1) * n + r) * m + q] : 0.0;
+                dl[rr][c] = 0.0;
+                qa[rr][c] = 0.0;
                 x1[rr][c] = ok ? P.X[((size_t)(i - 1) * n + r) * m + q] : 0.0;
                 x2[rr][c] = (ok && rgt) ? P.X[((size_t)i * n + r) * m + q] : 0.0;
             }
         }
         run_slabs<NP, double, slab_depth<NP, double>()>(pl, n, lane, buf, [&](int g, int q, const double* b) {
-            if (g == 0)
-                slab_axpy<NP, MC, double>(acc, b, x1, kS * q, n, -1.0, 1, lane);
-            else if (g == 1)
-                slab_axpy<NP, MC, double>(acc, b, x1, kS * q, n, -1.0, 2, lane);
-            else if (g == 2)
-                slab_axpy<NP, MC, double>(acc, b, x0, kS * q, n, -1.0, 0, lane);
-            else
-                slab_axpy<NP, MC, double>(acc, b, x2, kS * q, n, -1.0, 0, lane);
-        });
+            // g = 0: slab row c of D_i (elements with r <= c valid); g = 1:
+            // row c of E_i.  Rows past n are zero.
+            const int off = kS * q;
+#pragma unroll 1
+            for (int k0 = 0; k0 < kS; k0 += KB) {
+                double ps[MC][KB];
 #pragma unroll
-        for (int c = 0; c < MC; ++c) {
-            const int q = q0 + c;
-            double r2 = 0.0, b2 = 0.0;
+                for (int k = 0; k < KB; ++k) {
+                    const int cc = off + k0 + k;
+                    double xb[MC];
 #pragma unroll
-            for (int rr = 0; rr < RPL; ++rr) {
-                const int r = lane + kWave * rr;
-                if (r < n && q < m) {
-                    if (P.R32) P.R32[((size_t)(i - 1) * n + r) * m + q] = (float)acc[rr][c];
-                    r2 = fma(acc[rr][c], acc[rr][c], r2);
-                    b2 = fma(bb[rr][c], bb[rr][c], b2);
+                    for (int c = 0; c < MC; ++c) {
+                        double t = g == 0 ? x1[0][c] : x2[0][c];
+#pragma unroll
+                        for (int rr = 1; rr < RPL; ++rr)
+                            if (cc >= kWave * rr) t = g == 0 ? x1[rr][c] : x2[rr][c];
+                        xb[c] = -bcast(t, cc & (kWave - 1));
+                        ps[c][k] = 0.0;
+                    }
+#pragma unroll
+                    for (int rr = 0; rr < RPL; ++rr) {
+                        const int r = lane + kWave * rr;
+                        const double a = r < n ? b[(k0 + k) * LDB + r] : 0.0;
+                        // as element (r, c): D_i above the diagonal (r < c),
+                        // E_i^T; as element (c, r): D_i on and below it, E_i
+                        const double au = (g == 0 && r >= cc) ? 0.0 : a;
+                        const double al = (g == 0 && r > cc) ? 0.0 : a;
+#pragma unroll
+                        for (int c = 0; c < MC; ++c) {
+                            acc[rr][c] = fma(au, xb[c], acc[rr][c]);
+                            ps[c][k] = fma(al, x1[rr][c], ps[c][k]);
+                        }
+                    }
+                }
+                // row c = off + k0 + k gets its sum from lane k << SH; its
+                // owner is lane c % 64 in slot c / 64
+                const int base = off + k0, slot = base / kWave;
+                const int k = lane - (base & (kWave - 1));
+#pragma unroll
+                for (int c = 0; c < MC; ++c) {
+                    const double s = wave_sum_rows<KB>(ps[c], lane);
+                    const double t = __shfl(s, (k & (KB - 1)) << SH);
+                    if (k >= 0 && k < KB) {
+#pragma unroll
+                        for (int rr = 0; rr < RPL; ++rr) {
+                            if (rr == slot) {
+                                if (g == 0)
+                                    dl[rr][c] += t;
+                                else
+                                    qa[rr][c] += t;
+                            }
+                        }
+                    }
                 }
             }
+        });
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                r2 += __shfl_xor(r2, off);
-                b2 += __shfl_xor(b2, off);
+        for (int rr = 0; rr < RPL; ++rr) {
+            const int r = lane + kWave * rr;
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                const int q = q0 + c;
+                if (r < n && q < m) {
+                    P.P[((size_t)(i - 1) * n + r) * m + q] = acc[rr][c] - dl[rr][c];
+                    if (rgt) P.Q[((size_t)i * n + r) * m + q] = qa[rr][c];
+                }
             }
-            if (lane == 0 && q < m) {
-                P.part[((size_t)(i - 1) * m + q) * 2 + 0] = r2;
-                P.part[((size_t)(i - 1) * m + q) * 2 + 1] = b2;
-            }
+        }
+    }
+}
+
+// r_i = P_i - Q_i (Q_1 = 0), its FP32 copy and the partial norms; one
+// wavefront per block row.
+__global__ __launch_bounds__(kWave) void k_res_fin(Launch<ResidualDesc> L) {
+    ResidualDesc P;
+    int level;
+    int64_t row0;
+    fetch_item(L, P, level, row0);
+    if (P.state && P.state->done) return;
+    const int lane = threadIdx.x;
+    const int n = P.n, m = P.m;
+    const int64_t i = row0 + 1;
+    for (int q = 0; q < m; ++q) {
+        double r2 = 0.0, b2 = 0.0;
+        for (int r = lane; r < n; r += kWave) {
+            const size_t e = ((size_t)(i - 1) * n + r) * m + q;
+            const double v = i > 1 ? P.P[e] - P.Q[e] : P.P[e];
+            if (P.R32) P.R32[e] = (float)v;
+            const double bv = P.B[e];
+            r2 = fma(v, v, r2);
+            b2 = fma(bv, bv, b2);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            r2 += __shfl_xor(r2, off);
+            b2 += __shfl_xor(b2, off);
+        }
+        if (lane == 0) {
+            P.part[((size_t)(i - 1) * m + q) * 2 + 0] = r2;
+            P.part[((size_t)(i - 1) * m + q) * 2 + 1] = b2;
         }
     }
 }
@@ -587,6 +692,9 @@ hipError_t launch_res_np(const Launch<ResidualDesc>& p, int64_t items, int mc, h
         hipLaunchKernelGGL((k_res<NP, 1>), g, b, 0, st, p);
     else
         hipLaunchKernelGGL((k_res<NP, 4>), g, b, 0, st, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_res_fin, g, b, 0, st, p);
     return hipGetLastError();
 }
 

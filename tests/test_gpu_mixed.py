@@ -109,6 +109,23 @@ def test_fp64_info_reports_residual(btc):
     assert rr <= 1e-12
 
 
+@pytest.mark.parametrize("N,n,m", [(1, 7, 1), (2, 16, 1), (37, 24, 1), (64, 64, 1), (40, 96, 1), (33, 128, 1),
+                                   (21, 96, 3), (19, 40, 5), (9, 8, 4)])
+def test_device_residual_of_unrefined_iterate(btc, N, n, m):
+    """The FP64 residual of the first FP32 iterate (tolerance 1: no
+    correction) is well above rounding noise, so the device's column norms
+    must match the oracle's residual of the same iterate closely: every
+    block term, both triangles of D_i and both couplings of a row count."""
+    pr = inputs.block_tridiag(N, n, seed=5 + N + n + m, nrhs=m)
+    f = btc.Factor(dev(pr.D), dev(pr.E), precision=btc.BTC_FP32_IR, tol=1.0)
+    X, info = f.solve(dev(pr.B), want_info=True)
+    f.close()
+    assert info["converged"] and info["steps"] == 0, info
+    rr = oracle.relres(pr.D, pr.E, X.cpu().numpy(), pr.B)
+    assert rr > 1e-12
+    assert abs(info["relres"] - rr) <= 1e-6 * rr, (info["relres"], rr)
+
+
 def test_mixed_rejects_aliased_rhs(btc):
     pr = inputs.block_tridiag(9, 4, seed=1)
     B = dev(pr.B)
