@@ -470,28 +470,72 @@ __global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
 
 
 
+// Value of the exchange partner across lane bit H: DPP within rows of 16
+// lanes (the row mirror for bit 3, the half-row mirror for bit 2, quad
+// permutations for bits 1 and 0), LDS permute across rows.  Each pairing is
+// an involution whose pairs differ in bit H and otherwise only in lower bits.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long w = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)w, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(w >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int H>
+__device__ __forceinline__ double partner(double v) {
+    if constexpr (H == 8) return dpp_d<0x140>(v);       // row_mirror
+    else if constexpr (H == 4) return dpp_d<0x141>(v);  // row_half_mirror
+    else if constexpr (H == 2) return dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    else if constexpr (H == 1) return dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    else return __shfl_xor(v, H);
+}
+// Lane bit of exchange step T: bits 3, 2, 1, 0 first (a mirror also flips
+// the bits below its own, so those must not be bound to a value yet), then
+// 4 and 5.
+constexpr int step_bit(int t) { return t < 4 ? 8 >> t : 16 << (t - 4); }
+
+// Halving exchanges from step T on, W values per lane in play: the lane
+// keeps the half its step bit selects and adds its partner's copy of it.
+template <int W, int T>
+__device__ __forceinline__ void halve(double* v, int lane) {
+    if constexpr (W >= 1) {
+        constexpr int H = step_bit(T);
+        const bool up = (lane & H) != 0;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const double send = up ? v[j] : v[j + W];
+            const double keep = up ? v[j + W] : v[j];
+            v[j] = keep + partner<H>(send);
+        }
+        halve<W / 2, T + 1>(v, lane);
+    }
+}
+template <int T>
+__device__ __forceinline__ double all_sum(double s) {
+    if constexpr (T < 6) return all_sum<T + 1>(s + partner<step_bit(T)>(s));
+    else return s;
+}
 constexpr int ilog2_c(int v) { return v <= 1 ? 0 : 1 + ilog2_c(v / 2); }
 
-// Sum over the wavefront of KB values per lane: afterwards lane l holds the
-// total of value l >> (6 - log2 KB).  Each halving step keeps half of the
-// lane's values and adds the other half of its partner's, so KB values cost
-// KB - 1 exchanges plus the last 6 - log2 KB.
+// Sum over the wavefront of KB values per lane (KB a power of two <= 16).
+// Afterwards the lanes given by row_source hold the totals.  Every total is
+// formed by the same tree of additions whatever KB is, so chunking rows
+// differently does not change a bit of the result.
 template <int KB>
 __device__ __forceinline__ double wave_sum_rows(double (&v)[KB], int lane) {
+    static_assert(KB >= 1 && KB <= 16 && (KB & (KB - 1)) == 0, "power of two up to 16");
+    halve<KB / 2, 0>(v, lane);
+    return all_sum<ilog2_c(KB)>(v[0]);
+}
+// A lane that holds the total of value k after wave_sum_rows<KB>: step t of
+// the halving bound the value's bit KB / 2^(t+1) to lane bit step_bit(t).
+template <int KB>
+__device__ __forceinline__ int row_source(int k) {
+    int l = 0;
 #pragma unroll
-    for (int w = KB / 2, h = kWave / 2; w >= 1; w /= 2, h /= 2) {
-        const bool up = (lane & h) != 0;
-#pragma unroll
-        for (int j = 0; j < w; ++j) {
-            const double send = up ? v[j] : v[j + w];
-            const double keep = up ? v[j + w] : v[j];
-            v[j] = keep + __shfl_xor(send, h);
-        }
-    }
-    double s = v[0];
-#pragma unroll
-    for (int h = kWave >> (ilog2_c(KB) + 1); h >= 1; h /= 2) s += __shfl_xor(s, h);
-    return s;
+    for (int t = 0, w = KB / 2; w >= 1; ++t, w /= 2)
+        if (k & w) l |= step_bit(t);
+    return l;
 }
 
 template <int NP, int MC>
@@ -499,7 +543,6 @@ __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
     using G = Geo<NP>;
     constexpr int RPL = G::RPL, LDB = G::LDB;
     constexpr int KB = 4 / MC;              // slab rows per wavefront sum (4 sums live)
-    constexpr int SH = 6 - ilog2_c(KB);     // lane l holds the sum of row l >> SH
     static_assert(KB >= 1 && kS % KB == 0, "chunks divide the slab");
     __shared__ double buf[G::BUF];
     ResidualDesc P;
@@ -552,7 +595,7 @@ __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
         run_slabs<NP, double, slab_depth<NP, double>()>(pl, n, lane, buf, [&](int g, int q, const double* b) {
             // g = 0: slab row c of D_i (elements with r <= c valid); g = 1:
             // row c of E_i.  Rows past n are zero.
-            const int off = kS * q;
+            const int off = kS * q, dslot = off / kWave;
 #pragma unroll 1
             for (int k0 = 0; k0 < kS; k0 += KB) {
                 double ps[MC][KB];
@@ -572,26 +615,41 @@ __global__ __launch_bounds__(kWave) void k_res(Launch<ResidualDesc> L) {
 #pragma unroll
                     for (int rr = 0; rr < RPL; ++rr) {
                         const int r = lane + kWave * rr;
-                        const double a = r < n ? b[(k0 + k) * LDB + r] : 0.0;
-                        // as element (r, c): D_i above the diagonal (r < c),
-                        // E_i^T; as element (c, r): D_i on and below it, E_i
-                        const double au = (g == 0 && r >= cc) ? 0.0 : a;
-                        const double al = (g == 0 && r > cc) ? 0.0 : a;
+                        // columns r in [n, NP) of the slab are zero; lanes r >= NP
+                        // would read the next slab row (perhaps the unread
+                        // upper triangle of D_i) and feed the wavefront sums
+                        const double a = (NP % kWave == 0 || rr < RPL - 1 || r < NP) ? b[(k0 + k) * LDB + r] : 0.0;
+                        if (g == 0 && rr == dslot) {
+                            // the diagonal tile of D_i: as element (r, c) above
+                            // the diagonal (r < c), as element (c, r) on and
+                            // below it
+                            const double au = r >= cc ? 0.0 : a;
+                            const double al = r > cc ? 0.0 : a;
 #pragma unroll
-                        for (int c = 0; c < MC; ++c) {
-                            acc[rr][c] = fma(au, xb[c], acc[rr][c]);
-                            ps[c][k] = fma(al, x1[rr][c], ps[c][k]);
+                            for (int c = 0; c < MC; ++c) {
+                                acc[rr][c] = fma(au, xb[c], acc[rr][c]);
+                                ps[c][k] = fma(al, x1[rr][c], ps[c][k]);
+                            }
+                        } else {
+                            // D_i left of the diagonal tile (the rest of the
+                            // slab row is zero), E_i: both uses
+#pragma unroll
+                            for (int c = 0; c < MC; ++c) {
+                                acc[rr][c] = fma(a, xb[c], acc[rr][c]);
+                                ps[c][k] = fma(a, x1[rr][c], ps[c][k]);
+                            }
                         }
                     }
                 }
-                // row c = off + k0 + k gets its sum from lane k << SH; its
-                // owner is lane c % 64 in slot c / 64
+                // row c = off + k0 + k gets its sum from lane row_source(k);
+                // its owner is lane c % 64 in slot c / 64
                 const int base = off + k0, slot = base / kWave;
                 const int k = lane - (base & (kWave - 1));
+                const int src = row_source<KB>(k & (KB - 1));
 #pragma unroll
                 for (int c = 0; c < MC; ++c) {
                     const double s = wave_sum_rows<KB>(ps[c], lane);
-                    const double t = __shfl(s, (k & (KB - 1)) << SH);
+                    const double t = __shfl(s, src);
                     if (k >= 0 && k < KB) {
 #pragma unroll
                         for (int rr = 0; rr < RPL; ++rr) {

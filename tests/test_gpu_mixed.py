@@ -115,9 +115,12 @@ def test_device_residual_of_unrefined_iterate(btc, N, n, m):
     """The FP64 residual of the first FP32 iterate (tolerance 1: no
     correction) is well above rounding noise, so the device's column norms
     must match the oracle's residual of the same iterate closely: every
-    block term, both triangles of D_i and both couplings of a row count."""
+    block term, both triangles of D_i and both couplings of a row count.
+    The unread upper triangles hold NaN: nothing may multiply them, not even
+    by zero."""
     pr = inputs.block_tridiag(N, n, seed=5 + N + n + m, nrhs=m)
-    f = btc.Factor(dev(pr.D), dev(pr.E), precision=btc.BTC_FP32_IR, tol=1.0)
+    D = pr.D + np.triu(np.full((n, n), np.nan), 1)[None]
+    f = btc.Factor(dev(D), dev(pr.E), precision=btc.BTC_FP32_IR, tol=1.0)
     X, info = f.solve(dev(pr.B), want_info=True)
     f.close()
     assert info["converged"] and info["steps"] == 0, info
