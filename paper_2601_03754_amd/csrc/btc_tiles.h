@@ -124,13 +124,6 @@ __device__ __forceinline__ void tri_tile(int k, int& a, int& b) {
     b = k - a * (a + 1) / 2;
 }
 
-// Cholesky of the lower triangle of an NP x NP LDS tile by one wavefront,
-// lane r holding row r in registers.  The pivot of step j+1 is formed right
-// after step j from two readlanes (the new column j value of row j+1 is its
-// own multiplier), so the pivot chain never waits for the LDS broadcast; the
-// rest of the column is broadcast through a double-buffered LDS column for
-// the trailing update.  1/sqrt of the pivot: hardware estimate refined by two
-// Newton steps.  Writes L (zero strict upper part) back and 1/L_jj to invd.
 // Cholesky of an NP x NP tile (NP <= 16) by one wavefront with lane r holding
 // row r: the multipliers of column j reach the other columns by readlane
 // broadcasts (no LDS round trip on the pivot chain).  Same contract as
@@ -142,13 +135,14 @@ __device__ __forceinline__ bool potrf_small(double* __restrict__ A, double* __re
     double a[NP];
 #pragma unroll
     for (int c = 0; c < NP; ++c) a[c] = (lane < NP && c <= lane) ? A[lane * LD + c] : 0.0;
-    // 1/sqrt(p): hardware estimate refined by two Newton steps
+    // 1/sqrt(p): hardware estimate r refined by one third-order step.  With
+    // e = 1 - p r^2, 1/sqrt(p) = r (1 - e)^(-1/2) = r (1 + e/2 + 3e^2/8 + ...);
+    // the estimate's e of about 1e-7 leaves a truncation term near 1e-22, and
+    // the chain is four dependent operations instead of two Newton steps' six.
     auto rsqrt_refined = [](double p) {
-        double r = __builtin_amdgcn_rsq(p);
-        double e = fma(-p * r, r, 1.0);
-        r = fma(0.5 * r, e, r);
-        e = fma(-p * r, r, 1.0);
-        return fma(0.5 * r, e, r);
+        const double r = __builtin_amdgcn_rsq(p);
+        const double e = fma(-p * r, r, 1.0);
+        return fma(r * e, fma(e, 0.375, 0.5), r);
     };
     double piv = readlane_d(a[0], 0);
     double r = rsqrt_refined(piv);
@@ -184,6 +178,13 @@ __device__ __forceinline__ bool potrf_small(double* __restrict__ A, double* __re
     return ok;
 }
 
+// Cholesky of the lower triangle of an NP x NP LDS tile by one wavefront,
+// lane r holding row r in registers.  The pivot of step j+1 is formed right
+// after step j from two readlanes (the new column j value of row j+1 is its
+// own multiplier), so the pivot chain never waits for the LDS broadcast; the
+// rest of the column is broadcast through a double-buffered LDS column for
+// the trailing update.  1/sqrt of the pivot: hardware estimate refined by two
+// Newton steps.  Writes L (zero strict upper part) back and 1/L_jj to invd.
 template <int NP, int LD = NP + 1>
 __device__ __forceinline__ bool potrf_lookahead(double* __restrict__ A, double* __restrict__ invd,
                                                 double (*__restrict__ colbuf)[kWave]) {
