@@ -160,3 +160,18 @@ def test_batched_large_equals_single_bitwise(btc, precision):
     for h in hs:
         btc.btc_destroy(h)
     r.close()
+
+
+@pytest.mark.parametrize("N,n", [(4096, 64), (1024, 128), (16384, 32)])
+def test_full_size_device_residual(btc, N, n):
+    """At the full benchmark sizes, the device's FP64 residual of the first,
+    unrefined FP32 iterate (tolerance 1: no correction) matches the oracle's
+    residual of the same iterate to 1e-6 relative."""
+    pr = inputs.block_tridiag(N, n, c=4.0, seed=inputs.sweep_seed(N, n), nrhs=1)
+    f = btc.Factor(dev(pr.D), dev(pr.E), precision=btc.BTC_FP32_IR, tol=1.0)
+    X, info = f.solve(dev(pr.B), want_info=True)
+    f.close()
+    assert info["converged"] and info["steps"] == 0, info
+    rr = oracle.relres(pr.D, pr.E, X.cpu().numpy(), pr.B)
+    assert rr > 1e-12
+    assert abs(info["relres"] - rr) <= 1e-6 * rr, (info["relres"], rr)
