@@ -468,8 +468,6 @@ __global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
 // partial squared norms of r_i and b_i.  Work items of consecutive block rows
 // share an XCD (xcd_local_block).
 
-
-
 // Value of the exchange partner across lane bit H: DPP within rows of 16
 // lanes (the row mirror for bit 3, the half-row mirror for bit 2, quad
 // permutations for bits 1 and 0), LDS permute across rows.  Each pairing is
