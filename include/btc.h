@@ -109,9 +109,10 @@ typedef struct {
  *   opt            NULL for FP64 defaults
  *   stream         hipStream_t or NULL
  *   out            receives the new handle (host pointer, not NULL)
- * The handle allocates its device memory with hipMalloc here; it is freed by
- * btc_destroy.  Argument errors: -1..-7 for the argument at that position
- * (-5 for an unknown precision or a negative max_refine / tol).
+ * The handle allocates its device memory here, through the allocator set by
+ * btc_set_allocator (default hipMalloc); it is freed by btc_destroy.
+ * Argument errors: -1..-7 for the argument at that position (-5 for an
+ * unknown precision or a negative max_refine / tol).
  */
 BTC_API int btc_factor(const double *A_diag, const double *A_off, int64_t N, int64_t n,
                const btc_options *opt, void *stream, btc_handle *out);
@@ -143,8 +144,14 @@ BTC_API int btc_refactor(btc_handle h, const double *A_diag, const double *A_off
  * Refinement stops on its own on the device (no host synchronisation) once
  * the target is met, once a step reduces the residual by less than 2x, or
  * after max_refine corrections.  Returns BTC_ERR_NOT_SPD (without writing X)
- * if the factorization is known to have broken down.  Solves on one handle
- * must not run concurrently.
+ * if the factorization is known to have broken down.
+ * Concurrency: once the factorization has completed, the factor is only
+ * read, and solves of one handle may run concurrently on different streams:
+ * a solve uses the handle's workspace on the stream that last used it, or on
+ * another stream when the last solve that used it has finished; otherwise it
+ * takes a workspace of its own from the allocator (btc_set_allocator) for the
+ * duration of the call, released in stream order.  Calls from several host
+ * threads on one handle must be serialised by the caller.
  */
 BTC_API int btc_solve(btc_handle h, const double *B, double *X, int64_t nrhs, void *stream,
               btc_solve_info *info);
@@ -158,7 +165,8 @@ BTC_API int btc_solve(btc_handle h, const double *B, double *X, int64_t nrhs, vo
  */
 BTC_API int btc_status(btc_handle h, int64_t *info);
 
-/* btc_destroy -- free the handle and its device memory (NULL is a no-op). */
+/* btc_destroy -- wait for the handle's work on every stream it was used
+ * on, then free the handle and its device memory (NULL is a no-op). */
 BTC_API void btc_destroy(btc_handle h);
 
 /*
@@ -375,19 +383,31 @@ BTC_API int btc_level_work(int32_t op, int32_t precision, int64_t N, int64_t n, 
 
 /*
  * btc_factor_batched -- factor `count` independent instances (handles from
- * btc_create, host arrays of device pointers), walking their levels together.
+ * btc_create, of any shapes and precisions; host arrays of device pointers),
+ * walking their levels together: one group of launches per level, each
+ * launch carrying the nodes of every instance at that level.  The batched
+ * calls take a runner rather than a stream: the runner is the stream plus
+ * the side streams and staging buffers its launches use, and it is what a
+ * HIP graph of the level schedule is recorded from (btc_graph_begin).
+ *   info   NULL, or a host array of count entries: synchronises with the
+ *          runner and writes each instance's status as btc_status does.
  */
 BTC_API int btc_factor_batched(btc_runner r, int32_t count, const btc_handle *h, const double *const *A_diag,
-                               const double *const *A_off);
+                               const double *const *A_off, int64_t *info);
 
 /*
- * btc_solve_batched -- solve `count` independent instances, nrhs columns
- * each (BTC_FP32_IR handles are refined in FP64 as in btc_solve; X must not
- * alias B for them).  Status per handle: btc_status; refinement outcome:
- * btc_refine_info.
+ * btc_solve_batched -- solve `count` independent instances, instance k with
+ * nrhs[k] >= 1 columns (host array); BTC_FP32_IR / BTC_BF16_IR handles are
+ * refined in FP64 as in btc_solve (X must not alias B for them).
+ *   info   NULL, or a host array of count entries: synchronises with the
+ *          runner and fills each as btc_solve_info (an instance whose factor
+ *          broke down gets steps = 0, converged = 0, relres = -1).
+ * Without info: status per handle btc_status, refinement outcome
+ * btc_refine_info.  Inside a graph recording (btc_graph_begin) info must be
+ * NULL.
  */
 BTC_API int btc_solve_batched(btc_runner r, int32_t count, const btc_handle *h, const double *const *B,
-                              double *const *X, int64_t nrhs);
+                              double *const *X, const int64_t *nrhs, btc_solve_info *info);
 
 /*
  * btc_refine_info -- synchronise with the handle's stream and report the
@@ -436,7 +456,14 @@ typedef struct {
     double t_admit;      /* admission (memory and the client's previous request permitting) */
     double t_done;       /* the device finished the request's last step (observed by step/poll) */
     int32_t refactored;  /* 1 if the request factored (new matrix, or a re-admitted client) */
+    int32_t converged;   /* 1 if the result met the target: mixed precision, the refinement's
+                            residual test passed; FP64, the factorization succeeded */
+    int64_t info;        /* status of the client's factor as btc_status reports it (0: ok,
+                            k > 0: block k not positive definite; X is then not written) */
+    int32_t steps;       /* refinement corrections applied (0 for BTC_FP64) */
     int32_t pad;
+    double relres;       /* mixed precision: the FP64 max-column relative residual of X as the
+                            last convergence test measured it; FP64 path: -1 (not computed) */
 } btc_server_completion;
 
 BTC_API int btc_server_create(const btc_server_options *opt, void *stream, btc_server *out);
@@ -447,7 +474,13 @@ BTC_API int btc_server_add_client(btc_server s, int64_t N, int64_t n, int64_t *c
 /*
  * Queue a request (device pointers, valid until the request completes):
  * A_diag / A_off non-NULL for "refactor + solve", NULL for "solve" (the first
- * request of a client must bring a matrix); B, X [N][n][nrhs].
+ * request of a client must bring a matrix); B, X [N][n][nrhs].  A solve-only
+ * request refers to the matrix of the client's previous refactorization
+ * (requests of one client are admitted in submission order); if the client
+ * was evicted meanwhile, that matrix is factored again, so it must stay valid
+ * until a later refactorization of the client has completed.  Returns
+ * BTC_ERR_UNSUPPORTED when the request's footprint (btc_footprint_bytes)
+ * alone exceeds the HBM budget.
  */
 BTC_API int btc_server_submit(btc_server s, int64_t client, const double *A_diag, const double *A_off,
                               const double *B, double *X, int64_t nrhs, int64_t *ticket);
@@ -469,6 +502,22 @@ BTC_API btc_handle btc_server_client_handle(btc_server s, int64_t client);
 BTC_API btc_runner btc_server_runner(btc_server s);
 
 BTC_API void btc_server_destroy(btc_server s);
+
+/*
+ * btc_set_allocator -- source of every DEVICE allocation the library makes
+ * from now on (factors, solve workspaces, runner and graph descriptor
+ * buffers; pinned host staging memory is not affected): alloc(bytes, stream,
+ * ctx) returns memory of the current device usable in stream order on
+ * `stream` (NULL on failure, reported as BTC_ERR_OOM), free_(ptr, stream,
+ * ctx) releases it in that order.  Both NULL restores HIP's allocator
+ * (hipMalloc; hipMallocAsync for the memory of one call).  Objects keep the
+ * functions they allocated with, so the hook may change while they live; the
+ * functions must stay callable until those objects are destroyed.  Intended
+ * for a framework's caching allocator (the Python binding installs torch's).
+ * Returns -1 when exactly one of the two functions is NULL.
+ */
+BTC_API int btc_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
+                              void (*free_)(void *ptr, void *stream, void *ctx), void *ctx);
 
 /* btc_error_string -- static text for a return code. */
 BTC_API const char *btc_error_string(int code);

@@ -61,7 +61,32 @@ class btc_kernel_stat(ctypes.Structure):
 
 class btc_server_completion(ctypes.Structure):
     _fields_ = [("ticket", i64), ("client", i64), ("t_submit", dbl), ("t_admit", dbl), ("t_done", dbl),
-                ("refactored", i32), ("pad", i32)]
+                ("refactored", i32), ("converged", i32), ("info", i64), ("steps", i32), ("pad", i32),
+                ("relres", dbl)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(vp, ctypes.c_size_t, vp, vp)
+_FREE_FN = ctypes.CFUNCTYPE(None, vp, vp, vp)
+
+
+def _torch_alloc(size, stream, ctx):
+    # memory of the current device from torch's caching allocator, bound to
+    # the library's stream (stream-ordered reuse); 0 reports out of memory
+    try:
+        return torch.cuda.caching_allocator_alloc(int(size), torch.cuda.current_device(), int(stream or 0))
+    except Exception:
+        return 0
+
+
+def _torch_free(ptr, stream, ctx):
+    try:
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+_alloc_cb = _ALLOC_FN(_torch_alloc)
+_free_cb = _FREE_FN(_torch_free)
 
 
 class BtcError(RuntimeError):
@@ -113,9 +138,11 @@ def lib():
         L.btc_runner_destroy.restype = None
         L.btc_runner_destroy.argtypes = [vp]
         L.btc_factor_batched.restype = ctypes.c_int
-        L.btc_factor_batched.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
+        L.btc_factor_batched.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(i64)]
         L.btc_solve_batched.restype = ctypes.c_int
-        L.btc_solve_batched.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i64]
+        L.btc_solve_batched.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                        ctypes.POINTER(i64), ctypes.POINTER(btc_solve_info)]
         L.btc_refine_info.restype = ctypes.c_int
         L.btc_refine_info.argtypes = [vp, ctypes.POINTER(btc_solve_info)]
         L.btc_server_create.restype = ctypes.c_int
@@ -159,8 +186,24 @@ def lib():
         L.btc_server_runner.argtypes = [vp]
         L.btc_version.restype = ctypes.c_int
         L.btc_version.argtypes = []
+        L.btc_set_allocator.restype = ctypes.c_int
+        L.btc_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
         _lib = L
+        # device memory of the library comes from torch's caching allocator
+        _check(L.btc_set_allocator(_alloc_cb, _free_cb, None), "btc_set_allocator")
     return _lib
+
+
+def btc_set_allocator(use_torch: bool = True) -> None:
+    """Route the library's device allocations through torch's caching
+    allocator (the default once the library is loaded), or back to HIP's own
+    allocator (use_torch=False)."""
+    L = lib()
+    if use_torch:
+        _check(L.btc_set_allocator(_alloc_cb, _free_cb, None), "btc_set_allocator")
+    else:
+        _check(L.btc_set_allocator(ctypes.cast(None, _ALLOC_FN), ctypes.cast(None, _FREE_FN), None),
+               "btc_set_allocator")
 
 
 def btc_error_string(code: int) -> str:
@@ -303,8 +346,14 @@ class Runner:
         r = vp()
         _check(lib().btc_runner_create(self.stream, ctypes.byref(r)), "btc_runner_create")
         self.handle = r.value
+        # matrices of the handles factored through this runner: the mixed
+        # precision paths read them again for the FP64 residual, so they stay
+        # referenced until the handle is factored again or the runner closes
+        self._mats = {}
 
     def run(self, steps) -> None:
+        """Enqueue raw steps (the caller keeps every tensor they point to
+        alive while the device may read it)."""
         arr = (btc_step * max(1, len(steps)))(*steps)
         _check(lib().btc_runner_run(self.handle, len(steps), arr), "btc_runner_run")
 
@@ -317,19 +366,39 @@ class Runner:
     def sync(self) -> None:
         _check(lib().btc_runner_sync(self.handle), "btc_runner_sync")
 
-    def factor_batched(self, handles, A_diags, A_offs) -> None:
+    def factor_batched(self, handles, A_diags, A_offs, want_info: bool = False):
+        """Factor the instances together; with want_info, synchronise and
+        return each instance's status (0 or the failing block)."""
         n = len(handles)
+        info = (i64 * max(1, n))() if want_info else None
+        for h, a, o in zip(handles, A_diags, A_offs):
+            self._mats[h] = (a, o)
         _check(lib().btc_factor_batched(self.handle, n, _ptr_array(handles),
                                         _ptr_array([_dev(a, "A_diag") for a in A_diags]),
-                                        _ptr_array([_dev(a, "A_off") if a.numel() else 0 for a in A_offs])),
+                                        _ptr_array([_dev(a, "A_off") if a.numel() else 0 for a in A_offs]),
+                                        info),
                "btc_factor_batched")
+        return [int(info[k]) for k in range(n)] if want_info else None
 
-    def solve_batched(self, handles, Bs, Xs, nrhs: int) -> None:
+    def solve_batched(self, handles, Bs, Xs, nrhs=None, want_info: bool = False):
+        """Solve the instances together; nrhs per instance (default: the
+        last dimension of each B).  With want_info, synchronise and return
+        each instance's outcome (steps, converged, relres)."""
         n = len(handles)
+        if nrhs is None:
+            nrhs = [b.shape[-1] if b.dim() == 3 else 1 for b in Bs]
+        elif isinstance(nrhs, int):
+            nrhs = [nrhs] * n
+        m = (i64 * max(1, n))(*[int(v) for v in nrhs])
+        info = (btc_solve_info * max(1, n))() if want_info else None
         _check(lib().btc_solve_batched(self.handle, n, _ptr_array(handles),
                                        _ptr_array([_dev(b, "B") for b in Bs]),
-                                       _ptr_array([_dev(x, "X") for x in Xs]), nrhs),
+                                       _ptr_array([_dev(x, "X") for x in Xs]), m, info),
                "btc_solve_batched")
+        if not want_info:
+            return None
+        return [{"steps": info[k].steps, "converged": bool(info[k].converged), "relres": info[k].relres}
+                for k in range(n)]
 
     def graph_begin(self) -> None:
         """Record the following runner calls instead of running them."""
@@ -352,6 +421,7 @@ class Runner:
         if getattr(self, "handle", None):
             lib().btc_runner_destroy(self.handle)
             self.handle = None
+            self._mats.clear()
 
     def __del__(self):
         try:
@@ -442,6 +512,7 @@ class Server:
         _check(lib().btc_server_create(ctypes.byref(opt), self.stream, ctypes.byref(h)), "btc_server_create")
         self.handle = h.value
         self._live = {}
+        self._mats = {}
         self._buf = (btc_server_completion * 4096)()
 
     def add_client(self, N: int, n: int) -> int:
@@ -456,8 +527,21 @@ class Server:
         po = (_dev(A[1], "A_off") if A[1].numel() else 0) if A is not None else 0
         _check(lib().btc_server_submit(self.handle, client, pa, po, _dev(B, "B"), _dev(X, "X"), nrhs,
                                        ctypes.byref(t)), "btc_server_submit")
-        self._live[t.value] = (B, X, A)
+        self._live[t.value] = (client, B, X, A)
+        if A is not None:
+            self._mats.setdefault(client, []).append((t.value, A))
         return t.value
+
+    def _release(self, ticket: int) -> None:
+        # drop the request's tensors; once a refactorization has completed,
+        # the client's older matrices are no longer referenced by the server
+        # (a later eviction refactors with this one)
+        ent = self._live.pop(ticket, None)
+        if ent is None:
+            return
+        client, _, _, A = ent
+        if A is not None:
+            self._mats[client] = [(t, a) for (t, a) in self._mats.get(client, []) if t >= ticket]
 
     def step(self) -> int:
         rc = lib().btc_server_step(self.handle)
@@ -474,8 +558,10 @@ class Server:
             for k in range(cnt.value):
                 d = self._buf[k]
                 out.append({"ticket": d.ticket, "client": d.client, "t_submit": d.t_submit,
-                            "t_admit": d.t_admit, "t_done": d.t_done, "refactored": bool(d.refactored)})
-                self._live.pop(d.ticket, None)
+                            "t_admit": d.t_admit, "t_done": d.t_done, "refactored": bool(d.refactored),
+                            "converged": bool(d.converged), "info": d.info, "steps": d.steps,
+                            "relres": d.relres})
+                self._release(d.ticket)
             if cnt.value < len(self._buf):
                 return out
             wait = False
@@ -498,6 +584,7 @@ class Server:
             lib().btc_server_destroy(self.handle)
             self.handle = None
             self._live.clear()
+            self._mats.clear()
 
     def __del__(self):
         try:

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -15,13 +16,32 @@
 
 namespace btc_host {
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v) { *p = v; }
+
+namespace {
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+}  // namespace
+
+Allocator current_allocator() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
 }  // namespace btc_host
 
 using namespace btc_host;
 
 extern "C" {
 
-BTC_API int btc_version(void) { return 200; }
+BTC_API int btc_version(void) { return 300; }
+
+BTC_API int btc_set_allocator(void* (*alloc)(size_t, void*, void*), void (*free_)(void*, void*, void*), void* ctx) {
+    if ((alloc == nullptr) != (free_ == nullptr)) return -1;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.free_ = free_;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+    return BTC_OK;
+}
 
 BTC_API const char* btc_error_string(int code) {
     switch (code) {
@@ -72,17 +92,19 @@ BTC_API int btc_create(int64_t N, int64_t n, const btc_options* opt, btc_handle*
     h->tol = (opt && opt->tol > 0.0) ? opt->tol : BTC_DEFAULT_TOL;
     h->levels = num_levels(N);
     (void)hipGetDevice(&h->device);
+    h->alloc = current_allocator();
     const size_t nn = (size_t)N * (size_t)n * (size_t)n;
-    hipError_t e = hipMalloc(&h->info, sizeof(unsigned long long));
+    auto get = [h](auto*& p, size_t bytes) { return dev_alloc(h->alloc, (void**)&p, bytes, h->stream); };
+    hipError_t e = get(h->info, sizeof(unsigned long long));
     if (is_mixed(prec)) {
-        if (e == hipSuccess) e = hipMalloc(&h->S64, nn * sizeof(double));
-        if (e == hipSuccess) e = hipMalloc(&h->L32, nn * sizeof(float));
-        if (e == hipSuccess) e = hipMalloc(&h->R32, nn * sizeof(float));
-        if (e == hipSuccess) e = hipMalloc(&h->T32, nn * sizeof(float));
+        if (e == hipSuccess) e = get(h->S64, nn * sizeof(double));
+        if (e == hipSuccess) e = get(h->L32, nn * sizeof(float));
+        if (e == hipSuccess) e = get(h->R32, nn * sizeof(float));
+        if (e == hipSuccess) e = get(h->T32, nn * sizeof(float));
     } else {
-        if (e == hipSuccess) e = hipMalloc(&h->Ld, nn * sizeof(double));
-        if (e == hipSuccess) e = hipMalloc(&h->Rb, nn * sizeof(double));
-        if (e == hipSuccess) e = hipMalloc(&h->Tb, nn * sizeof(double));
+        if (e == hipSuccess) e = get(h->Ld, nn * sizeof(double));
+        if (e == hipSuccess) e = get(h->Rb, nn * sizeof(double));
+        if (e == hipSuccess) e = get(h->Tb, nn * sizeof(double));
     }
     if (e != hipSuccess) {
         free_all(h);
@@ -146,22 +168,16 @@ BTC_API int btc_refactor(btc_handle h, const double* A_diag, const double* A_off
     return launch_factor(h, A_diag, A_off, (hipStream_t)stream);
 }
 
-BTC_API int btc_solve(btc_handle h, const double* B, double* X, int64_t nrhs, void* stream,
-                      btc_solve_info* info) {
-    if (!h) return -1;
-    if (!B) return -2;
-    if (!X) return -3;
-    if (nrhs < 0) return -4;
-    if (!h->factored) return -1;
-    if (h->failed_known) return BTC_ERR_NOT_SPD;
-    if (nrhs == 0) return BTC_OK;
+}  // extern "C"
+
+namespace btc_host {
+
+// Enqueue a solve (and, for the mixed paths, its refinement) with the
+// workspace w; fills *info (synchronising) when it is not NULL.  Allocates
+// nothing.
+int solve_with(btc_handle h, const Workspace& w, const double* B, double* X, int64_t nrhs, hipStream_t st,
+               btc_solve_info* info) {
     const bool mixed = is_mixed(h->precision);
-    if (mixed && X == B) return -3;  // refinement reads b after x is written
-    hipStream_t st = (hipStream_t)stream;
-    int rc = ensure_workspace(h, nrhs);
-    if (rc != BTC_OK) return rc;
-    Workspace w = carve(h, h->ws_m);  // one layout per allocation
-    h->stream = st;
     hipError_t e = hipSuccess;
     const int np = btc::padded_block((int)h->n);
     if (!mixed) {
@@ -199,7 +215,7 @@ BTC_API int btc_solve(btc_handle h, const double* B, double* X, int64_t nrhs, vo
         if (!info) return BTC_OK;
     }
     unsigned long long v = 0;
-    rc = read_info(h, st, &v);
+    int rc = read_info(h, st, &v);
     if (rc != BTC_OK) return rc;
     if (v != kInfoOk) {
         h->failed_known = true;
@@ -212,6 +228,75 @@ BTC_API int btc_solve(btc_handle h, const double* B, double* X, int64_t nrhs, vo
     info->converged = mixed ? s.converged : 1;
     info->relres = s.relres;
     return BTC_OK;
+}
+
+// Argument checks shared by btc_solve and btc_solve_noalloc (0: go on,
+// 1: nothing to do, < 0: error code).
+int check_solve(btc_handle h, const double* B, double* X, int64_t nrhs) {
+    if (!h) return -1;
+    if (!B) return -2;
+    if (!X) return -3;
+    if (nrhs < 0) return -4;
+    if (!h->factored) return -1;
+    if (h->failed_known) return BTC_ERR_NOT_SPD;
+    if (nrhs == 0) return 1;
+    if (is_mixed(h->precision) && X == B) return -3;  // refinement reads b after x is written
+    return 0;
+}
+
+void note_stream(btc_handle h, hipStream_t st) {
+    for (hipStream_t s : h->streams)
+        if (s == st) return;
+    h->streams.push_back(st);
+}
+
+}  // namespace btc_host
+
+extern "C" {
+
+BTC_API int btc_solve(btc_handle h, const double* B, double* X, int64_t nrhs, void* stream,
+                      btc_solve_info* info) {
+    int rc = check_solve(h, B, X, nrhs);
+    if (rc != 0) return rc < 0 ? rc : BTC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    note_stream(h, st);
+    // the handle's workspace serves solves on its stream, and solves on
+    // another stream once the last solve that used it has finished; a solve
+    // that would overlap one still running elsewhere gets a workspace of its
+    // own for the duration of the call (stream-ordered)
+    bool own = true;
+    if (h->ws && h->ws_stream != st) {
+        if (!h->ws_ev_valid) {
+            own = false;
+        } else {
+            const hipError_t q = hipEventQuery(h->ws_ev);
+            own = q == hipSuccess;
+        }
+    }
+    if (own && nrhs > h->ws_m) {
+        // growing the workspace synchronises with the streams that used it
+        h->stream = st;
+        rc = ensure_workspace(h, nrhs);
+        if (rc != BTC_OK) return rc;
+    }
+    if (own) {
+        const Workspace w = carve(h, h->ws_m);  // one layout per allocation
+        h->stream = st;
+        rc = solve_with(h, w, B, X, nrhs, st, info);
+        if (!h->ws_ev && hipEventCreateWithFlags(&h->ws_ev, hipEventDisableTiming) != hipSuccess) h->ws_ev = nullptr;
+        h->ws_stream = st;
+        h->ws_ev_valid = h->ws_ev && hipEventRecord(h->ws_ev, st) == hipSuccess;
+        return rc;
+    }
+    void* mem = nullptr;
+    const Allocator a = current_allocator();
+    hipError_t e = dev_alloc_async(a, &mem, workspace_bytes(h->N, h->n, h->precision, nrhs), st);
+    if (e != hipSuccess) return to_code(e);
+    const Workspace w = carve_at(mem, h->N, h->n, h->precision, nrhs);
+    h->stream = st;
+    rc = solve_with(h, w, B, X, nrhs, st, info);
+    dev_free_async(a, mem, st);
+    return rc;
 }
 
 BTC_API int btc_status(btc_handle h, int64_t* info) {
@@ -228,7 +313,9 @@ BTC_API int btc_status(btc_handle h, int64_t* info) {
 
 BTC_API void btc_destroy(btc_handle h) {
     if (!h) return;
+    // wait for the handle's work on every stream it was used on
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (hipStream_t s : h->streams) (void)hipStreamSynchronize(s);
     free_all(h);
     delete h;
 }

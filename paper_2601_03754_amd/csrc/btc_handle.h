@@ -19,6 +19,57 @@ constexpr unsigned long long kInfoOk = ~0ull;
 
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v);
 
+// Device memory source (btc_set_allocator): the caller's functions, or HIP's
+// own allocator when none is set.  Every object that allocates keeps the
+// source it allocated from, so that a later change of the hook does not
+// mismatch allocations and frees.
+struct Allocator {
+    void* (*alloc)(size_t, void*, void*) = nullptr;
+    void (*free_)(void*, void*, void*) = nullptr;
+    void* ctx = nullptr;
+};
+
+Allocator current_allocator();
+
+// Long-lived memory (factors, handle workspaces, descriptor buffers).
+inline hipError_t dev_alloc(const Allocator& a, void** p, size_t bytes, hipStream_t st) {
+    *p = nullptr;
+    if (a.alloc) {
+        *p = a.alloc(bytes, (void*)st, a.ctx);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+inline void dev_free(const Allocator& a, void* p, hipStream_t st) {
+    if (!p) return;
+    if (a.free_)
+        a.free_(p, (void*)st, a.ctx);
+    else
+        (void)hipFree(p);
+}
+
+// Memory of one call, ordered on its stream: freed on the stream once the
+// call's work is enqueued (HIP's stream-ordered allocator when no hook is
+// set; a hook receives the stream and must order the reuse itself, as a
+// caching allocator bound to that stream does).
+inline hipError_t dev_alloc_async(const Allocator& a, void** p, size_t bytes, hipStream_t st) {
+    *p = nullptr;
+    if (a.alloc) {
+        *p = a.alloc(bytes, (void*)st, a.ctx);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMallocAsync(p, bytes, st);
+}
+
+inline void dev_free_async(const Allocator& a, void* p, hipStream_t st) {
+    if (!p) return;
+    if (a.free_)
+        a.free_(p, (void*)st, a.ctx);
+    else
+        (void)hipFreeAsync(p, st);
+}
+
 }  // namespace btc_host
 
 struct btc_handle_s {
@@ -39,10 +90,20 @@ struct btc_handle_s {
     float* R32 = nullptr;
     float* T32 = nullptr;
     unsigned long long* info = nullptr;
-    // solve workspace, grown on demand (one allocation)
+    // solve workspace, grown on demand (one allocation); ws_ev marks the end
+    // of the last btc_solve that used it on ws_stream (a solve on another
+    // stream before that point takes a workspace of its own)
     void* ws = nullptr;
     int64_t ws_m = 0;
+    hipStream_t ws_stream = nullptr;
+    hipEvent_t ws_ev = nullptr;
+    bool ws_ev_valid = false;
+    btc_host::Allocator alloc;     // source of every device allocation of the handle
     hipStream_t stream = nullptr;  // stream of the last call
+    std::vector<hipStream_t> streams;  // every stream a solve of the handle ran on
+    // factor kernel family of every level, fixed when level 0 of a
+    // factorization is enqueued (the tune table may change meanwhile)
+    int8_t fkind[64] = {};
     bool factored = false;
     bool failed_known = false;     // a status check saw a breakdown
     const double* A_diag = nullptr;
@@ -82,13 +143,15 @@ inline int to_code(hipError_t e) {
 }
 
 template <class P>
-inline void dfree(P*& p) {
-    if (p) (void)hipFree((void*)p);
+inline void dfree(btc_handle h, P*& p) {
+    dev_free(h->alloc, (void*)p, h->stream);
     p = nullptr;
 }
 
 inline void free_all(btc_handle h) {
     if (!h) return;
+    if (h->ws_ev) (void)hipEventDestroy(h->ws_ev);
+    h->ws_ev = nullptr;
     for (auto& t : h->pending) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
@@ -96,15 +159,15 @@ inline void free_all(btc_handle h) {
     h->pending.clear();
     for (auto e : h->pool) (void)hipEventDestroy(e);
     h->pool.clear();
-    dfree(h->Ld);
-    dfree(h->Rb);
-    dfree(h->Tb);
-    dfree(h->S64);
-    dfree(h->L32);
-    dfree(h->R32);
-    dfree(h->T32);
-    dfree(h->info);
-    dfree(h->ws);
+    dfree(h, h->Ld);
+    dfree(h, h->Rb);
+    dfree(h, h->Tb);
+    dfree(h, h->S64);
+    dfree(h, h->L32);
+    dfree(h, h->R32);
+    dfree(h, h->T32);
+    dfree(h, h->info);
+    dfree(h, h->ws);
 }
 
 inline hipEvent_t take_event(btc_handle h) {
@@ -169,12 +232,14 @@ struct Workspace {
     btc::IrState* ir = nullptr;
 };
 
-inline Workspace carve(btc_handle h, int64_t m) {
+// Workspace layout of an (N, n, precision) system with m right-hand sides in
+// the memory at `base` (workspace_bytes long, 256-byte aligned).
+inline Workspace carve_at(void* base, int64_t N, int64_t n, int32_t prec, int64_t m) {
     Workspace w;
-    const size_t v = (size_t)h->N * (size_t)h->n * (size_t)m;
-    char* p = (char*)h->ws;
+    const size_t v = (size_t)N * (size_t)n * (size_t)m;
+    char* p = (char*)base;
     auto align = [](char* q) { return (char*)(((uintptr_t)q + 255) & ~(uintptr_t)255); };
-    if (is_mixed(h->precision)) {
+    if (is_mixed(prec)) {
         w.r = (float*)p;
         p += v * sizeof(float);
         w.y = (float*)p;
@@ -195,7 +260,7 @@ inline Workspace carve(btc_handle h, int64_t m) {
     }
     p = align(p);
     w.part = (double*)p;
-    p += 2 * (size_t)h->N * (size_t)m * sizeof(double);
+    p += 2 * (size_t)N * (size_t)m * sizeof(double);
     p = align(p);
     w.rp = (double*)p;
     p += v * sizeof(double);
@@ -206,14 +271,18 @@ inline Workspace carve(btc_handle h, int64_t m) {
     return w;
 }
 
+inline Workspace carve(btc_handle h, int64_t m) { return carve_at(h->ws, h->N, h->n, h->precision, m); }
+
 inline int ensure_workspace(btc_handle h, int64_t m) {
     if (m <= h->ws_m && h->ws) return BTC_OK;
     if (h->ws) {
         if (h->stream) (void)hipStreamSynchronize(h->stream);
-        dfree(h->ws);
+        if (h->ws_stream && h->ws_stream != h->stream) (void)hipStreamSynchronize(h->ws_stream);
+        dfree(h, h->ws);
     }
     h->ws_m = 0;
-    hipError_t e = hipMalloc(&h->ws, workspace_bytes(h->N, h->n, h->precision, m));
+    h->ws_ev_valid = false;
+    hipError_t e = dev_alloc(h->alloc, &h->ws, workspace_bytes(h->N, h->n, h->precision, m), h->stream);
     if (e != hipSuccess) {
         h->ws = nullptr;
         return to_code(e);
@@ -259,7 +328,7 @@ void tune_set(int op, int kind, int np, int bucket, int variant);
 // 3 tile-parallel FP64 (np > 64, or np 64 where the autotuner chose it),
 // 4 tile-parallel mixed, 5 mixed with BF16 products, 6 tile-parallel mixed
 // with BF16 products.
-inline int factor_kind(btc_handle h, int level) {
+inline int tuned_factor_kind(btc_handle h, int level) {
     const int np = factor_np(h);
     const bool mixed = is_mixed(h->precision);
     const int tiled = mixed ? (is_bf16(h->precision) ? 6 : 4) : 3;
@@ -272,6 +341,15 @@ inline int factor_kind(btc_handle h, int level) {
     if (np <= 32 && tune_variant(BTC_OP_FACTOR, 0, np, bucket) == 1) return 0;
     return 1;
 }
+
+// Fix the kernel family of every level from the tune table (when level 0 of
+// a factorization is enqueued: all levels of one factorization then agree
+// on the separator-update protocol).
+inline void snapshot_factor_kinds(btc_handle h) {
+    for (int l = 0; l < h->levels && l < 64; ++l) h->fkind[l] = (int8_t)tuned_factor_kind(h, l);
+}
+
+inline int factor_kind(btc_handle h, int level) { return h->fkind[level]; }
 
 inline bool tiled_kind(int kind) { return kind == 3 || kind == 4 || kind == 6; }
 
@@ -316,6 +394,7 @@ inline hipError_t launch_factor_any(btc_handle h, const btc::Launch<btc::FactorD
 }
 
 inline int launch_factor(btc_handle h, const double* A_diag, const double* A_off, hipStream_t st) {
+    snapshot_factor_kinds(h);
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, h->info, kInfoOk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return to_code(e);
@@ -421,6 +500,14 @@ inline btc::IrDesc ir_desc(btc_handle h, const Workspace& w, int64_t m, double t
     d.max_steps = max_steps;
     return d;
 }
+
+// Solve entry points (btc_api.hip): the enqueue of one solve with a given
+// workspace, the shared argument checks (0: go on, 1: nothing to do, < 0:
+// error), and the record of a stream a handle was used on.
+int solve_with(btc_handle h, const Workspace& w, const double* B, double* X, int64_t nrhs, hipStream_t st,
+               btc_solve_info* info);
+int check_solve(btc_handle h, const double* B, double* X, int64_t nrhs);
+void note_stream(btc_handle h, hipStream_t st);
 
 inline int read_info(btc_handle h, hipStream_t st, unsigned long long* v) {
     hipError_t e = hipStreamSynchronize(st);

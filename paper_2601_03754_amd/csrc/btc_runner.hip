@@ -62,6 +62,7 @@ struct Call {
 
 struct btc_runner_s {
     hipStream_t st = nullptr;
+    btc_host::Allocator alloc;  // source of the descriptor buffers
     struct Slot {
         char* host = nullptr;
         size_t hcap = 0;
@@ -98,6 +99,7 @@ struct btc_graph_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     char* dev = nullptr;
+    btc_host::Allocator alloc;
     hipStream_t cap = nullptr;
 };
 
@@ -179,10 +181,10 @@ int slot_reserve(btc_runner r, btc_runner_s::Slot& s, size_t bytes) {
     if (bytes > s.dcap) {
         // the device buffer may still be read by launches of an earlier call
         if (hipStreamSynchronize(r->st) != hipSuccess) return BTC_ERR_HIP;
-        if (s.dev) (void)hipFree(s.dev);
+        dev_free(r->alloc, s.dev, r->st);
         s.dev = nullptr;
         const size_t cap = std::max(bytes, (size_t)1 << 16) * 2;
-        if (hipMalloc((void**)&s.dev, cap) != hipSuccess) {
+        if (dev_alloc(r->alloc, (void**)&s.dev, cap, r->st) != hipSuccess) {
             s.dcap = 0;
             return BTC_ERR_OOM;
         }
@@ -261,6 +263,7 @@ BTC_API int btc_runner_create(void* stream, btc_runner* out) {
     btc_runner r = new (std::nothrow) btc_runner_s();
     if (!r) return BTC_ERR_OOM;
     r->st = (hipStream_t)stream;
+    r->alloc = current_allocator();
     bool ok = true;
     for (auto& s : r->slot) ok = ok && hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&r->fork, hipEventDisableTiming) == hipSuccess;
@@ -285,7 +288,7 @@ BTC_API void btc_runner_destroy(btc_runner r) {
         if (r->side[k]) (void)hipStreamSynchronize(r->side[k]);
     for (auto& s : r->slot) {
         if (s.host) (void)hipHostFree(s.host);
-        if (s.dev) (void)hipFree(s.dev);
+        dev_free(r->alloc, s.dev, r->st);
         if (s.ev) (void)hipEventDestroy(s.ev);
     }
     for (int k = 0; k < btc_runner_s::kSide; ++k) {
@@ -316,6 +319,9 @@ int prepare_steps(btc_runner r, int32_t count, const btc_step* steps, hipStream_
                 const int e = ensure_workspace(h, steps[k].nrhs);
                 if (e != BTC_OK) return e;
             }
+            // the workspace is now in use on the runner's stream
+            h->ws_stream = st;
+            h->ws_ev_valid = false;
         }
     }
 
@@ -335,6 +341,7 @@ void build_call(btc_runner r, int32_t count, const btc_step* steps, hipStream_t 
         h->stream = st;
         if (s.op == BTC_OP_FACTOR) {
             if (s.level == 0) {
+                snapshot_factor_kinds(h);
                 resets.push_back(h->info);
                 h->A_diag = s.A_diag;
                 h->A_off = s.A_off;
@@ -606,7 +613,7 @@ BTC_API void btc_graph_destroy(btc_graph g) {
     if (g->cap) (void)hipStreamSynchronize(g->cap);
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    if (g->dev) (void)hipFree(g->dev);
+    dev_free(g->alloc, g->dev, g->cap);
     if (g->cap) (void)hipStreamDestroy(g->cap);
     delete g;
 }
@@ -629,7 +636,8 @@ BTC_API int btc_graph_end(btc_runner r, btc_graph* out) {
     // the recorded work of the runner's stream must be done before the
     // descriptors are uploaded and the capture starts
     hipError_t e = hipStreamSynchronize(r->st);
-    if (e == hipSuccess) e = hipMalloc(&g->dev, host.size());
+    g->alloc = current_allocator();
+    if (e == hipSuccess) e = dev_alloc(g->alloc, (void**)&g->dev, host.size(), r->st);
     if (e == hipSuccess) e = hipMemcpy(g->dev, host.data(), host.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
@@ -724,10 +732,11 @@ BTC_API int btc_runner_sync(btc_runner r) {
 // level, so that each launch carries the nodes of all instances at that level.
 
 BTC_API int btc_factor_batched(btc_runner r, int32_t count, const btc_handle* h, const double* const* A_diag,
-                               const double* const* A_off) {
+                               const double* const* A_off, int64_t* info) {
     if (!r) return -1;
     if (count < 0) return -2;
     if (count > 0 && (!h || !A_diag || !A_off)) return -3;
+    if (info && r->recording) return -6;
     int levels = 0;
     for (int32_t k = 0; k < count; ++k) {
         if (!h[k]) return -3;
@@ -749,18 +758,27 @@ BTC_API int btc_factor_batched(btc_runner r, int32_t count, const btc_handle* h,
         const int rc = btc_runner_run(r, (int32_t)steps.size(), steps.data());
         if (rc != BTC_OK) return rc;
     }
+    if (!info) return BTC_OK;
+    const hipError_t e = hipStreamSynchronize(r->st);
+    if (e != hipSuccess) return to_code(e);
+    for (int32_t k = 0; k < count; ++k) {
+        const int rc = btc_status(h[k], &info[k]);
+        if (rc != BTC_OK) return rc;
+    }
     return BTC_OK;
 }
 
 BTC_API int btc_solve_batched(btc_runner r, int32_t count, const btc_handle* h, const double* const* B,
-                              double* const* X, int64_t nrhs) {
+                              double* const* X, const int64_t* nrhs, btc_solve_info* info) {
     if (!r) return -1;
     if (count < 0) return -2;
     if (count > 0 && (!h || !B || !X)) return -3;
-    if (nrhs < 1) return -6;
+    if (count > 0 && !nrhs) return -6;
+    if (info && r->recording) return -7;
     int levels = 0, rounds = 1;
     bool any_mixed = false;
     for (int32_t k = 0; k < count; ++k) {
+        if (nrhs[k] < 1) return -6;
         if (!h[k] || !h[k]->factored) return -3;
         if (is_mixed(h[k]->precision) && B[k] == X[k]) return -4;
         levels = std::max(levels, h[k]->levels);
@@ -781,7 +799,7 @@ BTC_API int btc_solve_batched(btc_runner r, int32_t count, const btc_handle* h, 
             s.level = level;
             s.B = B[k];
             s.X = X[k];
-            s.nrhs = nrhs;
+            s.nrhs = nrhs[k];
             s.first = first;
             steps.push_back(s);
         }
@@ -797,7 +815,31 @@ BTC_API int btc_solve_batched(btc_runner r, int32_t count, const btc_handle* h, 
         if (any_mixed && rc == BTC_OK) rc = run_op(BTC_OP_RESIDUAL, 0, true, 0);
         if (any_mixed && rc == BTC_OK) rc = run_op(BTC_OP_REFINE_TEST, 0, true, 0);
     }
-    return rc;
+    if (rc != BTC_OK || !info) return rc;
+    const hipError_t e = hipStreamSynchronize(r->st);
+    if (e != hipSuccess) return to_code(e);
+    for (int32_t k = 0; k < count; ++k) {
+        if (is_mixed(h[k]->precision)) {
+            rc = btc_refine_info(h[k], &info[k]);
+        } else {
+            int64_t st = 0;
+            rc = btc_status(h[k], &st);
+            if (rc == BTC_OK && st != 0) rc = BTC_ERR_NOT_SPD;
+            if (rc == BTC_OK) {
+                info[k].steps = 0;
+                info[k].converged = 1;
+                info[k].relres = -1.0;  // not computed by the FP64 path
+            }
+        }
+        if (rc == BTC_ERR_NOT_SPD) {
+            info[k].steps = 0;
+            info[k].converged = 0;
+            info[k].relres = -1.0;
+            rc = BTC_OK;
+        }
+        if (rc != BTC_OK) return rc;
+    }
+    return BTC_OK;
 }
 
 }  // extern "C"

@@ -43,19 +43,46 @@ using namespace btc_host;
 
 namespace {
 
-// Copy of refinement flags (device) into the pinned ring (host memory the
-// device writes through its mapped address).
-constexpr int kGather = 128;
-struct FlagGather {
-    const int32_t* src[kGather];
-    int32_t dst[kGather];
-    int32_t count;
-    int32_t* flags;
+// Outcome of a request step as the host reads it: the factor's status word,
+// and for the mixed paths the refinement state after a convergence test.
+struct ReqStatus {
+    unsigned long long info;  // ~0: every pivot block positive definite
+    int32_t done;             // refinement finished (converged, stalled, NaN or budget spent)
+    int32_t steps;            // low-precision solves applied
+    int32_t converged;
+    int32_t pad;
+    double relres;
 };
 
-__global__ void k_gather_flags(FlagGather a) {
+// Copy of request outcomes (device) into the pinned ring (host memory the
+// device writes through its mapped address).
+constexpr int kGather = 64;
+struct StatusGather {
+    const unsigned long long* info[kGather];
+    const btc::IrState* ir[kGather];  // null: no refinement state (FP64 path)
+    int32_t dst[kGather];
+    int32_t count;
+    ReqStatus* ring;
+};
+
+__global__ void k_gather_status(StatusGather a) {
     const int t = threadIdx.x;
-    if (t < a.count) a.flags[a.dst[t]] = *a.src[t];
+    if (t < a.count) {
+        ReqStatus r{};
+        r.info = *a.info[t];
+        if (a.ir[t]) {
+            const btc::IrState s = *a.ir[t];
+            r.done = s.done;
+            r.steps = s.steps;
+            r.converged = s.converged;
+            r.relres = s.relres;
+        } else {
+            r.done = 1;
+            r.converged = 1;
+            r.relres = -1.0;
+        }
+        a.ring[a.dst[t]] = r;
+    }
     __threadfence_system();
 }
 
@@ -67,8 +94,12 @@ double now_s() {
 struct Client {
     int64_t N = 0, n = 0;
     btc_handle h = nullptr;
-    const double* A_diag = nullptr;  // matrix of the resident factor (or the last one seen)
+    // matrix of the client's newest ADMITTED refactorization (admission is
+    // in per-client order, so this is the matrix every later solve-only
+    // request of the client refers to, also after an eviction)
+    const double* A_diag = nullptr;
     const double* A_off = nullptr;
+    bool has_matrix = false;  // some submitted request brought a matrix
     bool busy = false;
     uint64_t last_use = 0;
     size_t bytes = 0;
@@ -92,11 +123,16 @@ struct Req {
     uint64_t last_tick = 0;  // id of the newest tick that references this request
 };
 
+struct Poll {
+    Req* r;
+    int slot;        // pinned ring slot of the gathered status
+    bool last;       // the request's last plan step is in this tick
+};
+
 struct Tick {
     uint64_t id = 0;
     hipEvent_t ev = nullptr;
-    std::vector<Req*> finishing;                  // last plan step in this tick
-    std::vector<std::pair<Req*, int>> polls;      // refinement flag copies (request, pinned slot)
+    std::vector<Poll> polls;  // status copies of refinement tests and of finishing requests
 };
 
 }  // namespace
@@ -110,8 +146,8 @@ struct btc_server_s {
     std::vector<Req*> active;
     std::deque<Tick> ticks;
     std::vector<hipEvent_t> ev_pool;
-    int32_t* flags = nullptr;      // pinned ring of refinement flags (host view)
-    int32_t* flags_dev = nullptr;  // the same memory as the device sees it
+    ReqStatus* flags = nullptr;      // pinned ring of request outcomes (host view)
+    ReqStatus* flags_dev = nullptr;  // the same memory as the device sees it
     int flag_cap = 0, flag_next = 0;
     size_t resident = 0;
     uint64_t clock = 0;
@@ -123,12 +159,35 @@ struct btc_server_s {
 
 namespace {
 
+// Evict idle resident clients other than `keep`, least recently used first,
+// until `more` bytes fit in the budget.  0: they fit; 1: they do not (some
+// client still holds memory while a request of it is in flight: wait).
+int make_room(btc_server s, const Client* keep, size_t more) {
+    while (s->resident + more > s->opt.hbm_budget) {
+        Client* victim = nullptr;
+        for (auto& o : s->clients)
+            if (&o != keep && o.h && !o.busy && (!victim || o.last_use < victim->last_use)) victim = &o;
+        if (!victim) return 1;
+        (void)hipStreamSynchronize(s->st);
+        btc_destroy(victim->h);
+        victim->h = nullptr;
+        s->resident -= victim->bytes;
+        victim->bytes = 0;
+    }
+    return 0;
+}
+
+// Resident memory for a request of client c with nrhs right-hand sides.
+// 0: admitted; 1: wait for memory; < 0: error.  Requests whose footprint
+// alone exceeds the budget are refused at submission, so after every idle
+// client is evicted only clients with requests in flight hold memory, and
+// they release it (become evictable) when those requests complete.
 int admit_client(btc_server s, Client& c, int64_t nrhs) {
     const int32_t prec = s->opt.precision;
     if (c.h) {
         if (nrhs > c.h->ws_m) {
             const size_t more = btc_footprint_bytes(c.N, c.n, prec, nrhs) - c.bytes;
-            if (s->resident + more > s->opt.hbm_budget) return 1;
+            if (make_room(s, &c, more)) return 1;
             if (ensure_workspace(c.h, nrhs) != BTC_OK) return BTC_ERR_OOM;
             s->resident += more;
             c.bytes += more;
@@ -137,18 +196,7 @@ int admit_client(btc_server s, Client& c, int64_t nrhs) {
     }
     const size_t need = btc_footprint_bytes(c.N, c.n, prec, nrhs);
     if (need == 0) return BTC_ERR_UNSUPPORTED;
-    while (s->resident + need > s->opt.hbm_budget) {
-        // evict the least recently used idle resident client
-        Client* victim = nullptr;
-        for (auto& o : s->clients)
-            if (o.h && !o.busy && (!victim || o.last_use < victim->last_use)) victim = &o;
-        if (!victim) return 1;  // wait for memory
-        (void)hipStreamSynchronize(s->st);
-        btc_destroy(victim->h);
-        victim->h = nullptr;
-        s->resident -= victim->bytes;
-        victim->bytes = 0;
-    }
+    if (make_room(s, &c, need)) return 1;
     btc_options o{};
     o.precision = prec;
     o.max_refine = s->opt.max_refine;
@@ -179,6 +227,8 @@ void build_plan(btc_server s, Req* r, Client& c) {
     const int L = h->levels;
     const bool factor = r->A_diag != nullptr || !h->factored;
     if (r->A_diag) {
+        // requests are admitted in per-client order: from here on this is
+        // the matrix an evicted client's solve-only requests refactor with
         c.A_diag = r->A_diag;
         c.A_off = r->A_off;
     }
@@ -249,7 +299,7 @@ void build_plan(btc_server s, Req* r, Client& c) {
     }
 }
 
-void complete(btc_server s, Req* r, double t) {
+void complete(btc_server s, Req* r, double t, const ReqStatus& st) {
     if (r->retired) return;
     r->retired = true;
     Client& c = s->clients[(size_t)r->client];
@@ -262,6 +312,11 @@ void complete(btc_server s, Req* r, double t) {
     d.t_admit = r->t_admit;
     d.t_done = t;
     d.refactored = r->refactored ? 1 : 0;
+    d.info = st.info == kInfoOk ? 0 : (int64_t)st.info;
+    const bool mixed = is_mixed(s->opt.precision);
+    d.steps = mixed ? std::max(0, st.steps - 1) : 0;
+    d.converged = (d.info == 0 && st.converged) ? 1 : 0;
+    d.relres = d.info == 0 ? st.relres : -1.0;
     s->done.push_back(d);
 }
 
@@ -275,9 +330,13 @@ void harvest(btc_server s, bool wait) {
             break;
         }
         const double tn = now_s();
-        for (auto& p : t.polls)
-            if (s->flags[p.second] != 0) complete(s, p.first, tn);
-        for (Req* r : t.finishing) complete(s, r, tn);
+        for (auto& p : t.polls) {
+            const ReqStatus st = s->flags[p.slot];
+            // a request is done after its last step, or earlier once its
+            // refinement has stopped (the steps still queued for it return
+            // at once), or once its factorization has broken down
+            if (p.last || st.done != 0 || st.info != kInfoOk) complete(s, p.r, tn, st);
+        }
         s->ev_pool.push_back(t.ev);
         s->ticks.pop_front();
     }
@@ -314,7 +373,7 @@ BTC_API int btc_server_create(const btc_server_options* opt, void* stream, btc_s
     int rc = btc_runner_create(stream, &s->runner);
     if (rc == BTC_OK) {
         s->flag_cap = 1 << 16;
-        if (hipHostMalloc((void**)&s->flags, sizeof(int32_t) * s->flag_cap, hipHostMallocMapped) != hipSuccess)
+        if (hipHostMalloc((void**)&s->flags, sizeof(ReqStatus) * s->flag_cap, hipHostMallocMapped) != hipSuccess)
             rc = BTC_ERR_OOM;
         else if (hipHostGetDevicePointer((void**)&s->flags_dev, s->flags, 0) != hipSuccess)
             rc = BTC_ERR_HIP;
@@ -345,12 +404,14 @@ BTC_API int btc_server_submit(btc_server s, int64_t client, const double* A_diag
                               const double* B, double* X, int64_t nrhs, int64_t* ticket) {
     if (!s) return -1;
     if (client < 0 || client >= (int64_t)s->clients.size()) return -2;
-    const Client& c = s->clients[(size_t)client];
+    Client& c = s->clients[(size_t)client];
     if (A_diag && c.N > 1 && !A_off) return -4;
-    if (!A_diag && !c.A_diag) return -3;  // a first request must bring the matrix
+    if (!A_diag && !c.has_matrix) return -3;  // a first request must bring the matrix
     if (!B) return -5;
     if (!X || (is_mixed(s->opt.precision) && X == B)) return -6;
     if (nrhs < 1) return -7;
+    // a request that could never be admitted, even alone
+    if (btc_footprint_bytes(c.N, c.n, s->opt.precision, nrhs) > s->opt.hbm_budget) return BTC_ERR_UNSUPPORTED;
     Req* r = new (std::nothrow) Req();
     if (!r) return BTC_ERR_OOM;
     r->ticket = s->next_ticket++;
@@ -361,11 +422,7 @@ BTC_API int btc_server_submit(btc_server s, int64_t client, const double* A_diag
     r->X = X;
     r->nrhs = nrhs;
     r->t_submit = now_s();
-    if (A_diag) {
-        // the newest matrix of the client is what an eviction falls back to
-        s->clients[(size_t)client].A_diag = A_diag;
-        s->clients[(size_t)client].A_off = A_off;
-    }
+    if (A_diag) c.has_matrix = true;
     s->pending.push_back(r);
     if (ticket) *ticket = r->ticket;
     return BTC_OK;
@@ -402,33 +459,37 @@ BTC_API int btc_server_step(btc_server s) {
     for (Req* r : s->active) {
         if (r->retired || r->pc >= r->plan.size()) continue;  // done, or waiting for its last tick
         r->last_tick = t.id;
-        bool more = true;
+        bool more = true, test = false;
         while (more && r->pc < r->plan.size()) {
             more = r->joint[r->pc] != 0;
             const btc_step& st = r->plan[r->pc++];
             s->scratch.push_back(st);
-            if (st.op == BTC_OP_REFINE_TEST && r->pc < r->plan.size()) {
-                t.polls.push_back({r, s->flag_next});
-                s->flag_next = (s->flag_next + 1) % s->flag_cap;
-            }
+            test = test || st.op == BTC_OP_REFINE_TEST;
         }
-        if (r->pc == r->plan.size()) t.finishing.push_back(r);
+        const bool last = r->pc == r->plan.size();
+        if (test || last) {
+            t.polls.push_back({r, s->flag_next, last});
+            s->flag_next = (s->flag_next + 1) % s->flag_cap;
+        }
     }
     if (s->scratch.empty()) return (int)(s->pending.size() + s->active.size());
     int rc = btc_runner_run(s->runner, (int32_t)s->scratch.size(), s->scratch.data());
     if (rc != BTC_OK) return rc;
-    // the convergence flags of this tick's tests, copied into the pinned
-    // ring by one small kernel (not one copy command per test)
-    FlagGather ga{};
-    ga.flags = s->flags_dev;
+    // the outcomes of this tick's tests and finishing requests, copied into
+    // the pinned ring by one small kernel (not one copy command each)
+    StatusGather ga{};
+    ga.ring = s->flags_dev;
+    const bool mixed = is_mixed(s->opt.precision);
     for (size_t k = 0; k < t.polls.size(); ++k) {
         const auto& p = t.polls[k];
-        const Workspace w = carve(p.first->plan[0].h, p.first->plan[0].h->ws_m);
-        s->flags[p.second] = 0;
-        ga.src[ga.count] = &w.ir->done;
-        ga.dst[ga.count] = p.second;
+        btc_handle h = p.r->plan[0].h;
+        const Workspace w = carve(h, h->ws_m);
+        s->flags[p.slot] = ReqStatus{};
+        ga.info[ga.count] = h->info;
+        ga.ir[ga.count] = mixed ? w.ir : nullptr;
+        ga.dst[ga.count] = p.slot;
         if (++ga.count == kGather || k + 1 == t.polls.size()) {
-            hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(kGather), 0, s->st, ga);
+            hipLaunchKernelGGL(k_gather_status, dim3(1), dim3(kGather), 0, s->st, ga);
             if (hipGetLastError() != hipSuccess) return BTC_ERR_HIP;
             ga.count = 0;
         }

@@ -90,20 +90,29 @@ def lambda_min(D: np.ndarray, E: np.ndarray) -> float:
 
 
 def block_tridiag(N: int, n: int, c: float = 4.0, seed: int = 0, nrhs: int = 1,
-                  margin: bool = False) -> Problem:
+                  margin: bool = False, lam0: float | None = None) -> Problem:
     """One instance.  ``margin=False``: D_i = G G^T/n + c I (literal shift).
-    ``margin=True``: the shift is chosen so that lambda_min(Psi) == c."""
+    ``margin=True``: the shift is chosen so that lambda_min(Psi) == c, with
+    lambda_min of the unshifted matrix from LAPACK's banded eigensolver, or
+    ``lam0`` when the caller has it (large instances: the banded eigensolver
+    is too slow there)."""
     if N < 1 or n < 1:
         raise ValueError("N and n must be positive")
     GG, E, B = _draw(N, n, nrhs, seed)
     eye = np.eye(n)
     if margin:
-        lam0 = lambda_min(GG, E)
+        if lam0 is None:
+            lam0 = lambda_min(GG, E)
         shift = c - lam0
     else:
         shift = c
     D = GG + shift * eye[None, :, :]
     return Problem(D=D, E=E, B=B, c=float(shift))
+
+
+def unshifted(N: int, n: int, seed: int = 0, nrhs: int = 1):
+    """(G G^T / n, E, B) of the recipe before any identity shift."""
+    return _draw(N, n, nrhs, seed)
 
 
 def laplacian(N: int, n: int, nrhs: int = 1, seed: int = 0) -> Problem:

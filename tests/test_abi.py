@@ -37,7 +37,8 @@ def test_header_declares_entry_points():
     names = declared_symbols()
     for must in ("btc_factor", "btc_solve", "btc_refactor", "btc_status", "btc_destroy",
                  "btc_footprint_bytes", "btc_export_factor", "btc_permutation", "btc_create",
-                 "btc_runner_create", "btc_runner_run", "btc_factor_batched", "btc_solve_batched"):
+                 "btc_runner_create", "btc_runner_run", "btc_factor_batched", "btc_solve_batched",
+                 "btc_set_allocator"):
         assert must in names
 
 
@@ -88,8 +89,8 @@ def test_argument_errors_before_device_work(lib):
     assert L.btc_runner_run(None, 0, None) == -1
     assert L.btc_runner_create(None, None) == -2
     assert L.btc_runner_query(None) == -1
-    assert L.btc_factor_batched(None, 0, None, None, None) == -1
-    assert L.btc_solve_batched(None, 0, None, None, None, 1) == -1
+    assert L.btc_factor_batched(None, 0, None, None, None, None) == -1
+    assert L.btc_solve_batched(None, 0, None, None, None, None, None) == -1
     assert L.btc_refine_info(None, None) == -1
     L.btc_runner_destroy(None)
     assert "argument" in lib.btc_error_string(-3)
@@ -183,6 +184,17 @@ def test_tune_table_host_only(lib):
     assert L.btc_tune_get(0, 0, 8, -1, ctypes.byref(v)) == -4
     assert L.btc_tune_set(R, 0, 8, 0, 2) == -5
     assert L.btc_autotune(None, None, None, None, None, 1, 1, None) == -1
+
+
+def test_allocator_hook_arguments(lib):
+    """btc_set_allocator takes both functions or neither; loading the
+    binding installs torch's caching allocator, and it can be switched back
+    to HIP's own and on again (host state only, no device call)."""
+    L = lib.lib()
+    assert L.btc_set_allocator(lib._alloc_cb, ctypes.cast(None, lib._FREE_FN), None) == -1
+    assert L.btc_set_allocator(ctypes.cast(None, lib._ALLOC_FN), lib._free_cb, None) == -1
+    lib.btc_set_allocator(False)
+    lib.btc_set_allocator(True)
 
 
 def test_bf16_footprint_matches_mixed(lib):

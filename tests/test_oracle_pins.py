@@ -239,6 +239,39 @@ def test_residual_matches_dense_product(N, n, m):
     assert np.allclose(R.reshape(N * n, m), ref, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("N,n,k", [(9, 3, 13), (16, 2, 9), (31, 1, 15)])
+def test_relres_closed_form(N, n, k):
+    """The relative residual is the maximum over right-hand-side columns of
+    ||b_j - Psi x_j||_2 / ||b_j||_2.  Closed form: for the block Laplacian
+    tridiag(-I, 2I, -I) and an iterate that is a multiple d_j of the unit
+    vector e_k (k an interior scalar row, 0-based), column k of Psi holds
+    2, -1, -1 at rows k, k-n, k+n, so Psi x_j = d_j (2 e_k - e_{k-n} -
+    e_{k+n}).  With b_j supported on rows far from k, ||b_j - Psi x_j||^2 =
+    ||b_j||^2 + 6 d_j^2.  Three columns with different ratios pin the
+    reduction: a norm over rows, a Frobenius norm over all columns, a mean
+    or a minimum over columns would each give another number."""
+    D = np.tile(2.0 * np.eye(n), (N, 1, 1))
+    E = np.tile(-np.eye(n), (N - 1, 1, 1))
+    dim = N * n
+    d = np.array([0.5, 3.0, 1e-3])
+    bnorm = np.array([2.0, 1.5, 4.0])
+    B = np.zeros((dim, 3))
+    X = np.zeros((dim, 3))
+    far = [r for r in range(dim) if abs(r - k) > n]
+    for j in range(3):
+        B[far[j], j] = bnorm[j]          # one entry, so ||b_j|| = bnorm[j]
+        X[k, j] = d[j]
+    expect = np.sqrt(1.0 + 6.0 * d ** 2 / bnorm ** 2)
+    got = oracle.relres(D, E, X.reshape(N, n, 3), B.reshape(N, n, 3))
+    assert got == pytest.approx(expect.max(), rel=1e-15)
+    assert np.argmax(expect) == 1                      # the largest ratio is not the first column
+    assert abs(got - expect.min()) > 0.1 and abs(got - expect.mean()) > 0.1
+    fro = np.sqrt((bnorm ** 2 + 6 * d ** 2).sum() / (bnorm ** 2).sum())
+    assert abs(got - fro) > 0.1
+    # an exact solution has zero residual; x = 0 has relative residual 1
+    assert oracle.relres(D, E, np.zeros((N, n, 3)), B.reshape(N, n, 3)) == pytest.approx(1.0, rel=1e-15)
+
+
 @pytest.mark.parametrize("N", [1, 2, 7, 16, 33, 100])
 def test_sequential_cost_formula(N):
     """Section "Computational Complexity": Algorithm 1 costs
