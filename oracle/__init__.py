@@ -65,6 +65,16 @@ def _load():
         lib.orc_solve_seq.argtypes = [i64, i64, i64, dp, dp, dp, dp]
         lib.orc_residual.restype = None
         lib.orc_residual.argtypes = [i64, i64, i64, dp, dp, dp, dp, dp]
+        lib.orc_factor_order.restype = i64
+        lib.orc_factor_order.argtypes = [i64, i64, ip, dp, dp, dp, dp, dp, ip, ip, ip, ip]
+        lib.orc_solve_order.restype = None
+        lib.orc_solve_order.argtypes = [i64, i64, i64, ip, dp, dp, dp, ip, ip, dp, dp]
+        lib.orc_kstage_order.restype = None
+        lib.orc_kstage_order.argtypes = [i64, i64, ip]
+        lib.orc_partition_sizes.restype = i64
+        lib.orc_partition_sizes.argtypes = [i64, i64, ip]
+        lib.orc_partition_order.restype = None
+        lib.orc_partition_order.argtypes = [i64, i64, ip, ip, ip]
         _lib = lib
     return _lib
 
@@ -191,6 +201,67 @@ def solve(D, E, B) -> np.ndarray:
     if info != 0:
         raise np.linalg.LinAlgError("block %d is not positive definite" % info)
     return solve_nd(Ld, Rb, Tb, B)
+
+
+# --------------------------------------------------------------------------
+# Other elimination orders (section "Parallel Cholesky Factorization").
+
+def kstage_order(N: int, k: int) -> np.ndarray:
+    """First k multi-stage levels, then the remaining blocks in natural order
+    (k = 0: Algorithm 1; 1: single-stage; 2: two-stage)."""
+    out = np.zeros(N, dtype=np.int64)
+    _load().orc_kstage_order(N, k, _ip(out))
+    return out
+
+
+def partition_sizes(N: int, p: int) -> np.ndarray:
+    """Chunk sizes N_1..N_p of Proposition 1 (rounded as the paper states)."""
+    out = np.zeros(p, dtype=np.int64)
+    rc = int(_load().orc_partition_sizes(N, p, _ip(out)))
+    if rc != 0:
+        raise ValueError("no partition of %d blocks into %d chunks" % (N, p))
+    return out
+
+
+def partition_order(N: int, p: int, sizes=None):
+    """(order, phase) of the partition permutation of Algorithm 2."""
+    sizes = partition_sizes(N, p) if sizes is None else np.ascontiguousarray(sizes, dtype=np.int64)
+    order = np.zeros(N, dtype=np.int64)
+    phase = np.zeros(N, dtype=np.int64)
+    _load().orc_partition_order(N, p, _ip(sizes), _ip(order), _ip(phase))
+    return order, phase
+
+
+def factor_order(D, E, order, phase=None, counts: bool = False):
+    """Block Cholesky of P Psi P^T for the elimination order `order`: (Ld,
+    Ro, To, rn, ln, info), indexed by original block; with counts, also the
+    potrf/trsm/syrk/gemm counts (per phase when phase is given)."""
+    D, E, N, n = _shape(D, E)
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    Ld, Ro, To = (np.zeros((N, n, n)) for _ in range(3))
+    rn = np.zeros(N, dtype=np.int64)
+    ln = np.zeros(N, dtype=np.int64)
+    nph = 1 if phase is None else int(np.max(phase)) + 1
+    cnt = np.zeros(4 * nph, dtype=np.int64)
+    ph = None if phase is None else np.ascontiguousarray(phase, dtype=np.int64)
+    info = int(_load().orc_factor_order(N, n, _ip(order), _dp(D), _dp(E), _dp(Ld), _dp(Ro), _dp(To),
+                                        _ip(rn), _ip(ln), _ip(ph) if ph is not None else None, _ip(cnt)))
+    out = (Ld, Ro, To, rn, ln, info)
+    if counts:
+        return out + (cnt.reshape(nph, 4),)
+    return out
+
+
+def solve_order(order, Ld, Ro, To, rn, ln, B) -> np.ndarray:
+    Ld, Ro, To = _f64(Ld), _f64(Ro), _f64(To)
+    N, n, _ = Ld.shape
+    B = _f64(B).reshape(N, n, -1)
+    m = B.shape[2]
+    X = np.empty_like(B)
+    _load().orc_solve_order(N, n, m, _ip(np.ascontiguousarray(order, dtype=np.int64)), _dp(Ld), _dp(Ro),
+                            _dp(To), _ip(np.ascontiguousarray(rn, dtype=np.int64)),
+                            _ip(np.ascontiguousarray(ln, dtype=np.int64)), _dp(B), _dp(X))
+    return X
 
 
 # --------------------------------------------------------------------------

@@ -405,3 +405,192 @@ void orc_residual(int64_t N, int64_t n, int64_t m, const double *D, const double
         if (i < N) sub_atx(n, m, BLK(E, i), VEC(X, i + 1), r);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Other elimination orders of the same chain (section "Parallel Cholesky
+ * Factorization": the partition permutation of Algorithm 2, the single-stage
+ * permutation, and the two-stage variant of the strategy comparison; the
+ * multi-stage order is orc_nd_order).  Each is the Cholesky factorization of
+ * P Psi P^T for another block permutation P, written as the same right-looking
+ * block elimination as orc_factor_nd: in every one of these orders a block,
+ * when it is eliminated, is coupled to at most one not-yet-eliminated block on
+ * each side (its left and right neighbours at that time), so the column of
+ * block i holds L_ii and at most two blocks below it:
+ *   Ro[i] = the factor block at (row rn[i], column i)   (rn[i] > i, or 0: none)
+ *   To[i] = the TRANSPOSE of the factor block at (row ln[i], column i)
+ *                                                        (ln[i] < i, or 0: none)
+ * with the same convention as Rb / Tb of orc_factor_nd (T_i = L_ii^{-1} C where C
+ * is the coupling block at (row i, column ln[i])).  Eliminating i:
+ *   L_ii = chol(S_i); R_i = C_{rn,i} L_ii^{-T}; S_rn -= R_i R_i^T;
+ *   T_i = L_ii^{-1} C_{i,ln}; S_ln -= T_i^T T_i; C_{rn,ln} = -R_i T_i (fill),
+ * after which rn and ln are each other's neighbours.
+ *
+ * order: the 1-based original block indices in elimination order (a
+ * permutation of 1..N).  Returns 0, or the 1-based index of the first block
+ * whose pivot is not positive definite.  counts as in orc_factor_nd; when
+ * phase is not NULL, counts are kept per phase[i] (counts + 4*phase[i]). */
+int64_t orc_factor_order(int64_t N, int64_t n, const int64_t *order, const double *D, const double *E,
+                         double *Ld, double *Ro, double *To, int64_t *rn, int64_t *ln,
+                         const int64_t *phase, int64_t *counts)
+{
+    const size_t bs = (size_t)n * (size_t)n;
+    double *S = (double *)malloc(bs * (size_t)N * sizeof(double));
+    /* CR[j]: coupling between j and its current right neighbour R[j], stored
+     * as the block at (row R[j], column j); indexed by the lower endpoint. */
+    double *CR = (double *)calloc(bs * (size_t)N, sizeof(double));
+    double *F = (double *)malloc(bs * sizeof(double));
+    int64_t *Rn = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N + 2));
+    int64_t *Lnb = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N + 2));
+    int64_t info = 0;
+    if (!S || !CR || !F || !Rn || !Lnb) {
+        free(S); free(CR); free(F); free(Rn); free(Lnb);
+        return -1;
+    }
+    for (int64_t i = 1; i <= N; ++i) {
+        sym_from_lower(n, BLK(D, i), BLK(S, i));
+        Rn[i] = i < N ? i + 1 : 0;
+        Lnb[i] = i > 1 ? i - 1 : 0;
+    }
+    for (int64_t i = 1; i < N; ++i) memcpy(BLK(CR, i), BLK(E, i), bs * sizeof(double));
+    memset(Ld, 0, bs * (size_t)N * sizeof(double));
+    memset(Ro, 0, bs * (size_t)N * sizeof(double));
+    memset(To, 0, bs * (size_t)N * sizeof(double));
+    for (int64_t p = 0; p < N && info == 0; ++p) {
+        const int64_t i = order[p];
+        int64_t *cnt = counts ? counts + (phase ? 4 * phase[i - 1] : 0) : NULL;
+        const int64_t r = Rn[i], l = Lnb[i];
+        rn[i - 1] = r;
+        ln[i - 1] = l;
+        double *L = BLK(Ld, i);
+        memcpy(L, BLK(S, i), bs * sizeof(double));
+        bump(cnt, 0);
+        if (orc_dense_chol(n, L) != 0) {
+            info = i;
+            break;
+        }
+        if (r) {
+            double *Rm = BLK(Ro, i);
+            memcpy(Rm, BLK(CR, i), bs * sizeof(double));
+            trsm_right_lower_t(n, L, Rm);
+            bump(cnt, 1);
+            sub_aat(n, BLK(S, r), Rm);
+            bump(cnt, 2);
+        }
+        if (l) {
+            double *Tm = BLK(To, i);
+            memcpy(Tm, BLK(CR, l), bs * sizeof(double));  /* block (i, l): C_{i,l} */
+            trsm_left_lower(n, L, Tm, n);
+            bump(cnt, 1);
+            sub_ata(n, BLK(S, l), Tm);
+            bump(cnt, 2);
+        }
+        if (r && l) {
+            /* the fill couples l and r: block (r, l) = -R_i T_i */
+            neg_ab(n, BLK(Ro, i), BLK(To, i), F);
+            bump(cnt, 3);
+            memcpy(BLK(CR, l), F, bs * sizeof(double));
+        }
+        /* i leaves the graph: its neighbours become each other's */
+        if (l) Rn[l] = r;
+        if (r) Lnb[r] = l;
+    }
+    free(S); free(CR); free(F); free(Rn); free(Lnb);
+    return info;
+}
+
+/* Solve with the factor of orc_factor_order: forward substitution in
+ * elimination order (y_i = L_ii^{-1} y_i; y_rn -= R_i y_i; y_ln -= T_i^T y_i),
+ * then backward substitution in reverse order (x_i -= R_i^T x_rn;
+ * x_i -= T_i x_ln; x_i = L_ii^{-T} x_i). */
+void orc_solve_order(int64_t N, int64_t n, int64_t m, const int64_t *order, const double *Ld,
+                     const double *Ro, const double *To, const int64_t *rn, const int64_t *ln,
+                     const double *B, double *X)
+{
+    const size_t vs = (size_t)n * (size_t)m;
+    if (X != B) memmove(X, B, vs * (size_t)N * sizeof(double));
+    for (int64_t p = 0; p < N; ++p) {
+        const int64_t i = order[p];
+        trsm_left_lower(n, BLK(Ld, i), VEC(X, i), m);
+        if (rn[i - 1]) sub_ax(n, m, BLK(Ro, i), VEC(X, i), VEC(X, rn[i - 1]));
+        if (ln[i - 1]) sub_atx(n, m, BLK(To, i), VEC(X, i), VEC(X, ln[i - 1]));
+    }
+    for (int64_t p = N - 1; p >= 0; --p) {
+        const int64_t i = order[p];
+        if (rn[i - 1]) sub_atx(n, m, BLK(Ro, i), VEC(X, rn[i - 1]), VEC(X, i));
+        if (ln[i - 1]) sub_ax(n, m, BLK(To, i), VEC(X, ln[i - 1]), VEC(X, i));
+        trsm_left_lower_t(n, BLK(Ld, i), VEC(X, i), m);
+    }
+}
+
+/* k-stage order: the first k levels of the multi-stage permutation (odd
+ * blocks, odd multiples of 2, ..., of 2^(k-1)), then the remaining blocks (the
+ * multiples of 2^k) in natural order, eliminated one after the other as in
+ * Algorithm 1.  k = 0: natural order (Algorithm 1); k = 1: the single-stage
+ * permutation Phi_1; k = 2: the two-stage variant; k >= floor(log2 N)+1: the
+ * multi-stage order. */
+void orc_kstage_order(int64_t N, int64_t k, int64_t *order)
+{
+    int64_t p = 0, s = 1;
+    for (int64_t l = 0; l < k && s <= N; ++l, s *= 2)
+        for (int64_t i = s; i <= N; i += 2 * s) order[p++] = i;
+    for (int64_t i = s; i <= N; i += s) order[p++] = i;
+}
+
+/* Chunk sizes of the partition permutation with p chunks (section "Partition
+ * Permutation", Proposition 1): the first chunk costs (7/3 N_1 - 1) n^3 and
+ * every other (19/3 N_k - 1) n^3, so the balanced sizes are N_k* =
+ * (7N - 7p + 7)/(7p + 12) for k > 1 and N_1 = N - (p-1) - (p-1) N_k (p-1
+ * blocks are pivots).  N_k* is rounded down and up; of the two the one with
+ * the smaller larger phase cost is kept (ties: rounded down).  sizes[0..p-1]
+ * receives N_1..N_p; returns 0, or -1 when no chunk sizes >= 1 exist. */
+int64_t orc_partition_sizes(int64_t N, int64_t p, int64_t *sizes)
+{
+    if (p < 1) return -1;
+    if (p == 1) {
+        sizes[0] = N;
+        return N >= 1 ? 0 : -1;
+    }
+    const double nk = (7.0 * (double)N - 7.0 * (double)p + 7.0) / (7.0 * (double)p + 12.0);
+    int64_t best = -1;
+    double best_cost = 0.0;
+    for (int64_t c = (int64_t)floor(nk); c <= (int64_t)ceil(nk); ++c) {
+        if (c < 1) continue;
+        const int64_t n1 = N - (p - 1) - (p - 1) * c;
+        if (n1 < 1) continue;
+        const double c1 = 7.0 / 3.0 * (double)n1 - 1.0, ck = 19.0 / 3.0 * (double)c - 1.0;
+        const double cost = c1 > ck ? c1 : ck;
+        if (best < 0 || cost < best_cost) {
+            best = c;
+            best_cost = cost;
+        }
+    }
+    if (best < 0) return -1;
+    sizes[0] = N - (p - 1) - (p - 1) * best;
+    for (int64_t k = 1; k < p; ++k) sizes[k] = best;
+    return 0;
+}
+
+/* Partition order (Algorithm 2): chunk 1 = blocks 1..N_1, pivot A_2 = block
+ * N_1+1, chunk 2 = the next N_2 blocks, pivot A_3, ..., chunk p; the blocks of
+ * every chunk in natural order, chunk after chunk, then the p-1 pivots in
+ * natural order.  phase[i-1] (nullable) receives k-1 for the blocks of chunk
+ * k and p for the pivots (for per-chunk operation counts, cf. the cost table
+ * of section "Partition Permutation"). */
+void orc_partition_order(int64_t N, int64_t p, const int64_t *sizes, int64_t *order, int64_t *phase)
+{
+    int64_t q = 0, b = 1;
+    int64_t *piv = (int64_t *)malloc(sizeof(int64_t) * (size_t)(p > 1 ? p : 1));
+    for (int64_t k = 0; k < p; ++k) {
+        for (int64_t t = 0; t < sizes[k]; ++t, ++b) {
+            order[q++] = b;
+            if (phase) phase[b - 1] = k;
+        }
+        if (k + 1 < p) {
+            piv[k] = b;
+            if (phase) phase[b - 1] = p;
+            ++b;
+        }
+    }
+    for (int64_t k = 0; k + 1 < p; ++k) order[q++] = piv[k];
+    free(piv);
+}
