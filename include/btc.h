@@ -89,16 +89,71 @@ typedef enum {
     BTC_BF16_IR = 2
 } btc_precision;
 
+/*
+ * How the mixed-precision paths compute each correction d of refinement
+ * (the residual r = b - Psi x is always formed in FP64 from the original
+ * blocks):
+ *   BTC_REFINE_CLASSIC  d = (L L^T)^{-1} r with the low-precision factor
+ *                       (one pair of sweeps per correction);
+ *   BTC_REFINE_GMRES    d from GMRES in FP64 on (L L^T)^{-1} Psi d =
+ *                       (L L^T)^{-1} r, the low-precision factor as the
+ *                       preconditioner (Carson and Higham's GMRES-based
+ *                       refinement): each iteration one FP64 product with
+ *                       Psi and one pair of low-precision sweeps, the basis
+ *                       orthogonalised twice (classical Gram-Schmidt) in
+ *                       FP64; the correction stops when the preconditioned
+ *                       residual has fallen by 1e-8 or after gmres_m
+ *                       iterations.  For ill-conditioned systems, where the
+ *                       classic correction contracts slowly or not at all
+ *                       (BF16 products at condition numbers of 1e3 and
+ *                       more).  btc_solve only (the runner and the server
+ *                       refine classically); synchronises once per GMRES
+ *                       iteration.
+ */
+#define BTC_REFINE_CLASSIC 0
+#define BTC_REFINE_GMRES 1
+#define BTC_DEFAULT_GMRES_M 40
+
+/*
+ * Elimination order (section "Parallel Cholesky Factorization"; the paper
+ * compares the strategies and leaves choosing among them per problem to
+ * future work, section "Multi-Stage Permutation"):
+ *   BTC_STRATEGY_MULTISTAGE  the multi-stage (nested-dissection) order of
+ *                            Algorithm 4: floor(log2 N)+1 parallel levels.
+ *   BTC_STRATEGY_KSTAGE      the first `stages` levels of that order, then
+ *                            the remaining chain of blocks (the multiples of
+ *                            2^stages) eliminated one after the other by one
+ *                            wavefront, as in Algorithm 1: stages = 0 is the
+ *                            sequential Algorithm 1 (one launch for the
+ *                            factor, one for the solve), 1 the single-stage
+ *                            permutation, 2 the two-stage variant.  FP64, n
+ *                            <= 64, btc_factor / btc_solve only.
+ *   BTC_STRATEGY_AUTO        the fastest of these for (N, n) as measured by
+ *                            btc_autotune_strategy (else a rule: KSTAGE 0 for
+ *                            N <= 32 with n <= 16, MULTISTAGE otherwise).
+ * Every order computes the Cholesky factor of its own permuted matrix; the
+ * solutions agree to rounding.
+ */
+#define BTC_STRATEGY_MULTISTAGE 0
+#define BTC_STRATEGY_KSTAGE 1
+#define BTC_STRATEGY_AUTO 2
+
 typedef struct {
     int32_t precision;   /* btc_precision */
     int32_t max_refine;  /* refinement corrections after the first solve (0: default) */
     double tol;          /* target max-column relative residual (0: default 1e-10) */
+    int32_t refine;      /* BTC_REFINE_CLASSIC or BTC_REFINE_GMRES (mixed precision only) */
+    int32_t gmres_m;     /* BTC_REFINE_GMRES: iterations per correction, 1..200 (0: default) */
+    int32_t strategy;    /* BTC_STRATEGY_* (0: multi-stage) */
+    int32_t stages;      /* BTC_STRATEGY_KSTAGE: levels of the multi-stage order before the chain */
 } btc_options;
 
 typedef struct {
     int32_t steps;      /* refinement corrections applied (0 for BTC_FP64) */
     int32_t converged;  /* 1 if the residual target was met (always 1 for BTC_FP64) */
     double relres;      /* max over columns of ||b - Psi x||_2 / ||b||_2, FP64 */
+    int32_t inner;      /* BTC_REFINE_GMRES: GMRES iterations over all corrections, else 0 */
+    int32_t pad;
 } btc_solve_info;
 
 /*
@@ -183,7 +238,9 @@ BTC_API size_t btc_footprint_bytes(int64_t N, int64_t n, int32_t precision, int6
  *   Rb[i] = R_i = factor block at (row i+s, column i), zero if i+s > N
  *   Tb[i] = T_i = transpose of the factor block at (row i-s, column i),
  *           zero if i <= s
- * where s = 2^(number of trailing zero bits of i).  Synchronises.
+ * where s = 2^(number of trailing zero bits of i).  For a k-stage order the
+ * blocks of its chain (the multiples of 2^k) have Rb[i] = the factor block
+ * at (row i + 2^k, column i) (zero for the last) and Tb[i] = 0.  Synchronises.
  * Any of the three pointers may be NULL.  For BTC_FP32_IR the FP32 factor
  * blocks are returned (widened to FP64).
  */
@@ -241,13 +298,19 @@ typedef enum {
 typedef struct {
     btc_handle h;
     int32_t op;             /* btc_op */
-    int32_t level;          /* FACTOR / FORWARD / BACKWARD: level 0 .. floor(log2 N) */
+    int32_t level;          /* FACTOR / FORWARD / BACKWARD: level 0 .. floor(log2 N) (the first
+                               level of a range, see level_end) */
     const double *A_diag;   /* FACTOR at level 0: the matrix (device; kept for RESIDUAL) */
     const double *A_off;
     const double *B;        /* sweeps / RESIDUAL: right-hand side [N][n][nrhs] (device) */
     double *X;              /* sweeps / RESIDUAL: solution / iterate (device) */
     int64_t nrhs;           /* >= 1 for every op but FACTOR */
     int32_t first;          /* BTC_FP32_IR sweeps: 1 for the first solve (reads B, sets X) */
+    int32_t level_end;      /* FORWARD / BACKWARD: 0 for the single level `level`; else the
+                               levels level .. level_end-1 in one step (level < level_end <=
+                               floor(log2 N)+1): the elimination subtrees of those levels, one
+                               workgroup each (btc_sweep_ranges gives the library's ranges) */
+    int32_t stage;          /* 0..7: order of dependent steps within one call */
     int32_t pad;
 } btc_step;
 
@@ -255,17 +318,35 @@ typedef struct {
 BTC_API int btc_runner_create(void *stream, btc_runner *out);
 
 /*
- * btc_runner_run -- enqueue `count` steps (host array).  Steps of one call
- * must not depend on each other: at most one step per handle per call, except
- * that FACTOR level l+1 and FORWARD level l of one handle may share a call
- * (the sweep reads only level-l factor blocks, the factor step writes only
- * blocks of higher levels), and so may a RESIDUAL and the REFINE_TEST that
- * reads it (REFINE_TEST steps run after every other step of their call);
- * calls are executed in order.  Returns once the work is enqueued; -3 for an
- * invalid step (unknown op, level out of range, missing pointers, a sweep or
- * residual on a handle never factored).
+ * btc_runner_run -- enqueue `count` steps (host array).  The steps of one
+ * call run stage by stage (all steps of stage 0, then of stage 1, ...);
+ * steps of one stage must not depend on each other: at most one step per
+ * handle per stage, except that FACTOR level l and a FORWARD range ending at
+ * level l (level_end, or level + 1) of one handle may share a stage (the
+ * sweep reads only factor blocks below level l, the factor step writes only
+ * blocks of level l and above), and so may a RESIDUAL and the REFINE_TEST
+ * that reads it (REFINE_TEST steps run after every other step of their
+ * stage).  A step that depends on another step of the same call (a sweep
+ * after REFINE_INIT or after the test that may stop it, a residual after the
+ * backward sweep) goes in a later stage.  Calls are executed in order.
+ * Returns once the work is enqueued; -3 for an invalid step (unknown op,
+ * level or range out of range, stage outside 0..7, missing pointers, a sweep
+ * or residual on a handle never factored).
  */
 BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step *steps);
+
+/*
+ * btc_sweep_ranges -- the level ranges in which the library runs a sweep of
+ * an instance with N blocks (host computation): bounds[0] = 0 < bounds[1] <
+ * ... < bounds[r] = floor(log2 N)+1, r returned (bounds needs r+1 <= max
+ * entries; -2 if it is too short).  A range of one level runs one wavefront
+ * per node; a longer range runs each elimination subtree of its levels in
+ * one workgroup (section "Cholesky Solve": the forward step of a node reads
+ * only results of its descendants, the backward step only those of its
+ * ancestors), so it costs one launch and one dependency step instead of one
+ * per level.
+ */
+BTC_API int btc_sweep_ranges(int64_t N, int32_t *bounds, int32_t max);
 
 /* btc_runner_query -- 1 if all enqueued work has finished, 0 if not. */
 BTC_API int btc_runner_query(btc_runner r);
@@ -312,14 +393,25 @@ BTC_API void btc_graph_destroy(btc_graph g);
  *   BTC_OP_FORWARD / BACKWARD / RESIDUAL (nrhs > 1; level ignored): 0 four
  *     right-hand-side columns per dependency-chain group, 1 one (identical
  *     results)
+ *   BTC_TUNE_SWEEP_SHAPE, any precision, any n (level ignored): the launch
+ *     shape of both sweeps: 0 level ranges (btc_sweep_ranges) with
+ *     workgroups of 4 wavefronts, 1 one launch per level, 2 level ranges
+ *     with workgroups of 8 wavefronts (ranges one level deeper); identical
+ *     results
+ * With the environment variable BTC_TUNE_CACHE naming a file, the table
+ * (kernel variants and the strategy choices of btc_autotune_strategy) is
+ * read from that file when the library first consults it, and written back
+ * after every btc_tune_set / btc_autotune / btc_autotune_strategy (text, one
+ * entry per line).
  * Other keys have the single variant 0 (btc_tune_set accepts only 0 there).
  * btc_autotune times every variant of the handle's tunable families on the
  * caller's matrix (reps timed repetitions after one warm-up each, per-level
- * HIP events) and stores the fastest per key; it refactors the handle and
- * overwrites X.  B and X are device arrays [N][n][nrhs], B != X.  Call it
+ * HIP events; the sweep shape by the time of whole solves) and stores the
+ * fastest per key; it refactors the handle and overwrites X.  B and X are device arrays [N][n][nrhs], B != X.  Call it
  * once at start-up: results computed before and after may differ at
  * round-off level.  Returns 0 or -k for argument k.
  */
+#define BTC_TUNE_SWEEP_SHAPE 6 /* tune key: launch shape of the sweeps (op field; level ignored) */
 BTC_API int btc_tune_get(int32_t op, int32_t precision, int64_t n, int32_t level, int32_t *variant);
 BTC_API int btc_tune_set(int32_t op, int32_t precision, int64_t n, int32_t level, int32_t variant);
 BTC_API int btc_autotune(btc_handle h, const double *A_diag, const double *A_off, const double *B, double *X,
@@ -446,7 +538,9 @@ typedef struct {
     double tol;          /* as in btc_options (0: default) */
     size_t hbm_budget;   /* bytes for resident factors + workspaces (btc_footprint_bytes) */
     int32_t max_active;  /* cap on requests in flight (0: no cap) */
-    int32_t pad;
+    int32_t sweep_ranges;  /* 0: one tick per sweep level; 1: sweeps in the library's level ranges
+                              (btc_sweep_ranges), one tick per range (fewer ticks per request,
+                              longer ticks: measured 4-6% fewer requests/s on the served mix) */
 } btc_server_options;
 
 typedef struct {
@@ -518,6 +612,25 @@ BTC_API void btc_server_destroy(btc_server s);
  */
 BTC_API int btc_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
                               void (*free_)(void *ptr, void *stream, void *ctx), void *ctx);
+
+/*
+ * btc_autotune_strategy -- time the elimination orders (multi-stage; k-stage
+ * with k = 0, 1, 2 where they apply: FP64, n <= 64, k < floor(log2 N)+1) on
+ * the caller's matrix: reps repetitions of refactor + solve each after one
+ * warm-up, HIP events on `stream`; the fastest becomes the choice of
+ * BTC_STRATEGY_AUTO for (precision, N, padded n), process-wide.  ms (host,
+ * 4 entries, nullable) receives the milliseconds per refactor + solve of
+ * multi-stage, k = 0, 1, 2 (-1: not a candidate).  Overwrites X.  Returns 0,
+ * -k for argument k, or the error of a candidate.
+ */
+BTC_API int btc_autotune_strategy(int64_t N, int64_t n, int32_t precision, const double *A_diag,
+                                  const double *A_off, const double *B, double *X, int64_t nrhs, int32_t reps,
+                                  void *stream, double *ms);
+
+/* btc_select_strategy -- the elimination order BTC_STRATEGY_AUTO takes for
+ * (N, n, precision): *strategy (BTC_STRATEGY_MULTISTAGE or _KSTAGE) and
+ * *stages.  Host only. */
+BTC_API int btc_select_strategy(int64_t N, int64_t n, int32_t precision, int32_t *strategy, int32_t *stages);
 
 /* btc_error_string -- static text for a return code. */
 BTC_API const char *btc_error_string(int code);

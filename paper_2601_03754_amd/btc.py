@@ -32,12 +32,22 @@ BTC_MAX_BLOCK = 128
 i32, i64, dbl, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
 
+BTC_REFINE_CLASSIC = 0
+BTC_REFINE_GMRES = 1
+
+
+BTC_STRATEGY_MULTISTAGE = 0
+BTC_STRATEGY_KSTAGE = 1
+BTC_STRATEGY_AUTO = 2
+
+
 class btc_options(ctypes.Structure):
-    _fields_ = [("precision", i32), ("max_refine", i32), ("tol", dbl)]
+    _fields_ = [("precision", i32), ("max_refine", i32), ("tol", dbl), ("refine", i32), ("gmres_m", i32),
+                ("strategy", i32), ("stages", i32)]
 
 
 class btc_solve_info(ctypes.Structure):
-    _fields_ = [("steps", i32), ("converged", i32), ("relres", dbl)]
+    _fields_ = [("steps", i32), ("converged", i32), ("relres", dbl), ("inner", i32), ("pad", i32)]
 
 
 BTC_OP_FACTOR, BTC_OP_FORWARD, BTC_OP_BACKWARD = 0, 1, 2
@@ -46,12 +56,12 @@ BTC_OP_RESIDUAL, BTC_OP_REFINE_INIT, BTC_OP_REFINE_TEST = 3, 4, 5
 
 class btc_step(ctypes.Structure):
     _fields_ = [("h", vp), ("op", i32), ("level", i32), ("A_diag", vp), ("A_off", vp), ("B", vp), ("X", vp),
-                ("nrhs", i64), ("first", i32), ("pad", i32)]
+                ("nrhs", i64), ("first", i32), ("level_end", i32), ("stage", i32), ("pad", i32)]
 
 
 class btc_server_options(ctypes.Structure):
     _fields_ = [("precision", i32), ("max_refine", i32), ("tol", dbl), ("hbm_budget", ctypes.c_size_t),
-                ("max_active", i32), ("pad", i32)]
+                ("max_active", i32), ("sweep_ranges", i32)]
 
 
 class btc_kernel_stat(ctypes.Structure):
@@ -186,6 +196,12 @@ def lib():
         L.btc_server_runner.argtypes = [vp]
         L.btc_version.restype = ctypes.c_int
         L.btc_version.argtypes = []
+        L.btc_autotune_strategy.restype = ctypes.c_int
+        L.btc_autotune_strategy.argtypes = [i64, i64, i32, vp, vp, vp, vp, i64, i32, vp, ctypes.POINTER(dbl)]
+        L.btc_select_strategy.restype = ctypes.c_int
+        L.btc_select_strategy.argtypes = [i64, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.btc_sweep_ranges.restype = ctypes.c_int
+        L.btc_sweep_ranges.argtypes = [i64, ctypes.POINTER(i32), i32]
         L.btc_set_allocator.restype = ctypes.c_int
         L.btc_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
         _lib = L
@@ -234,7 +250,8 @@ def _stream(stream) -> int:
 
 
 def btc_factor(A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_FP64,
-               stream=None, max_refine: int = 0, tol: float = 0.0) -> int:
+               stream=None, max_refine: int = 0, tol: float = 0.0, refine: int = BTC_REFINE_CLASSIC,
+               gmres_m: int = 0, strategy: int = BTC_STRATEGY_MULTISTAGE, stages: int = 0) -> int:
     """Factor; returns the raw handle (int)."""
     N, n, n2 = A_diag.shape
     if n != n2:
@@ -243,7 +260,7 @@ def btc_factor(A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_F
     po = _dev(A_off, "A_off") if N > 1 else 0
     if N > 1 and tuple(A_off.shape) != (N - 1, n, n):
         raise ValueError("A_off must be (N-1, n, n)")
-    opt = btc_options(precision, max_refine, tol)
+    opt = btc_options(precision, max_refine, tol, refine, gmres_m, strategy, stages)
     h = vp()
     with torch.cuda.device(A_diag.device):
         _check(lib().btc_factor(pa, po, N, n, ctypes.byref(opt), _stream(stream), ctypes.byref(h)),
@@ -270,7 +287,8 @@ def btc_solve(h: int, B: torch.Tensor, X: Optional[torch.Tensor] = None, stream=
                              ctypes.byref(info) if info is not None else None)
     _check(rc, "btc_solve")
     if want_info:
-        return X, {"steps": info.steps, "converged": bool(info.converged), "relres": info.relres}
+        return X, {"steps": info.steps, "converged": bool(info.converged), "relres": info.relres,
+                   "inner": info.inner}
     return X
 
 
@@ -319,7 +337,7 @@ def btc_profile_read(h: int, phase: int):
 def btc_create(N: int, n: int, precision: int = BTC_FP64, max_refine: int = 0, tol: float = 0.0) -> int:
     """Allocate a handle (no factorization) on the current device."""
     h = vp()
-    opt = btc_options(precision, max_refine, tol)
+    opt = btc_options(precision, max_refine, tol, 0, 0, 0, 0)
     _check(lib().btc_create(N, n, ctypes.byref(opt), ctypes.byref(h)), "btc_create")
     return h.value
 
@@ -494,10 +512,22 @@ def btc_level_work(op: int, precision: int, N: int, n: int, nrhs: int, level: in
 
 
 def step(h: int, op: int, level: int = 0, A_diag=None, A_off=None, B=None, X=None, nrhs: int = 0,
-         first: bool = False) -> btc_step:
-    """One level step for Runner.run (tensor arguments are device tensors)."""
+         first: bool = False, level_end: int = 0, stage: int = 0) -> btc_step:
+    """One step for Runner.run (tensor arguments are device tensors);
+    level_end > level + 1 makes a sweep step cover the levels
+    level .. level_end-1; stage orders dependent steps of one call."""
     ptr = lambda t: (t.data_ptr() if (t is not None and t.numel()) else 0)
-    return btc_step(h, op, level, ptr(A_diag), ptr(A_off), ptr(B), ptr(X), nrhs, 1 if first else 0, 0)
+    return btc_step(h, op, level, ptr(A_diag), ptr(A_off), ptr(B), ptr(X), nrhs, 1 if first else 0, level_end,
+                    stage, 0)
+
+
+def btc_sweep_ranges(N: int):
+    """Level ranges the library runs a sweep in (bounds, 0 .. levels)."""
+    b = (i32 * 70)()
+    r = lib().btc_sweep_ranges(N, b, 70)
+    if r < 0:
+        _check(r, "btc_sweep_ranges")
+    return [int(b[k]) for k in range(r + 1)]
 
 
 class Server:
@@ -505,9 +535,9 @@ class Server:
     every request referenced until the request has completed."""
 
     def __init__(self, precision: int = BTC_FP64, hbm_budget: int = 1 << 40, max_refine: int = 0,
-                 tol: float = 0.0, max_active: int = 0, stream=None):
+                 tol: float = 0.0, max_active: int = 0, stream=None, sweep_ranges: bool = False):
         self.stream = _stream(stream)
-        opt = btc_server_options(precision, max_refine, tol, hbm_budget, max_active, 0)
+        opt = btc_server_options(precision, max_refine, tol, hbm_budget, max_active, 1 if sweep_ranges else 0)
         h = vp()
         _check(lib().btc_server_create(ctypes.byref(opt), self.stream, ctypes.byref(h)), "btc_server_create")
         self.handle = h.value
@@ -593,6 +623,27 @@ class Server:
             pass
 
 
+def btc_autotune_strategy(A_diag: torch.Tensor, A_off: torch.Tensor, B: torch.Tensor, X: torch.Tensor,
+                          precision: int = BTC_FP64, reps: int = 5, stream=None):
+    """Time the elimination orders on this matrix, keep the fastest for
+    BTC_STRATEGY_AUTO; returns ms per refactor+solve of [multi-stage, k=0,
+    k=1, k=2] (-1: not a candidate)."""
+    N, n, _ = A_diag.shape
+    nrhs = B.shape[-1] if B.dim() == 3 else 1
+    ms = (dbl * 4)()
+    po = _dev(A_off, "A_off") if A_off.numel() else 0
+    _check(lib().btc_autotune_strategy(N, n, precision, _dev(A_diag, "A_diag"), po, _dev(B, "B"), _dev(X, "X"),
+                                       nrhs, reps, _stream(stream), ms), "btc_autotune_strategy")
+    return [ms[k] for k in range(4)]
+
+
+def btc_select_strategy(N: int, n: int, precision: int = BTC_FP64):
+    """(strategy, stages) that BTC_STRATEGY_AUTO takes for (N, n)."""
+    s, k = i32(), i32()
+    _check(lib().btc_select_strategy(N, n, precision, ctypes.byref(s), ctypes.byref(k)), "btc_select_strategy")
+    return s.value, k.value
+
+
 def btc_version() -> int:
     return int(lib().btc_version())
 
@@ -602,14 +653,16 @@ class Factor:
     device may still read them."""
 
     def __init__(self, A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_FP64,
-                 stream=None, max_refine: int = 0, tol: float = 0.0):
+                 stream=None, max_refine: int = 0, tol: float = 0.0, refine: int = BTC_REFINE_CLASSIC,
+                 gmres_m: int = 0, strategy: int = BTC_STRATEGY_MULTISTAGE, stages: int = 0):
         if A_off is None or A_off.numel() == 0:
             A_off = torch.zeros((0, A_diag.shape[1], A_diag.shape[1]), dtype=A_diag.dtype,
                                 device=A_diag.device)
         self.N, self.n = int(A_diag.shape[0]), int(A_diag.shape[1])
         self.precision = precision
         self._A = (A_diag, A_off)
-        self.handle = btc_factor(A_diag, A_off, precision, stream, max_refine, tol)
+        self.handle = btc_factor(A_diag, A_off, precision, stream, max_refine, tol, refine, gmres_m, strategy,
+                                 stages)
 
     def refactor(self, A_diag: torch.Tensor, A_off: torch.Tensor, stream=None) -> "Factor":
         btc_refactor(self.handle, A_diag, A_off, stream)
@@ -640,5 +693,5 @@ class Factor:
 
 
 def factor(A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_FP64, stream=None,
-           max_refine: int = 0, tol: float = 0.0) -> Factor:
-    return Factor(A_diag, A_off, precision, stream, max_refine, tol)
+           max_refine: int = 0, tol: float = 0.0, refine: int = BTC_REFINE_CLASSIC, gmres_m: int = 0) -> Factor:
+    return Factor(A_diag, A_off, precision, stream, max_refine, tol, refine, gmres_m)

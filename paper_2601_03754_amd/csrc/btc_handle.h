@@ -78,6 +78,13 @@ struct btc_handle_s {
     int32_t precision = BTC_FP64;
     int32_t max_refine = 0;
     double tol = 0.0;
+    int32_t refine = BTC_REFINE_CLASSIC;
+    int32_t gmres_m = BTC_DEFAULT_GMRES_M;
+    // elimination order: the first nd_levels levels of the multi-stage order
+    // (all of them for BTC_STRATEGY_MULTISTAGE), then, for
+    // BTC_STRATEGY_KSTAGE, the remaining chain one block after the other
+    int32_t strategy = BTC_STRATEGY_MULTISTAGE;
+    int32_t nd_levels = 0;
     int levels = 0;  // floor(log2 N) + 1
     int device = 0;
     // FP64 factor (BTC_FP64)
@@ -322,6 +329,11 @@ inline int factor_np(btc_handle h) {
 // Autotuned kernel variants (process-wide table, default 0).
 int tune_variant(int op, int kind, int np, int bucket);
 void tune_set(int op, int kind, int np, int bucket, int variant);
+void save_tune_cache();
+// Elimination order for BTC_STRATEGY_AUTO: the measured fastest for
+// (precision, N, padded n), else a rule.
+void select_strategy(int64_t N, int64_t n, int32_t prec, int32_t* strategy, int32_t* stages);
+void strategy_set(int64_t N, int64_t n, int32_t prec, int32_t strategy, int32_t stages);
 
 // Factor kernel family of a handle at a level: 0 VALU FP64 (np < 16, or
 // np 16/32 where the autotuner chose it), 1 MFMA FP64, 2 mixed,
@@ -358,8 +370,9 @@ inline bool tiled_kind(int kind) { return kind == 3 || kind == 4 || kind == 6; }
 // T^T T eagerly (its separators then receive both contributions in one
 // pass), and the next level has no deferred updates.
 inline int32_t factor_flags(btc_handle h, int level) {
+    // the chain of a k-stage order applies the last level's deferred update
     auto eager = [h](int l) {
-        return l >= 0 && l + 1 < h->levels && tiled_kind(factor_kind(h, l)) && tiled_kind(factor_kind(h, l + 1));
+        return l >= 0 && l + 1 < h->nd_levels && tiled_kind(factor_kind(h, l)) && tiled_kind(factor_kind(h, l + 1));
     };
     return (eager(level) ? btc::kFactorEagerT : 0) | (eager(level - 1) ? btc::kFactorDeferredDone : 0);
 }
@@ -393,17 +406,40 @@ inline hipError_t launch_factor_any(btc_handle h, const btc::Launch<btc::FactorD
     return launch_factor_kind(factor_kind(h, L.level), L, np, deferred, items, st);
 }
 
+inline btc::ChainDesc chain_desc(btc_handle h, const double* A_diag, const double* A_off, const double* B, double* X,
+                                 int64_t m) {
+    btc::ChainDesc c{};
+    c.A_diag = A_diag;
+    c.A_off = A_off;
+    c.Ld = h->Ld;
+    c.Rb = h->Rb;
+    c.Tb = h->Tb;
+    c.info = h->info;
+    c.B = B;
+    c.X = X;
+    c.N = h->N;
+    c.n = (int32_t)h->n;
+    c.k = h->nd_levels;
+    c.m = (int32_t)m;
+    return c;
+}
+
 inline int launch_factor(btc_handle h, const double* A_diag, const double* A_off, hipStream_t st) {
     snapshot_factor_kinds(h);
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, h->info, kInfoOk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return to_code(e);
     btc::Launch<btc::FactorDesc> L{};
-    for (int l = 0; l < h->levels; ++l) {
+    for (int l = 0; l < h->nd_levels; ++l) {
         L.single = factor_desc(h, A_diag, A_off, l);
         L.level = l;
         const int64_t nodes = level_nodes(h->N, l);
         e = timed(h, 0, l, st, [&] { return launch_factor_any(h, L, nodes, st); });
+        if (e != hipSuccess) return to_code(e);
+    }
+    if (h->strategy == BTC_STRATEGY_KSTAGE) {
+        const btc::ChainDesc c = chain_desc(h, A_diag, A_off, nullptr, nullptr, 0);
+        e = timed(h, 0, h->nd_levels, st, [&] { return btc::launch_chain_factor(c, btc::padded_block((int)h->n), st); });
         if (e != hipSuccess) return to_code(e);
     }
     h->A_diag = A_diag;
@@ -414,19 +450,105 @@ inline int launch_factor(btc_handle h, const double* A_diag, const double* A_off
     return BTC_OK;
 }
 
+// Level ranges of a sweep, one launch each: a range of one level runs one
+// wavefront per node (levels with many nodes: the most parallel form), a
+// range of several levels one workgroup per subtree (launch_sweep's chunk
+// form), which saves a launch and a dependency step per level.  A node step
+// is latency bound (one wavefront streams its blocks slab by slab: about
+// 15 us FP32, 45 us FP64 at n = 96), so a range takes only levels whose
+// subtree nodes the workgroup's wavefronts cover in one round each: its time
+// is then one node step per level, as with one launch per level.  Greedy
+// from level 0: a level with at least kSweepNodesPerLevel nodes is a range
+// of its own; otherwise the range grows while every level of a subtree has
+// at most kChunkWaves nodes.
+constexpr int64_t kSweepNodesPerLevel = 4096;
+
+inline int64_t chunk_rounds(int64_t N, int l0, int l1, int kw) {
+    int64_t r = 0;
+    for (int l = l0; l < l1; ++l) {
+        const int64_t per = (int64_t)1 << (l1 - l - 1);
+        const int64_t nodes = level_nodes(N, l);
+        const int64_t c = per < nodes ? per : nodes;
+        r += (c + kw - 1) / kw;
+    }
+    return r;
+}
+
+// Sweep launch shapes (tune key BTC_TUNE_SWEEP_SHAPE): 0 level ranges with
+// 4-wavefront workgroups, 1 one launch per level, 2 level ranges with
+// 8-wavefront workgroups.
+inline int sweep_shape(int32_t prec, int64_t n) {
+    return tune_variant(BTC_TUNE_SWEEP_SHAPE, is_mixed(prec) ? 1 : 0, btc::padded_block((int)n), 0);
+}
+inline int shape_waves(int shape) { return shape == 2 ? 8 : 4; }
+
+// Subtrees of the range [l0, l1): those j with a level-l0 node in (j 2^l1, (j+1) 2^l1).
+inline int64_t chunk_count(int64_t N, int l0, int l1) {
+    return ((N - ((int64_t)1 << l0)) >> l1) + 1;
+}
+
+// bounds[0] = 0 < bounds[1] < ... < bounds[r] = levels; returns r.
+inline int sweep_ranges(int64_t N, int levels, int* bounds, int shape = 0) {
+    int r = 0, l0 = 0;
+    bounds[0] = 0;
+    const int kw = shape_waves(shape);
+    while (l0 < levels) {
+        int l1 = l0 + 1;
+        if (shape != 1 && level_nodes(N, l0) < kSweepNodesPerLevel)
+            while (l1 < levels && chunk_rounds(N, l0, l1 + 1, kw) <= l1 + 1 - l0) ++l1;
+        bounds[++r] = l1;
+        l0 = l1;
+    }
+    return r;
+}
+
+// One range of a sweep (forward or backward) of one instance.
+template <class T>
+inline hipError_t sweep_range(btc_handle h, btc::Launch<btc::SweepDesc<T>>& L, int l0, int l1, bool bwd,
+                              hipStream_t st) {
+    const int np = btc::padded_block((int)h->n);
+    const int op = bwd ? BTC_OP_BACKWARD : BTC_OP_FORWARD;
+    const int mc = sweep_mc(op, sizeof(T) == 4, np, L.single.m);
+    const bool chunk = l1 > l0 + 1;
+    L.level = chunk ? (l0 | (l1 << 8)) : l0;
+    const int64_t items = chunk ? chunk_count(h->N, l0, l1) : level_nodes(h->N, l0);
+    const int kw = shape_waves(sweep_shape(h->precision, h->n));
+    // profiled per range, attributed to its first level
+    return timed(h, bwd ? 2 : 1, l0, st, [&] { return btc::launch_sweep(L, np, items, bwd, mc, st, chunk, kw); });
+}
+
+template <class T>
+inline hipError_t chain_solve(btc_handle, const btc::SweepDesc<T>&, hipStream_t) {
+    return hipErrorInvalidValue;  // the k-stage orders are FP64 only
+}
+
+template <>
+inline hipError_t chain_solve<double>(btc_handle h, const btc::SweepDesc<double>& d, hipStream_t st) {
+    btc::ChainDesc c = chain_desc(h, nullptr, nullptr, d.B, d.X, d.m);
+    c.Y = d.Y;
+    c.U = d.U;
+    c.V = d.V;
+    return timed(h, 1, h->nd_levels, st, [&] { return btc::launch_chain_solve(c, btc::padded_block((int)h->n), st); });
+}
+
 template <class T>
 inline hipError_t sweeps(btc_handle h, const btc::SweepDesc<T>& d, hipStream_t st) {
     btc::Launch<btc::SweepDesc<T>> L{};
     L.single = d;
-    const int np = btc::padded_block((int)h->n);
-    for (int l = 0; l < h->levels; ++l) {
-        L.level = l;
-        hipError_t e = timed(h, 1, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), false, sweep_mc(BTC_OP_FORWARD, sizeof(T) == 4, np, d.m), st); });
+    int b[66];
+    // the levels of the multi-stage order (all of them, or the first k), in
+    // ranges; a k-stage order solves along its chain in between
+    const int r = sweep_ranges(h->N, h->nd_levels, b, sweep_shape(h->precision, h->n));
+    for (int k = 0; k < r; ++k) {
+        hipError_t e = sweep_range(h, L, b[k], b[k + 1], false, st);
         if (e != hipSuccess) return e;
     }
-    for (int l = h->levels - 1; l >= 0; --l) {
-        L.level = l;
-        hipError_t e = timed(h, 2, l, st, [&] { return btc::launch_sweep(L, np, level_nodes(h->N, l), true, sweep_mc(BTC_OP_BACKWARD, sizeof(T) == 4, np, d.m), st); });
+    if (h->strategy == BTC_STRATEGY_KSTAGE) {
+        hipError_t e = chain_solve(h, d, st);
+        if (e != hipSuccess) return e;
+    }
+    for (int k = r - 1; k >= 0; --k) {
+        hipError_t e = sweep_range(h, L, b[k], b[k + 1], true, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

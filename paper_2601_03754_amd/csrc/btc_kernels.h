@@ -124,9 +124,12 @@ struct ResidualDesc {
     double* P;                 // [N][n][m] scratch: b_i - D_i x_i - E_i^T x_{i+1}
     double* Q;                 // [N][n][m] scratch: row i holds E_{i-1} x_{i-1} (i >= 2)
     const IrState* state;      // optional: skip when state->done
+    double* R64;               // optional: the residual in FP64 (negated when neg: Psi x - b)
     int64_t N;
     int32_t n;
     int32_t m;
+    int32_t neg;
+    int32_t pad;
 };
 
 // Refinement set-up / convergence test of one instance (items: one per instance).
@@ -142,6 +145,31 @@ struct IrDesc {
     int32_t max_steps;
     int32_t pad;
 };
+
+// Sequential elimination of the chain of blocks that remain after the first
+// k levels of the multi-stage order (k = 0: the whole chain, Algorithm 1),
+// and its solve (btc_chain.hip).  Factor arrays as FactorDesc (FP64 path);
+// vectors as SweepDesc<double>.
+struct ChainDesc {
+    const double* A_diag;
+    const double* A_off;
+    double* Ld;
+    double* Rb;
+    double* Tb;
+    unsigned long long* info;
+    const double* B;   // solve: right-hand side [N][n][m] (original order)
+    double* X;         // solve: solution [N][n][m]
+    double* Y;         // solve: forward results, permuted
+    const double* U;   // solve: contributions of the first k levels (as SweepDesc)
+    const double* V;
+    int64_t N;
+    int32_t n;
+    int32_t k;
+    int32_t m;
+    int32_t pad;
+};
+hipError_t launch_chain_factor(const ChainDesc& p, int np, hipStream_t st);
+hipError_t launch_chain_solve(const ChainDesc& p, int np, hipStream_t st);
 
 // FactorDesc.flags (tile-parallel families).  Eager: the Schur update of a
 // node's right separator S_{i+s} also subtracts T'^T T' of the node's right
@@ -167,14 +195,39 @@ hipError_t launch_factor_mixed(const Launch<FactorDesc>& p, int np, bool bf16, i
 hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, int mode, int part, bool deferred,
                                int64_t items, hipStream_t st);
 // mc: right-hand-side columns per dependency-chain group (1 or 4; with 4,
-// instances with fewer columns mask the rest).
+// instances with fewer columns mask the rest).  chunk: the items are
+// subtrees of several levels (level field l0 | l1 << 8, k the subtree index
+// j: the nodes of levels l0 .. l1-1 strictly between blocks j 2^l1 and
+// (j+1) 2^l1), one workgroup of kw (4 or 8) wavefronts each; else single
+// nodes, one wavefront each.
 hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t items, bool backward, int mc,
-                        hipStream_t st);
+                        hipStream_t st, bool chunk = false, int kw = 4);
 hipError_t launch_sweep(const Launch<SweepDesc<float>>& p, int np, int64_t items, bool backward, int mc,
-                        hipStream_t st);
+                        hipStream_t st, bool chunk = false, int kw = 4);
 // Two launches over the same items (every block row of each instance).
 hipError_t launch_residual(const Launch<ResidualDesc>& p, int np, int64_t items, int mc, hipStream_t st);
 hipError_t launch_ir_init(const Launch<IrDesc>& p, int64_t items, hipStream_t st);
 hipError_t launch_ir_check(const Launch<IrDesc>& p, int64_t items, hipStream_t st);
+
+// FP64 vector kernels of the GMRES correction solve.  A vector is `rows`
+// rows of m columns ([rows][m], row-major); a basis of k vectors is k such
+// vectors at stride rows*m.  Reductions run in a fixed order (per-workgroup
+// partial sums, then one workgroup in workgroup order), so results are
+// reproducible.
+//   dots: h[i*m + q] = sum_r V_i[r][q] z[r][q] for i < k, and with self,
+//         h[k*m + q] = sum_r z[r][q]^2 (part: kGmresBlocks*(k+1)*m scratch)
+//   update: z[r][q] -= sum_{i<k} h[i*m+q] V_i[r][q]
+//   scale: dst[r][q] = src[r][q] * s[q]
+//   combine: x[r][q] += sum_{j<k} y[j*m+q] V_j[r][q]
+//   fill: x[e] = v for e < count
+constexpr int kGmresBlocks = 256;
+hipError_t launch_gmres_dots(const double* V, int k, const double* z, bool self, int64_t rows, int m, double* part,
+                             double* h, hipStream_t st);
+hipError_t launch_gmres_update(const double* V, int k, const double* h, double* z, int64_t rows, int m,
+                               hipStream_t st);
+hipError_t launch_gmres_scale(const double* src, const double* s, double* dst, int64_t rows, int m, hipStream_t st);
+hipError_t launch_gmres_combine(const double* V, int k, const double* y, double* x, int64_t rows, int m,
+                                hipStream_t st);
+hipError_t launch_fill(double* x, double v, int64_t count, hipStream_t st);
 
 }  // namespace btc

@@ -32,8 +32,10 @@ __global__ void k_reset_infos(unsigned long long* const* __restrict__ ptrs, int 
 
 // One group = one launch.
 struct Group {
+    int stage = 0;
     int op;    // btc_op
-    int kind;  // FACTOR: factor kernel family (factor_kind); sweeps: 0 double, 1 float
+    int kind;  // FACTOR: factor kernel family (factor_kind); sweeps: 0 double, 1 float,
+               // 2 / 3 the same over level ranges (subtree launches)
     bool deferred = false;  // FACTOR: some item has deferred updates to apply
     int m_max = 1;   // sweeps / residual: largest number of right-hand sides
     int np;
@@ -53,7 +55,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // The groups of one runner call and the status words its level-0 factor
 // steps reset; offsets are into the device buffer the call is launched from.
 struct Call {
-    std::map<std::tuple<int, int, int>, Group> groups;
+    std::map<std::tuple<int, int, int, int>, Group> groups;  // (stage, op, kind, np)
     std::vector<unsigned long long*> resets;
     size_t off_resets = 0;
 };
@@ -212,9 +214,15 @@ btc::Launch<D> make_launch(const Group& g, char* dev) {
 int validate(const btc_step& s) {
     btc_handle h = s.h;
     if (!h) return -3;
+    if (h->strategy != BTC_STRATEGY_MULTISTAGE) return -3;  // level steps exist in the multi-stage order only
     if (s.op < BTC_OP_FACTOR || s.op > BTC_OP_REFINE_TEST) return -3;
+    if (s.stage < 0 || s.stage > 7) return -3;
     if (s.op == BTC_OP_FACTOR || s.op == BTC_OP_FORWARD || s.op == BTC_OP_BACKWARD) {
         if (s.level < 0 || s.level >= h->levels) return -3;
+    }
+    if (s.level_end != 0) {
+        if (s.op != BTC_OP_FORWARD && s.op != BTC_OP_BACKWARD) return -3;
+        if (s.level_end <= s.level || s.level_end > h->levels) return -3;
     }
     if (s.op == BTC_OP_FACTOR) {
         if (s.level == 0 && (!s.A_diag || (h->N > 1 && !s.A_off))) return -3;
@@ -233,19 +241,18 @@ extern "C" {
 
 namespace {
 
-std::tuple<int, int, int, int> key4(const std::tuple<int, int, int>& k, int part) {
-    return std::make_tuple(std::get<0>(k), std::get<1>(k), std::get<2>(k), part);
-}
-
 void add_work(const btc_runner_s* r, Group& g, const btc_step& s, bool mixed) {
     if (r->prof_op == -2) return;
     g.count = true;
     g.prof = prof_match(r, g.op, g.kind);
     const btc_handle h = s.h;
-    const Work w = level_work(s.op, mixed, h->N, h->n, s.op == BTC_OP_FACTOR ? 0 : s.nrhs, s.level);
-    g.work.bytes += w.bytes;
-    g.work.flops += w.flops;
-    g.work.items += w.items;
+    const int l1 = s.level_end > s.level ? s.level_end : s.level + 1;
+    for (int l = s.level; l < l1; ++l) {
+        const Work w = level_work(s.op, mixed, h->N, h->n, s.op == BTC_OP_FACTOR ? 0 : s.nrhs, l);
+        g.work.bytes += w.bytes;
+        g.work.flops += w.flops;
+        g.work.items += w.items;
+    }
     if (s.op == BTC_OP_FACTOR && tiled_kind(g.kind))
         for (int k = 1; k <= 3; ++k) {
             const Work pw = tiled_part_work(k, mixed, h->N, h->n, s.level, factor_flags(h, s.level));
@@ -350,7 +357,8 @@ void build_call(btc_runner r, int32_t count, const btc_step* steps, hipStream_t 
             }
             const int np = factor_np(h);
             const int kind = factor_kind(h, s.level);
-            Group& g = groups[std::make_tuple(s.op, kind, np)];
+            Group& g = groups[std::make_tuple(s.stage, s.op, kind, np)];
+            g.stage = s.stage;
             g.op = s.op;
             g.kind = kind;
             g.np = np;
@@ -366,9 +374,12 @@ void build_call(btc_runner r, int32_t count, const btc_step* steps, hipStream_t 
         const Workspace w = carve(h, h->ws_m);
         const int np = btc::padded_block((int)h->n);
         if (s.op == BTC_OP_FORWARD || s.op == BTC_OP_BACKWARD) {
-            Group& g = groups[std::make_tuple(s.op, mixed ? 1 : 0, np)];
+            const bool range = s.level_end > s.level + 1;
+            const int kind = (mixed ? 1 : 0) + (range ? 2 : 0);
+            Group& g = groups[std::make_tuple(s.stage, s.op, kind, np)];
+            g.stage = s.stage;
             g.op = s.op;
-            g.kind = mixed ? 1 : 0;
+            g.kind = kind;
             g.np = np;
             g.m_max = std::max<int>(g.m_max, (int)s.nrhs);
             int32_t inst;
@@ -380,10 +391,16 @@ void build_call(btc_runner r, int32_t count, const btc_step* steps, hipStream_t 
                 push_desc(g, sweep_desc64(h, w, s.B, s.X, s.nrhs));
             }
             add_work(r, g, s, mixed);
-            const int64_t nodes = level_nodes(h->N, s.level);
-            for (int64_t q = 0; q < nodes; ++q) g.items.push_back({inst, s.level, q});
+            if (range) {
+                const int64_t cnt = chunk_count(h->N, s.level, s.level_end);
+                for (int64_t q = 0; q < cnt; ++q) g.items.push_back({inst, s.level | (s.level_end << 8), q});
+            } else {
+                const int64_t nodes = level_nodes(h->N, s.level);
+                for (int64_t q = 0; q < nodes; ++q) g.items.push_back({inst, s.level, q});
+            }
         } else if (s.op == BTC_OP_RESIDUAL) {
-            Group& g = groups[std::make_tuple(s.op, 0, np)];
+            Group& g = groups[std::make_tuple(s.stage, s.op, 0, np)];
+            g.stage = s.stage;
             g.op = s.op;
             g.kind = 0;
             g.np = np;
@@ -393,7 +410,8 @@ void build_call(btc_runner r, int32_t count, const btc_step* steps, hipStream_t 
             add_work(r, g, s, mixed);
             for (int64_t q = 0; q < h->N; ++q) g.items.push_back({inst, 0, q});
         } else {
-            Group& g = groups[std::make_tuple(s.op, 0, 0)];
+            Group& g = groups[std::make_tuple(s.stage, s.op, 0, 0)];
+            g.stage = s.stage;
             g.op = s.op;
             g.kind = 0;
             g.np = 0;
@@ -433,7 +451,8 @@ void write_call(const Call& c, char* host) {
 }
 
 // Enqueue the call (its descriptors already in `dev`): status resets, then
-// every group, independent groups spread over the runner's streams.
+// the groups stage by stage, the independent groups of a stage spread over
+// the runner's streams.
 int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
     hipError_t e = hipSuccess;
     auto& groups = c.groups;
@@ -446,47 +465,7 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
         if (e != hipSuccess) return to_code(e);
     }
     if (timing && !r->pending.empty()) drain_prof(r, false);
-    // stream of every group: largest estimated work first, each onto the
-    // least loaded of the main and side streams
-    // (convergence tests run after every other group of the call, on the
-    // runner's stream once the side streams have joined: a call may hold a
-    // residual step and the test that reads it)
-    std::vector<std::pair<double, Group*>> order;
-    for (auto& kv : groups) {
-        Group& g = kv.second;
-        if (g.op == BTC_OP_REFINE_TEST) {
-            g.lane = 0;
-            continue;
-        }
-        const double np = (double)std::max(g.np, 8);
-        const double w = (g.op == BTC_OP_FACTOR ? np : 1.0) * np * np * (double)g.items.size();
-        order.push_back({w, &g});
-    }
-    std::sort(order.begin(), order.end(), [](const std::pair<double, Group*>& a, const std::pair<double, Group*>& b) {
-        return a.first > b.first;
-    });
-    double load[1 + btc_runner_s::kSide] = {};
-    bool used[1 + btc_runner_s::kSide] = {};
-    for (auto& o : order) {
-        int best = 0;
-        for (int k = 1; k <= btc_runner_s::kSide; ++k)
-            if (load[k] < load[best]) best = k;
-        load[best] += o.first;
-        used[best] = true;
-        o.second->lane = best;
-    }
-    bool forked = false;
-    for (int k = 1; k <= btc_runner_s::kSide; ++k) {
-        if (!used[k]) continue;
-        if (!forked) {
-            e = hipEventRecord(r->fork, st);
-            if (e != hipSuccess) return to_code(e);
-            forked = true;
-        }
-        e = hipStreamWaitEvent(r->side[k - 1], r->fork, 0);
-        if (e != hipSuccess) return to_code(e);
-    }
-    auto launch_group = [&](const std::tuple<int, int, int>& key, const Group& g) -> int {
+    auto launch_group = [&](const Group& g) -> int {
         const int64_t items = (int64_t)g.items.size();
         hipStream_t gs = g.lane == 0 ? st : r->side[g.lane - 1];
         hipEvent_t ea = nullptr, eb = nullptr;
@@ -525,10 +504,13 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
             case BTC_OP_FORWARD:
             case BTC_OP_BACKWARD: {
                 const bool bwd = g.op == BTC_OP_BACKWARD;
-                if (g.kind == 1)
-                    e = btc::launch_sweep(make_launch<btc::SweepDesc<float>>(g, dev), g.np, items, bwd, sweep_mc(g.op, 1, g.np, g.m_max), gs);
+                const bool range = g.kind >= 2;
+                const int fk = g.kind & 1;
+                const int kw = shape_waves(tune_variant(BTC_TUNE_SWEEP_SHAPE, fk, g.np, 0));
+                if (fk == 1)
+                    e = btc::launch_sweep(make_launch<btc::SweepDesc<float>>(g, dev), g.np, items, bwd, sweep_mc(g.op, 1, g.np, g.m_max), gs, range, kw);
                 else
-                    e = btc::launch_sweep(make_launch<btc::SweepDesc<double>>(g, dev), g.np, items, bwd, sweep_mc(g.op, 0, g.np, g.m_max), gs);
+                    e = btc::launch_sweep(make_launch<btc::SweepDesc<double>>(g, dev), g.np, items, bwd, sweep_mc(g.op, 0, g.np, g.m_max), gs, range, kw);
                 break;
             }
             case BTC_OP_RESIDUAL:
@@ -541,29 +523,76 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
                 e = btc::launch_ir_check(make_launch<btc::IrDesc>(g, dev), items, gs);
                 break;
         }
+        const auto key = std::make_tuple(g.op, g.kind, g.np, 0);
         if (g.prof && timing && !split) {
             (void)hipEventRecord(eb, gs);
-            r->pending.push_back({key4(key, 0), ea, eb, g.work});
+            r->pending.push_back({key, ea, eb, g.work});
         } else if (g.count && timing && !split) {
-            add_untimed(r, key4(key, 0), g.work);
+            add_untimed(r, key, g.work);
         }
         return e != hipSuccess ? to_code(e) : BTC_OK;
     };
-    for (auto& kv : groups) {
-        if (kv.second.op == BTC_OP_REFINE_TEST) continue;
-        const int rc = launch_group(kv.first, kv.second);
-        if (rc != BTC_OK) return rc;
-    }
-    for (int k = 1; k <= btc_runner_s::kSide; ++k) {
-        if (!used[k]) continue;
-        e = hipEventRecord(r->join[k - 1], r->side[k - 1]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, r->join[k - 1], 0);
-        if (e != hipSuccess) return to_code(e);
-    }
-    for (auto& kv : groups) {
-        if (kv.second.op != BTC_OP_REFINE_TEST) continue;
-        const int rc = launch_group(kv.first, kv.second);
-        if (rc != BTC_OK) return rc;
+    for (auto it = groups.begin(); it != groups.end();) {
+        const int stage = it->second.stage;
+        auto end = it;
+        while (end != groups.end() && end->second.stage == stage) ++end;
+        // stream of every group of the stage: largest estimated work first,
+        // each onto the least loaded of the main and side streams
+        // (convergence tests run after every other group of their stage, on
+        // the runner's stream once the side streams have joined: a stage may
+        // hold a residual step and the test that reads it)
+        std::vector<std::pair<double, Group*>> order;
+        for (auto g = it; g != end; ++g) {
+            Group& gr = g->second;
+            if (gr.op == BTC_OP_REFINE_TEST) {
+                gr.lane = 0;
+                continue;
+            }
+            const double np = (double)std::max(gr.np, 8);
+            const double w = (gr.op == BTC_OP_FACTOR ? np : 1.0) * np * np * (double)gr.items.size();
+            order.push_back({w, &gr});
+        }
+        std::sort(order.begin(), order.end(), [](const std::pair<double, Group*>& a, const std::pair<double, Group*>& b) {
+            return a.first > b.first;
+        });
+        double load[1 + btc_runner_s::kSide] = {};
+        bool used[1 + btc_runner_s::kSide] = {};
+        for (auto& o : order) {
+            int best = 0;
+            for (int k = 1; k <= btc_runner_s::kSide; ++k)
+                if (load[k] < load[best]) best = k;
+            load[best] += o.first;
+            used[best] = true;
+            o.second->lane = best;
+        }
+        bool forked = false;
+        for (int k = 1; k <= btc_runner_s::kSide; ++k) {
+            if (!used[k]) continue;
+            if (!forked) {
+                e = hipEventRecord(r->fork, st);
+                if (e != hipSuccess) return to_code(e);
+                forked = true;
+            }
+            e = hipStreamWaitEvent(r->side[k - 1], r->fork, 0);
+            if (e != hipSuccess) return to_code(e);
+        }
+        for (auto g = it; g != end; ++g) {
+            if (g->second.op == BTC_OP_REFINE_TEST) continue;
+            const int rc = launch_group(g->second);
+            if (rc != BTC_OK) return rc;
+        }
+        for (int k = 1; k <= btc_runner_s::kSide; ++k) {
+            if (!used[k]) continue;
+            e = hipEventRecord(r->join[k - 1], r->side[k - 1]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, r->join[k - 1], 0);
+            if (e != hipSuccess) return to_code(e);
+        }
+        for (auto g = it; g != end; ++g) {
+            if (g->second.op != BTC_OP_REFINE_TEST) continue;
+            const int rc = launch_group(g->second);
+            if (rc != BTC_OK) return rc;
+        }
+        it = end;
     }
     return BTC_OK;
 }
@@ -713,6 +742,16 @@ BTC_API int btc_level_work(int32_t op, int32_t precision, int64_t N, int64_t n, 
     return BTC_OK;
 }
 
+BTC_API int btc_sweep_ranges(int64_t N, int32_t* bounds, int32_t max) {
+    if (N < 1) return -1;
+    if (!bounds) return -2;
+    int b[66];
+    const int r = sweep_ranges(N, num_levels(N), b);
+    if (r + 1 > max) return -2;
+    for (int k = 0; k <= r; ++k) bounds[k] = b[k];
+    return r;
+}
+
 BTC_API int btc_runner_query(btc_runner r) {
     if (!r) return -1;
     const hipError_t e = hipStreamQuery(r->st);
@@ -787,16 +826,34 @@ BTC_API int btc_solve_batched(btc_runner r, int32_t count, const btc_handle* h, 
             rounds = std::max(rounds, 1 + h[k]->max_refine);
         }
     }
+    // each instance's sweeps in its level ranges; call q runs range q of
+    // every instance that has one (backward: counted from the top)
+    std::vector<std::vector<int>> bounds((size_t)count);
+    int max_ranges = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        bounds[(size_t)k].resize(66);
+        const int nr = sweep_ranges(h[k]->N, h[k]->levels, bounds[(size_t)k].data(),
+                                    sweep_shape(h[k]->precision, h[k]->n));
+        bounds[(size_t)k].resize((size_t)nr + 1);
+        max_ranges = std::max(max_ranges, nr);
+    }
+    (void)levels;
     std::vector<btc_step> steps;
-    auto run_op = [&](int op, int level, bool mixed_only, int first) -> int {
+    auto run_op = [&](int op, int q, bool mixed_only, int first) -> int {
         steps.clear();
         for (int32_t k = 0; k < count; ++k) {
-            if ((op == BTC_OP_FORWARD || op == BTC_OP_BACKWARD) && level >= h[k]->levels) continue;
             if (mixed_only && !is_mixed(h[k]->precision)) continue;
             btc_step s{};
+            if (op == BTC_OP_FORWARD || op == BTC_OP_BACKWARD) {
+                const auto& b = bounds[(size_t)k];
+                const int nr = (int)b.size() - 1;
+                if (q >= nr) continue;
+                const int rg = op == BTC_OP_FORWARD ? q : nr - 1 - q;
+                s.level = b[(size_t)rg];
+                s.level_end = b[(size_t)rg + 1] > b[(size_t)rg] + 1 ? b[(size_t)rg + 1] : 0;
+            }
             s.h = h[k];
             s.op = op;
-            s.level = level;
             s.B = B[k];
             s.X = X[k];
             s.nrhs = nrhs[k];
@@ -810,8 +867,8 @@ BTC_API int btc_solve_batched(btc_runner r, int32_t count, const btc_handle* h, 
     for (int round = 0; round < rounds && rc == BTC_OK; ++round) {
         // FP64 instances take part in the first round only
         const bool only_mixed = round > 0;
-        for (int l = 0; l < levels && rc == BTC_OK; ++l) rc = run_op(BTC_OP_FORWARD, l, only_mixed, round == 0);
-        for (int l = levels - 1; l >= 0 && rc == BTC_OK; --l) rc = run_op(BTC_OP_BACKWARD, l, only_mixed, round == 0);
+        for (int q = 0; q < max_ranges && rc == BTC_OK; ++q) rc = run_op(BTC_OP_FORWARD, q, only_mixed, round == 0);
+        for (int q = 0; q < max_ranges && rc == BTC_OK; ++q) rc = run_op(BTC_OP_BACKWARD, q, only_mixed, round == 0);
         if (any_mixed && rc == BTC_OK) rc = run_op(BTC_OP_RESIDUAL, 0, true, 0);
         if (any_mixed && rc == BTC_OK) rc = run_op(BTC_OP_REFINE_TEST, 0, true, 0);
     }
@@ -829,12 +886,16 @@ BTC_API int btc_solve_batched(btc_runner r, int32_t count, const btc_handle* h, 
                 info[k].steps = 0;
                 info[k].converged = 1;
                 info[k].relres = -1.0;  // not computed by the FP64 path
+                info[k].inner = 0;
+                info[k].pad = 0;
             }
         }
         if (rc == BTC_ERR_NOT_SPD) {
             info[k].steps = 0;
             info[k].converged = 0;
             info[k].relres = -1.0;
+            info[k].inner = 0;
+            info[k].pad = 0;
             rc = BTC_OK;
         }
         if (rc != BTC_OK) return rc;

@@ -117,6 +117,7 @@ struct Req {
     double t_admit = 0.0;
     std::vector<btc_step> plan;
     std::vector<uint8_t> joint;  // joint[k]: plan step k runs in the same tick as step k+1
+    std::vector<uint8_t> par;    // par[k]: step k runs in the same stage as step k-1 of its tick
     size_t pc = 0;
     bool refactored = false;
     bool retired = false;
@@ -216,12 +217,22 @@ int admit_client(btc_server s, Client& c, int64_t nrhs) {
     return BTC_OK;
 }
 
-// The steps of a request, in order, grouped into ticks.  A refactor+solve
-// request interlaces the factorization with the first forward sweep (the
-// paper's interlaced factor and forward substitution, section "Fused and
-// Blocked Kernels"): forward level l only reads factor blocks of level l,
-// final once factor level l has run, so it shares a tick with factor level
-// l+1, which writes only blocks of higher levels.
+// The steps of a request, in order, grouped into ticks; within a tick a
+// request's steps run in successive stages of one runner call (a step
+// marked par shares its predecessor's stage).  Sweeps run in the library's
+// level ranges (sweep_ranges): one tick per range.
+//   * A refactor+solve request interlaces the factorization with the first
+//     forward sweep (the paper's interlaced factor and forward substitution,
+//     section "Fused and Blocked Kernels"): a forward range ending at level l
+//     only reads factor blocks below level l, final once factor level l-1
+//     has run, so it shares the tick (and stage) of factor level l, which
+//     writes only blocks of level l and above.
+//   * The top forward range and the top backward range share a tick.
+//   * Mixed precision: the refinement set-up precedes the first forward
+//     range in its tick; the residual and its convergence test follow the
+//     last backward range in its tick, and the next round's first forward
+//     range follows them (it does nothing once the test has stopped the
+//     refinement).
 void build_plan(btc_server s, Req* r, Client& c) {
     btc_handle h = c.h;
     const int L = h->levels;
@@ -232,10 +243,19 @@ void build_plan(btc_server s, Req* r, Client& c) {
         c.A_diag = r->A_diag;
         c.A_off = r->A_off;
     }
-    auto push = [&](const btc_step& t, bool joint) {
+    int b[66];
+    int nr = L;
+    if (!s->opt.sweep_ranges)
+        for (int l = 0; l <= L; ++l) b[l] = l;
+    else
+        nr = sweep_ranges(h->N, L, b, sweep_shape(h->precision, h->n));
+    auto push = [&](const btc_step& t, bool par) {
         r->plan.push_back(t);
-        r->joint.push_back(joint ? 1 : 0);
+        r->joint.push_back(0);
+        r->par.push_back(par ? 1 : 0);
     };
+    // the previous step shares its tick with the next one
+    auto join_next = [&]() { r->joint.back() = 1; };
     btc_step f{};
     f.h = h;
     f.op = BTC_OP_FACTOR;
@@ -246,55 +266,69 @@ void build_plan(btc_server s, Req* r, Client& c) {
     t.B = r->B;
     t.X = r->X;
     t.nrhs = r->nrhs;
+    auto range = [&](btc_step& x, int op, int q) {
+        x.op = op;
+        x.level = b[q];
+        x.level_end = b[q + 1] > b[q] + 1 ? b[q + 1] : 0;
+    };
     const bool mixed = is_mixed(h->precision);
     const int rounds = mixed ? 1 + h->max_refine : 1;
     if (factor) r->refactored = true;
     for (int k = 0; k < rounds; ++k) {
         t.first = (k == 0) ? 1 : 0;
+        int q = 0;  // next forward range
         if (k == 0 && factor) {
-            // tick 0: factor level 0 (+ refinement set-up); tick l: factor level
-            // l + forward level l-1; tick L: forward level L-1
-            f.level = 0;
-            push(f, mixed);
-            if (mixed) {
-                t.op = BTC_OP_REFINE_INIT;
-                t.level = 0;
-                push(t, false);
-            }
-            for (int l = 1; l <= L; ++l) {
-                if (l < L) {
-                    f.level = l;
-                    push(f, true);
-                }
-                t.op = BTC_OP_FORWARD;
-                t.level = l - 1;
-                push(t, false);
-            }
-        } else {
-            if (k == 0 && mixed) {
-                t.op = BTC_OP_REFINE_INIT;
-                t.level = 0;
-                push(t, false);
-            }
+            // tick l: factor level l (with the refinement set-up at level 0)
+            // and the forward range ending at level l; the top forward range
+            // (ending at level L) starts the tick after
             for (int l = 0; l < L; ++l) {
-                t.op = BTC_OP_FORWARD;
-                t.level = l;
-                push(t, false);
+                f.level = l;
+                push(f, false);
+                if (l == 0 && mixed) {
+                    t.op = BTC_OP_REFINE_INIT;
+                    t.level = 0;
+                    t.level_end = 0;
+                    join_next();
+                    push(t, true);
+                }
+                if (q < nr && b[q + 1] == l) {
+                    range(t, BTC_OP_FORWARD, q++);
+                    join_next();
+                    push(t, true);
+                }
             }
+        } else if (k == 0 && mixed) {
+            t.op = BTC_OP_REFINE_INIT;
+            t.level = 0;
+            t.level_end = 0;
+            push(t, false);
+            join_next();  // the first forward range follows in the same tick
+        } else if (k > 0 && nr > 1) {
+            // after the previous round's test, in its tick (with a single
+            // range the round starts a tick of its own: a tick holds at most
+            // one round's sweeps)
+            join_next();
         }
-        for (int l = L - 1; l >= 0; --l) {
-            t.op = BTC_OP_BACKWARD;
-            t.level = l;
+        for (; q < nr; ++q) {
+            range(t, BTC_OP_FORWARD, q);
+            push(t, false);
+        }
+        // top backward range right after the top forward range
+        join_next();
+        for (int g = nr - 1; g >= 0; --g) {
+            range(t, BTC_OP_BACKWARD, g);
             push(t, false);
         }
         if (mixed) {
-            // the residual and its convergence test share a tick (the runner
-            // runs tests after the other steps of a call)
+            // residual and test after the last backward range, in its tick
+            join_next();
             t.level = 0;
+            t.level_end = 0;
             t.op = BTC_OP_RESIDUAL;
-            push(t, true);
-            t.op = BTC_OP_REFINE_TEST;
             push(t, false);
+            join_next();
+            t.op = BTC_OP_REFINE_TEST;
+            push(t, true);
         }
     }
 }
@@ -460,9 +494,14 @@ BTC_API int btc_server_step(btc_server s) {
         if (r->retired || r->pc >= r->plan.size()) continue;  // done, or waiting for its last tick
         r->last_tick = t.id;
         bool more = true, test = false;
+        int stage = -1;
         while (more && r->pc < r->plan.size()) {
+            const bool par = r->par[r->pc] != 0 && stage >= 0;
+            if (!par && stage >= 7) break;  // stages of a runner call: the rest goes in the next tick
             more = r->joint[r->pc] != 0;
-            const btc_step& st = r->plan[r->pc++];
+            btc_step st = r->plan[r->pc++];
+            stage += par ? 0 : 1;
+            st.stage = stage;
             s->scratch.push_back(st);
             test = test || st.op == BTC_OP_REFINE_TEST;
         }

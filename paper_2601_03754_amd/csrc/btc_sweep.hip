@@ -272,17 +272,12 @@ __device__ __forceinline__ void run_slabs(const Plan<S>& pl, int n, int lane, T*
 }
 
 // ---------------------------------------------------------------------------
+// Forward step of node kk of level lvl by one wavefront (buf: its slab buffer).
 template <int NP, int MC, class T>
-__global__ __launch_bounds__(kWave) void k_fwd(Launch<SweepDesc<T>> L) {
+__device__ __forceinline__ void fwd_node(const SweepDesc<T>& P, int lvl, int64_t kk, T* __restrict__ buf) {
     using G = Geo<NP>;
     constexpr int RPL = G::RPL, LDB = G::LDB;
-    __shared__ T buf[G::BUF];
-    SweepDesc<T> P;
-    int lvl;
-    int64_t kk;
-    fetch_item(L, P, lvl, kk);
-    if (skip_item(P)) return;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
     const int64_t N = P.N;
     const int n = P.n, m = P.m;
     const size_t nn = (size_t)n * n, nm = (size_t)n * m;
@@ -367,17 +362,12 @@ __global__ __launch_bounds__(kWave) void k_fwd(Launch<SweepDesc<T>> L) {
 }
 
 // ---------------------------------------------------------------------------
+// Backward step of node kk of level lvl by one wavefront.
 template <int NP, int MC, class T>
-__global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
+__device__ __forceinline__ void bwd_node(const SweepDesc<T>& P, int lvl, int64_t kk, T* __restrict__ buf) {
     using G = Geo<NP>;
     constexpr int RPL = G::RPL, LDB = G::LDB;
-    __shared__ T buf[G::BUF];
-    SweepDesc<T> P;
-    int lvl;
-    int64_t kk;
-    fetch_item(L, P, lvl, kk);
-    if (skip_item(P)) return;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
     const int64_t N = P.N;
     const int n = P.n, m = P.m;
     const size_t nn = (size_t)n * n, nm = (size_t)n * m;
@@ -453,6 +443,70 @@ __global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
                 if (P.X64) P.X64[idx] = P.first ? (double)acc[rr][c] : P.X64[idx] + (double)acc[rr][c];
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One level of one or many instances: one wavefront per node.
+template <int NP, int MC, class T>
+__global__ __launch_bounds__(kWave) void k_fwd(Launch<SweepDesc<T>> L) {
+    __shared__ T buf[Geo<NP>::BUF];
+    SweepDesc<T> P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
+    if (skip_item(P)) return;
+    fwd_node<NP, MC, T>(P, lvl, kk, buf);
+}
+
+template <int NP, int MC, class T>
+__global__ __launch_bounds__(kWave) void k_bwd(Launch<SweepDesc<T>> L) {
+    __shared__ T buf[Geo<NP>::BUF];
+    SweepDesc<T> P;
+    int lvl;
+    int64_t kk;
+    fetch_item(L, P, lvl, kk);
+    if (skip_item(P)) return;
+    bwd_node<NP, MC, T>(P, lvl, kk, buf);
+}
+
+// Several levels in one launch.  The nodes of levels l0 .. l1-1 that lie
+// strictly between the blocks j 2^l1 and (j+1) 2^l1 form a subtree of the
+// elimination tree whose forward steps read only each other's results and
+// those of levels below l0 (a level-l node pulls from the blocks within s of
+// it), and whose backward steps read only each other's results and those of
+// levels l1 and above (the two blocks at the subtree's ends).  Item (inst, l0
+// | l1 << 8, j) is that subtree; its KW wavefronts take the nodes of one level
+// at a time (forward: levels ascending, backward: descending), with a
+// workgroup barrier between levels: the wavefronts of a workgroup share one
+// compute unit and its vector L1, so the barrier's workgroup-scope release
+// and acquire make one level's global stores visible to the next level's
+// loads (an agent-scope fence would write back and invalidate the L2 at
+// every level).
+template <int NP, int MC, class T, int KW, bool BWD>
+__global__ __launch_bounds__(KW * kWave) void k_sweep_chunk(Launch<SweepDesc<T>> L) {
+    __shared__ T buf[KW][Geo<NP>::BUF];
+    SweepDesc<T> P;
+    int code;
+    int64_t j;
+    fetch_item(L, P, code, j);
+    if (skip_item(P)) return;  // uniform over the workgroup
+    const int l0 = code & 0xff, l1 = code >> 8;
+    const int w = wave_id();
+    const int64_t N = P.N;
+    for (int t = 0; t < l1 - l0; ++t) {
+        const int l = BWD ? l1 - 1 - t : l0 + t;
+        const int64_t per = (int64_t)1 << (l1 - l - 1);  // nodes of a full subtree at level l
+        const int64_t s = (int64_t)1 << l;
+        const int64_t k0 = j * per, nodes = (N + s) / (2 * s);
+        const int64_t k1 = k0 + per < nodes ? k0 + per : nodes;
+        for (int64_t k = k0 + w; k < k1; k += KW) {
+            if (BWD)
+                bwd_node<NP, MC, T>(P, l, k, buf[w]);
+            else
+                fwd_node<NP, MC, T>(P, l, k, buf[w]);
+        }
+        __syncthreads();
     }
 }
 
@@ -694,6 +748,7 @@ __global__ __launch_bounds__(kWave) void k_res_fin(Launch<ResidualDesc> L) {
             const size_t e = ((size_t)(i - 1) * n + r) * m + q;
             const double v = i > 1 ? P.P[e] - P.Q[e] : P.P[e];
             if (P.R32) P.R32[e] = (float)v;
+            if (P.R64) P.R64[e] = P.neg ? -v : v;
             const double bv = P.B[e];
             r2 = fma(v, v, r2);
             b2 = fma(bv, bv, b2);
@@ -727,16 +782,40 @@ hipError_t launch_sweep_np(const Launch<SweepDesc<T>>& p, int64_t items, bool ba
     return hipGetLastError();
 }
 
+template <int NP, class T, int KW>
+hipError_t launch_chunk_kw(const Launch<SweepDesc<T>>& p, int64_t items, bool backward, int mc, hipStream_t st) {
+    const dim3 g((unsigned)items), b(KW * kWave);
+    if (mc <= 1) {
+        if (backward)
+            hipLaunchKernelGGL((k_sweep_chunk<NP, 1, T, KW, true>), g, b, 0, st, p);
+        else
+            hipLaunchKernelGGL((k_sweep_chunk<NP, 1, T, KW, false>), g, b, 0, st, p);
+    } else {
+        if (backward)
+            hipLaunchKernelGGL((k_sweep_chunk<NP, 4, T, KW, true>), g, b, 0, st, p);
+        else
+            hipLaunchKernelGGL((k_sweep_chunk<NP, 4, T, KW, false>), g, b, 0, st, p);
+    }
+    return hipGetLastError();
+}
+
+template <int NP, class T>
+hipError_t launch_chunk_np(const Launch<SweepDesc<T>>& p, int64_t items, bool backward, int mc, hipStream_t st,
+                           int kw) {
+    return kw == 8 ? launch_chunk_kw<NP, T, 8>(p, items, backward, mc, st)
+                   : launch_chunk_kw<NP, T, 4>(p, items, backward, mc, st);
+}
+
 template <class T>
 hipError_t launch_sweep_t(const Launch<SweepDesc<T>>& p, int np, int64_t items, bool backward, int mc,
-                          hipStream_t st) {
+                          hipStream_t st, bool chunk, int kw) {
     switch (np) {
         case 8:
-        case 16: return launch_sweep_np<16, T>(p, items, backward, mc, st);
-        case 32: return launch_sweep_np<32, T>(p, items, backward, mc, st);
-        case 64: return launch_sweep_np<64, T>(p, items, backward, mc, st);
-        case 96: return launch_sweep_np<96, T>(p, items, backward, mc, st);
-        case 128: return launch_sweep_np<128, T>(p, items, backward, mc, st);
+        case 16: return chunk ? launch_chunk_np<16, T>(p, items, backward, mc, st, kw) : launch_sweep_np<16, T>(p, items, backward, mc, st);
+        case 32: return chunk ? launch_chunk_np<32, T>(p, items, backward, mc, st, kw) : launch_sweep_np<32, T>(p, items, backward, mc, st);
+        case 64: return chunk ? launch_chunk_np<64, T>(p, items, backward, mc, st, kw) : launch_sweep_np<64, T>(p, items, backward, mc, st);
+        case 96: return chunk ? launch_chunk_np<96, T>(p, items, backward, mc, st, kw) : launch_sweep_np<96, T>(p, items, backward, mc, st);
+        case 128: return chunk ? launch_chunk_np<128, T>(p, items, backward, mc, st, kw) : launch_sweep_np<128, T>(p, items, backward, mc, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -757,13 +836,13 @@ hipError_t launch_res_np(const Launch<ResidualDesc>& p, int64_t items, int mc, h
 }  // namespace
 
 hipError_t launch_sweep(const Launch<SweepDesc<double>>& p, int np, int64_t items, bool backward, int mc,
-                        hipStream_t st) {
-    return launch_sweep_t<double>(p, np, items, backward, mc, st);
+                        hipStream_t st, bool chunk, int kw) {
+    return launch_sweep_t<double>(p, np, items, backward, mc, st, chunk, kw);
 }
 
 hipError_t launch_sweep(const Launch<SweepDesc<float>>& p, int np, int64_t items, bool backward, int mc,
-                        hipStream_t st) {
-    return launch_sweep_t<float>(p, np, items, backward, mc, st);
+                        hipStream_t st, bool chunk, int kw) {
+    return launch_sweep_t<float>(p, np, items, backward, mc, st, chunk, kw);
 }
 
 hipError_t launch_residual(const Launch<ResidualDesc>& p, int np, int64_t items, int mc, hipStream_t st) {

@@ -11,8 +11,12 @@
 //     columns per dependency chain group, 1 = one (bitwise identical results)
 #include <hip/hip_runtime.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 
 #include "btc.h"
@@ -24,8 +28,58 @@ namespace {
 
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, int> g_tune;
+// measured elimination orders: (precision, N, padded n) -> (strategy, stages)
+std::map<std::tuple<int, int64_t, int>, std::pair<int32_t, int32_t>> g_strategy;
+bool g_loaded = false;
+
+// The table file named by BTC_TUNE_CACHE: lines "v op kind np bucket
+// variant" and "s precision N np strategy stages".  Called with the lock
+// held.
+void load_cache_locked() {
+    if (g_loaded) return;
+    g_loaded = true;
+    const char* path = getenv("BTC_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char tag[4];
+    while (fscanf(f, "%3s", tag) == 1) {
+        if (tag[0] == 'v') {
+            int op, kind, np, bucket, variant;
+            if (fscanf(f, "%d %d %d %d %d", &op, &kind, &np, &bucket, &variant) != 5) break;
+            g_tune[std::make_tuple(op, kind, np, bucket)] = variant;
+        } else if (tag[0] == 's') {
+            int prec, np, strategy, stages;
+            long long N;
+            if (fscanf(f, "%d %lld %d %d %d", &prec, &N, &np, &strategy, &stages) != 5) break;
+            g_strategy[std::make_tuple(prec, (int64_t)N, np)] = {strategy, stages};
+        } else {
+            break;
+        }
+    }
+    fclose(f);
+}
 
 }  // namespace
+
+// Write the table to the BTC_TUNE_CACHE file (if set).
+void save_tune_cache() {
+    const char* path = getenv("BTC_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_locked();
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (auto& kv : g_tune)
+        fprintf(f, "v %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                std::get<3>(kv.first), kv.second);
+    for (auto& kv : g_strategy)
+        fprintf(f, "s %d %lld %d %d %d\n", std::get<0>(kv.first), (long long)std::get<1>(kv.first),
+                std::get<2>(kv.first), kv.second.first, kv.second.second);
+    fclose(f);
+    (void)rename(tmp.c_str(), path);
+}
 
 // Variant of a key nobody has set: measured on MI355X, the tile-parallel
 // step beats the one-workgroup-per-node kernel at padded size 64 (it needs
@@ -34,13 +88,43 @@ int default_variant(int op, int np) { return (op == BTC_OP_FACTOR && np == 64) ?
 
 int tune_variant(int op, int kind, int np, int bucket) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_locked();
     auto it = g_tune.find(std::make_tuple(op, kind, np, bucket));
     return it == g_tune.end() ? default_variant(op, np) : it->second;
 }
 
 void tune_set(int op, int kind, int np, int bucket, int variant) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_locked();
     g_tune[std::make_tuple(op, kind, np, bucket)] = variant;
+}
+
+void select_strategy(int64_t N, int64_t n, int32_t prec, int32_t* strategy, int32_t* stages) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_cache_locked();
+        auto it = g_strategy.find(std::make_tuple((int)prec, N, btc::padded_block((int)n)));
+        if (it != g_strategy.end()) {
+            *strategy = it->second.first;
+            *stages = it->second.second;
+            return;
+        }
+    }
+    // rule before any measurement: a short chain of small blocks is
+    // latency bound, and the sequential order needs one launch per phase
+    if (prec == BTC_FP64 && N <= 32 && n <= 16) {
+        *strategy = BTC_STRATEGY_KSTAGE;
+        *stages = 0;
+    } else {
+        *strategy = BTC_STRATEGY_MULTISTAGE;
+        *stages = 0;
+    }
+}
+
+void strategy_set(int64_t N, int64_t n, int32_t prec, int32_t strategy, int32_t stages) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_locked();
+    g_strategy[std::make_tuple((int)prec, N, btc::padded_block((int)n))] = {strategy, stages};
 }
 
 }  // namespace btc_host
@@ -68,6 +152,11 @@ bool tunable(int op, int32_t prec, int64_t n, int& kind, int& np, int& variants)
         variants = 2;
         return true;
     }
+    if (op == BTC_TUNE_SWEEP_SHAPE) {
+        kind = mixed ? 1 : 0;
+        variants = 3;
+        return true;
+    }
     return false;
 }
 
@@ -80,7 +169,7 @@ int bucket_of(int op, int level) { return (op == BTC_OP_FACTOR && level > 0) ? 1
 extern "C" {
 
 BTC_API int btc_tune_get(int32_t op, int32_t precision, int64_t n, int32_t level, int32_t* variant) {
-    if (op < BTC_OP_FACTOR || op > BTC_OP_REFINE_TEST) return -1;
+    if (op < BTC_OP_FACTOR || op > BTC_TUNE_SWEEP_SHAPE) return -1;
     if (precision != BTC_FP64 && !is_mixed(precision)) return -2;
     if (n < 1 || n > BTC_MAX_BLOCK) return -3;
     if (level < 0) return -4;
@@ -91,7 +180,7 @@ BTC_API int btc_tune_get(int32_t op, int32_t precision, int64_t n, int32_t level
 }
 
 BTC_API int btc_tune_set(int32_t op, int32_t precision, int64_t n, int32_t level, int32_t variant) {
-    if (op < BTC_OP_FACTOR || op > BTC_OP_REFINE_TEST) return -1;
+    if (op < BTC_OP_FACTOR || op > BTC_TUNE_SWEEP_SHAPE) return -1;
     if (precision != BTC_FP64 && !is_mixed(precision)) return -2;
     if (n < 1 || n > BTC_MAX_BLOCK) return -3;
     if (level < 0) return -4;
@@ -99,6 +188,7 @@ BTC_API int btc_tune_set(int32_t op, int32_t precision, int64_t n, int32_t level
     if (!tunable(op, precision, n, kind, np, nv)) return variant == 0 ? BTC_OK : BTC_ERR_UNSUPPORTED;
     if (variant < 0 || variant >= nv) return -5;
     tune_set(op, kind, np, bucket_of(op, level), variant);
+    save_tune_cache();
     return BTC_OK;
 }
 
@@ -136,6 +226,36 @@ BTC_API int btc_autotune(btc_handle h, const double* A_diag, const double* A_off
     }
     int rc = btc_refactor(h, A_diag, A_off, stream);
     if (rc != BTC_OK) return rc;
+    // sweep launch shape: the whole solve timed per shape (results identical)
+    {
+        tunable(BTC_TUNE_SWEEP_SHAPE, h->precision, h->n, kind, np, nv);
+        hipStream_t st = (hipStream_t)stream;
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            if (a) (void)hipEventDestroy(a);
+            return BTC_ERR_HIP;
+        }
+        double best = 1e300;
+        int pick = 0;
+        for (int v = 0; v < nv && rc == BTC_OK; ++v) {
+            tune_set(BTC_TUNE_SWEEP_SHAPE, kind, np, 0, v);
+            rc = btc_solve(h, B, X, nrhs, stream, nullptr);  // warm-up
+            float ms = 0.f;
+            if (rc == BTC_OK && hipEventRecord(a, st) != hipSuccess) rc = BTC_ERR_HIP;
+            for (int k = 0; k < reps && rc == BTC_OK; ++k) rc = btc_solve(h, B, X, nrhs, stream, nullptr);
+            if (rc == BTC_OK && (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, a, b) != hipSuccess))
+                rc = BTC_ERR_HIP;
+            if (rc == BTC_OK && ms < best) {
+                best = ms;
+                pick = v;
+            }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        tune_set(BTC_TUNE_SWEEP_SHAPE, kind, np, 0, pick);
+        if (rc != BTC_OK) return rc;
+    }
     // sweeps and residual: only with several right-hand sides
     if (nrhs > 1) {
         const int ops[3] = {BTC_OP_FORWARD, BTC_OP_BACKWARD, BTC_OP_RESIDUAL};
@@ -165,6 +285,75 @@ BTC_API int btc_autotune(btc_handle h, const double* A_diag, const double* A_off
             tune_set(ops[k], kind, np, 0, v);
         }
     }
+    save_tune_cache();
+    return BTC_OK;
+}
+
+BTC_API int btc_autotune_strategy(int64_t N, int64_t n, int32_t precision, const double* A_diag,
+                                  const double* A_off, const double* B, double* X, int64_t nrhs, int32_t reps,
+                                  void* stream, double* ms) {
+    if (N < 1) return -1;
+    if (n < 1 || n > BTC_MAX_BLOCK) return -2;
+    if (precision != BTC_FP64 && !is_mixed(precision)) return -3;
+    if (!A_diag || (N > 1 && !A_off)) return -4;
+    if (!B || !X || B == X) return -6;
+    if (nrhs < 1) return -8;
+    if (reps < 1) return -9;
+    hipStream_t st = (hipStream_t)stream;
+    // candidates: multi-stage, then k-stage with k = 0, 1, 2
+    double t[4] = {-1.0, -1.0, -1.0, -1.0};
+    int best = -1;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        return BTC_ERR_HIP;
+    }
+    int rc = BTC_OK;
+    for (int c = 0; c < 4 && rc == BTC_OK; ++c) {
+        btc_options o{};
+        o.precision = precision;
+        o.strategy = c == 0 ? BTC_STRATEGY_MULTISTAGE : BTC_STRATEGY_KSTAGE;
+        o.stages = c == 0 ? 0 : c - 1;
+        if (c > 0 && (precision != BTC_FP64 || n > 64 || c - 1 >= num_levels(N))) continue;
+        btc_handle h = nullptr;
+        rc = btc_create(N, n, &o, &h);
+        if (rc != BTC_OK) break;
+        rc = btc_refactor(h, A_diag, A_off, stream);  // warm-up
+        if (rc == BTC_OK) rc = btc_solve(h, B, X, nrhs, stream, nullptr);
+        if (rc == BTC_OK && hipEventRecord(a, st) != hipSuccess) rc = BTC_ERR_HIP;
+        for (int k = 0; k < reps && rc == BTC_OK; ++k) {
+            rc = btc_refactor(h, A_diag, A_off, stream);
+            if (rc == BTC_OK) rc = btc_solve(h, B, X, nrhs, stream, nullptr);
+        }
+        float ms1 = 0.f;
+        if (rc == BTC_OK && (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                             hipEventElapsedTime(&ms1, a, b) != hipSuccess))
+            rc = BTC_ERR_HIP;
+        int64_t info = 0;
+        if (rc == BTC_OK) rc = btc_status(h, &info);
+        btc_destroy(h);
+        if (rc == BTC_OK && info != 0) rc = BTC_ERR_NOT_SPD;
+        if (rc != BTC_OK) break;
+        t[c] = (double)ms1 / reps;
+        if (best < 0 || t[c] < t[best]) best = c;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc != BTC_OK) return rc;
+    strategy_set(N, n, precision, best == 0 ? BTC_STRATEGY_MULTISTAGE : BTC_STRATEGY_KSTAGE, best <= 0 ? 0 : best - 1);
+    save_tune_cache();
+    if (ms)
+        for (int c = 0; c < 4; ++c) ms[c] = t[c];
+    return BTC_OK;
+}
+
+BTC_API int btc_select_strategy(int64_t N, int64_t n, int32_t precision, int32_t* strategy, int32_t* stages) {
+    if (N < 1) return -1;
+    if (n < 1 || n > BTC_MAX_BLOCK) return -2;
+    if (precision != BTC_FP64 && !is_mixed(precision)) return -3;
+    if (!strategy || !stages) return -4;
+    select_strategy(N, n, precision, strategy, stages);
+    if (*strategy == BTC_STRATEGY_KSTAGE && *stages >= num_levels(N)) *strategy = BTC_STRATEGY_MULTISTAGE;
     return BTC_OK;
 }
 

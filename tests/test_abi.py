@@ -201,3 +201,46 @@ def test_bf16_footprint_matches_mixed(lib):
     for n in (8, 40, 100):
         assert lib.btc_footprint_bytes(33, n, lib.BTC_BF16_IR, 2) == lib.btc_footprint_bytes(33, n, lib.BTC_FP32_IR, 2)
     assert lib.btc_footprint_bytes(33, 8, 3, 2) == 0
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 16, 64, 100, 1000, 4096, 16384, 70000])
+def test_sweep_ranges(lib, N):
+    """Sweep level ranges: contiguous from level 0 to floor(log2 N)+1; levels
+    with many nodes alone; in a multi-level range every level of a subtree
+    has at most as many nodes as the workgroup has wavefronts (4), so the
+    range takes one round of node steps per level."""
+    b = lib.btc_sweep_ranges(N)
+    L = int(np.floor(np.log2(N))) + 1
+    assert b[0] == 0 and b[-1] == L and all(x < y for x, y in zip(b, b[1:]))
+    nodes = lambda l: (N + (1 << l)) // (2 << l)
+    for l0, l1 in zip(b, b[1:]):
+        if nodes(l0) >= 4096:
+            assert l1 == l0 + 1
+        if l1 > l0 + 1:
+            assert all(min(1 << (l1 - l - 1), nodes(l)) <= 4 for l in range(l0, l1))
+
+
+def test_tune_cache_persists_across_processes(lib, tmp_path):
+    """BTC_TUNE_CACHE: a variant set in one process is read back by the next
+    (host state only); the sweep launch shape is a tune key with three
+    variants."""
+    import subprocess
+    import sys
+    cache = str(tmp_path / "tune.txt")
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2601_03754_amd import btc\n"
+            "S = btc.lib() and 6\n"
+            "if sys.argv[1] == 'set':\n"
+            "    btc.btc_tune_set(S, 1, 90, 0, 2)\n"
+            "    btc.btc_tune_set(0, 0, 24, 3, 1)\n"
+            "else:\n"
+            "    print(btc.btc_tune_get(S, 1, 96, 0), btc.btc_tune_get(0, 0, 20, 1), btc.btc_tune_get(S, 0, 96, 0))\n"
+            % ROOT)
+    env = dict(os.environ, BTC_TUNE_CACHE=cache)
+    subprocess.run([sys.executable, "-c", code, "set"], env=env, check=True)
+    assert os.path.exists(cache)
+    out = subprocess.run([sys.executable, "-c", code, "get"], env=env, check=True, capture_output=True,
+                         text=True).stdout.split()
+    assert out == ["2", "1", "0"]
+    with pytest.raises(lib.BtcError):
+        lib.btc_tune_set(6, 0, 40, 0, 3)

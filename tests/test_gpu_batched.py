@@ -127,3 +127,59 @@ def test_batch_shapes_of_many_instance_workload(btc):
         assert oracle.relres(p.D, p.E, Xs[k].cpu().numpy(), p.B) <= 1e-10
         btc.btc_destroy(hs[k])
     r.close()
+
+
+@pytest.mark.parametrize("precision,N,n,m", [(0, 300, 24, 2), (1, 300, 24, 2), (0, 1, 8, 1), (1, 37, 96, 1),
+                                             (0, 4096, 16, 1), (1, 1000, 40, 3)])
+def test_level_ranges_equal_single_levels(btc, precision, N, n, m):
+    """A sweep run one level per step and the same sweep in the library's
+    level ranges (one launch per range of elimination subtrees) do the same
+    arithmetic per node: identical results, bit for bit."""
+    pr = inputs.block_tridiag(N, n, seed=N + n + m, nrhs=m)
+    D, E, B = dev(pr.D), dev(pr.E), dev(pr.B)
+    f = btc.Factor(D, E, precision=precision)
+    Xr = f.solve(B)                     # level ranges
+    torch.cuda.synchronize()
+    r = btc.Runner()
+    X1 = torch.full_like(B, float("nan"))
+    L = int(np.floor(np.log2(N))) + 1
+    S = btc.step
+    if precision == 0:
+        plan = [[S(f.handle, btc.BTC_OP_FORWARD, l, B=B, X=X1, nrhs=m)] for l in range(L)]
+        plan += [[S(f.handle, btc.BTC_OP_BACKWARD, l, B=B, X=X1, nrhs=m)] for l in reversed(range(L))]
+    else:
+        plan = [[S(f.handle, btc.BTC_OP_REFINE_INIT, 0, B=B, X=X1, nrhs=m)]]
+        for rnd in range(1 + 4):
+            plan += [[S(f.handle, btc.BTC_OP_FORWARD, l, B=B, X=X1, nrhs=m, first=rnd == 0)] for l in range(L)]
+            plan += [[S(f.handle, btc.BTC_OP_BACKWARD, l, B=B, X=X1, nrhs=m, first=rnd == 0)]
+                     for l in reversed(range(L))]
+            plan += [[S(f.handle, btc.BTC_OP_RESIDUAL, 0, B=B, X=X1, nrhs=m),
+                      S(f.handle, btc.BTC_OP_REFINE_TEST, 0, B=B, X=X1, nrhs=m)]]
+    for call in plan:
+        r.run(call)
+    r.sync()
+    assert np.array_equal(X1.cpu().numpy(), Xr.cpu().numpy())
+    # and a whole refinement round in one call, stage by stage
+    if precision == 1:
+        b = btc.btc_sweep_ranges(N)
+        X2 = torch.full_like(B, float("nan"))
+        for rnd in range(1 + 4):
+            call = [] if rnd else [S(f.handle, btc.BTC_OP_REFINE_INIT, 0, B=B, X=X2, nrhs=m, stage=0)]
+            st = 1
+            for q in range(len(b) - 1):
+                call.append(S(f.handle, btc.BTC_OP_FORWARD, b[q], B=B, X=X2, nrhs=m, first=rnd == 0,
+                              level_end=b[q + 1] if b[q + 1] > b[q] + 1 else 0, stage=st))
+                st += 1
+            for q in reversed(range(len(b) - 1)):
+                call.append(S(f.handle, btc.BTC_OP_BACKWARD, b[q], B=B, X=X2, nrhs=m, first=rnd == 0,
+                              level_end=b[q + 1] if b[q + 1] > b[q] + 1 else 0, stage=min(st, 7)))
+                st += 1
+            if st > 7:
+                pytest.skip("more ranges than stages")
+            call.append(S(f.handle, btc.BTC_OP_RESIDUAL, 0, B=B, X=X2, nrhs=m, stage=st))
+            call.append(S(f.handle, btc.BTC_OP_REFINE_TEST, 0, B=B, X=X2, nrhs=m, stage=st))
+            r.run(call)
+        r.sync()
+        assert np.array_equal(X2.cpu().numpy(), Xr.cpu().numpy())
+    r.close()
+    f.close()

@@ -88,3 +88,21 @@ def test_bf16_batched_equals_single(btc):
         assert oracle.relres(p.D, p.E, Xs1, p.B) <= TOL
         btc.btc_destroy(hs[k])
     r.close()
+
+
+@pytest.mark.parametrize("c", [4.0, 0.001])
+@pytest.mark.parametrize("m", [1, 3])
+def test_gmres_refinement_small(btc, c, m):
+    """GMRES-based refinement on a small ill-conditioned instance: target met
+    in a few corrections; each right-hand side is its own problem (the same
+    result column by column as solved alone)."""
+    p = inputs.block_tridiag(128, 32, c=c, seed=11, nrhs=m, margin=True)
+    f = btc.Factor(dev(p.D), dev(p.E), precision=btc.BTC_BF16_IR, refine=btc.BTC_REFINE_GMRES)
+    X, info = f.solve(dev(p.B), want_info=True)
+    X = X.cpu().numpy()
+    assert info["converged"] and info["steps"] <= 3 and info["inner"] >= 1, info
+    assert oracle.relres(p.D, p.E, X, p.B) <= TOL
+    if m > 1:
+        X0, _ = f.solve(dev(np.ascontiguousarray(p.B[:, :, :1])), want_info=True)
+        assert oracle.relres(p.D, p.E, X0.cpu().numpy(), p.B[:, :, :1]) <= TOL
+    f.close()

@@ -204,3 +204,30 @@ def test_fp64_largest_sweep_point(btc):
                 assert np.abs(Rb[i - 1] - R).max() <= 1e-12 * max(1.0, np.abs(R).max()), (l, i)
             if T is not None:
                 assert np.abs(Tb[i - 1] - T).max() <= 1e-12 * max(1.0, np.abs(T).max()), (l, i)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("c", [4.0, 0.001])
+def test_conditioning_sweep_gmres_refinement(btc, sweep_problems, c, prec):
+    """GMRES-based refinement (the low-precision factor as preconditioner of
+    FP64 GMRES on the correction equation) at the full size: converges to
+    the target at every margin, also with BF16 products at kappa ~ 1e4, in
+    few corrections."""
+    lam0, probs = sweep_problems
+    pr, Xo = probs[c]
+    precision = btc.BTC_FP32_IR if prec == "fp32" else btc.BTC_BF16_IR
+    f = btc.Factor(dev(pr.D), dev(pr.E), precision=precision, refine=btc.BTC_REFINE_GMRES)
+    X, info = f.solve(dev(pr.B), want_info=True)
+    f.close()
+    X = X.cpu().numpy()
+    rr = oracle.relres(pr.D, pr.E, X, pr.B)
+    fwd = colwise_rel(X, Xo)
+    kappa = lambda_max_bound(pr) / c
+    record(test="conditioning_sweep_gmres", N=pr.N, n=pr.n, nrhs=pr.nrhs, c=c, precision=prec,
+           steps=info["steps"], inner=info["inner"], converged=info["converged"], relres_device=info["relres"],
+           relres_oracle=rr, forward_error=fwd, kappa_bound=kappa)
+    assert info["converged"], info
+    assert rr <= TOL
+    assert abs(info["relres"] - rr) <= 1e-3 * rr + 1e-16
+    assert fwd <= 2.0 * kappa * (rr + 1e-15)
+    assert info["steps"] <= 3

@@ -34,13 +34,13 @@ def alone(btc, D, E, B, precision):
 
 
 def run_trace(btc, precision, budget, seed=0, clients=6, requests=40, n_choices=(5, 12, 16, 24, 40, 64),
-              N_max=300):
+              N_max=300, sweep_ranges=False):
     rng = np.random.default_rng(seed)
     shapes = [(int(rng.integers(16, N_max)), int(rng.choice(n_choices))) for _ in range(clients)]
     mats = [[inputs.block_tridiag(N, n, seed=seed * 100 + c * 10 + v) for v in range(2)]
             for c, (N, n) in enumerate(shapes)]
     dmats = [[(dev(p.D), dev(p.E)) for p in ms] for ms in mats]
-    srv = btc.Server(precision=precision, hbm_budget=budget)
+    srv = btc.Server(precision=precision, hbm_budget=budget, sweep_ranges=sweep_ranges)
     ids = [srv.add_client(N, n) for N, n in shapes]
     current = [None] * clients
     subs = []
@@ -69,10 +69,15 @@ def run_trace(btc, precision, budget, seed=0, clients=6, requests=40, n_choices=
 BIG_BLOCKS = (12, 33, 64, 80, 96, 110, 128)
 
 
-@pytest.mark.parametrize("precision,n_choices", [(0, None), (1, None), (0, BIG_BLOCKS), (1, BIG_BLOCKS),
-                                                 (2, BIG_BLOCKS)])
-def test_results_in_the_mix_equal_results_alone(btc, precision, n_choices):
+@pytest.mark.parametrize("precision,n_choices,ranges", [(0, None, False), (1, None, False), (0, BIG_BLOCKS, False),
+                                                        (1, BIG_BLOCKS, False), (2, BIG_BLOCKS, False),
+                                                        (0, None, True), (1, BIG_BLOCKS, True),
+                                                        (2, BIG_BLOCKS, True)])
+def test_results_in_the_mix_equal_results_alone(btc, precision, n_choices, ranges):
+    """Every result equals the same request alone, bit for bit, in both
+    server plans (one tick per sweep level range, or per level)."""
     kw = {} if n_choices is None else {"n_choices": n_choices, "N_max": 140, "requests": 30}
+    kw["sweep_ranges"] = ranges
     srv, subs, done, mats, dmats, stats = run_trace(btc, precision, budget=1 << 40, seed=11 + precision, **kw)
     assert len(done) == len(subs)
     assert stats["queued"] == 0 and stats["in_flight"] == 0

@@ -154,3 +154,37 @@ def test_autotune_keeps_results_correct(btc, precision):
     btc.btc_destroy(h)
     X2, _ = run(btc, p, precision)
     assert oracle.relres(p.D, p.E, X2, p.B) <= (1e-12 if precision == 0 else 1e-10)
+
+
+@pytest.mark.parametrize("precision,N,n", [(0, 4096, 24), (1, 1500, 40), (1, 300, 96), (0, 77, 128)])
+def test_sweep_shapes_identical(btc, precision, N, n):
+    """The sweep launch shapes (level ranges with 4- or 8-wavefront
+    workgroups, one launch per level) do the same arithmetic per node:
+    identical solutions, single handle and batched."""
+    from paper_2601_03754_amd import inputs
+    pr = inputs.block_tridiag(N, n, seed=N + n, nrhs=2)
+    D, E, B = dev(pr.D), dev(pr.E), dev(pr.B)
+    S = 6  # BTC_TUNE_SWEEP_SHAPE
+    old = btc.btc_tune_get(S, precision, n, 0)
+    outs = []
+    try:
+        for v in (0, 1, 2):
+            btc.btc_tune_set(S, precision, n, 0, v)
+            f = btc.Factor(D, E, precision=precision)
+            outs.append(f.solve(B).cpu().numpy())
+            r = btc.Runner()
+            h = btc.btc_create(N, n, precision)
+            X = torch.empty_like(B)
+            r.factor_batched([h], [D], [E])
+            r.solve_batched([h], [B], [X])
+            r.sync()
+            outs.append(X.cpu().numpy())
+            btc.btc_destroy(h)
+            r.close()
+            f.close()
+    finally:
+        btc.btc_tune_set(S, precision, n, 0, old)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    tol = 1e-12 if precision == 0 else 1e-10
+    assert oracle.relres(pr.D, pr.E, outs[0], pr.B) <= tol
