@@ -10,9 +10,9 @@ Every request is either a solve against the client's resident factor with a
 new right-hand side (70%) or a refactorization with new matrix values
 followed by a solve (30%).  The headline runs the server closed-loop at
 saturation: every client always has one request outstanding and submits its
-next one as soon as the previous one completes.  A step is 256 completed
-requests (one per client on average); W untimed steps, then K timed steps
-bracketed by device synchronisation.  The mixed-precision path (FP32 factor
+next one as soon as the previous one completes.  A step is 4096 completed
+requests (16 per client on average; --step-requests); W untimed steps, then K
+timed steps bracketed by device synchronisation.  The mixed-precision path (FP32 factor
 and sweeps, FP64 Schur complements, pivot factorizations, residual and
 iterative refinement to a 1e-10 relative residual) is the headline; the plain
 FP64 path runs the same trace beside it.  Latency (p50/p99) is measured per
@@ -28,9 +28,16 @@ library records on the stream each launch runs on (independent groups of one
 server step run concurrently on up to four streams, so a timed launch may
 share the GPU); its algorithmic bytes/flops per launch come from
 btc_level_work.  "roofline_aggregate" divides the algorithmic bytes and flops
-of every kernel of the timed region by its wall time.  The CPU baseline is
-the FP64 oracle (plain C, one thread) on a bounded sample of the same
-requests.  Prints ONE JSON line.
+of every kernel of the timed region by its wall time.  Every completed
+request reports its outcome (factor status, converged flag, the FP64
+residual of its last convergence test): the line counts them ("verified")
+and splits latency by request class ("per_class").  The CPU baseline is
+Algorithm 1 of the oracle (plain C, FP64) on every host core over a bounded
+sample of the same requests, with the single-threaded nested-dissection
+oracle beside it.  "configs" holds the other benchmark configurations: the
+FP64 sweep table (N x n: time, GFLOP/s, GB/s, roofline fractions), the
+many-instance batch (instances/s, with and without autotuning) and the
+latency of every elimination order at N = 16, n = 8.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -89,7 +96,7 @@ def roofline_entry(stat):
     t_hbm = bpl / (HBM_PEAK_GBS * 1e9)
     # FP32 peak for the FP32 kernel families (mixed factor: its products run on
     # FP32 matrix cores; FP32 sweeps), FP64 peak otherwise
-    fp32 = (stat["op"] == 0 and stat["kind"] in (2, 4)) or (stat["op"] in (1, 2) and stat["kind"] == 1)
+    fp32 = (stat["op"] == 0 and stat["kind"] in (2, 4)) or (stat["op"] in (1, 2) and stat["kind"] in (1, 3))
     fpeak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
     t_alu = fpl / (fpeak * 1e12)
     if t_hbm >= t_alu:
@@ -103,7 +110,8 @@ def roofline_entry(stat):
     r["algorithmic_bytes_per_launch"] = bpl
     r["algorithmic_flops_per_launch"] = fpl
     kind = FACTOR_KIND.get(stat["kind"], str(stat["kind"])) if stat["op"] == 0 else \
-        ("fp32" if stat["kind"] == 1 else "fp64") if stat["op"] in (1, 2) else "fp64"
+        ("fp32" if stat["kind"] & 1 else "fp64") + (" ranges" if stat["kind"] >= 2 else "") \
+        if stat["op"] in (1, 2) else "fp64"
     r["kernel"] = "%s %s np=%d" % (OPS[stat["op"]], kind, stat["np"])
     if stat.get("part"):
         r["kernel"] += " " + TILED_PART[stat["part"]]
@@ -139,10 +147,10 @@ class Served:
     """One server (one precision) over the clients, with the bookkeeping of
     the requests a run submits."""
 
-    def __init__(self, btc, clients, precision, seed):
+    def __init__(self, btc, clients, precision, seed, sweep_ranges=False, hbm_budget=1 << 46):
         self.btc = btc
         self.cl = clients
-        self.srv = btc.Server(precision=precision, hbm_budget=1 << 46)
+        self.srv = btc.Server(precision=precision, hbm_budget=hbm_budget, sweep_ranges=sweep_ranges)
         self.ids = [self.srv.add_client(N, n) for N, n in clients.shapes]
         self.rng = np.random.default_rng(seed)
         self.ver = [0] * len(self.ids)
@@ -240,12 +248,12 @@ def run_served(args, btc):
     shapes = inputs.served_clients(args.clients, seed=0)
     log("generating inputs of %d clients on the device" % len(shapes))
     cl = Clients(shapes)
-    per_step = len(shapes)
+    per_step = args.step_requests
     paths = {}
     rates_out = []
     roof = None
     for name, prec in (("mixed", btc.BTC_FP32_IR), ("fp64", btc.BTC_FP64)):
-        sv = Served(btc, cl, prec, seed=1)
+        sv = Served(btc, cl, prec, seed=1, sweep_ranges=args.sweep_ranges)
         rh = sv.srv.runner_handle()
         # warm-up: first requests factor every client; profile every group
         btc.runner_profile(rh, -1, -1)
@@ -262,9 +270,25 @@ def run_served(args, btc):
         lat = lat_ms(done)
         loop = dict(sv.last_loop)
         relres = sv.verify()
+        # every completion carries the outcome of its request: the factor's
+        # status, and for the mixed path the converged flag and the FP64
+        # residual its last convergence test measured
+        conv = sum(1 for d in done if d["converged"] and d["info"] == 0)
+        dev_rr = [d["relres"] for d in done if d["relres"] >= 0]
+        per_class = {}
+        for cls, sel in (("solve", False), ("refactor_solve", True)):
+            dd = [d for d in done if bool(d["refactored"]) == sel]
+            lc = lat_ms(dd)
+            per_class[cls] = {"requests": len(dd), "share": len(dd) / max(1, len(done)),
+                              "p50_ms": pct(lc, 50), "p99_ms": pct(lc, 99),
+                              "steps_max": max([d["steps"] for d in dd], default=0)}
         ent = {"value": len(done) / wall, "ms_per_step": wall * 1e3 / args.steps,
-               "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "requests": len(done),
+               "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "requests": len(done), "wall_s": wall,
                "refactor_share": float(np.mean([d["refactored"] for d in done])),
+               "verified": {"requests": len(done), "converged": conv,
+                            "relres_max_device": max(dev_rr) if dev_rr else None,
+                            "relres_max_last_torch": relres},
+               "per_class": per_class,
                "server_ticks": loop["ticks"], "host_step_frac": loop["host_step_s"] / loop["wall_s"],
                "max_relres_last": relres,
                "warmup_kernel_ms": [{"kernel": roofline_entry(s)["kernel"], "ms": round(s["ms"], 3),
@@ -322,6 +346,155 @@ def cpu_baseline_served(shapes, budget_s, wall_cap_s=90.0):
         served += 1
         used.append((N, n, bool(refactor)))
     return served / t_work, served, t_work, used
+
+
+def cpu_baseline_alg1(shapes, budget_s, max_clients=48):
+    """The natural-order Algorithm 1 of the oracle (plain C, FP64) on every
+    host core over requests of the same mix: the first clients' systems
+    (inputs drawn beforehand, not timed), one request each (30% refactor +
+    solve, 70% solve against a factor computed beforehand), spread over
+    os.cpu_count() threads (the oracle releases the interpreter lock);
+    requests per wall second.  Stops early once `budget_s` of wall time is
+    spent."""
+    import os
+    import threading
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2601_03754_amd import inputs
+    oracle.build()
+    rng = np.random.default_rng(5)
+    cores = os.cpu_count() or 1
+    reqs = []
+    t_gen = time.perf_counter()
+    for c, (N, n) in enumerate(shapes[:max_clients]):
+        pr = inputs.block_tridiag(N, n, c=4.0, seed=c, nrhs=1)
+        refactor = rng.random() >= SOLVE_FRAC
+        fac = None if refactor else oracle.factor_seq(pr.D, pr.E)
+        reqs.append((pr, refactor, fac))
+        if time.perf_counter() - t_gen > 60.0:
+            break
+    lock = threading.Lock()
+    done = [0]
+    t0 = time.perf_counter()
+    stop = t0 + budget_s
+
+    def work(k):
+        if time.perf_counter() > stop:
+            return
+        pr, refactor, fac = reqs[k]
+        Dh, Eh, info = oracle.factor_seq(pr.D, pr.E) if refactor else fac
+        oracle.solve_seq(Dh, Eh, pr.B)
+        with lock:
+            done[0] += 1
+
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(work, range(len(reqs))))
+    wall = time.perf_counter() - t0
+    return done[0] / wall, done[0], wall, cores
+
+
+# ---------------------------------------------------------------------------
+# benchmark configurations beside the served headline
+
+def sweep_table(btc, Ns=(64, 256, 1024, 4096, 16384), ns=(16, 32, 64, 128), reps=5):
+    """FP64 single instance, refactor + solve per call, every (N, n) of the
+    sweep: time per call (median over reps, HIP events), GFLOP/s of the
+    method's work and algorithmic GB/s (btc_level_work), fraction of the
+    FP64 and HBM peaks."""
+    import torch
+    from paper_2601_03754_amd import inputs
+    rows = []
+    for N in Ns:
+        for n in ns:
+            D, E, B = inputs.block_tridiag_device(N, n, 4.0, seed=inputs.sweep_seed(N, n), nrhs=1)
+            X = torch.empty_like(B)
+            f = btc.Factor(D, E)
+            f.solve(B, X)
+            L = int(math.floor(math.log2(N))) + 1
+            by = fl = 0.0
+            for op in (btc.BTC_OP_FACTOR, btc.BTC_OP_FORWARD, btc.BTC_OP_BACKWARD):
+                for l in range(L):
+                    b_, f_ = btc.btc_level_work(op, 0, N, n, 1, l)
+                    by += b_
+                    fl += f_
+            ts = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                f.refactor(D, E)
+                f.solve(B, X)
+                b.record()
+                b.synchronize()
+                ts.append(a.elapsed_time(b))
+            rr = relres_torch(D, E, X, B)
+            f.close()
+            ms = float(np.median(ts))
+            rows.append({"N": N, "n": n, "ms": round(ms, 4), "gflops": round(fl / (ms * 1e-3) / 1e9, 1),
+                         "gbs": round(by / (ms * 1e-3) / 1e9, 1),
+                         "fp64_frac": round(fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+                         "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "relres": rr})
+            del D, E, B, X
+            torch.cuda.empty_cache()
+    return rows
+
+
+def batch_rate(btc, count=512, reps=3, tune=False):
+    """The many-instance batch: 512 instances (N ~ U{32..2048}, n ~ U{8, 16,
+    24, 32, 48}), FP32 factors with FP64 refinement, batched factor + solve
+    through one runner (one launch group per level or level range);
+    instances per second (median over reps), every result verified."""
+    import torch
+    from paper_2601_03754_amd import inputs
+    shapes = inputs.batch_shapes(count, seed=0)
+    mats = [inputs.block_tridiag_device(N, n, 4.0, seed=k, nrhs=1) for k, (N, n) in enumerate(shapes)]
+    if tune:
+        # the autotuner on one instance of every block size of the batch
+        # (variants are keyed by padded block size)
+        seen = set()
+        for k, (N, n) in enumerate(shapes):
+            if n in seen:
+                continue
+            seen.add(n)
+            D, E, B = mats[k]
+            h = btc.btc_create(N, n, btc.BTC_FP32_IR)
+            btc.btc_refactor(h, D, E)
+            btc.btc_autotune(h, D, E, B, torch.empty_like(B), reps=3)
+            btc.btc_destroy(h)
+    r = btc.Runner()
+    hs = [btc.btc_create(N, n, btc.BTC_FP32_IR) for N, n in shapes]
+    Xs = [torch.empty_like(m[2]) for m in mats]
+    ts = []
+    for rep in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r.factor_batched(hs, [m[0] for m in mats], [m[1] for m in mats])
+        r.solve_batched(hs, [m[2] for m in mats], Xs, 1)
+        r.sync()
+        if rep:
+            ts.append(time.perf_counter() - t0)
+    info = r.solve_batched(hs, [m[2] for m in mats], Xs, 1, want_info=True)
+    worst = max(relres_torch(m[0], m[1], X, m[2]) for m, X in zip(mats, Xs))
+    for h in hs:
+        btc.btc_destroy(h)
+    r.close()
+    t = float(np.median(ts))
+    return {"instances": count, "seconds": t, "instances_per_s": count / t,
+            "converged": sum(1 for i in info if i["converged"]), "relres_max": worst}
+
+
+def latency_strategies(btc, N=16, n=8, reps=200):
+    """The smallest configuration (N = 16, n = 8, FP64): milliseconds per
+    refactor + solve of every elimination order, and the one the AUTO
+    strategy then takes."""
+    import torch
+    from paper_2601_03754_amd import inputs
+    D, E, B = inputs.block_tridiag_device(N, n, 4.0, seed=0, nrhs=1)
+    X = torch.empty_like(B)
+    ms = btc.btc_autotune_strategy(D, E, B, X, reps=reps)
+    pick = btc.btc_select_strategy(N, n)
+    names = ["multistage", "sequential (k=0)", "single-stage (k=1)", "two-stage (k=2)"]
+    return {"N": N, "n": n, "us_per_factor_solve": {names[k]: round(ms[k] * 1e3, 2) for k in range(4) if ms[k] > 0},
+            "auto_pick": names[0] if pick[0] == btc.BTC_STRATEGY_MULTISTAGE else names[1 + pick[1]]}
 
 
 # ---------------------------------------------------------------------------
@@ -389,13 +562,19 @@ def main():
     ap.add_argument("--rates", default="1000,10000,50000",
                     help="open-loop Poisson arrival rates (req/s), comma separated; empty: none")
     ap.add_argument("--rate-seconds", type=float, default=1.0)
-    ap.add_argument("--rate-requests", type=int, default=12000)
+    ap.add_argument("--rate-requests", type=int, default=50000)
     ap.add_argument("--N", type=int, default=4096)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_ir"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--step-requests", type=int, default=4096,
+                    help="served workload: requests per step (16 per client by default)")
+    ap.add_argument("--sweep-ranges", action="store_true",
+                    help="served workload: one server tick per sweep level range instead of per level")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other configurations (sweep table, batch, latency per strategy)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every instance is factored and solved on a single device; "
@@ -460,13 +639,26 @@ def main():
 
     shapes, paths, rates = run_served(args, btc)
     mixed, fp64 = paths["mixed"], paths["fp64"]
+    extras = None
+    if not args.no_extras:
+        log("other configurations: sweep table, batch, latency per strategy")
+        extras = {"sweep_fp64": sweep_table(btc),
+                  "batch": batch_rate(btc),
+                  "batch_autotuned": batch_rate(btc, tune=True),
+                  "latency_n16_n8": latency_strategies(btc)}
+        log("batch: %.0f instances/s, autotuned %.0f" % (extras["batch"]["instances_per_s"],
+                                                         extras["batch_autotuned"]["instances_per_s"]))
     cpu = None
     if not args.no_cpu_baseline:
-        rate, cnt, el, used = cpu_baseline_served(shapes, args.cpu_budget)
-        cpu = {"value": rate, "unit": "req/s", "cores": 1, "kind": "oracle",
-               "sample": "the first %d clients' systems (same shapes and mix; seeded host draws), one request "
-                         "each, FP64 oracle single-threaded, %.1f s of oracle time; solve-only requests count "
-                         "only the solve" % (cnt, el)}
+        rate, cnt, el, cores = cpu_baseline_alg1(shapes, args.cpu_budget)
+        r1, cnt1, el1, _ = cpu_baseline_served(shapes, args.cpu_budget / 3, wall_cap_s=30.0)
+        cpu = {"value": rate, "unit": "req/s", "cores": cores, "kind": "oracle",
+               "sample": "Algorithm 1 (natural-order block Cholesky, plain C, FP64) over %d requests of the "
+                         "same mix (the first clients' systems, seeded host draws; 30%% refactor + solve, 70%% "
+                         "solve against a factor computed beforehand), on all %d host threads, %.1f s wall"
+                         % (cnt, cores, el),
+               "nd_single_core": {"value": r1, "unit": "req/s", "cores": 1,
+                                  "sample": "nested-dissection oracle, one thread, %d requests, %.1f s" % (cnt1, el1)}}
     line = {
         "metric": METRIC,
         "value": mixed["value"],
@@ -483,8 +675,9 @@ def main():
         "config": {"workload": "served: 256 clients, N log-uniform [64, 4096], n uniform {12..96}, nrhs 1, "
                                "70% solve on the resident factor / 30% refactor+solve, closed loop at "
                                "saturation; mixed precision with FP64 refinement to 1e-10",
-                   "clients": len(shapes), "step_requests": len(shapes), "diag_shift": 4.0,
-                   "relres_target": RELRES_TARGET},
+                   "clients": len(shapes), "step_requests": args.step_requests, "diag_shift": 4.0,
+                   "relres_target": RELRES_TARGET,
+                   "server_sweeps": "one tick per level range" if args.sweep_ranges else "one tick per level"},
         "p50_ms": mixed["p50_ms"],
         "p99_ms": mixed["p99_ms"],
         "max_relres_last": mixed["max_relres_last"],
@@ -495,6 +688,7 @@ def main():
         "roofline": mixed.get("roofline"),
         "roofline_aggregate": mixed.get("aggregate"),
         "cpu_baseline": cpu,
+        "configs": extras,
     }
     print(json.dumps(line))
 
