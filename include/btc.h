@@ -212,6 +212,25 @@ BTC_API int btc_solve(btc_handle h, const double *B, double *X, int64_t nrhs, vo
               btc_solve_info *info);
 
 /*
+ * btc_solve_noalloc -- btc_solve for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops or harnesses that must
+ * not call hipMalloc or a framework allocator): the same kernels and results
+ * as btc_solve, with the solve workspace in a fixed device array of the
+ * library (BTC_NOALLOC_MAX_BYTES, one per GPU the library runs on, held until
+ * the process ends) instead of allocated memory.  The workspace needs
+ * 40 N n nrhs + 16 N nrhs + 1024 bytes (FP64) or 36 N n nrhs + 16 N nrhs +
+ * 1024 (mixed precision), as btc_footprint_bytes counts it; larger requests
+ * return BTC_ERR_UNSUPPORTED without enqueuing anything.  The current device
+ * must be the handle's (-1 otherwise).  Every call on one GPU shares that
+ * array: calls whose work overlaps on one GPU (other streams, other handles)
+ * race and must be ordered by the caller.  Allocates nothing, also when info
+ * is given.
+ */
+#define BTC_NOALLOC_MAX_BYTES (64u << 20)
+BTC_API int btc_solve_noalloc(btc_handle h, const double *B, double *X, int64_t nrhs, void *stream,
+                              btc_solve_info *info);
+
+/*
  * btc_status -- synchronise with the handle's last stream and report the
  * numerical outcome of the last factorization: *info = 0 if every pivot block
  * was positive definite, otherwise the 1-based ORIGINAL index of the first
