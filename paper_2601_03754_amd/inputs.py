@@ -160,3 +160,74 @@ def block_tridiag_device(N: int, n: int, c: float = 4.0, seed: int = 0, nrhs: in
     E = torch.randn((max(N - 1, 0), n, n), generator=g, device=device, dtype=torch.float64) / math.sqrt(n)
     B = torch.randn((N, n, max(nrhs, 1)), generator=g, device=device, dtype=torch.float64)
     return D, E, B
+
+
+# ---------------------------------------------------------------------------
+# Block-banded and arrow structures (the method's extensions).
+
+@dataclass
+class BandedProblem:
+    A_band: np.ndarray  # (N, b+1, n, n): A_band[i, k] = block (i, i-k), k = 0 symmetric
+    B: np.ndarray       # (N, n, nrhs)
+    c: float            # lower bound of the smallest eigenvalue
+
+    @property
+    def b(self) -> int:
+        return self.A_band.shape[1] - 1
+
+
+def block_banded(N: int, n: int, b: int, c: float = 1.0, seed: int = 0, nrhs: int = 1) -> BandedProblem:
+    """Block-banded SPD matrix of block bandwidth b.  Recipe:
+        rng = default_rng(seed); G = rng.standard_normal((N, n, n))
+        O = rng.standard_normal((N, b, n, n)) / sqrt(n)   # A_band[i, k] = O[i, k-1], k >= 1
+        (blocks with i - k < 0 set to zero)
+        D_i = G_i G_i^T / n + (c + rho_i) I,  rho_i = sum of the spectral norms
+              of the off-diagonal blocks of block row i (both sides)
+        B = rng.standard_normal((N, n, nrhs))
+    By the block Gershgorin theorem every eigenvalue is at least c."""
+    if N < 1 or n < 1 or b < 1:
+        raise ValueError("N, n and b must be positive")
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((N, n, n))
+    O = rng.standard_normal((N, b, n, n)) / math.sqrt(n)
+    B = rng.standard_normal((N, n, nrhs))
+    for k in range(1, b + 1):
+        O[:min(k, N), k - 1] = 0.0
+    norms = np.linalg.norm(O, ord=2, axis=(2, 3))  # (N, b): ||block (i, i-k)||
+    rho = norms.sum(axis=1)
+    for k in range(1, min(b, N - 1) + 1):
+        # block (i, i-k) also sits in block row i-k (transposed)
+        rho[:N - k] += norms[k:, k - 1]
+    A = np.empty((N, b + 1, n, n))
+    A[:, 0] = np.matmul(G, G.transpose(0, 2, 1)) / n + (c + rho)[:, None, None] * np.eye(n)[None]
+    A[:, 1:] = O
+    return BandedProblem(A_band=A, B=B, c=float(c))
+
+
+@dataclass
+class ArrowProblem:
+    D: np.ndarray  # (N, n, n) diagonal blocks of Psi
+    E: np.ndarray  # (N-1, n, n) sub-diagonal blocks of Psi
+    F: np.ndarray  # (N*n, m) border: the rows of Psi, the columns of the tip
+    C: np.ndarray  # (m, m) tip, symmetric
+    B: np.ndarray  # (N*n + m, nrhs)
+    c: float       # lower bound of the smallest eigenvalue of the tip's Schur complement
+
+
+def arrow(N: int, n: int, m: int, c: float = 1.0, seed: int = 0, nrhs: int = 1) -> ArrowProblem:
+    """Arrow matrix [[Psi, F], [F^T, C]].  Recipe: Psi is block_banded(N, n,
+    1, c, seed) (smallest eigenvalue >= c); then with
+    rng = default_rng(seed + 1):
+        F = rng.standard_normal((N*n, m)) / sqrt(N*n)
+        H = rng.standard_normal((m, m));  C = H H^T / m + (c + ||F||_2^2 / c) I
+        B = rng.standard_normal((N*n + m, nrhs))
+    so that C - F^T Psi^{-1} F >= c I."""
+    t = block_banded(N, n, 1, c=c, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    K = N * n
+    F = rng.standard_normal((K, m)) / math.sqrt(K)
+    H = rng.standard_normal((m, m))
+    fn = float(np.linalg.norm(F, 2)) if m else 0.0
+    C = H @ H.T / max(m, 1) + (c + fn * fn / c) * np.eye(m)
+    B = rng.standard_normal((K + m, nrhs))
+    return ArrowProblem(D=t.A_band[:, 0].copy(), E=t.A_band[1:, 1].copy(), F=F, C=C, B=B, c=float(c))
