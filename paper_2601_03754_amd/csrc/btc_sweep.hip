@@ -272,6 +272,39 @@ __device__ __forceinline__ void run_slabs(const Plan<S>& pl, int n, int lane, T*
 }
 
 // ---------------------------------------------------------------------------
+// a minus the contributions left for node i of level lvl by its descendants:
+// u from node i - 2^l2 and v from node i + 2^l2 for every l2 < lvl,
+// subtracted in level order.  The loads go out in groups of eight before any
+// subtraction, so their latencies overlap (a top-level node pulls from up to
+// twice its level count of places); a contribution that does not exist reads
+// slot 0 and subtracts +0, which leaves every value unchanged bit for bit.
+template <class T>
+__device__ __forceinline__ T pull(const SweepDesc<T>& P, T a, int64_t i, int lvl, size_t off, size_t nm) {
+    const int64_t N = P.N;
+    for (int g = 0; g < lvl; g += 8) {
+        T cu[8], cv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int l2 = g + u;
+            const bool okl = l2 < lvl;
+            const int64_t s2 = (int64_t)1 << (okl ? l2 : 0);
+            const bool okr = okl && i + s2 <= N;
+            const size_t iu = okl ? (size_t)perm_pos(N, l2, i - s2) * nm + off : 0;
+            const size_t iv = okr ? (size_t)perm_pos(N, l2, i + s2) * nm + off : 0;
+            const T x = P.U[iu], y = P.V[iv];
+            cu[u] = okl ? x : T(0);
+            cv[u] = okr ? y : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a -= cu[u];
+            a -= cv[u];
+        }
+    }
+    return a;
+}
+
+// ---------------------------------------------------------------------------
 // Forward step of node kk of level lvl by one wavefront (buf: its slab buffer).
 template <int NP, int MC, class T>
 __device__ __forceinline__ void fwd_node(const SweepDesc<T>& P, int lvl, int64_t kk, T* __restrict__ buf) {
@@ -305,12 +338,7 @@ __device__ __forceinline__ void fwd_node(const SweepDesc<T>& P, int lvl, int64_t
                 if (r < n && q < m) {
                     const size_t bidx = ((size_t)(i - 1) * n + r) * m + q;
                     a = P.B64 ? (T)P.B64[bidx] : P.B[bidx];
-                    for (int l2 = 0; l2 < lvl; ++l2) {
-                        const int64_t s2 = (int64_t)1 << l2;
-                        const size_t off = (size_t)r * m + q;
-                        a -= P.U[(size_t)perm_pos(N, l2, i - s2) * nm + off];
-                        if (i + s2 <= N) a -= P.V[(size_t)perm_pos(N, l2, i + s2) * nm + off];
-                    }
+                    a = pull(P, a, i, lvl, (size_t)r * m + q, nm);
                 }
                 acc[rr][c] = a;
                 u[rr][c] = T(0);
