@@ -651,6 +651,109 @@ BTC_API int btc_autotune_strategy(int64_t N, int64_t n, int32_t precision, const
  * *stages.  Host only. */
 BTC_API int btc_select_strategy(int64_t N, int64_t n, int32_t precision, int32_t *strategy, int32_t *stages);
 
+/* ------------------------------------------------------------------------
+ * Block-banded and arrow extensions.  The paper names both structures as
+ * extensions of the method without giving an algorithm for either (arrow
+ * structures: section "Multi-Stage Permutation", after the remark that the
+ * permutation also arises in block cyclic reduction; block-banded matrices of
+ * a larger bandwidth: section "Conclusion").  FP64 inputs, all precisions
+ * (the mixed modes refine every solve of the block-tridiagonal part to the
+ * handle's target).
+ * ------------------------------------------------------------------------ */
+typedef struct btc_banded_s *btc_banded; /* opaque; owned by the library */
+typedef struct btc_arrow_s *btc_arrow;   /* opaque; owned by the library */
+
+/*
+ * btc_banded_create -- factor a symmetric positive definite block-banded
+ * matrix: N block rows of order n, block bandwidth b >= 1 (block (i, j) is
+ * zero for |i - j| > b).  b consecutive block rows and columns are grouped
+ * into one super-block of order b*n, which makes the matrix block tridiagonal
+ * with ceil(N/b) super-blocks; that matrix is factored by the multi-stage
+ * method (btc_factor with opt).  A missing part of the last super-block is
+ * completed with identity rows and columns, decoupled from the band.
+ *   A_band  device, FP64, shape (N, b+1, n, n) row-major: A_band[i][k] is the
+ *           block at (i, i-k) (0-based); k = 0 the diagonal block, only its
+ *           lower triangle read; blocks with i - k < 0 are not read.  Read
+ *           during the call only: the super-blocks are packed into memory the
+ *           object owns (from the allocator of btc_set_allocator).
+ *   b*n <= BTC_MAX_BLOCK, else BTC_ERR_UNSUPPORTED.
+ * Argument errors: -1..-7 for the argument at that position.  A breakdown is
+ * reported by btc_banded_status.
+ */
+BTC_API int btc_banded_create(const btc_options *opt, int64_t N, int64_t n, int64_t b, const double *A_band,
+                              void *stream, btc_banded *out);
+
+/* btc_banded_refactor -- pack and factor a new band of the same (N, n, b). */
+BTC_API int btc_banded_refactor(btc_banded h, const double *A_band, void *stream);
+
+/*
+ * btc_banded_solve -- X = A^{-1} B; B and X device FP64, (N*n) x nrhs
+ * row-major, as btc_solve (refinement and info likewise).  When b does not
+ * divide N the solve runs on zero-padded copies taken from the allocator for
+ * the duration of the call.
+ */
+BTC_API int btc_banded_solve(btc_banded h, const double *B, double *X, int64_t nrhs, void *stream,
+                             btc_solve_info *info);
+
+/* btc_banded_status -- as btc_status; *info is a 1-based super-block index. */
+BTC_API int btc_banded_status(btc_banded h, int64_t *info);
+
+/* btc_banded_inner -- the block-tridiagonal handle of the super-blocks (for
+ * btc_export_factor); owned by the banded object. */
+BTC_API btc_handle btc_banded_inner(btc_banded h);
+
+/* btc_banded_destroy -- wait for its work, free everything (NULL is a no-op). */
+BTC_API void btc_banded_destroy(btc_banded h);
+
+/*
+ * btc_arrow_create -- factor the arrow matrix
+ *       A = [[Psi, F], [F^T, C]]
+ * with Psi the block-tridiagonal matrix of (A_diag, A_off, N, n) as in
+ * btc_factor, F its dense border ((N*n) x m, row-major: row r of F holds the
+ * m couplings of row r of Psi with the tip) and C the m x m tip (symmetric,
+ * lower triangle read), 0 <= m <= 128.  Psi is eliminated first by the
+ * multi-stage method (opt as in btc_factor), then the tip:
+ *   Z = Psi^{-1} F,  S = C - F^T Z (Schur complement),  S = L_S L_S^T,
+ * so that the Cholesky factor of A in this order is [[L, 0], [F^T L^{-T},
+ * L_S]] with L the factor of Psi.  F is copied into memory the object owns;
+ * A_diag / A_off follow btc_factor's rules (kept for the residual in the
+ * mixed-precision modes); C is read during the call only.
+ * Argument errors: -1..-10 for the argument at that position; m > 128 or
+ * n > BTC_MAX_BLOCK: BTC_ERR_UNSUPPORTED.  Breakdowns: btc_arrow_status.
+ */
+BTC_API int btc_arrow_create(const btc_options *opt, int64_t N, int64_t n, int64_t m, const double *A_diag,
+                             const double *A_off, const double *F, const double *C, void *stream,
+                             btc_arrow *out);
+
+/* btc_arrow_refactor -- factor a new arrow of the same (N, n, m). */
+BTC_API int btc_arrow_refactor(btc_arrow h, const double *A_diag, const double *A_off, const double *F,
+                               const double *C, void *stream);
+
+/*
+ * btc_arrow_solve -- X = A^{-1} B; B and X device FP64, (N*n + m) x nrhs
+ * row-major (the rows of Psi first, then the m rows of the tip):
+ *   y = Psi^{-1} b1 (btc_solve, into the first N*n rows of X; `info` is that
+ *   solve's), x2 = L_S^{-T} L_S^{-1} (b2 - F^T y), x1 = y - Z x2.
+ * Takes its partial products' workspace from the allocator for the call.
+ */
+BTC_API int btc_arrow_solve(btc_arrow h, const double *B, double *X, int64_t nrhs, void *stream,
+                            btc_solve_info *info);
+
+/* btc_arrow_status -- synchronise; *info_psi as btc_status for Psi, *info_tip
+ * 0 or the 1-based column of the first non-positive pivot of S (meaningful
+ * only when *info_psi is 0). */
+BTC_API int btc_arrow_status(btc_arrow h, int64_t *info_psi, int64_t *info_tip);
+
+/* btc_arrow_export -- synchronise and copy L_S (m x m, row-major, upper part
+ * 0) and Z ((N*n) x m) to host memory (either pointer may be NULL). */
+BTC_API int btc_arrow_export(btc_arrow h, double *Ls, double *Z);
+
+/* btc_arrow_inner -- the handle of Psi (owned by the arrow object). */
+BTC_API btc_handle btc_arrow_inner(btc_arrow h);
+
+/* btc_arrow_destroy -- wait for its work, free everything (NULL is a no-op). */
+BTC_API void btc_arrow_destroy(btc_arrow h);
+
 /* btc_error_string -- static text for a return code. */
 BTC_API const char *btc_error_string(int code);
 

@@ -204,6 +204,33 @@ def lib():
         L.btc_sweep_ranges.argtypes = [i64, ctypes.POINTER(i32), i32]
         L.btc_set_allocator.restype = ctypes.c_int
         L.btc_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
+        L.btc_banded_create.restype = ctypes.c_int
+        L.btc_banded_create.argtypes = [ctypes.POINTER(btc_options), i64, i64, i64, vp, vp, ctypes.POINTER(vp)]
+        L.btc_banded_refactor.restype = ctypes.c_int
+        L.btc_banded_refactor.argtypes = [vp, vp, vp]
+        L.btc_banded_solve.restype = ctypes.c_int
+        L.btc_banded_solve.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(btc_solve_info)]
+        L.btc_banded_status.restype = ctypes.c_int
+        L.btc_banded_status.argtypes = [vp, ctypes.POINTER(i64)]
+        L.btc_banded_inner.restype = vp
+        L.btc_banded_inner.argtypes = [vp]
+        L.btc_banded_destroy.restype = None
+        L.btc_banded_destroy.argtypes = [vp]
+        L.btc_arrow_create.restype = ctypes.c_int
+        L.btc_arrow_create.argtypes = [ctypes.POINTER(btc_options), i64, i64, i64, vp, vp, vp, vp, vp,
+                                       ctypes.POINTER(vp)]
+        L.btc_arrow_refactor.restype = ctypes.c_int
+        L.btc_arrow_refactor.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.btc_arrow_solve.restype = ctypes.c_int
+        L.btc_arrow_solve.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(btc_solve_info)]
+        L.btc_arrow_status.restype = ctypes.c_int
+        L.btc_arrow_status.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.btc_arrow_export.restype = ctypes.c_int
+        L.btc_arrow_export.argtypes = [vp, vp, vp]
+        L.btc_arrow_inner.restype = vp
+        L.btc_arrow_inner.argtypes = [vp]
+        L.btc_arrow_destroy.restype = None
+        L.btc_arrow_destroy.argtypes = [vp]
         _lib = L
         # device memory of the library comes from torch's caching allocator
         _check(L.btc_set_allocator(_alloc_cb, _free_cb, None), "btc_set_allocator")
@@ -695,3 +722,135 @@ class Factor:
 def factor(A_diag: torch.Tensor, A_off: torch.Tensor, precision: int = BTC_FP64, stream=None,
            max_refine: int = 0, tol: float = 0.0, refine: int = BTC_REFINE_CLASSIC, gmres_m: int = 0) -> Factor:
     return Factor(A_diag, A_off, precision, stream, max_refine, tol, refine, gmres_m)
+
+
+# ---------------------------------------------------------------------------
+# Block-banded and arrow extensions
+
+def _options(precision, max_refine, tol, refine=BTC_REFINE_CLASSIC, gmres_m=0, strategy=BTC_STRATEGY_MULTISTAGE,
+             stages=0):
+    return btc_options(precision, max_refine, tol, refine, gmres_m, strategy, stages)
+
+
+def _info_dict(inf: btc_solve_info) -> dict:
+    return {"steps": inf.steps, "converged": bool(inf.converged), "relres": inf.relres, "inner": inf.inner}
+
+
+class Banded:
+    """Owner of a btc_banded object: a block-banded SPD matrix A_band of shape
+    (N, b+1, n, n) (A_band[i, k] = block (i, i-k)), factored as ceil(N/b)
+    super-blocks of order b*n."""
+
+    def __init__(self, A_band: torch.Tensor, precision: int = BTC_FP64, stream=None, max_refine: int = 0,
+                 tol: float = 0.0):
+        N, b1, n, n2 = A_band.shape
+        if n != n2 or b1 < 2:
+            raise ValueError("A_band must have shape (N, b+1, n, n) with b >= 1")
+        self.N, self.n, self.b = int(N), int(n), int(b1) - 1
+        opt = _options(precision, max_refine, tol)
+        h = vp()
+        _check(lib().btc_banded_create(ctypes.byref(opt), self.N, self.n, self.b, _dev(A_band, "A_band"),
+                                       _stream(stream), ctypes.byref(h)), "btc_banded_create")
+        self.handle = h.value
+
+    def refactor(self, A_band: torch.Tensor, stream=None) -> "Banded":
+        _check(lib().btc_banded_refactor(self.handle, _dev(A_band, "A_band"), _stream(stream)),
+               "btc_banded_refactor")
+        return self
+
+    def solve(self, B: torch.Tensor, X: Optional[torch.Tensor] = None, stream=None, want_info: bool = False):
+        if X is None:
+            X = torch.empty_like(B)
+        nrhs = B.numel() // (self.N * self.n)
+        inf = btc_solve_info()
+        _check(lib().btc_banded_solve(self.handle, _dev(B, "B"), _dev(X, "X"), nrhs, _stream(stream),
+                                      ctypes.byref(inf) if want_info else None), "btc_banded_solve")
+        return (X, _info_dict(inf)) if want_info else X
+
+    @property
+    def info(self) -> int:
+        v = i64()
+        _check(lib().btc_banded_status(self.handle, ctypes.byref(v)), "btc_banded_status")
+        return v.value
+
+    def export(self):
+        """(Ld, Rb, Tb) of the super-block factor (btc_export_factor)."""
+        N2 = -(-self.N // self.b)
+        return btc_export_factor(lib().btc_banded_inner(self.handle), N2, self.b * self.n)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().btc_banded_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Arrow:
+    """Owner of a btc_arrow object: [[Psi, F], [F^T, C]] with Psi the block
+    tridiagonal (A_diag, A_off), F of shape (N*n, m), C of shape (m, m).
+    Keeps A_diag / A_off referenced (the mixed modes read them in solves)."""
+
+    def __init__(self, A_diag: torch.Tensor, A_off: torch.Tensor, F: torch.Tensor, C: torch.Tensor,
+                 precision: int = BTC_FP64, stream=None, max_refine: int = 0, tol: float = 0.0):
+        self.N, self.n = int(A_diag.shape[0]), int(A_diag.shape[1])
+        self.m = int(F.shape[1]) if F.dim() == 2 else 0
+        if A_off is None or A_off.numel() == 0:
+            A_off = torch.zeros((0, self.n, self.n), dtype=A_diag.dtype, device=A_diag.device)
+        opt = _options(precision, max_refine, tol)
+        h = vp()
+        self._A = (A_diag, A_off)
+        _check(lib().btc_arrow_create(ctypes.byref(opt), self.N, self.n, self.m, _dev(A_diag, "A_diag"),
+                                      _dev(A_off, "A_off") if A_off.numel() else None,
+                                      _dev(F, "F") if self.m else None, _dev(C, "C") if self.m else None,
+                                      _stream(stream), ctypes.byref(h)), "btc_arrow_create")
+        self.handle = h.value
+
+    def refactor(self, A_diag, A_off, F, C, stream=None) -> "Arrow":
+        if A_off is None or A_off.numel() == 0:
+            A_off = torch.zeros((0, self.n, self.n), dtype=A_diag.dtype, device=A_diag.device)
+        _check(lib().btc_arrow_refactor(self.handle, _dev(A_diag, "A_diag"),
+                                        _dev(A_off, "A_off") if A_off.numel() else None,
+                                        _dev(F, "F") if self.m else None, _dev(C, "C") if self.m else None,
+                                        _stream(stream)), "btc_arrow_refactor")
+        self._A = (A_diag, A_off)
+        return self
+
+    def solve(self, B: torch.Tensor, X: Optional[torch.Tensor] = None, stream=None, want_info: bool = False):
+        if X is None:
+            X = torch.empty_like(B)
+        nrhs = B.numel() // (self.N * self.n + self.m)
+        inf = btc_solve_info()
+        _check(lib().btc_arrow_solve(self.handle, _dev(B, "B"), _dev(X, "X"), nrhs, _stream(stream),
+                                     ctypes.byref(inf) if want_info else None), "btc_arrow_solve")
+        return (X, _info_dict(inf)) if want_info else X
+
+    @property
+    def info(self):
+        """(info of Psi, info of the tip)."""
+        a, t = i64(), i64()
+        _check(lib().btc_arrow_status(self.handle, ctypes.byref(a), ctypes.byref(t)), "btc_arrow_status")
+        return a.value, t.value
+
+    def export(self):
+        """(L_S, Z) on the host: the tip's Cholesky factor (m x m) and Psi^{-1} F."""
+        Ls = np.zeros((self.m, self.m))
+        Z = np.zeros((self.N * self.n, self.m))
+        _check(lib().btc_arrow_export(self.handle, Ls.ctypes.data if self.m else None,
+                                      Z.ctypes.data if self.m else None), "btc_arrow_export")
+        return Ls, Z
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().btc_arrow_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
