@@ -447,22 +447,12 @@ def batch_rate(btc, count=512, reps=3, tune=False):
     from paper_2601_03754_amd import inputs
     shapes = inputs.batch_shapes(count, seed=0)
     mats = [inputs.block_tridiag_device(N, n, 4.0, seed=k, nrhs=1) for k, (N, n) in enumerate(shapes)]
-    if tune:
-        # the autotuner on one instance of every block size of the batch
-        # (variants are keyed by padded block size)
-        seen = set()
-        for k, (N, n) in enumerate(shapes):
-            if n in seen:
-                continue
-            seen.add(n)
-            D, E, B = mats[k]
-            h = btc.btc_create(N, n, btc.BTC_FP32_IR)
-            btc.btc_refactor(h, D, E)
-            btc.btc_autotune(h, D, E, B, torch.empty_like(B), reps=3)
-            btc.btc_destroy(h)
     r = btc.Runner()
     hs = [btc.btc_create(N, n, btc.BTC_FP32_IR) for N, n in shapes]
     Xs = [torch.empty_like(m[2]) for m in mats]
+    if tune:
+        # the autotuner on the batch itself, as the batched calls run it
+        r.autotune(hs, [m[0] for m in mats], [m[1] for m in mats], [m[2] for m in mats], Xs, 1, reps=3)
     ts = []
     for rep in range(reps + 1):
         torch.cuda.synchronize()

@@ -431,6 +431,23 @@ BTC_API void btc_graph_destroy(btc_graph g);
  * round-off level.  Returns 0 or -k for argument k.
  */
 #define BTC_TUNE_SWEEP_SHAPE 6 /* tune key: launch shape of the sweeps (op field; level ignored) */
+/*
+ * btc_autotune_batched -- tune the table for a batch of instances as
+ * btc_factor_batched / btc_solve_batched run it (one launch per level
+ * carrying the nodes of every instance favours other variants than one
+ * instance alone): every key the batch touches (factor per level bucket,
+ * sweep shape, and with more than one right-hand side the sweeps and the
+ * residual) is tried variant by variant on the whole batched factor + solve,
+ * the other keys at their current choice, and the fastest kept (median of
+ * reps timed calls after one warm-up; one pass of coordinate descent).
+ * Arguments as btc_factor_batched and btc_solve_batched (B[k] != X[k]);
+ * leaves every instance factored and solved with the final choices and
+ * writes the BTC_TUNE_CACHE file if set.  Returns 0, -k for argument k, or
+ * an error of the batched calls.
+ */
+BTC_API int btc_autotune_batched(btc_runner r, int32_t count, const btc_handle *h, const double *const *A_diag,
+                                 const double *const *A_off, const double *const *B, double *const *X,
+                                 const int64_t *nrhs, int32_t reps);
 BTC_API int btc_tune_get(int32_t op, int32_t precision, int64_t n, int32_t level, int32_t *variant);
 BTC_API int btc_tune_set(int32_t op, int32_t precision, int64_t n, int32_t level, int32_t variant);
 BTC_API int btc_autotune(btc_handle h, const double *A_diag, const double *A_off, const double *B, double *X,

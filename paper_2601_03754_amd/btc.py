@@ -204,6 +204,9 @@ def lib():
         L.btc_sweep_ranges.argtypes = [i64, ctypes.POINTER(i32), i32]
         L.btc_set_allocator.restype = ctypes.c_int
         L.btc_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
+        L.btc_autotune_batched.restype = ctypes.c_int
+        L.btc_autotune_batched.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                           ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64), i32]
         L.btc_banded_create.restype = ctypes.c_int
         L.btc_banded_create.argtypes = [ctypes.POINTER(btc_options), i64, i64, i64, vp, vp, ctypes.POINTER(vp)]
         L.btc_banded_refactor.restype = ctypes.c_int
@@ -444,6 +447,24 @@ class Runner:
             return None
         return [{"steps": info[k].steps, "converged": bool(info[k].converged), "relres": info[k].relres}
                 for k in range(n)]
+
+    def autotune(self, handles, A_diags, A_offs, Bs, Xs, nrhs=None, reps: int = 3) -> None:
+        """Tune the variant table on this batch as the batched calls run it
+        (btc_autotune_batched); leaves the instances factored and solved."""
+        n = len(handles)
+        if nrhs is None:
+            nrhs = [b.shape[-1] if b.dim() == 3 else 1 for b in Bs]
+        elif isinstance(nrhs, int):
+            nrhs = [nrhs] * n
+        for h, a, o in zip(handles, A_diags, A_offs):
+            self._mats[h] = (a, o)
+        m = (i64 * max(1, n))(*[int(v) for v in nrhs])
+        _check(lib().btc_autotune_batched(self.handle, n, _ptr_array(handles),
+                                          _ptr_array([_dev(a, "A_diag") for a in A_diags]),
+                                          _ptr_array([_dev(a, "A_off") if a.numel() else 0 for a in A_offs]),
+                                          _ptr_array([_dev(b, "B") for b in Bs]),
+                                          _ptr_array([_dev(x, "X") for x in Xs]), m, reps),
+               "btc_autotune_batched")
 
     def graph_begin(self) -> None:
         """Record the following runner calls instead of running them."""

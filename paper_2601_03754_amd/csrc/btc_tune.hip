@@ -14,10 +14,13 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <algorithm>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "btc.h"
 #include "btc_handle.h"
@@ -190,6 +193,93 @@ BTC_API int btc_tune_set(int32_t op, int32_t precision, int64_t n, int32_t level
     tune_set(op, kind, np, bucket_of(op, level), variant);
     save_tune_cache();
     return BTC_OK;
+}
+
+// Tune the table for a batch: every key the batch touches is tried variant
+// by variant (the others at their current choice) on the whole batched
+// factor + solve, and the fastest kept (coordinate descent, one pass, keys
+// in the order factor, sweep shape, sweeps, residual).
+BTC_API int btc_autotune_batched(btc_runner r, int32_t count, const btc_handle* h, const double* const* A_diag,
+                                 const double* const* A_off, const double* const* B, double* const* X,
+                                 const int64_t* nrhs, int32_t reps) {
+    if (!r) return -1;
+    if (count < 1) return -2;
+    if (!h || !A_diag || !A_off) return -3;
+    if (!B || !X) return -6;
+    if (!nrhs) return -8;
+    if (reps < 1) return -9;
+    bool multi = false;
+    for (int32_t k = 0; k < count; ++k) {
+        if (!h[k] || !A_diag[k] || (h[k]->N > 1 && !A_off[k])) return -3;
+        if (!B[k] || !X[k] || B[k] == X[k]) return -6;
+        if (nrhs[k] < 1) return -8;
+        multi = multi || nrhs[k] > 1;
+    }
+    struct Key {
+        int op, kind, np, bucket, nv;
+        bool operator<(const Key& o) const {
+            return std::tie(op, kind, np, bucket) < std::tie(o.op, o.kind, o.np, o.bucket);
+        }
+    };
+    std::map<Key, int> keys;  // key -> its place in the descent
+    const int order[6] = {BTC_OP_FACTOR, BTC_TUNE_SWEEP_SHAPE, BTC_OP_FORWARD, BTC_OP_BACKWARD, BTC_OP_RESIDUAL, -1};
+    for (int oi = 0; order[oi] >= 0; ++oi) {
+        const int op = order[oi];
+        if ((op == BTC_OP_FORWARD || op == BTC_OP_BACKWARD || op == BTC_OP_RESIDUAL) && !multi) continue;
+        for (int32_t k = 0; k < count; ++k) {
+            int kind, np, nv;
+            if (!tunable(op, h[k]->precision, h[k]->n, kind, np, nv)) continue;
+            const int nb = (op == BTC_OP_FACTOR && h[k]->levels > 1) ? 2 : 1;
+            for (int b = 0; b < nb; ++b) keys.emplace(Key{op, kind, np, b, nv}, oi);
+        }
+    }
+    std::vector<std::pair<int, Key>> seq;
+    for (auto& kv : keys) seq.push_back({kv.second, kv.first});
+    std::stable_sort(seq.begin(), seq.end(), [](const std::pair<int, Key>& a, const std::pair<int, Key>& b) {
+        return a.first < b.first;
+    });
+    // median wall time of reps batched factor + solve calls (after one warm-up)
+    auto run_once = [&]() -> int {
+        int rc = btc_factor_batched(r, count, h, A_diag, A_off, nullptr);
+        if (rc == BTC_OK) rc = btc_solve_batched(r, count, h, B, X, nrhs, nullptr);
+        if (rc == BTC_OK) rc = btc_runner_sync(r);
+        return rc;
+    };
+    auto time_batch = [&](double& ms) -> int {
+        int rc = run_once();
+        std::vector<double> t;
+        for (int k = 0; k < reps && rc == BTC_OK; ++k) {
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = run_once();
+            t.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+        }
+        if (rc != BTC_OK) return rc;
+        std::sort(t.begin(), t.end());
+        ms = t[t.size() / 2];
+        return BTC_OK;
+    };
+    for (auto& e : seq) {
+        const Key& k = e.second;
+        double best = 1e300;
+        int pick = tune_variant(k.op, k.kind, k.np, k.bucket);
+        for (int v = 0; v < k.nv; ++v) {
+            tune_set(k.op, k.kind, k.np, k.bucket, v);
+            double ms = 0.0;
+            const int rc = time_batch(ms);
+            if (rc != BTC_OK) {
+                tune_set(k.op, k.kind, k.np, k.bucket, pick);
+                return rc;
+            }
+            if (ms < best) {
+                best = ms;
+                pick = v;
+            }
+        }
+        tune_set(k.op, k.kind, k.np, k.bucket, pick);
+    }
+    save_tune_cache();
+    // leave every instance factored and solved with the final choices
+    return run_once();
 }
 
 BTC_API int btc_autotune(btc_handle h, const double* A_diag, const double* A_off, const double* B, double* X,

@@ -188,3 +188,31 @@ def test_sweep_shapes_identical(btc, precision, N, n):
         assert np.array_equal(o, outs[0])
     tol = 1e-12 if precision == 0 else 1e-10
     assert oracle.relres(pr.D, pr.E, outs[0], pr.B) <= tol
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autotune_batched_keeps_results_correct(btc, precision):
+    """btc_autotune_batched on a small mixed batch: the instances come back
+    factored and solved within the path's accuracy, and every key holds a
+    valid variant (the previous table is restored afterwards)."""
+    shapes = [(37, 7), (120, 16), (64, 28), (200, 40), (9, 60), (301, 12)]
+    keys = [(op, n, lvl) for op in (0, 1, 2, 3, 6) for n in (7, 16, 28, 40, 60, 12) for lvl in (0, 1)]
+    saved = {k: btc.btc_tune_get(k[0], precision, k[1], k[2]) for k in keys}
+    prs = [inputs.block_tridiag(N, n, seed=5 + k, nrhs=2) for k, (N, n) in enumerate(shapes)]
+    r = btc.Runner()
+    hs = [btc.btc_create(N, n, precision) for N, n in shapes]
+    Ds, Es, Bs = [dev(p.D) for p in prs], [dev(p.E) for p in prs], [dev(p.B) for p in prs]
+    Xs = [torch.empty_like(b) for b in Bs]
+    try:
+        r.autotune(hs, Ds, Es, Bs, Xs, reps=1)
+        torch.cuda.synchronize()
+        for (op, n, lvl) in keys:
+            assert btc.btc_tune_get(op, precision, n, lvl) in (0, 1, 2)
+        for p, X in zip(prs, Xs):
+            assert oracle.relres(p.D, p.E, X.cpu().numpy(), p.B) <= (1e-12 if precision == 0 else 1e-10)
+    finally:
+        for k, v in saved.items():
+            btc.btc_tune_set(k[0], precision, k[1], k[2], v)
+        for h in hs:
+            btc.btc_destroy(h)
+        r.close()
