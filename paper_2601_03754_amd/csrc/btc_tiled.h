@@ -261,20 +261,30 @@ constexpr int k2_waves() { return NP == 96 ? 8 : 4; }
 template <int NP>
 constexpr int k2_blocks() { return NP <= 64 ? 5 : NP <= 96 ? 2 : 1; }
 
-template <int NP, bool MIXED>
-__global__ __launch_bounds__(k2_waves<NP>() * kWave, (k2_blocks<NP>() * k2_waves<NP>() + 3) / 4) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
+// A launch of at most one node per compute unit is bound by one node's
+// latency, not by the throughput of nodes sharing a unit: at padded size 96
+// it takes twelve wavefronts, one compute unit each, so that all twelve
+// strips are solved in one round (measured at N = 4096: 38 against 43 us per
+// launch of the upper levels, FP64; 44 against 53 mixed).
+constexpr int kK2LatencyWaves = 12;
+constexpr int64_t kK2LatencyItems = 256;
+
+template <int NP, bool MIXED, int NW = k2_waves<NP>(), int NB = k2_blocks<NP>()>
+__global__ __launch_bounds__(NW * kWave, (NB * NW + 3) / 4) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
     using Pr = Prec<MIXED>;  // storage of the factor blocks
     using Pm = Prec<false>;  // the solves run in FP64 (latency bound: no gain from FP32)
     using F = typename Pr::F;
     using Acc = typename Pm::Acc;
     using Cfg = TiledCfg<NP>;
     constexpr int NT16 = Cfg::NT16;
-    constexpr int NW = k2_waves<NP>();
     // lower tiles of S_i, then of L_ii, the strict upper part of each
     // diagonal tile holding its inverse (transposed)
     __shared__ double sS[packed_lds_elems<NP>()];
     __shared__ double invd[NP];
     __shared__ __align__(16) double colbuf[2][kWave];
+    // one 16 x 16 tile per wavefront: R strip tiles pass through it between
+    // the row-major layout of R_i in HBM and the transposed register layout
+    __shared__ double xbuf[NW][kT * kLDI];
     __shared__ int fail;
     FactorDesc P;
     int lvl;
@@ -298,8 +308,40 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, (k2_blocks<NP>() * k2_waves
         gr = isR ? kT * t + i : kT * p + rr;
         gc = isR ? kT * p + rr : kT * t + i;
     };
-    // the coupling tile: level 0 reads the input couplings (FP64), higher
-    // levels the coupling left in the output slot by the previous level
+    // R strip tile elements in row order: lane (c, q), register v holds
+    // element (16t + 4v + q, 16p + c) of R_i, so that each load or store
+    // covers 16 consecutive columns of four rows
+    auto rpos = [&](int t, int p, int v, int& gr, int& gc) {
+        gr = kT * t + Pm::row(v, lane);
+        gc = kT * p + i;
+    };
+    // an R strip tile from that row order into the accumulator layout (and
+    // back), through the wavefront's LDS tile: element (r, c) of the R tile
+    // at xb[r][c]
+    double* xb = xbuf[w];
+    auto rows_to_acc = [&](const Acc& raw) {
+        Acc out;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xb[Pm::row(v, lane) * kLDI + i] = raw[v];
+        wave_lds_sync();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[v] = xb[i * kLDI + Pm::row(v, lane)];
+        wave_lds_sync();
+        return out;
+    };
+    auto acc_to_rows = [&](const Acc& x) {
+        Acc out;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xb[i * kLDI + Pm::row(v, lane)] = x[v];
+        wave_lds_sync();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[v] = xb[Pm::row(v, lane) * kLDI + i];
+        wave_lds_sync();
+        return out;
+    };
+    // the coupling tile (R strips: in row order): level 0 reads the input
+    // couplings (FP64), higher levels the coupling left in the output slot by
+    // the previous level
     auto load_coupling = [&](bool isR, int t, int p, bool live) {
         Acc acc;
         const int64_t cblk = isR ? d.i - 1 : d.i - 2;
@@ -308,7 +350,10 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, (k2_blocks<NP>() * k2_waves
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             int gr, gc;
-            gpos(isR, t, p, v, gr, gc);
+            if (isR)
+                rpos(t, p, v, gr, gc);
+            else
+                gpos(false, t, p, v, gr, gc);
             const bool ok = live && gr < n && gc < n;
             if (lvl == 0) {
                 double x;
@@ -349,7 +394,7 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, (k2_blocks<NP>() * k2_waves
         if (NT16 > 1) nx1 = load_coupling(isR, t, 1, true);
 #pragma unroll
         for (int p = 0; p < NT16; ++p) {
-            Acc acc = nx0;
+            Acc acc = isR ? rows_to_acc(nx0) : nx0;
             nx0 = nx1;
             if (p + 2 < NT16) nx1 = load_coupling(isR, t, p + 2, true);
             // acc -= L_p,qq X_qq (A from LDS, B = X_qq's registers)
@@ -372,13 +417,18 @@ __global__ __launch_bounds__(k2_waves<NP>() * kWave, (k2_blocks<NP>() * k2_waves
             X[p] = out;
         }
 #pragma unroll
-        for (int p = 0; p < NT16; ++p)
+        for (int p = 0; p < NT16; ++p) {
+            const Acc y = isR ? acc_to_rows(X[p]) : X[p];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 int gr, gc;
-                gpos(isR, t, p, v, gr, gc);
-                buf_st((F)X[p][v], rdst, elem_off<F>(gr, gc, n, gr < n && gc < n));
+                if (isR)
+                    rpos(t, p, v, gr, gc);
+                else
+                    gpos(false, t, p, v, gr, gc);
+                buf_st((F)y[v], rdst, elem_off<F>(gr, gc, n, gr < n && gc < n));
             }
+        }
     }
 }
 
@@ -520,8 +570,18 @@ hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int part, bool deferred,
     const unsigned g = (unsigned)items;
     if ((part == 0 || part == 1) && deferred)
         hipLaunchKernelGGL((k_tiled_syrk_deferred<NP, MIXED, BF16>), dim3(g * 2 * Cfg::NTRI32), dim3(256), 0, st, p);
-    if (part == 0 || part == 2)
-        hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED>), dim3(g), dim3(k2_waves<NP>() * kWave), 0, st, p);
+    if (part == 0 || part == 2) {
+        bool done = false;
+        if constexpr (NP == 96) {
+            if (items <= kK2LatencyItems) {
+                hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED, kK2LatencyWaves, 1>), dim3(g),
+                                   dim3(kK2LatencyWaves * kWave), 0, st, p);
+                done = true;
+            }
+        }
+        if (!done)
+            hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED>), dim3(g), dim3(k2_waves<NP>() * kWave), 0, st, p);
+    }
     if (part == 0 || part == 3)
         hipLaunchKernelGGL((k_tiled_update<NP, MIXED, BF16>), dim3(g * (Cfg::NTRI32 + Cfg::W32 * Cfg::W32)), dim3(256),
                            0, st, p);

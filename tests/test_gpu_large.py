@@ -30,7 +30,11 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-SHAPES = [(1, 65), (2, 96), (3, 128), (7, 80), (16, 96), (21, 100), (33, 128), (40, 127), (64, 65), (100, 112)]
+# (700, 96) and (600, 81): more than 256 nodes at level 0, so the pivot kernel
+# runs in both of its launch shapes (throughput shape at level 0, latency
+# shape above)
+SHAPES = [(1, 65), (2, 96), (3, 128), (7, 80), (16, 96), (21, 100), (33, 128), (40, 127), (64, 65), (100, 112),
+          (700, 96), (600, 81)]
 
 
 @pytest.mark.parametrize("N,n", SHAPES)
@@ -51,7 +55,7 @@ def test_fp64_large_blocks_match_oracle(btc, N, n):
     assert oracle.relres(pr.D, pr.E, X, pr.B) <= 1e-12
 
 
-@pytest.mark.parametrize("N,n", [(1, 70), (9, 96), (33, 128), (50, 90), (129, 120)])
+@pytest.mark.parametrize("N,n", [(1, 70), (9, 96), (33, 128), (50, 90), (129, 120), (700, 96)])
 def test_mixed_large_blocks_refine_to_target(btc, N, n):
     pr = inputs.block_tridiag(N, n, seed=4000 + N + n, nrhs=1)
     f = btc.Factor(dev(pr.D), dev(pr.E), precision=btc.BTC_FP32_IR)
