@@ -88,6 +88,42 @@ def relres_torch(D, E, X, B):
     return float((num / den).max())
 
 
+# HBM traffic of kernel groups measured with rocprofv3 PMC counters
+# (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by a plain copy kernel) over
+# a whole served run, divided by the algorithmic bytes of the same launches
+# (the run's group_totals): rows "| group | measured / algorithmic | sha1 |
+# sources |" of the committed summary.  The traffic of a launch is that ratio
+# times its algorithmic bytes.  A row counts only while the sha1 of its
+# sources (the kernel files, concatenated in the listed order) still matches.
+TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "pmc_traffic_served.md")
+
+
+def committed_traffic(group):
+    import hashlib
+    try:
+        lines = open(TRAFFIC_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2601_03754_amd", "csrc")
+    for ln in lines:
+        cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+        if len(cells) != 4 or cells[0] != group:
+            continue
+        try:
+            value = float(cells[1])
+        except ValueError:
+            continue
+        h = hashlib.sha1()
+        try:
+            for f in cells[3].split():
+                h.update(open(os.path.join(csrc, f.strip("`")), "rb").read())
+        except OSError:
+            return None
+        return value if h.hexdigest() == cells[2].strip("`") else None
+    return None
+
+
 def roofline_entry(stat):
     """Roofline object for one profiled kernel group."""
     avg_ms = stat["ms"] / stat["launches"]
@@ -115,6 +151,8 @@ def roofline_entry(stat):
     r["kernel"] = "%s %s np=%d" % (OPS[stat["op"]], kind, stat["np"])
     if stat.get("part"):
         r["kernel"] += " " + TILED_PART[stat["part"]]
+    ratio = committed_traffic(r["kernel"])
+    r["traffic"] = None if ratio is None else ratio * bpl
     return r
 
 
@@ -261,9 +299,17 @@ def run_served(args, btc):
         stats = btc.runner_profile_read(rh)
         dom = stats[0]
         # timed region: only the dominant group's family carries events
-        btc.runner_profile(rh, dom["op"], dom["kind"])
+        btc.runner_profile(rh, -1 if args.profile_all else dom["op"], -1 if args.profile_all else dom["kind"])
         done, wall = sv.closed_loop(per_step * args.steps)
         allstats = btc.runner_profile_read(rh)
+        totals = None
+        if args.profile_all:
+            totals = {}
+            for st_ in list(stats) + list(allstats):
+                t = totals.setdefault(roofline_entry(st_)["kernel"], {"launches": 0, "bytes": 0.0, "ms": 0.0})
+                t["launches"] += st_["launches"]
+                t["bytes"] += st_["bytes"]
+                t["ms"] += st_["ms"]
         tstats = [s for s in allstats
                   if (s["op"], s["kind"], s["np"], s["part"]) == (dom["op"], dom["kind"], dom["np"], dom["part"])]
         btc.runner_profile(rh, -2, -1)
@@ -294,6 +340,8 @@ def run_served(args, btc):
                "warmup_kernel_ms": [{"kernel": roofline_entry(s)["kernel"], "ms": round(s["ms"], 3),
                                      "launches": s["launches"],
                                      "gbs": round(s["bytes"] / (s["ms"] * 1e-3) / 1e9, 1)} for s in stats[:10]]}
+        if totals is not None:
+            ent["group_totals"] = totals
         if tstats:
             ent["roofline"] = roofline_entry(tstats[0])
         # every kernel of the timed region: algorithmic bytes / flops over its wall time
@@ -563,6 +611,10 @@ def main():
                     help="served workload: requests per step (16 per client by default)")
     ap.add_argument("--sweep-ranges", action="store_true",
                     help="served workload: one server tick per sweep level range instead of per level")
+    ap.add_argument("--profile-all", action="store_true",
+                    help="served workload: time every kernel group in the timed region too and report each "
+                         "group's launches and algorithmic bytes over the whole run (group_totals), to set "
+                         "hardware traffic counters of the same run against")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other configurations (sweep table, batch, latency per strategy)")
     args = ap.parse_args()
