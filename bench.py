@@ -530,9 +530,16 @@ def latency_strategies(btc, N=16, n=8, reps=200):
     X = torch.empty_like(B)
     ms = btc.btc_autotune_strategy(D, E, B, X, reps=reps)
     pick = btc.btc_select_strategy(N, n)
-    names = ["multistage", "sequential (k=0)", "single-stage (k=1)", "two-stage (k=2)"]
-    return {"N": N, "n": n, "us_per_factor_solve": {names[k]: round(ms[k] * 1e3, 2) for k in range(4) if ms[k] > 0},
-            "auto_pick": names[0] if pick[0] == btc.BTC_STRATEGY_MULTISTAGE else names[1 + pick[1]]}
+    names = ["multistage", "sequential (k=0)", "single-stage (k=1)", "two-stage (k=2)", "partition (p=2)",
+             "partition (p=4)"]
+    if pick[0] == btc.BTC_STRATEGY_MULTISTAGE:
+        auto = names[0]
+    elif pick[0] == btc.BTC_STRATEGY_KSTAGE:
+        auto = names[1 + pick[1]]
+    else:
+        auto = "partition (p=%d)" % pick[1]
+    return {"N": N, "n": n, "us_per_factor_solve": {names[k]: round(ms[k] * 1e3, 2) for k in range(6) if ms[k] > 0},
+            "auto_pick": auto}
 
 
 # ---------------------------------------------------------------------------

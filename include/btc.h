@@ -131,12 +131,23 @@ typedef enum {
  *   BTC_STRATEGY_AUTO        the fastest of these for (N, n) as measured by
  *                            btc_autotune_strategy (else a rule: KSTAGE 0 for
  *                            N <= 32 with n <= 16, MULTISTAGE otherwise).
+ *   BTC_STRATEGY_PARTITION   the partition order of Algorithm 2 with
+ *                            p = `stages` >= 2 chunks sized by Proposition 1
+ *                            (the first chunk N_1 blocks, the others N_k,
+ *                            one separating block between neighbours): every
+ *                            chunk eliminated in natural order by its own
+ *                            wavefront, all chunks at once, then the p - 1
+ *                            separating blocks in order.  FP64, n <= 64,
+ *                            btc_factor / btc_solve only; BTC_ERR_UNSUPPORTED
+ *                            when N is too small for p chunks of at least one
+ *                            block.
  * Every order computes the Cholesky factor of its own permuted matrix; the
  * solutions agree to rounding.
  */
 #define BTC_STRATEGY_MULTISTAGE 0
 #define BTC_STRATEGY_KSTAGE 1
 #define BTC_STRATEGY_AUTO 2
+#define BTC_STRATEGY_PARTITION 3
 
 typedef struct {
     int32_t precision;   /* btc_precision */
@@ -145,7 +156,8 @@ typedef struct {
     int32_t refine;      /* BTC_REFINE_CLASSIC or BTC_REFINE_GMRES (mixed precision only) */
     int32_t gmres_m;     /* BTC_REFINE_GMRES: iterations per correction, 1..200 (0: default) */
     int32_t strategy;    /* BTC_STRATEGY_* (0: multi-stage) */
-    int32_t stages;      /* BTC_STRATEGY_KSTAGE: levels of the multi-stage order before the chain */
+    int32_t stages;      /* BTC_STRATEGY_KSTAGE: levels of the multi-stage order before the chain;
+                            BTC_STRATEGY_PARTITION: number of chunks p */
 } btc_options;
 
 typedef struct {
@@ -198,7 +210,10 @@ BTC_API int btc_refactor(btc_handle h, const double *A_diag, const double *A_off
  *           relative residual of the solution).
  * Refinement stops on its own on the device (no host synchronisation) once
  * the target is met, once a step reduces the residual by less than 2x, or
- * after max_refine corrections.  Returns BTC_ERR_NOT_SPD (without writing X)
+ * after max_refine corrections; the launches of rounds after the stop exit
+ * at once.  When info is given (the call waits for the result anyway), the
+ * rounds after the first correction are enqueued only while the refinement
+ * has not stopped (one small device-to-host read per round).  Returns BTC_ERR_NOT_SPD (without writing X)
  * if the factorization is known to have broken down.
  * Concurrency: once the factorization has completed, the factor is only
  * read, and solves of one handle may run concurrently on different streams:
@@ -651,21 +666,22 @@ BTC_API int btc_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *c
 
 /*
  * btc_autotune_strategy -- time the elimination orders (multi-stage; k-stage
- * with k = 0, 1, 2 where they apply: FP64, n <= 64, k < floor(log2 N)+1) on
- * the caller's matrix: reps repetitions of refactor + solve each after one
+ * with k = 0, 1, 2 and partition with p = 2, 4 where they apply: FP64,
+ * n <= 64, k < floor(log2 N)+1, chunks of at least one block) on the
+ * caller's matrix: reps repetitions of refactor + solve each after one
  * warm-up, HIP events on `stream`; the fastest becomes the choice of
  * BTC_STRATEGY_AUTO for (precision, N, padded n), process-wide.  ms (host,
- * 4 entries, nullable) receives the milliseconds per refactor + solve of
- * multi-stage, k = 0, 1, 2 (-1: not a candidate).  Overwrites X.  Returns 0,
- * -k for argument k, or the error of a candidate.
+ * 6 entries, nullable) receives the milliseconds per refactor + solve of
+ * multi-stage, k = 0, 1, 2, p = 2, 4 (-1: not a candidate).  Overwrites X.
+ * Returns 0, -k for argument k, or the error of a candidate.
  */
 BTC_API int btc_autotune_strategy(int64_t N, int64_t n, int32_t precision, const double *A_diag,
                                   const double *A_off, const double *B, double *X, int64_t nrhs, int32_t reps,
                                   void *stream, double *ms);
 
 /* btc_select_strategy -- the elimination order BTC_STRATEGY_AUTO takes for
- * (N, n, precision): *strategy (BTC_STRATEGY_MULTISTAGE or _KSTAGE) and
- * *stages.  Host only. */
+ * (N, n, precision): *strategy (BTC_STRATEGY_MULTISTAGE, _KSTAGE or
+ * _PARTITION) and *stages.  Host only. */
 BTC_API int btc_select_strategy(int64_t N, int64_t n, int32_t precision, int32_t *strategy, int32_t *stages);
 
 /* ------------------------------------------------------------------------

@@ -39,6 +39,7 @@ BTC_REFINE_GMRES = 1
 BTC_STRATEGY_MULTISTAGE = 0
 BTC_STRATEGY_KSTAGE = 1
 BTC_STRATEGY_AUTO = 2
+BTC_STRATEGY_PARTITION = 3
 
 
 class btc_options(ctypes.Structure):
@@ -675,14 +676,14 @@ def btc_autotune_strategy(A_diag: torch.Tensor, A_off: torch.Tensor, B: torch.Te
                           precision: int = BTC_FP64, reps: int = 5, stream=None):
     """Time the elimination orders on this matrix, keep the fastest for
     BTC_STRATEGY_AUTO; returns ms per refactor+solve of [multi-stage, k=0,
-    k=1, k=2] (-1: not a candidate)."""
+    k=1, k=2, partition p=2, partition p=4] (-1: not a candidate)."""
     N, n, _ = A_diag.shape
     nrhs = B.shape[-1] if B.dim() == 3 else 1
-    ms = (dbl * 4)()
+    ms = (dbl * 6)()
     po = _dev(A_off, "A_off") if A_off.numel() else 0
     _check(lib().btc_autotune_strategy(N, n, precision, _dev(A_diag, "A_diag"), po, _dev(B, "B"), _dev(X, "X"),
                                        nrhs, reps, _stream(stream), ms), "btc_autotune_strategy")
-    return [ms[k] for k in range(4)]
+    return [ms[k] for k in range(6)]
 
 
 def btc_select_strategy(N: int, n: int, precision: int = BTC_FP64):

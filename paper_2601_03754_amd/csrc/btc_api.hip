@@ -84,13 +84,17 @@ BTC_API int btc_create(int64_t N, int64_t n, const btc_options* opt, btc_handle*
     if (opt && (opt->max_refine < 0 || !(opt->tol >= 0.0))) return -3;
     if (opt && (opt->refine < BTC_REFINE_CLASSIC || opt->refine > BTC_REFINE_GMRES)) return -3;
     if (opt && (opt->gmres_m < 0 || opt->gmres_m > 200)) return -3;
-    if (opt && (opt->strategy < BTC_STRATEGY_MULTISTAGE || opt->strategy > BTC_STRATEGY_AUTO || opt->stages < 0))
+    if (opt && (opt->strategy < BTC_STRATEGY_MULTISTAGE || opt->strategy > BTC_STRATEGY_PARTITION || opt->stages < 0))
         return -3;
     if (!out) return -4;
     int32_t strategy = opt ? opt->strategy : BTC_STRATEGY_MULTISTAGE, stages = opt ? opt->stages : 0;
     if (strategy == BTC_STRATEGY_AUTO) select_strategy(N, n, prec, &strategy, &stages);
     if (strategy == BTC_STRATEGY_KSTAGE && stages >= num_levels(N)) strategy = BTC_STRATEGY_MULTISTAGE;
     if (strategy == BTC_STRATEGY_KSTAGE && (prec != BTC_FP64 || n > 64)) return BTC_ERR_UNSUPPORTED;
+    int64_t part_n1 = 0, part_nk = 0;
+    if (strategy == BTC_STRATEGY_PARTITION &&
+        (prec != BTC_FP64 || n > 64 || !partition_sizes(N, stages, part_n1, part_nk)))
+        return BTC_ERR_UNSUPPORTED;
     *out = nullptr;
     btc_handle h = new (std::nothrow) btc_handle_s();
     if (!h) return BTC_ERR_OOM;
@@ -104,7 +108,12 @@ BTC_API int btc_create(int64_t N, int64_t n, const btc_options* opt, btc_handle*
     h->gmres_m = (opt && opt->gmres_m > 0) ? opt->gmres_m : BTC_DEFAULT_GMRES_M;
     h->levels = num_levels(N);
     h->strategy = strategy;
-    h->nd_levels = strategy == BTC_STRATEGY_KSTAGE ? stages : h->levels;
+    h->nd_levels = strategy == BTC_STRATEGY_KSTAGE ? stages : strategy == BTC_STRATEGY_PARTITION ? 0 : h->levels;
+    if (strategy == BTC_STRATEGY_PARTITION) {
+        h->parts = stages;
+        h->part_n1 = part_n1;
+        h->part_nk = part_nk;
+    }
     (void)hipGetDevice(&h->device);
     h->alloc = current_allocator();
     const size_t nn = (size_t)N * (size_t)n * (size_t)n;
@@ -141,7 +150,7 @@ BTC_API int btc_factor(const double* A_diag, const double* A_off, int64_t N, int
     if (opt && (opt->max_refine < 0 || !(opt->tol >= 0.0))) return -5;
     if (opt && (opt->refine < BTC_REFINE_CLASSIC || opt->refine > BTC_REFINE_GMRES)) return -5;
     if (opt && (opt->gmres_m < 0 || opt->gmres_m > 200)) return -5;
-    if (opt && (opt->strategy < BTC_STRATEGY_MULTISTAGE || opt->strategy > BTC_STRATEGY_AUTO || opt->stages < 0))
+    if (opt && (opt->strategy < BTC_STRATEGY_MULTISTAGE || opt->strategy > BTC_STRATEGY_PARTITION || opt->stages < 0))
         return -5;
     if (!out) return -7;
     *out = nullptr;
@@ -229,12 +238,23 @@ int solve_with(btc_handle h, const Workspace& w, const double* B, double* X, int
         R.single = residual_desc(h, w, B, X, nrhs, true);
         e = timed(h, 3, 0, st, [&] { return btc::launch_ir_init(I, 1, st); });
         if (e != hipSuccess) return to_code(e);
+        // A caller that asks for the outcome waits for the solve anyway: then
+        // every round after the first correction is enqueued only if the
+        // refinement has not stopped yet (one small read per round), instead
+        // of launches that would exit at once.
         for (int it = 0; it <= h->max_refine; ++it) {
             e = sweeps(h, sweep_desc32(h, w, B, X, nrhs, it == 0), st);
             if (e == hipSuccess)
                 e = timed(h, 3, 1, st, [&] { return btc::launch_residual(R, np, h->N, sweep_mc(BTC_OP_RESIDUAL, 0, np, nrhs), st); });
             if (e == hipSuccess) e = timed(h, 3, 2, st, [&] { return btc::launch_ir_check(I, 1, st); });
             if (e != hipSuccess) return to_code(e);
+            if (info && it >= 1 && it < h->max_refine) {
+                int32_t done = 0;
+                e = hipMemcpyAsync(&done, &w.ir->done, sizeof(done), hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (e != hipSuccess) return to_code(e);
+                if (done) break;
+            }
         }
         if (!info) return BTC_OK;
     }
@@ -604,6 +624,34 @@ BTC_API int btc_export_factor(btc_handle h, double* Ld, double* Rb, double* Tb) 
             e = hipMemcpy(tmp.data(), srcs[a], nn * (size_t)N * sizeof(double), hipMemcpyDeviceToHost);
         }
         if (e != hipSuccess) return to_code(e);
+        if (h->strategy == BTC_STRATEGY_PARTITION) {
+            // stored by original block: chunk blocks (R to the next block or
+            // the right separator, T to the left separator), separators (R'
+            // to the next separator; their T slot holds a chunk's fill)
+            for (int64_t i = 1; i <= N; ++i) {
+                bool sep = false, last = false, has_l = false;
+                int64_t j = 0;  // chunk of i, or separator index
+                if (i <= h->part_n1) {
+                    j = 0;
+                    last = i == h->part_n1;
+                } else {
+                    const int64_t off = i - h->part_n1 - 1, per = h->part_nk + 1;
+                    j = off / per + 1;
+                    sep = off % per == 0;
+                    last = !sep && off % per == h->part_nk;
+                    has_l = !sep;
+                }
+                bool present = a == 0;
+                if (a == 1) present = sep ? j + 1 < h->parts : (!last || j + 1 < h->parts);
+                if (a == 2) present = has_l;
+                double* dst = outs[a] + (size_t)(i - 1) * nn;
+                if (present)
+                    memcpy(dst, tmp.data() + (size_t)(i - 1) * nn, nn * sizeof(double));
+                else
+                    memset(dst, 0, nn * sizeof(double));
+            }
+            continue;
+        }
         for (int64_t i = 1; i <= N; ++i) {
             const int l = btc::level_of(i);
             const int64_t s = (int64_t)1 << l;

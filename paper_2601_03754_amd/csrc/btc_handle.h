@@ -4,6 +4,9 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
 #include <stdint.h>
 #include <string.h>
 
@@ -85,6 +88,9 @@ struct btc_handle_s {
     // BTC_STRATEGY_KSTAGE, the remaining chain one block after the other
     int32_t strategy = BTC_STRATEGY_MULTISTAGE;
     int32_t nd_levels = 0;
+    // BTC_STRATEGY_PARTITION: p chunks, N_1 blocks in the first, N_k in the others
+    int32_t parts = 0;
+    int64_t part_n1 = 0, part_nk = 0;
     int levels = 0;  // floor(log2 N) + 1
     int device = 0;
     // FP64 factor (BTC_FP64)
@@ -333,6 +339,32 @@ void save_tune_cache();
 // Elimination order for BTC_STRATEGY_AUTO: the measured fastest for
 // (precision, N, padded n), else a rule.
 void select_strategy(int64_t N, int64_t n, int32_t prec, int32_t* strategy, int32_t* stages);
+
+// Chunk sizes of the partition order with p >= 2 chunks (Proposition 1):
+// a chunk after the first costs (19/3 N_k - 1) n^3, the first (7/3 N_1 - 1)
+// n^3, with N_1 = N - (p-1) - (p-1) N_k (p - 1 separating blocks).  The
+// balance point (7N - 7p + 7) / (7p + 12) is rounded down and up, and the
+// rounding whose larger phase cost is smaller kept (ties: down).  False when
+// no chunk sizes of at least one block exist.
+inline bool partition_sizes(int64_t N, int64_t p, int64_t& n1, int64_t& nk) {
+    if (p < 2) return false;
+    const double star = (7.0 * (double)N - 7.0 * (double)p + 7.0) / (7.0 * (double)p + 12.0);
+    bool found = false;
+    double best = 0.0;
+    for (int64_t c = (int64_t)std::floor(star); c <= (int64_t)std::ceil(star); ++c) {
+        if (c < 1) continue;
+        const int64_t first = N - (p - 1) - (p - 1) * c;
+        if (first < 1) continue;
+        const double cost = std::max(7.0 / 3.0 * (double)first - 1.0, 19.0 / 3.0 * (double)c - 1.0);
+        if (!found || cost < best) {
+            found = true;
+            best = cost;
+            n1 = first;
+            nk = c;
+        }
+    }
+    return found;
+}
 void strategy_set(int64_t N, int64_t n, int32_t prec, int32_t strategy, int32_t stages);
 
 // Factor kernel family of a handle at a level: 0 VALU FP64 (np < 16, or
@@ -421,6 +453,9 @@ inline btc::ChainDesc chain_desc(btc_handle h, const double* A_diag, const doubl
     c.n = (int32_t)h->n;
     c.k = h->nd_levels;
     c.m = (int32_t)m;
+    c.parts = h->strategy == BTC_STRATEGY_PARTITION ? h->parts : 0;
+    c.n1 = h->part_n1;
+    c.nk = h->part_nk;
     return c;
 }
 
@@ -440,6 +475,10 @@ inline int launch_factor(btc_handle h, const double* A_diag, const double* A_off
     if (h->strategy == BTC_STRATEGY_KSTAGE) {
         const btc::ChainDesc c = chain_desc(h, A_diag, A_off, nullptr, nullptr, 0);
         e = timed(h, 0, h->nd_levels, st, [&] { return btc::launch_chain_factor(c, btc::padded_block((int)h->n), st); });
+        if (e != hipSuccess) return to_code(e);
+    } else if (h->strategy == BTC_STRATEGY_PARTITION) {
+        const btc::ChainDesc c = chain_desc(h, A_diag, A_off, nullptr, nullptr, 0);
+        e = timed(h, 0, 0, st, [&] { return btc::launch_part_factor(c, btc::padded_block((int)h->n), st); });
         if (e != hipSuccess) return to_code(e);
     }
     h->A_diag = A_diag;
@@ -528,6 +567,8 @@ inline hipError_t chain_solve<double>(btc_handle h, const btc::SweepDesc<double>
     c.Y = d.Y;
     c.U = d.U;
     c.V = d.V;
+    if (h->strategy == BTC_STRATEGY_PARTITION)
+        return timed(h, 1, 0, st, [&] { return btc::launch_part_solve(c, btc::padded_block((int)h->n), st); });
     return timed(h, 1, h->nd_levels, st, [&] { return btc::launch_chain_solve(c, btc::padded_block((int)h->n), st); });
 }
 
@@ -543,7 +584,7 @@ inline hipError_t sweeps(btc_handle h, const btc::SweepDesc<T>& d, hipStream_t s
         hipError_t e = sweep_range(h, L, b[k], b[k + 1], false, st);
         if (e != hipSuccess) return e;
     }
-    if (h->strategy == BTC_STRATEGY_KSTAGE) {
+    if (h->strategy == BTC_STRATEGY_KSTAGE || h->strategy == BTC_STRATEGY_PARTITION) {
         hipError_t e = chain_solve(h, d, st);
         if (e != hipSuccess) return e;
     }

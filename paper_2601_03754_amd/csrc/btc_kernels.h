@@ -166,10 +166,16 @@ struct ChainDesc {
     int32_t n;
     int32_t k;
     int32_t m;
-    int32_t pad;
+    int32_t parts;  // partition order: number of chunks p (0: a k-stage chain)
+    int64_t n1;     // partition order: blocks of the first chunk
+    int64_t nk;     // partition order: blocks of every other chunk
 };
 hipError_t launch_chain_factor(const ChainDesc& p, int np, hipStream_t st);
 hipError_t launch_chain_solve(const ChainDesc& p, int np, hipStream_t st);
+// Partition order (Algorithm 2): the chunks in parallel, then the chain of
+// the p - 1 separating blocks.
+hipError_t launch_part_factor(const ChainDesc& p, int np, hipStream_t st);
+hipError_t launch_part_solve(const ChainDesc& p, int np, hipStream_t st);
 
 // FactorDesc.flags (tile-parallel families).  Eager: the Schur update of a
 // node's right separator S_{i+s} also subtracts T'^T T' of the node's right

@@ -390,8 +390,13 @@ BTC_API int btc_autotune_strategy(int64_t N, int64_t n, int32_t precision, const
     if (nrhs < 1) return -8;
     if (reps < 1) return -9;
     hipStream_t st = (hipStream_t)stream;
-    // candidates: multi-stage, then k-stage with k = 0, 1, 2
-    double t[4] = {-1.0, -1.0, -1.0, -1.0};
+    // candidates: multi-stage, k-stage with k = 0, 1, 2, partition with p = 2, 4
+    constexpr int kCand = 6;
+    double t[kCand] = {-1.0, -1.0, -1.0, -1.0, -1.0, -1.0};
+    auto cand = [](int c, int32_t& strategy, int32_t& stages) {
+        strategy = c == 0 ? BTC_STRATEGY_MULTISTAGE : c <= 3 ? BTC_STRATEGY_KSTAGE : BTC_STRATEGY_PARTITION;
+        stages = c == 0 ? 0 : c <= 3 ? c - 1 : (c == 4 ? 2 : 4);
+    };
     int best = -1;
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
@@ -399,12 +404,14 @@ BTC_API int btc_autotune_strategy(int64_t N, int64_t n, int32_t precision, const
         return BTC_ERR_HIP;
     }
     int rc = BTC_OK;
-    for (int c = 0; c < 4 && rc == BTC_OK; ++c) {
+    for (int c = 0; c < kCand && rc == BTC_OK; ++c) {
         btc_options o{};
         o.precision = precision;
-        o.strategy = c == 0 ? BTC_STRATEGY_MULTISTAGE : BTC_STRATEGY_KSTAGE;
-        o.stages = c == 0 ? 0 : c - 1;
-        if (c > 0 && (precision != BTC_FP64 || n > 64 || c - 1 >= num_levels(N))) continue;
+        cand(c, o.strategy, o.stages);
+        if (c > 0 && (precision != BTC_FP64 || n > 64)) continue;
+        if (o.strategy == BTC_STRATEGY_KSTAGE && o.stages >= num_levels(N)) continue;
+        int64_t n1 = 0, nk = 0;
+        if (o.strategy == BTC_STRATEGY_PARTITION && !partition_sizes(N, o.stages, n1, nk)) continue;
         btc_handle h = nullptr;
         rc = btc_create(N, n, &o, &h);
         if (rc != BTC_OK) break;
@@ -430,10 +437,12 @@ BTC_API int btc_autotune_strategy(int64_t N, int64_t n, int32_t precision, const
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (rc != BTC_OK) return rc;
-    strategy_set(N, n, precision, best == 0 ? BTC_STRATEGY_MULTISTAGE : BTC_STRATEGY_KSTAGE, best <= 0 ? 0 : best - 1);
+    int32_t bs = BTC_STRATEGY_MULTISTAGE, bk = 0;
+    cand(best < 0 ? 0 : best, bs, bk);
+    strategy_set(N, n, precision, bs, bk);
     save_tune_cache();
     if (ms)
-        for (int c = 0; c < 4; ++c) ms[c] = t[c];
+        for (int c = 0; c < kCand; ++c) ms[c] = t[c];
     return BTC_OK;
 }
 
