@@ -520,6 +520,39 @@ def batch_rate(btc, count=512, reps=3, tune=False):
             "converged": sum(1 for i in info if i["converged"]), "relres_max": worst}
 
 
+def conditioning_sweep(btc):
+    """The conditioning sweep at its own size: N = 4096, n = 64, four
+    right-hand sides, the diagonal shifted so that lambda_min(Psi) = c for c
+    in {4, 0.1, 0.001} (lambda_min of the unshifted matrix from
+    tests/golden/margin_lambda0.json, written by the oracle-based bisection);
+    FP32 and BF16 factors with classic FP64 refinement and BF16 with GMRES-
+    based refinement: refinement steps, inner GMRES iterations, the device's
+    FP64 relative residual, and the solve time."""
+    import torch
+    from paper_2601_03754_amd import inputs
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                                    "margin_lambda0.json")))
+    out = []
+    for c in (4.0, 0.1, 0.001):
+        pr = inputs.block_tridiag(g["N"], g["n"], c=c, seed=g["seed"], nrhs=g["nrhs"], margin=True,
+                                  lam0=g["lambda0"])
+        D, E, B = (torch.from_numpy(a).to("cuda:0") for a in (pr.D, pr.E, pr.B))
+        for name, prec, refine in (("fp32_ir", btc.BTC_FP32_IR, btc.BTC_REFINE_CLASSIC),
+                                   ("bf16_ir", btc.BTC_BF16_IR, btc.BTC_REFINE_CLASSIC),
+                                   ("bf16_gmres_ir", btc.BTC_BF16_IR, btc.BTC_REFINE_GMRES)):
+            f = btc.Factor(D, E, precision=prec, refine=refine)
+            f.solve(B, want_info=True)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X, info = f.solve(B, want_info=True)
+            ms = (time.perf_counter() - t0) * 1e3
+            f.close()
+            out.append({"c": c, "path": name, "converged": info["converged"], "steps": info["steps"],
+                        "inner": info["inner"], "relres": info["relres"], "solve_ms": round(ms, 3)})
+        del D, E, B
+    return out
+
+
 def latency_strategies(btc, N=16, n=8, reps=200):
     """The smallest configuration (N = 16, n = 8, FP64): milliseconds per
     refactor + solve of every elimination order, and the one the AUTO
@@ -690,11 +723,12 @@ def main():
     mixed, fp64 = paths["mixed"], paths["fp64"]
     extras = None
     if not args.no_extras:
-        log("other configurations: sweep table, batch, latency per strategy")
+        log("other configurations: sweep table, batch, latency per strategy, conditioning sweep")
         extras = {"sweep_fp64": sweep_table(btc),
                   "batch": batch_rate(btc),
                   "batch_autotuned": batch_rate(btc, tune=True),
-                  "latency_n16_n8": latency_strategies(btc)}
+                  "latency_n16_n8": latency_strategies(btc),
+                  "conditioning_n4096_n64": conditioning_sweep(btc)}
         log("batch: %.0f instances/s, autotuned %.0f" % (extras["batch"]["instances_per_s"],
                                                          extras["batch_autotuned"]["instances_per_s"]))
     cpu = None

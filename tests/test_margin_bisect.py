@@ -6,7 +6,7 @@ eigensolver at sizes where that one is quick.  CPU only."""
 import pytest
 
 from paper_2601_03754_amd import inputs
-from test_gpu_full import lambda0_bisect
+from margin import lambda0_bisect
 
 
 @pytest.mark.parametrize("N,n,seed", [(64, 8, 1), (200, 12, 2), (33, 20, 3)])
