@@ -300,7 +300,9 @@ def run_served(args, btc):
         dom = stats[0]
         # timed region: only the dominant group's family carries events
         btc.runner_profile(rh, -1 if args.profile_all else dom["op"], -1 if args.profile_all else dom["kind"])
+        btc.runner_host_stats(rh, reset=True)
         done, wall = sv.closed_loop(per_step * args.steps)
+        hstat = btc.runner_host_stats(rh)
         allstats = btc.runner_profile_read(rh)
         totals = None
         if args.profile_all:
@@ -336,6 +338,15 @@ def run_served(args, btc):
                             "relres_max_last_torch": relres},
                "per_class": per_class,
                "server_ticks": loop["ticks"], "host_step_frac": loop["host_step_s"] / loop["wall_s"],
+               # where the host's time per tick goes: planning in the server,
+               # enqueueing in the runner, and waiting for the device to free
+               # a descriptor slot (the device is then the bottleneck)
+               "host_us_per_tick": {
+                   "step": loop["host_step_s"] / max(1, loop["ticks"]) * 1e6,
+                   "planning": (loop["host_step_s"] - hstat["run_s"]) / max(1, loop["ticks"]) * 1e6,
+                   "enqueue": (hstat["run_s"] - hstat["wait_s"]) / max(1, loop["ticks"]) * 1e6,
+                   "device_wait": hstat["wait_s"] / max(1, loop["ticks"]) * 1e6,
+                   "wall": loop["wall_s"] / max(1, loop["ticks"]) * 1e6},
                "max_relres_last": relres,
                "warmup_kernel_ms": [{"kernel": roofline_entry(s)["kernel"], "ms": round(s["ms"], 3),
                                      "launches": s["launches"],

@@ -388,6 +388,14 @@ BTC_API int btc_runner_query(btc_runner r);
 /* btc_runner_sync -- wait for all enqueued work. */
 BTC_API int btc_runner_sync(btc_runner r);
 
+/* btc_runner_host_stats -- host time spent in btc_runner_run since the
+ * runner was created (or last reset): *run_s in total, *wait_s of it blocked
+ * until the device released a descriptor staging slot (the runner keeps two;
+ * a call waits when the call two before it has not finished on the device),
+ * *calls the number of calls (any pointer may be NULL).  reset != 0 clears
+ * the counters after reading them. */
+BTC_API int btc_runner_host_stats(btc_runner r, double *run_s, double *wait_s, int64_t *calls, int reset);
+
 /* btc_runner_destroy -- wait for the runner's work and free it (NULL: no-op). */
 BTC_API void btc_runner_destroy(btc_runner r);
 

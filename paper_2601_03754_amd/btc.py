@@ -205,6 +205,9 @@ def lib():
         L.btc_sweep_ranges.argtypes = [i64, ctypes.POINTER(i32), i32]
         L.btc_set_allocator.restype = ctypes.c_int
         L.btc_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
+        L.btc_runner_host_stats.restype = ctypes.c_int
+        L.btc_runner_host_stats.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(i64),
+                                            ctypes.c_int]
         L.btc_autotune_batched.restype = ctypes.c_int
         L.btc_autotune_batched.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                            ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64), i32]
@@ -516,6 +519,15 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def runner_host_stats(r: int, reset: bool = False) -> dict:
+    """Host seconds in btc_runner_run (total, and blocked waiting for the
+    device) and the number of calls, since creation or the last reset."""
+    a, b, c = dbl(), dbl(), i64()
+    _check(lib().btc_runner_host_stats(r, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 1 if reset else 0),
+           "btc_runner_host_stats")
+    return {"run_s": a.value, "wait_s": b.value, "calls": c.value}
 
 
 def runner_profile(r: int, op: int = -1, kind: int = -1) -> None:

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <new>
@@ -95,6 +96,10 @@ struct btc_runner_s {
     bool recording = false;
     std::vector<Call> rec;
     std::vector<btc_handle> rec_handles;
+    // host time of btc_runner_run (seconds) and the part of it spent waiting
+    // for the device to release a staging slot
+    double host_run_s = 0.0, host_wait_s = 0.0;
+    int64_t host_calls = 0;
 };
 
 struct btc_graph_s {
@@ -167,7 +172,10 @@ namespace {
 
 int slot_reserve(btc_runner r, btc_runner_s::Slot& s, size_t bytes) {
     if (s.pending) {
-        if (hipEventSynchronize(s.ev) != hipSuccess) return BTC_ERR_HIP;
+        const auto t0 = std::chrono::steady_clock::now();
+        const hipError_t e = hipEventSynchronize(s.ev);
+        r->host_wait_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (e != hipSuccess) return BTC_ERR_HIP;
         s.pending = false;
     }
     if (bytes > s.hcap) {
@@ -600,8 +608,33 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
 
 }  // namespace
 
+namespace {
+int runner_run(btc_runner r, int32_t count, const btc_step* steps);
+}
+
 BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
     if (!r) return -1;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = runner_run(r, count, steps);
+    r->host_run_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    r->host_calls += 1;
+    return rc;
+}
+
+BTC_API int btc_runner_host_stats(btc_runner r, double* run_s, double* wait_s, int64_t* calls, int reset) {
+    if (!r) return -1;
+    if (run_s) *run_s = r->host_run_s;
+    if (wait_s) *wait_s = r->host_wait_s;
+    if (calls) *calls = r->host_calls;
+    if (reset) {
+        r->host_run_s = r->host_wait_s = 0.0;
+        r->host_calls = 0;
+    }
+    return BTC_OK;
+}
+
+namespace {
+int runner_run(btc_runner r, int32_t count, const btc_step* steps) {
     if (count < 0) return -2;
     if (count > 0 && !steps) return -3;
     if (count == 0) return BTC_OK;
@@ -626,6 +659,7 @@ BTC_API int btc_runner_run(btc_runner r, int32_t count, const btc_step* steps) {
     r->cur ^= 1;
     return launch_call(r, c, sl.dev, st, true);
 }
+}  // namespace
 
 
 BTC_API int btc_graph_begin(btc_runner r) {

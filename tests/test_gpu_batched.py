@@ -96,10 +96,17 @@ def test_runner_steps_at_different_levels_in_one_launch(btc):
 
     qa = plan(ha, Da, Ea, Ba, Xa, La)
     qb = [None] * 3 + plan(hb, Db, Eb, Bb, Xb, Lb)  # B arrives three ticks later
-    for t in range(max(len(qa), len(qb))):
+    btc.runner_host_stats(r.handle, reset=True)
+    ticks = max(len(qa), len(qb))
+    for t in range(ticks):
         batch = [q[t] for q in (qa, qb) if t < len(q) and q[t] is not None]
         r.run(batch)
     r.sync()
+    # the host-time counters: one call per tick, the wait part of the total
+    hs = btc.runner_host_stats(r.handle, reset=True)
+    assert hs["calls"] == ticks
+    assert 0.0 < hs["run_s"] and 0.0 <= hs["wait_s"] <= hs["run_s"]
+    assert btc.runner_host_stats(r.handle) == {"run_s": 0.0, "wait_s": 0.0, "calls": 0}
     for p, X, h in ((pa, Xa, ha), (pb, Xb, hb)):
         Xs, _, _ = single(btc, p, 0)
         assert np.array_equal(X.cpu().numpy(), Xs)
