@@ -46,7 +46,6 @@ __global__ __launch_bounds__(MfmaCfg<NP>::NT) void k_factor_level_mfma(Launch<Fa
     __shared__ double sC[NP * LD];         // S_{i+s}
     __shared__ double sInv[W][kT * kLDI];  // inverted diagonal tiles of L_ii (W = NP/16)
     __shared__ double invd[NP];
-    __shared__ __align__(16) double colbuf[2][kWave];
     __shared__ int fail;
 
     FactorDesc P;
@@ -124,7 +123,7 @@ __global__ __launch_bounds__(MfmaCfg<NP>::NT) void k_factor_level_mfma(Launch<Fa
     // diagonal tiles
     cr.put(sB, tid);
     cl.put(sD, tid);
-    const bool ok = potrf_blocked<NP, LD, W>(sS, invd, sInv, colbuf, &fail);
+    const bool ok = potrf_blocked<NP, LD, W>(sS, invd, sInv, &fail);
     if (!ok) {
         if (tid == 0) atomicMin(P.info, (unsigned long long)i);
         return;

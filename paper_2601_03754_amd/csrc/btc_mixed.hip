@@ -57,7 +57,6 @@ __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(Launch<Fa
     __shared__ float fInv[W][kT * kLDI];
     __shared__ double sInv[W][kT * kLDI];  // inverted diagonal tiles (FP64, W = NP/16)
     __shared__ double invd[NP];
-    __shared__ __align__(16) double colbuf[2][kWave];
     __shared__ int fail;
 
     FactorDesc P;
@@ -132,7 +131,7 @@ __global__ __launch_bounds__(MixCfg<NP>::NT) void k_factor_level_mixed(Launch<Fa
     // P3: couplings to LDS; blocked FP64 Cholesky of S_i by all wavefronts
     cr.put(fB, tid);
     cl.put(fD, tid);
-    const bool ok = potrf_blocked<NP, LD, W>(sS, invd, sInv, colbuf, &fail);
+    const bool ok = potrf_blocked<NP, LD, W>(sS, invd, sInv, &fail);
     if (!ok) {
         if (tid == 0) atomicMin(P.info, (unsigned long long)i);
         return;

@@ -252,14 +252,15 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
 // coupling tiles read straight from HBM into the accumulator layout, two
 // tiles ahead of their use.
 // Wavefronts of K2 and workgroups per compute unit (measured: at padded size
-// 64 five nodes of four wavefronts per CU beat three of eight; at 96 two of
-// eight beat three of four, whose strips take three rounds).
+// 64 four nodes of four wavefronts per CU beat five (whose register budget
+// of 96 spills) and three of eight; at 96 two of eight beat three of four,
+// whose strips take three rounds).
 template <int NP>
 constexpr int k2_waves() { return NP == 96 ? 8 : 4; }
 // The register budget is held to the workgroups per CU (the second launch
 // bound counts wavefronts per SIMD).
 template <int NP>
-constexpr int k2_blocks() { return NP <= 64 ? 5 : NP <= 96 ? 2 : 1; }
+constexpr int k2_blocks() { return NP <= 64 ? 4 : NP <= 96 ? 2 : 1; }
 
 // A launch of at most one node per compute unit is bound by one node's
 // latency, not by the throughput of nodes sharing a unit: at padded size 96
@@ -281,7 +282,6 @@ __global__ __launch_bounds__(NW * kWave, (NB * NW + 3) / 4) void k_tiled_potrf_t
     // diagonal tile holding its inverse (transposed)
     __shared__ double sS[packed_lds_elems<NP>()];
     __shared__ double invd[NP];
-    __shared__ __align__(16) double colbuf[2][kWave];
     // one 16 x 16 tile per wavefront: R strip tiles pass through it between
     // the row-major layout of R_i in HBM and the transposed register layout
     __shared__ double xbuf[NW][kT * kLDI];
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(NW * kWave, (NB * NW + 3) / 4) void k_tiled_potrf_t
     stage_lower_packed<NP, NW * kWave>(sS, src, n, tid);
     if (tid == 0) fail = 0;
     __syncthreads();
-    const bool ok = potrf_blocked<NP, kLDI, NW, PackedLds, 2>(sS, invd, nullptr, colbuf, &fail);
+    const bool ok = potrf_blocked<NP, kLDI, NW, PackedLds, 2>(sS, invd, nullptr, &fail, xbuf);
     if (!ok) {
         if (tid == 0) atomicMin(P.info, (unsigned long long)d.i);
         return;

@@ -124,10 +124,60 @@ __device__ __forceinline__ void tri_tile(int k, int& a, int& b) {
     b = k - a * (a + 1) / 2;
 }
 
-// Cholesky of an NP x NP tile (NP <= 16) by one wavefront with lane r holding
-// row r: the multipliers of column j reach the other columns by readlane
-// broadcasts (no LDS round trip on the pivot chain).  Same contract as
-// potrf_lookahead.
+// 1/sqrt(p): hardware estimate r refined by one third-order step.  With
+// e = 1 - p r^2, 1/sqrt(p) = r (1 - e)^(-1/2) = r (1 + e/2 + 3e^2/8 + ...);
+// the estimate's e of about 1e-7 leaves a truncation term near 1e-22, and
+// the chain is four dependent operations instead of two Newton steps' six.
+__device__ __forceinline__ double rsqrt_refined(double p) {
+    const double r = __builtin_amdgcn_rsq(p);
+    const double e = fma(-p * r, r, 1.0);
+    return fma(r * e, fma(e, 0.375, 0.5), r);
+}
+
+// Cholesky of a 16-column panel held one row per lane: lanes 0..NC-1 hold
+// the rows of the NC x NC diagonal tile (zeros above the diagonal), any other
+// lane a row below it (or zeros).  Column j: the pivot row's lane forms
+// L_jj, every lane below it its multiplier a_rj / L_jj (for the rows below
+// the tile this is the triangular solve x L_pp^T = a), and the multipliers of
+// the pivot rows reach the later columns by readlane broadcasts (no LDS round
+// trip on the chain).  On return a holds the rows of L, myinv 1/L_rr on lane
+// r < NC; false on a non-positive or NaN pivot.
+template <int NC>
+__device__ __forceinline__ bool chol_rows(double (&a)[NC], double& myinv) {
+    const int lane = threadIdx.x & (kWave - 1);
+    double piv = readlane_d(a[0], 0);
+    double r = rsqrt_refined(piv);
+    myinv = 1.0;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        ok = ok && (piv > 0.0);
+        double l = a[j] * r;
+        l = (lane == j) ? piv * r : l;
+        l = (lane < j) ? 0.0 : l;
+        myinv = (lane == j) ? r : myinv;
+        a[j] = l;
+        if (j + 1 < NC) {
+            // the next pivot first: its reciprocal square root overlaps the
+            // rest of this column's update
+            a[j + 1] = fma(-l, readlane_d(l, j + 1), a[j + 1]);
+            piv = readlane_d(a[j + 1], j + 1);
+            const double rn = rsqrt_refined(piv);
+            double lc[NC];
+#pragma unroll
+            for (int c = j + 2; c < NC; ++c) lc[c] = readlane_d(l, c);
+#pragma unroll
+            for (int c = j + 2; c < NC; ++c) a[c] = fma(-l, lc[c], a[c]);
+            r = rn;
+        }
+    }
+    return ok;
+}
+
+// Cholesky of the lower triangle of an NP x NP LDS tile (NP <= 16, row
+// stride LD) by one wavefront with lane r holding row r: writes L back (zero
+// strict upper part) and 1/L_jj to invd; false on a non-positive or NaN
+// pivot.
 template <int NP, int LD = NP + 1>
 __device__ __forceinline__ bool potrf_small(double* __restrict__ A, double* __restrict__ invd) {
     static_assert(NP <= 16, "small tiles only");
@@ -135,95 +185,8 @@ __device__ __forceinline__ bool potrf_small(double* __restrict__ A, double* __re
     double a[NP];
 #pragma unroll
     for (int c = 0; c < NP; ++c) a[c] = (lane < NP && c <= lane) ? A[lane * LD + c] : 0.0;
-    // 1/sqrt(p): hardware estimate r refined by one third-order step.  With
-    // e = 1 - p r^2, 1/sqrt(p) = r (1 - e)^(-1/2) = r (1 + e/2 + 3e^2/8 + ...);
-    // the estimate's e of about 1e-7 leaves a truncation term near 1e-22, and
-    // the chain is four dependent operations instead of two Newton steps' six.
-    auto rsqrt_refined = [](double p) {
-        const double r = __builtin_amdgcn_rsq(p);
-        const double e = fma(-p * r, r, 1.0);
-        return fma(r * e, fma(e, 0.375, 0.5), r);
-    };
-    double piv = readlane_d(a[0], 0);
-    double r = rsqrt_refined(piv);
-    double myinv = 1.0;
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        ok = ok && (piv > 0.0);
-        double l = a[j] * r;
-        l = (lane == j) ? piv * r : l;
-        l = (lane < j) ? 0.0 : l;
-        myinv = (lane == j) ? r : myinv;
-        a[j] = l;
-        if (j + 1 < NP) {
-            // the next pivot first: its reciprocal square root overlaps the
-            // rest of this column's update
-            a[j + 1] = fma(-l, readlane_d(l, j + 1), a[j + 1]);
-            piv = readlane_d(a[j + 1], j + 1);
-            const double rn = rsqrt_refined(piv);
-            double lc[NP];
-#pragma unroll
-            for (int c = j + 2; c < NP; ++c) lc[c] = readlane_d(l, c);
-#pragma unroll
-            for (int c = j + 2; c < NP; ++c) a[c] = fma(-l, lc[c], a[c]);
-            r = rn;
-        }
-    }
-    if (lane < NP) {
-#pragma unroll
-        for (int c = 0; c < NP; ++c) A[lane * LD + c] = (c <= lane) ? a[c] : 0.0;
-        invd[lane] = myinv;
-    }
-    return ok;
-}
-
-// Cholesky of the lower triangle of an NP x NP LDS tile by one wavefront,
-// lane r holding row r in registers.  The pivot of step j+1 is formed right
-// after step j from two readlanes (the new column j value of row j+1 is its
-// own multiplier), so the pivot chain never waits for the LDS broadcast; the
-// rest of the column is broadcast through a double-buffered LDS column for
-// the trailing update.  1/sqrt of the pivot: hardware estimate refined by two
-// Newton steps.  Writes L (zero strict upper part) back and 1/L_jj to invd.
-template <int NP, int LD = NP + 1>
-__device__ __forceinline__ bool potrf_lookahead(double* __restrict__ A, double* __restrict__ invd,
-                                                double (*__restrict__ colbuf)[kWave]) {
-    static_assert(NP <= kWave, "one lane per row");
-    const int lane = threadIdx.x & (kWave - 1);
-    double a[NP];
-#pragma unroll
-    for (int c = 0; c < NP; ++c) a[c] = (lane < NP && c <= lane) ? A[lane * LD + c] : 0.0;
-    double piv = readlane_d(a[0], 0);
-    double myinv = 1.0;  // 1/L_rr of this lane's row r
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        ok = ok && (piv > 0.0);
-        double r = __builtin_amdgcn_rsq(piv);
-        double e = fma(-piv * r, r, 1.0);
-        r = fma(0.5 * r, e, r);
-        e = fma(-piv * r, r, 1.0);
-        r = fma(0.5 * r, e, r);
-        const double d = piv * r;
-        double l = a[j] * r;
-        l = (lane == j) ? d : l;
-        l = (lane < j) ? 0.0 : l;
-        myinv = (lane == j) ? r : myinv;
-        a[j] = l;
-        if (j + 1 < NP) {
-            double* cb = colbuf[j & 1];
-            cb[lane] = l;
-            const double lj1 = readlane_d(l, j + 1);
-            a[j + 1] = fma(-l, lj1, a[j + 1]);
-            piv = readlane_d(a[j + 1], j + 1);
-#pragma unroll
-            for (int c0 = (j + 2) & ~1; c0 < NP; c0 += 2) {
-                const double2 v = *reinterpret_cast<const double2*>(cb + c0);
-                if (c0 >= j + 2) a[c0] = fma(-l, v.x, a[c0]);
-                a[c0 + 1] = fma(-l, v.y, a[c0 + 1]);
-            }
-        }
-    }
+    double myinv;
+    const bool ok = chol_rows<NP>(a, myinv);
     if (lane < NP) {
 #pragma unroll
         for (int c = 0; c < NP; ++c) A[lane * LD + c] = (c <= lane) ? a[c] : 0.0;
@@ -285,83 +248,151 @@ __device__ __forceinline__ void tile_inverse_upper(double* T, const double* __re
 
 // Blocked Cholesky of the lower triangle of an NP x NP LDS tile (row stride
 // LD) by all NW wavefronts of the workgroup (every thread must call it), in
-// 16-column panels: wavefront 0 factors the diagonal tile (potrf_small); the
-// rows below it are solved against it by substitution, one row per thread
-// (L_tp = A_tp L_pp^{-T}); the trailing lower tiles are updated, A_ab -=
-// L_ap L_bp^T (matrix cores, tiles spread over the wavefronts), wavefront 0
-// taking the next diagonal tile and factoring it right away (look-ahead:
-// the pivot chain does not wait for the rest of the trailing update).  The 16 x 16
-// diagonal tiles are inverted at the end, off the pivot chain, spread over
-// the wavefronts.  On return: L in the lower triangle (strict upper part of
-// each diagonal tile zeroed, tiles above the diagonal untouched), 1/L_jj in
-// invd, the inverted diagonal tiles in inv[NP/16] (row stride kLDI).  *fail
-// (LDS, 0 on entry) becomes 1 on a non-positive or NaN pivot; the result is
-// then false for every thread.
+// 16-column panels.  A panel is factored in registers, one row per lane, by
+// chol_rows: each panel wavefront holds the 16 rows of the diagonal tile in
+// lanes 0..15 (every panel wavefront repeats that part of the chain, so no
+// wavefront waits on another inside a panel) and up to 48 rows below it in
+// lanes 16..63, whose multipliers are the triangular solve L_tp = A_tp
+// L_pp^{-T}.  Look-ahead: the panel wavefronts of panel p+1 apply panel p's
+// update to their own tiles of column p+1 (A_ap -= L_ap L_(p+1)p^T; the
+// diagonal tile into the wavefront's scratch tile when two or more
+// wavefronts share the panel) and factor it at once, while the other
+// wavefronts update the trailing tiles right of column p+1 (matrix cores).
+// The 16 x 16 diagonal tiles are inverted at
+// the end, spread over the wavefronts.  On return: L in the lower triangle
+// (strict upper part of each diagonal tile zeroed, tiles above the diagonal
+// untouched), 1/L_jj in invd, the inverted diagonal tiles in inv[NP/16] (row
+// stride kLDI).  *fail (LDS, 0 on entry) becomes 1 on a non-positive or NaN
+// pivot; the result is then false for every thread.
 // INV: where the inverted diagonal tiles go: 1 the array inv (row stride
 // kLDI), 2 transposed into the strict upper part of each diagonal tile.
+// scr: one 16 x kLDI tile per panel wavefront, needed when a panel has more
+// than 48 rows below its diagonal tile (NP > 64).
 template <int NP, int LD, int NW, class Lay = SquareLds<LD>, int INV = 1>
 __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __restrict__ invd,
-                                              double (*__restrict__ inv)[kT * kLDI],
-                                              double (*__restrict__ colbuf)[kWave], int* fail) {
+                                              double (*__restrict__ inv)[kT * kLDI], int* fail,
+                                              double (*__restrict__ scr)[kT * kLDI] = nullptr) {
     constexpr int NTL = NP / kT;
     constexpr int LT = Lay::LDT;
-    static_assert(NW >= 2 || NTL == 1, "the look-ahead needs a second wavefront");
+    constexpr int kBelow = kWave - kT;  // rows below the diagonal tile per panel wavefront
+    // wavefronts that factor panel q
+    constexpr auto pwaves = [](int q) { return NP - (q + 1) * kT <= 0 ? 1 : (NP - (q + 1) * kT + kBelow - 1) / kBelow; };
+    static_assert(pwaves(0) <= NW, "too few wavefronts for the first panel");
+    static_assert(NTL <= 2 || pwaves(1) < NW, "the trailing update needs a wavefront outside the panel");
+    static_assert(kBelow % kT == 0, "whole tiles per panel wavefront");
+    constexpr int kTilesBelow = kBelow / kT;
+    constexpr bool kShared = pwaves(0) > 1;  // some panel has two or more wavefronts
     const int tid = threadIdx.x;
     const int w = wave_id();
-    if (w == 0) {
-        const bool ok = potrf_small<kT, LT>(Lay::tile(A, 0, 0), invd);
-        if (!ok && (tid & 63) == 0) *fail = 1;
+    const int lane = tid & 63;
+    double a[kT];
+    double myinv = 1.0;
+    // this wavefront's rows of panel q into registers (lanes 0..15 from the
+    // diagonal tile at D with row stride ldd, the others from the tiles below)
+    auto load_rows = [&](int q, const double* D, int ldd) {
+        const int below = NP - (q + 1) * kT;
+        const int rb = kBelow * w + lane - kT;
+        const bool diag = lane < kT;
+        const bool has = diag || rb < below;
+        // every lane loads from a valid row (a lane without a row reads the
+        // diagonal tile's first row and keeps zeros)
+        const double* row = diag ? D + lane * ldd : has ? Lay::tile(A, q + 1 + rb / kT, q) + (rb % kT) * LT : D;
+#pragma unroll
+        for (int c = 0; c < kT; ++c) {
+            const double x = row[c];
+            a[c] = (has && (!diag || c <= lane)) ? x : 0.0;
+        }
+    };
+    // wavefront 0's rows of the factored diagonal tile q: into the tile
+    // itself when it factored the panel alone (no other wavefront reads that
+    // tile), else into its scratch tile, copied into place after the barrier
+    // (the other panel wavefronts read the unfactored tile before it)
+    auto store_diag = [&](int q) {
+        if (w == 0 && lane < kT) {
+            const bool alone = !kShared || pwaves(q) == 1;
+            double* row = alone ? Lay::tile(A, q, q) + lane * LT : scr[0] + lane * kLDI;
+#pragma unroll
+            for (int c = 0; c < kT; ++c) row[c] = (c <= lane) ? a[c] : 0.0;
+        }
+    };
+    auto place_diag = [&](int q) {
+        if (kShared && pwaves(q) > 1 && w == 0) {
+            wave_lds_sync();
+            for (int e = lane; e < kT * kT; e += kWave)
+                Lay::tile(A, q, q)[(e / kT) * LT + e % kT] = scr[0][(e / kT) * kLDI + e % kT];
+            wave_lds_sync();
+        }
+    };
+    // factor panel q (rows loaded), store the rows below the diagonal tile
+    // and 1/L_jj
+    auto factor_rows = [&](int q) {
+        const bool ok = chol_rows<kT>(a, myinv);
+        if (!ok && lane == 0) *fail = 1;
+        const int below = NP - (q + 1) * kT;
+        const int rb = kBelow * w + lane - kT;
+        if (lane >= kT && rb < below) {
+            double* row = Lay::tile(A, q + 1 + rb / kT, q) + (rb % kT) * LT;
+#pragma unroll
+            for (int c = 0; c < kT; ++c) row[c] = a[c];
+        }
+        if (w == 0 && lane < kT) invd[q * kT + lane] = myinv;
+        store_diag(q);
+    };
+    // A_ab -= L_ap L_bp^T
+    auto update = [&](int ta, int tb, int p) {
+        double* Tab = Lay::tile(A, ta, tb);
+        d4 acc;
+        acc_load_lds<LT>(acc, Tab, 0, 0);
+        mma_tile<LT, LT, false, true, true>(acc, Lay::tile(A, ta, p), 0, 0, Lay::tile(A, tb, p), 0, 0, kT);
+        acc_store_lds<LT>(acc, Tab, 0, 0);
+    };
+    if (w < pwaves(0)) {
+        load_rows(0, Lay::tile(A, 0, 0), LT);
+        factor_rows(0);
     }
     __syncthreads();
     if (*fail) return false;
 #pragma unroll 1
-    for (int p = 0; p < NTL; ++p) {
-        const int c0 = p * kT;
-        const double* D = Lay::tile(A, p, p);
-        // rows below the diagonal tile: x L_pp^T = a, forward substitution
-        // by columns (each finished x_c updates the later ones independently)
-        const int rows = NP - c0 - kT;
-        for (int t = tid; t < rows; t += NW * kWave) {
-            double* row = Lay::tile(A, p + 1 + t / kT, p) + (t % kT) * LT;
-            double x[kT];
-#pragma unroll
-            for (int c = 0; c < kT; ++c) x[c] = row[c];
-#pragma unroll
-            for (int c = 0; c < kT; ++c) {
-                x[c] *= invd[c0 + c];
-#pragma unroll
-                for (int k = c + 1; k < kT; ++k) x[k] = fma(-x[c], D[k * LT + c], x[k]);
+    for (int p = 0; p + 1 < NTL; ++p) {
+        const int q = p + 1;
+        const int pw = kShared ? pwaves(q) : 1;
+        place_diag(p);
+        if (w < pw) {
+            // this wavefront's tiles of column q below the diagonal tile
+#pragma unroll 1
+            for (int t = 0; t < kTilesBelow; ++t) {
+                const int ta = q + 1 + kTilesBelow * w + t;
+                if (ta < NTL) update(ta, q, p);
             }
-#pragma unroll
-            for (int c = 0; c < kT; ++c) row[c] = x[c];
-        }
-        __syncthreads();
-        const int m = NTL - 1 - p;
-        if (m == 0) break;
-        // trailing update A_ab -= L_ap L_bp^T.  Look-ahead: wavefront 0
-        // updates the next diagonal tile and factors it at once, while the
-        // others update the rest of the trailing tiles.
-        auto update = [&](int k) {
-            int ta, tb;
-            tri_tile(k, ta, tb);
-            const int a = p + 1 + ta, b = p + 1 + tb;
-            double* Tab = Lay::tile(A, a, b);
+            // the diagonal tile: in place when this wavefront factors the
+            // panel alone, else into its scratch tile
             d4 acc;
-            acc_load_lds<LT>(acc, Tab, 0, 0);
-            mma_tile<LT, LT, false, true, true>(acc, Lay::tile(A, a, p), 0, 0, Lay::tile(A, b, p), 0, 0, kT);
-            acc_store_lds<LT>(acc, Tab, 0, 0);
-        };
-        if (w == 0) {
-            update(0);
-            wave_lds_sync();
-            const bool ok = potrf_small<kT, LT>(Lay::tile(A, p + 1, p + 1), invd + c0 + kT);
-            if (!ok && (tid & 63) == 0) *fail = 1;
+            acc_load_lds<LT>(acc, Lay::tile(A, q, q), 0, 0);
+            mma_tile<LT, LT, false, true, true>(acc, Lay::tile(A, q, p), 0, 0, Lay::tile(A, q, p), 0, 0, kT);
+            if (!kShared || pw == 1) {
+                acc_store_lds<LT>(acc, Lay::tile(A, q, q), 0, 0);
+                wave_lds_sync();
+                load_rows(q, Lay::tile(A, q, q), LT);
+            } else {
+                acc_store_lds<kLDI>(acc, scr[w], 0, 0);
+                wave_lds_sync();
+                load_rows(q, scr[w], kLDI);
+            }
+            factor_rows(q);
         } else {
-            for (int k = w; k < m * (m + 1) / 2; k += NW - 1) update(k);
+            // the trailing tiles right of column q
+            const int m = NTL - 1 - q;
+            for (int k = w - pw; k < m * (m + 1) / 2; k += NW - pw) {
+                int ta, tb;
+                tri_tile(k, ta, tb);
+                update(q + 1 + ta, q + 1 + tb, p);
+            }
         }
         __syncthreads();
         if (*fail) return false;
     }
+    place_diag(NTL - 1);
+    __syncthreads();
     if (INV == 1)
         for (int t = w; t < NTL; t += NW) tile_inverse<LT, double>(Lay::tile(A, t, t), 0, invd + t * kT, inv[t]);
     else
