@@ -293,7 +293,7 @@ __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __
         const int below = NP - (q + 1) * kT;
         const int rb = kBelow * w + lane - kT;
         const bool diag = lane < kT;
-        const bool has = diag || rb < below;
+        const bool has = diag || (lane - kT < kBelow && rb < below);
         // every lane loads from a valid row (a lane without a row reads the
         // diagonal tile's first row and keeps zeros)
         const double* row = diag ? D + lane * ldd : has ? Lay::tile(A, q + 1 + rb / kT, q) + (rb % kT) * LT : D;
@@ -330,7 +330,7 @@ __device__ __forceinline__ bool potrf_blocked(double* __restrict__ A, double* __
         if (!ok && lane == 0) *fail = 1;
         const int below = NP - (q + 1) * kT;
         const int rb = kBelow * w + lane - kT;
-        if (lane >= kT && rb < below) {
+        if (lane >= kT && lane - kT < kBelow && rb < below) {
             double* row = Lay::tile(A, q + 1 + rb / kT, q) + (rb % kT) * LT;
 #pragma unroll
             for (int c = 0; c < kT; ++c) row[c] = a[c];
