@@ -185,10 +185,10 @@ class Served:
     """One server (one precision) over the clients, with the bookkeeping of
     the requests a run submits."""
 
-    def __init__(self, btc, clients, precision, seed, sweep_ranges=False, hbm_budget=1 << 46):
+    def __init__(self, btc, clients, precision, seed, sweep_ranges=False, hbm_budget=1 << 46, lanes=0):
         self.btc = btc
         self.cl = clients
-        self.srv = btc.Server(precision=precision, hbm_budget=hbm_budget, sweep_ranges=sweep_ranges)
+        self.srv = btc.Server(precision=precision, hbm_budget=hbm_budget, sweep_ranges=sweep_ranges, lanes=lanes)
         self.ids = [self.srv.add_client(N, n) for N, n in clients.shapes]
         self.rng = np.random.default_rng(seed)
         self.ver = [0] * len(self.ids)
@@ -275,6 +275,35 @@ class Served:
         self.srv.close()
 
 
+def prof_on(btc, rhs, op, kind):
+    for r in rhs:
+        btc.runner_profile(r, op, kind)
+
+
+def prof_read(btc, rhs):
+    """Launch-profile totals summed over the server's lane runners, largest
+    time first."""
+    agg = {}
+    for r in rhs:
+        for st in btc.runner_profile_read(r):
+            k = (st["op"], st["kind"], st["np"], st["part"])
+            if k in agg:
+                for f in ("launches", "items", "ms", "bytes", "flops"):
+                    agg[k][f] += st[f]
+            else:
+                agg[k] = dict(st)
+    return sorted(agg.values(), key=lambda st: -st["ms"])
+
+
+def host_stats(btc, rhs, reset=False):
+    tot = {"run_s": 0.0, "wait_s": 0.0, "calls": 0}
+    for r in rhs:
+        h = btc.runner_host_stats(r, reset=reset)
+        for k in tot:
+            tot[k] += h[k]
+    return tot
+
+
 def lat_ms(done, key="t_submit", drop=0.05):
     d = done[int(len(done) * drop):]
     return [(x["t_done"] - x[key]) * 1e3 for x in d]
@@ -291,19 +320,21 @@ def run_served(args, btc):
     rates_out = []
     roof = None
     for name, prec in (("mixed", btc.BTC_FP32_IR), ("fp64", btc.BTC_FP64)):
-        sv = Served(btc, cl, prec, seed=1, sweep_ranges=args.sweep_ranges)
-        rh = sv.srv.runner_handle()
+        sv = Served(btc, cl, prec, seed=1, sweep_ranges=args.sweep_ranges, lanes=args.lanes)
+        rhs = sv.srv.runner_handles()
         # warm-up: first requests factor every client; profile every group
-        btc.runner_profile(rh, -1, -1)
+        prof_on(btc, rhs, -1, -1)
         sv.closed_loop(per_step * max(1, args.warmup))
-        stats = btc.runner_profile_read(rh)
+        stats = prof_read(btc, rhs)
         dom = stats[0]
         # timed region: only the dominant group's family carries events
-        btc.runner_profile(rh, -1 if args.profile_all else dom["op"], -1 if args.profile_all else dom["kind"])
-        btc.runner_host_stats(rh, reset=True)
+        prof_on(btc, rhs, -1 if args.profile_all else dom["op"], -1 if args.profile_all else dom["kind"])
+        host_stats(btc, rhs, reset=True)
+        sv.srv.host_stats(reset=True)
         done, wall = sv.closed_loop(per_step * args.steps)
-        hstat = btc.runner_host_stats(rh)
-        allstats = btc.runner_profile_read(rh)
+        hstat = host_stats(btc, rhs)
+        sstat = sv.srv.host_stats()
+        allstats = prof_read(btc, rhs)
         totals = None
         if args.profile_all:
             totals = {}
@@ -314,7 +345,7 @@ def run_served(args, btc):
                 t["ms"] += st_["ms"]
         tstats = [s for s in allstats
                   if (s["op"], s["kind"], s["np"], s["part"]) == (dom["op"], dom["kind"], dom["np"], dom["part"])]
-        btc.runner_profile(rh, -2, -1)
+        prof_on(btc, rhs, -2, -1)
         lat = lat_ms(done)
         loop = dict(sv.last_loop)
         relres = sv.verify()
@@ -337,16 +368,20 @@ def run_served(args, btc):
                             "relres_max_device": max(dev_rr) if dev_rr else None,
                             "relres_max_last_torch": relres},
                "per_class": per_class,
-               "server_ticks": loop["ticks"], "host_step_frac": loop["host_step_s"] / loop["wall_s"],
+               "lanes": len(rhs), "server_ticks": sstat["ticks"], "step_calls": loop["ticks"],
+               "host_step_frac": loop["host_step_s"] / loop["wall_s"],
                # where the host's time per tick goes: planning in the server,
-               # enqueueing in the runner, and waiting for the device to free
-               # a descriptor slot (the device is then the bottleneck)
+               # enqueueing in the runners, and waiting for the device (for
+               # the oldest tick in flight, or for a runner's descriptor
+               # slot); a host that waits on every tick leaves the device as
+               # the bottleneck
                "host_us_per_tick": {
-                   "step": loop["host_step_s"] / max(1, loop["ticks"]) * 1e6,
-                   "planning": (loop["host_step_s"] - hstat["run_s"]) / max(1, loop["ticks"]) * 1e6,
-                   "enqueue": (hstat["run_s"] - hstat["wait_s"]) / max(1, loop["ticks"]) * 1e6,
-                   "device_wait": hstat["wait_s"] / max(1, loop["ticks"]) * 1e6,
-                   "wall": loop["wall_s"] / max(1, loop["ticks"]) * 1e6},
+                   "step": loop["host_step_s"] / max(1, sstat["ticks"]) * 1e6,
+                   "planning": (loop["host_step_s"] - hstat["run_s"] - sstat["wait_s"])
+                   / max(1, sstat["ticks"]) * 1e6,
+                   "enqueue": (hstat["run_s"] - hstat["wait_s"]) / max(1, sstat["ticks"]) * 1e6,
+                   "device_wait": (hstat["wait_s"] + sstat["wait_s"]) / max(1, sstat["ticks"]) * 1e6,
+                   "wall": loop["wall_s"] / max(1, sstat["ticks"]) * 1e6},
                "max_relres_last": relres,
                "warmup_kernel_ms": [{"kernel": roofline_entry(s)["kernel"], "ms": round(s["ms"], 3),
                                      "launches": s["launches"],
@@ -361,7 +396,7 @@ def run_served(args, btc):
         ent["aggregate"] = {"bytes": tb, "flops": tf, "gbs": tb / wall / 1e9, "tflops": tf / wall / 1e12,
                             "hbm_frac": tb / wall / 1e9 / HBM_PEAK_GBS}
         log("%s closed loop: %.0f req/s, p50 %.2f ms, p99 %.2f ms, relres %.2e, %d ticks, host step %.0f%%"
-            % (name, ent["value"], ent["p50_ms"], ent["p99_ms"], relres, loop["ticks"],
+            % (name, ent["value"], ent["p50_ms"], ent["p99_ms"], relres, sstat["ticks"],
                100 * ent["host_step_frac"]))
         for rate in args.rates:
             nreq = int(min(args.rate_requests, max(200, rate * args.rate_seconds)))
@@ -662,6 +697,11 @@ def main():
                     help="served workload: requests per step (16 per client by default)")
     ap.add_argument("--sweep-ranges", action="store_true",
                     help="served workload: one server tick per sweep level range instead of per level")
+    ap.add_argument("--lanes", type=int, default=3,
+                    help="served workload: server lanes (0 or 1: one tick over all clients; 2..4: clients "
+                         "split by padded block size class, each lane ticking on its own stream; three "
+                         "lanes keep the server's streams within the four hardware queues HIP opens by "
+                         "default)")
     ap.add_argument("--profile-all", action="store_true",
                     help="served workload: time every kernel group in the timed region too and report each "
                          "group's launches and algorithmic bytes over the whole run (group_totals), to set "
@@ -771,7 +811,8 @@ def main():
                                "saturation; mixed precision with FP64 refinement to 1e-10",
                    "clients": len(shapes), "step_requests": args.step_requests, "diag_shift": 4.0,
                    "relres_target": RELRES_TARGET,
-                   "server_sweeps": "one tick per level range" if args.sweep_ranges else "one tick per level"},
+                   "server_sweeps": "one tick per level range" if args.sweep_ranges else "one tick per level",
+                   "server_lanes": max(1, args.lanes)},
         "p50_ms": mixed["p50_ms"],
         "p99_ms": mixed["p99_ms"],
         "max_relres_last": mixed["max_relres_last"],

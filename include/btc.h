@@ -600,6 +600,13 @@ typedef struct {
     int32_t sweep_ranges;  /* 0: one tick per sweep level; 1: sweeps in the library's level ranges
                               (btc_sweep_ranges), one tick per range (fewer ticks per request,
                               longer ticks: measured 4-6% fewer requests/s on the served mix) */
+    int32_t lanes;         /* 0 or 1: one tick at a time over all clients on the server's stream,
+                              its groups spread over four streams; 2..4: clients split by padded
+                              block size class (<= 16, 32, 64, 96 and 128) into that many lanes,
+                              each with its own ticks on a stream the server creates, so a lane of
+                              small blocks is not held to the pace of the largest; every lane tick
+                              first waits for the work queued on the server's stream so far (the
+                              requests' inputs) */
 } btc_server_options;
 
 typedef struct {
@@ -638,8 +645,11 @@ BTC_API int btc_server_add_client(btc_server s, int64_t N, int64_t n, int64_t *c
 BTC_API int btc_server_submit(btc_server s, int64_t client, const double *A_diag, const double *A_off,
                               const double *B, double *X, int64_t nrhs, int64_t *ticket);
 
-/* Admit and enqueue one step of every request in flight; returns the number
- * of requests queued or in flight (>= 0) or an error code. */
+/* Admit queued requests, then enqueue one tick (the next step of every
+ * request in flight on the lane) on each lane with fewer than three ticks in
+ * flight; if no lane can take one, first wait for the oldest tick in flight.
+ * Returns the number of requests queued or in flight (>= 0) or an error
+ * code. */
 BTC_API int btc_server_step(btc_server s);
 
 /* Hand out up to `max` completions (wait != 0: first wait for all enqueued work). */
@@ -650,9 +660,18 @@ BTC_API int btc_server_stats(btc_server s, int64_t *queued, int64_t *in_flight, 
 /* The resident handle of a client (NULL if not resident); owned by the server. */
 BTC_API btc_handle btc_server_client_handle(btc_server s, int64_t client);
 
-/* The runner the server enqueues its steps on (owned by the server; for
- * btc_runner_profile / btc_runner_profile_read). */
+/* The runner the server enqueues the steps of its first lane on (owned by
+ * the server; for btc_runner_profile / btc_runner_profile_read). */
 BTC_API btc_runner btc_server_runner(btc_server s);
+
+/* The runner of lane `lane` (0 .. lanes-1; lane 0 is btc_server_runner), or
+   NULL for another index. */
+BTC_API btc_runner btc_server_lane_runner(btc_server s, int32_t lane);
+
+/* Host seconds btc_server_step spent blocked on the oldest tick in flight
+ * (no lane could take another), and the ticks enqueued over all lanes, since
+ * creation or the last reset (reset != 0 zeroes them after reading). */
+BTC_API int btc_server_host_stats(btc_server s, double *wait_s, int64_t *ticks, int reset);
 
 BTC_API void btc_server_destroy(btc_server s);
 

@@ -62,7 +62,7 @@ class btc_step(ctypes.Structure):
 
 class btc_server_options(ctypes.Structure):
     _fields_ = [("precision", i32), ("max_refine", i32), ("tol", dbl), ("hbm_budget", ctypes.c_size_t),
-                ("max_active", i32), ("sweep_ranges", i32)]
+                ("max_active", i32), ("sweep_ranges", i32), ("lanes", i32)]
 
 
 class btc_kernel_stat(ctypes.Structure):
@@ -195,6 +195,10 @@ def lib():
         L.btc_autotune.argtypes = [vp, vp, vp, vp, vp, i64, i32, vp]
         L.btc_server_runner.restype = vp
         L.btc_server_runner.argtypes = [vp]
+        L.btc_server_lane_runner.restype = vp
+        L.btc_server_lane_runner.argtypes = [vp, i32]
+        L.btc_server_host_stats.restype = ctypes.c_int
+        L.btc_server_host_stats.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.c_int]
         L.btc_version.restype = ctypes.c_int
         L.btc_version.argtypes = []
         L.btc_autotune_strategy.restype = ctypes.c_int
@@ -596,9 +600,10 @@ class Server:
     every request referenced until the request has completed."""
 
     def __init__(self, precision: int = BTC_FP64, hbm_budget: int = 1 << 40, max_refine: int = 0,
-                 tol: float = 0.0, max_active: int = 0, stream=None, sweep_ranges: bool = False):
+                 tol: float = 0.0, max_active: int = 0, stream=None, sweep_ranges: bool = False, lanes: int = 0):
         self.stream = _stream(stream)
-        opt = btc_server_options(precision, max_refine, tol, hbm_budget, max_active, 1 if sweep_ranges else 0)
+        opt = btc_server_options(precision, max_refine, tol, hbm_budget, max_active, 1 if sweep_ranges else 0,
+                                 lanes)
         h = vp()
         _check(lib().btc_server_create(ctypes.byref(opt), self.stream, ctypes.byref(h)), "btc_server_create")
         self.handle = h.value
@@ -669,6 +674,23 @@ class Server:
     def runner_handle(self) -> int:
         """The server's step runner (for runner_profile / runner_profile_read)."""
         return lib().btc_server_runner(self.handle) or 0
+
+    def host_stats(self, reset: bool = False) -> dict:
+        """Host seconds btc_server_step blocked on the oldest tick, and the
+        ticks enqueued over all lanes (since creation or the last reset)."""
+        a, t = dbl(), i64()
+        _check(lib().btc_server_host_stats(self.handle, ctypes.byref(a), ctypes.byref(t), 1 if reset else 0),
+               "btc_server_host_stats")
+        return {"wait_s": a.value, "ticks": t.value}
+
+    def runner_handles(self) -> list:
+        """The step runners of every lane."""
+        out = []
+        while True:
+            r = lib().btc_server_lane_runner(self.handle, len(out))
+            if not r:
+                return out
+            out.append(r)
 
     def close(self):
         if getattr(self, "handle", None):

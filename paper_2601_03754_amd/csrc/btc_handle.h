@@ -135,6 +135,10 @@ struct btc_handle_s {
 
 namespace btc_host {
 
+// A step runner whose groups spread over its stream and `sides` side streams
+// (btc_runner_create takes the most).
+int runner_create(void* stream, int sides, btc_runner* out);
+
 inline bool is_mixed(int32_t p) { return p == BTC_FP32_IR || p == BTC_BF16_IR; }
 inline bool is_bf16(int32_t p) { return p == BTC_BF16_IR; }
 

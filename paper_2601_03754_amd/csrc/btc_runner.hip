@@ -79,6 +79,7 @@ struct btc_runner_s {
     // stream and up to kSide side streams (fork after the upload, join before
     // the call returns, so later work on the main stream sees all of it).
     static constexpr int kSide = 3;
+    int nside = kSide;  // side streams in use
     hipStream_t side[kSide] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kSide] = {};
@@ -273,16 +274,24 @@ void add_work(const btc_runner_s* r, Group& g, const btc_step& s, bool mixed) {
 }  // namespace
 
 BTC_API int btc_runner_create(void* stream, btc_runner* out) {
+    return btc_host::runner_create(stream, btc_runner_s::kSide, out);
+}
+
+}  // extern "C"
+
+int btc_host::runner_create(void* stream, int sides, btc_runner* out) {
     if (!out) return -2;
+    if (sides < 0 || sides > btc_runner_s::kSide) return -3;
     *out = nullptr;
     btc_runner r = new (std::nothrow) btc_runner_s();
     if (!r) return BTC_ERR_OOM;
     r->st = (hipStream_t)stream;
+    r->nside = sides;
     r->alloc = current_allocator();
     bool ok = true;
     for (auto& s : r->slot) ok = ok && hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&r->fork, hipEventDisableTiming) == hipSuccess;
-    for (int k = 0; k < btc_runner_s::kSide; ++k) {
+    for (int k = 0; k < sides; ++k) {
         ok = ok && hipStreamCreateWithFlags(&r->side[k], hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&r->join[k], hipEventDisableTiming) == hipSuccess;
     }
@@ -293,6 +302,8 @@ BTC_API int btc_runner_create(void* stream, btc_runner* out) {
     *out = r;
     return BTC_OK;
 }
+
+extern "C" {
 
 BTC_API void btc_runner_destroy(btc_runner r) {
     if (!r) return;
@@ -567,7 +578,7 @@ int launch_call(btc_runner r, Call& c, char* dev, hipStream_t st, bool timing) {
         bool used[1 + btc_runner_s::kSide] = {};
         for (auto& o : order) {
             int best = 0;
-            for (int k = 1; k <= btc_runner_s::kSide; ++k)
+            for (int k = 1; k <= r->nside; ++k)
                 if (load[k] < load[best]) best = k;
             load[best] += o.first;
             used[best] = true;

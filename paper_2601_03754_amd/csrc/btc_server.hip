@@ -18,6 +18,9 @@
 //     exceeded, resident clients with no request in flight are evicted, least
 //     recently used first, and a later "solve" request of an evicted client is
 //     run as "refactor + solve" with the client's last matrix.
+// Lanes (option): clients split by padded block size class, each class set
+// with its own stream, runner and ticks, so small blocks are not held to the
+// pace of the largest; a step call enqueues a tick on every lane with room.
 // Completion: each tick records an event; a request completes when the event
 // of the tick holding its last step has fired.  A mixed-precision request
 // whose refinement has converged is retired early: the convergence flags of
@@ -100,6 +103,7 @@ struct Client {
     const double* A_diag = nullptr;
     const double* A_off = nullptr;
     bool has_matrix = false;  // some submitted request brought a matrix
+    int lane = 0;             // the lane (stream and runner) of the client's steps
     bool busy = false;
     uint64_t last_use = 0;
     size_t bytes = 0;
@@ -136,16 +140,37 @@ struct Tick {
     std::vector<Poll> polls;  // status copies of refinement tests and of finishing requests
 };
 
+// A lane: a stream, a runner on it, and the ticks in flight on it.  Clients
+// of one padded block size class share a lane; lanes tick independently.
+struct Lane {
+    hipStream_t st = nullptr;
+    bool own = false;  // stream created by the server
+    btc_runner runner = nullptr;
+    std::deque<Tick> ticks;
+};
+
+// Ticks a lane keeps in flight: the running one, the next one queued behind
+// it, and one more being enqueued (the runner's two descriptor slots).
+constexpr size_t kLaneDepth = 3;
+constexpr int kSizeClasses = 4;
+// Side streams of each lane's runner when there are several lanes: none
+// (measured on the served mix: with lanes, the fork and join of side
+// streams cost more than the concurrency they add, 30-60% fewer requests/s).
+constexpr int kLaneSides = 0;
+
 }  // namespace
 
 struct btc_server_s {
     btc_server_options opt{};
-    hipStream_t st = nullptr;
-    btc_runner runner = nullptr;
+    // the caller's stream: with one lane the server's ticks run on it; with
+    // several, every lane tick first waits for the work queued on it so far
+    // (the requests' inputs)
+    hipStream_t user_st = nullptr;
+    hipEvent_t user_ev = nullptr;
+    std::vector<Lane> lanes;
     std::vector<Client> clients;
     std::deque<Req*> pending;
     std::vector<Req*> active;
-    std::deque<Tick> ticks;
     std::vector<hipEvent_t> ev_pool;
     ReqStatus* flags = nullptr;      // pinned ring of request outcomes (host view)
     ReqStatus* flags_dev = nullptr;  // the same memory as the device sees it
@@ -156,6 +181,8 @@ struct btc_server_s {
     int64_t next_ticket = 1;
     std::vector<btc_server_completion> done;
     std::vector<btc_step> scratch;
+    double host_wait_s = 0.0;  // btc_server_step blocked on the oldest tick
+    int64_t lane_ticks = 0;    // ticks enqueued over all lanes
 };
 
 namespace {
@@ -169,7 +196,8 @@ int make_room(btc_server s, const Client* keep, size_t more) {
         for (auto& o : s->clients)
             if (&o != keep && o.h && !o.busy && (!victim || o.last_use < victim->last_use)) victim = &o;
         if (!victim) return 1;
-        (void)hipStreamSynchronize(s->st);
+        // steps issued before an early retirement may still run on its lane
+        (void)hipStreamSynchronize(s->lanes[(size_t)victim->lane].st);
         btc_destroy(victim->h);
         victim->h = nullptr;
         s->resident -= victim->bytes;
@@ -205,7 +233,7 @@ int admit_client(btc_server s, Client& c, int64_t nrhs) {
     btc_handle h = nullptr;
     int rc = btc_create(c.N, c.n, &o, &h);
     if (rc != BTC_OK) return rc;
-    h->stream = s->st;
+    h->stream = s->lanes[(size_t)c.lane].st;
     rc = ensure_workspace(h, nrhs);
     if (rc != BTC_OK) {
         btc_destroy(h);
@@ -354,28 +382,33 @@ void complete(btc_server s, Req* r, double t, const ReqStatus& st) {
     s->done.push_back(d);
 }
 
-// Retire every tick whose event has fired (in order).
+// Retire every tick whose event has fired (in order on each lane; with wait,
+// every tick).
 void harvest(btc_server s, bool wait) {
-    while (!s->ticks.empty()) {
-        Tick& t = s->ticks.front();
-        if (wait) {
-            (void)hipEventSynchronize(t.ev);
-        } else if (hipEventQuery(t.ev) != hipSuccess) {
-            break;
+    for (Lane& ln : s->lanes) {
+        while (!ln.ticks.empty()) {
+            Tick& t = ln.ticks.front();
+            if (wait) {
+                (void)hipEventSynchronize(t.ev);
+            } else if (hipEventQuery(t.ev) != hipSuccess) {
+                break;
+            }
+            const double tn = now_s();
+            for (auto& p : t.polls) {
+                const ReqStatus st = s->flags[p.slot];
+                // a request is done after its last step, or earlier once its
+                // refinement has stopped (the steps still queued for it return
+                // at once), or once its factorization has broken down
+                if (p.last || st.done != 0 || st.info != kInfoOk) complete(s, p.r, tn, st);
+            }
+            s->ev_pool.push_back(t.ev);
+            ln.ticks.pop_front();
         }
-        const double tn = now_s();
-        for (auto& p : t.polls) {
-            const ReqStatus st = s->flags[p.slot];
-            // a request is done after its last step, or earlier once its
-            // refinement has stopped (the steps still queued for it return
-            // at once), or once its factorization has broken down
-            if (p.last || st.done != 0 || st.info != kInfoOk) complete(s, p.r, tn, st);
-        }
-        s->ev_pool.push_back(t.ev);
-        s->ticks.pop_front();
     }
     // drop retired requests that no outstanding tick refers to any more
-    const uint64_t oldest = s->ticks.empty() ? UINT64_MAX : s->ticks.front().id;
+    uint64_t oldest = UINT64_MAX;
+    for (const Lane& ln : s->lanes)
+        if (!ln.ticks.empty()) oldest = std::min(oldest, ln.ticks.front().id);
     auto it = std::remove_if(s->active.begin(), s->active.end(), [oldest](Req* r) {
         if (r->retired && r->last_tick < oldest) {
             delete r;
@@ -386,6 +419,95 @@ void harvest(btc_server s, bool wait) {
     s->active.erase(it, s->active.end());
 }
 
+// Padded block size class of n: 0 (up to 16), 1 (32), 2 (64), 3 (96, 128).
+int size_class(int64_t n) {
+    const int np = btc::padded_block((int)n);
+    return np <= 16 ? 0 : np <= 32 ? 1 : np <= 64 ? 2 : 3;
+}
+
+// One tick on lane li: the next steps of every in-flight request of the
+// lane's clients, as one runner call, then the gather of the tick's request
+// outcomes and the tick's event.  Returns 1 if the lane had steps to run.
+int issue_tick(btc_server s, int li, int* rc_out) {
+    Lane& ln = s->lanes[(size_t)li];
+    Tick t;
+    t.id = s->next_tick;
+    s->scratch.clear();
+    for (Req* r : s->active) {
+        if (r->retired || r->pc >= r->plan.size()) continue;  // done, or waiting for its last tick
+        if (s->clients[(size_t)r->client].lane != li) continue;
+        r->last_tick = t.id;
+        bool more = true, test = false;
+        int stage = -1;
+        while (more && r->pc < r->plan.size()) {
+            const bool par = r->par[r->pc] != 0 && stage >= 0;
+            if (!par && stage >= 7) break;  // stages of a runner call: the rest goes in the next tick
+            more = r->joint[r->pc] != 0;
+            btc_step st = r->plan[r->pc++];
+            stage += par ? 0 : 1;
+            st.stage = stage;
+            s->scratch.push_back(st);
+            test = test || st.op == BTC_OP_REFINE_TEST;
+        }
+        const bool last = r->pc == r->plan.size();
+        if (test || last) {
+            t.polls.push_back({r, s->flag_next, last});
+            s->flag_next = (s->flag_next + 1) % s->flag_cap;
+        }
+    }
+    *rc_out = BTC_OK;
+    if (s->scratch.empty()) return 0;
+    s->next_tick++;
+    if (s->user_ev) {
+        if (hipEventRecord(s->user_ev, s->user_st) != hipSuccess ||
+            hipStreamWaitEvent(ln.st, s->user_ev, 0) != hipSuccess) {
+            *rc_out = BTC_ERR_HIP;
+            return 1;
+        }
+    }
+    int rc = btc_runner_run(ln.runner, (int32_t)s->scratch.size(), s->scratch.data());
+    if (rc != BTC_OK) {
+        *rc_out = rc;
+        return 1;
+    }
+    // the outcomes of this tick's tests and finishing requests, copied into
+    // the pinned ring by one small kernel (not one copy command each)
+    StatusGather ga{};
+    ga.ring = s->flags_dev;
+    const bool mixed = is_mixed(s->opt.precision);
+    for (size_t k = 0; k < t.polls.size(); ++k) {
+        const auto& p = t.polls[k];
+        btc_handle h = p.r->plan[0].h;
+        const Workspace w = carve(h, h->ws_m);
+        s->flags[p.slot] = ReqStatus{};
+        ga.info[ga.count] = h->info;
+        ga.ir[ga.count] = mixed ? w.ir : nullptr;
+        ga.dst[ga.count] = p.slot;
+        if (++ga.count == kGather || k + 1 == t.polls.size()) {
+            hipLaunchKernelGGL(k_gather_status, dim3(1), dim3(kGather), 0, ln.st, ga);
+            if (hipGetLastError() != hipSuccess) {
+                *rc_out = BTC_ERR_HIP;
+                return 1;
+            }
+            ga.count = 0;
+        }
+    }
+    if (!s->ev_pool.empty()) {
+        t.ev = s->ev_pool.back();
+        s->ev_pool.pop_back();
+    } else if (hipEventCreateWithFlags(&t.ev, hipEventDisableTiming) != hipSuccess) {
+        *rc_out = BTC_ERR_HIP;
+        return 1;
+    }
+    if (hipEventRecord(t.ev, ln.st) != hipSuccess) {
+        *rc_out = BTC_ERR_HIP;
+        return 1;
+    }
+    ln.ticks.push_back(std::move(t));
+    s->lane_ticks += 1;
+    return 1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -393,7 +515,7 @@ extern "C" {
 BTC_API int btc_server_create(const btc_server_options* opt, void* stream, btc_server* out) {
     if (!opt) return -1;
     if (opt->precision != BTC_FP64 && !is_mixed(opt->precision)) return -1;
-    if (opt->max_refine < 0 || opt->max_active < 0 || !(opt->tol >= 0.0)) return -1;
+    if (opt->max_refine < 0 || opt->max_active < 0 || !(opt->tol >= 0.0) || opt->lanes < 0) return -1;
     if (!out) return -3;
     *out = nullptr;
     btc_server s = new (std::nothrow) btc_server_s();
@@ -403,8 +525,25 @@ BTC_API int btc_server_create(const btc_server_options* opt, void* stream, btc_s
         s->opt.max_refine = is_bf16(s->opt.precision) ? BTC_DEFAULT_MAX_REFINE_BF16 : BTC_DEFAULT_MAX_REFINE;
     if (s->opt.tol == 0.0) s->opt.tol = BTC_DEFAULT_TOL;
     if (s->opt.max_active == 0) s->opt.max_active = 1 << 20;
-    s->st = (hipStream_t)stream;
-    int rc = btc_runner_create(stream, &s->runner);
+    const int nl = s->opt.lanes <= 1 ? 1 : std::min<int>(s->opt.lanes, kSizeClasses);
+    s->lanes.resize((size_t)nl);
+    s->user_st = (hipStream_t)stream;
+    int rc = BTC_OK;
+    if (nl > 1 && hipEventCreateWithFlags(&s->user_ev, hipEventDisableTiming) != hipSuccess) rc = BTC_ERR_HIP;
+    for (int k = 0; k < nl && rc == BTC_OK; ++k) {
+        Lane& ln = s->lanes[(size_t)k];
+        if (nl == 1) {
+            ln.st = (hipStream_t)stream;
+        } else if (hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking) != hipSuccess) {
+            rc = BTC_ERR_HIP;
+            break;
+        } else {
+            ln.own = true;
+        }
+        // one lane spreads a tick's groups over three side streams; several
+        // lanes run side by side, each on its stream alone
+        rc = runner_create(ln.st, nl == 1 ? 3 : kLaneSides, &ln.runner);
+    }
     if (rc == BTC_OK) {
         s->flag_cap = 1 << 16;
         if (hipHostMalloc((void**)&s->flags, sizeof(ReqStatus) * s->flag_cap, hipHostMallocMapped) != hipSuccess)
@@ -429,6 +568,8 @@ BTC_API int btc_server_add_client(btc_server s, int64_t N, int64_t n, int64_t* c
     Client c;
     c.N = N;
     c.n = n;
+    // size classes spread evenly over the lanes
+    c.lane = size_class(n) * (int)s->lanes.size() / kSizeClasses;
     s->clients.push_back(c);
     *client = (int64_t)s->clients.size() - 1;
     return BTC_OK;
@@ -486,61 +627,28 @@ BTC_API int btc_server_step(btc_server s) {
         it = s->pending.erase(it);
     }
 
-    // one step of every in-flight request
-    Tick t;
-    t.id = s->next_tick++;
-    s->scratch.clear();
-    for (Req* r : s->active) {
-        if (r->retired || r->pc >= r->plan.size()) continue;  // done, or waiting for its last tick
-        r->last_tick = t.id;
-        bool more = true, test = false;
-        int stage = -1;
-        while (more && r->pc < r->plan.size()) {
-            const bool par = r->par[r->pc] != 0 && stage >= 0;
-            if (!par && stage >= 7) break;  // stages of a runner call: the rest goes in the next tick
-            more = r->joint[r->pc] != 0;
-            btc_step st = r->plan[r->pc++];
-            stage += par ? 0 : 1;
-            st.stage = stage;
-            s->scratch.push_back(st);
-            test = test || st.op == BTC_OP_REFINE_TEST;
+    // one tick on every lane with fewer than kLaneDepth ticks in flight; if
+    // no lane could take one, wait for the oldest tick in flight
+    for (;;) {
+        bool issued = false, blocked = false;
+        for (int li = 0; li < (int)s->lanes.size(); ++li) {
+            if (s->lanes[(size_t)li].ticks.size() >= kLaneDepth) {
+                blocked = true;
+                continue;
+            }
+            int rc = BTC_OK;
+            issued = issue_tick(s, li, &rc) != 0 || issued;
+            if (rc != BTC_OK) return rc;
         }
-        const bool last = r->pc == r->plan.size();
-        if (test || last) {
-            t.polls.push_back({r, s->flag_next, last});
-            s->flag_next = (s->flag_next + 1) % s->flag_cap;
-        }
+        if (issued || !blocked) break;
+        Lane* old = nullptr;
+        for (Lane& ln : s->lanes)
+            if (!ln.ticks.empty() && (!old || ln.ticks.front().id < old->ticks.front().id)) old = &ln;
+        const double t0 = now_s();
+        (void)hipEventSynchronize(old->ticks.front().ev);
+        s->host_wait_s += now_s() - t0;
+        harvest(s, false);
     }
-    if (s->scratch.empty()) return (int)(s->pending.size() + s->active.size());
-    int rc = btc_runner_run(s->runner, (int32_t)s->scratch.size(), s->scratch.data());
-    if (rc != BTC_OK) return rc;
-    // the outcomes of this tick's tests and finishing requests, copied into
-    // the pinned ring by one small kernel (not one copy command each)
-    StatusGather ga{};
-    ga.ring = s->flags_dev;
-    const bool mixed = is_mixed(s->opt.precision);
-    for (size_t k = 0; k < t.polls.size(); ++k) {
-        const auto& p = t.polls[k];
-        btc_handle h = p.r->plan[0].h;
-        const Workspace w = carve(h, h->ws_m);
-        s->flags[p.slot] = ReqStatus{};
-        ga.info[ga.count] = h->info;
-        ga.ir[ga.count] = mixed ? w.ir : nullptr;
-        ga.dst[ga.count] = p.slot;
-        if (++ga.count == kGather || k + 1 == t.polls.size()) {
-            hipLaunchKernelGGL(k_gather_status, dim3(1), dim3(kGather), 0, s->st, ga);
-            if (hipGetLastError() != hipSuccess) return BTC_ERR_HIP;
-            ga.count = 0;
-        }
-    }
-    if (!s->ev_pool.empty()) {
-        t.ev = s->ev_pool.back();
-        s->ev_pool.pop_back();
-    } else if (hipEventCreateWithFlags(&t.ev, hipEventDisableTiming) != hipSuccess) {
-        return BTC_ERR_HIP;
-    }
-    if (hipEventRecord(t.ev, s->st) != hipSuccess) return BTC_ERR_HIP;
-    s->ticks.push_back(std::move(t));
     return (int)(s->pending.size() + s->active.size());
 }
 
@@ -572,19 +680,41 @@ BTC_API btc_handle btc_server_client_handle(btc_server s, int64_t client) {
 
 BTC_API void btc_server_destroy(btc_server s) {
     if (!s) return;
-    if (s->st) (void)hipStreamSynchronize(s->st);
+    for (auto& ln : s->lanes)
+        if (ln.st) (void)hipStreamSynchronize(ln.st);
     for (Req* r : s->pending) delete r;
     for (Req* r : s->active) delete r;
-    for (auto& t : s->ticks)
-        if (t.ev) (void)hipEventDestroy(t.ev);
+    for (auto& ln : s->lanes)
+        for (auto& t : ln.ticks)
+            if (t.ev) (void)hipEventDestroy(t.ev);
     for (auto e : s->ev_pool) (void)hipEventDestroy(e);
     for (auto& c : s->clients)
         if (c.h) btc_destroy(c.h);
-    if (s->runner) btc_runner_destroy(s->runner);
+    for (auto& ln : s->lanes) {
+        if (ln.runner) btc_runner_destroy(ln.runner);
+        if (ln.own && ln.st) (void)hipStreamDestroy(ln.st);
+    }
     if (s->flags) (void)hipHostFree(s->flags);
+    if (s->user_ev) (void)hipEventDestroy(s->user_ev);
     delete s;
 }
 
 }  // extern "C"
 
-BTC_API btc_runner btc_server_runner(btc_server s) { return s ? s->runner : nullptr; }
+BTC_API btc_runner btc_server_runner(btc_server s) { return s && !s->lanes.empty() ? s->lanes[0].runner : nullptr; }
+
+BTC_API int btc_server_host_stats(btc_server s, double* wait_s, int64_t* ticks, int reset) {
+    if (!s) return -1;
+    if (wait_s) *wait_s = s->host_wait_s;
+    if (ticks) *ticks = s->lane_ticks;
+    if (reset) {
+        s->host_wait_s = 0.0;
+        s->lane_ticks = 0;
+    }
+    return BTC_OK;
+}
+
+BTC_API btc_runner btc_server_lane_runner(btc_server s, int32_t lane) {
+    if (!s || lane < 0 || lane >= (int32_t)s->lanes.size()) return nullptr;
+    return s->lanes[(size_t)lane].runner;
+}

@@ -34,13 +34,13 @@ def alone(btc, D, E, B, precision):
 
 
 def run_trace(btc, precision, budget, seed=0, clients=6, requests=40, n_choices=(5, 12, 16, 24, 40, 64),
-              N_max=300, sweep_ranges=False):
+              N_max=300, sweep_ranges=False, lanes=0):
     rng = np.random.default_rng(seed)
     shapes = [(int(rng.integers(16, N_max)), int(rng.choice(n_choices))) for _ in range(clients)]
     mats = [[inputs.block_tridiag(N, n, seed=seed * 100 + c * 10 + v) for v in range(2)]
             for c, (N, n) in enumerate(shapes)]
     dmats = [[(dev(p.D), dev(p.E)) for p in ms] for ms in mats]
-    srv = btc.Server(precision=precision, hbm_budget=budget, sweep_ranges=sweep_ranges)
+    srv = btc.Server(precision=precision, hbm_budget=budget, sweep_ranges=sweep_ranges, lanes=lanes)
     ids = [srv.add_client(N, n) for N, n in shapes]
     current = [None] * clients
     subs = []
@@ -69,15 +69,19 @@ def run_trace(btc, precision, budget, seed=0, clients=6, requests=40, n_choices=
 BIG_BLOCKS = (12, 33, 64, 80, 96, 110, 128)
 
 
-@pytest.mark.parametrize("precision,n_choices,ranges", [(0, None, False), (1, None, False), (0, BIG_BLOCKS, False),
-                                                        (1, BIG_BLOCKS, False), (2, BIG_BLOCKS, False),
-                                                        (0, None, True), (1, BIG_BLOCKS, True),
-                                                        (2, BIG_BLOCKS, True)])
-def test_results_in_the_mix_equal_results_alone(btc, precision, n_choices, ranges):
+@pytest.mark.parametrize("precision,n_choices,ranges,lanes", [
+    (0, None, False, 0), (1, None, False, 0), (0, BIG_BLOCKS, False, 0),
+    (1, BIG_BLOCKS, False, 0), (2, BIG_BLOCKS, False, 0),
+    (0, None, True, 0), (1, BIG_BLOCKS, True, 0), (2, BIG_BLOCKS, True, 0),
+    # clients split into lanes by block size class, each lane ticking alone
+    (0, BIG_BLOCKS, False, 4), (1, BIG_BLOCKS, False, 4), (1, None, False, 2), (2, BIG_BLOCKS, True, 3)])
+def test_results_in_the_mix_equal_results_alone(btc, precision, n_choices, ranges, lanes):
     """Every result equals the same request alone, bit for bit, in both
-    server plans (one tick per sweep level range, or per level)."""
+    server plans (one tick per sweep level range, or per level) and with the
+    clients in one lane or several."""
     kw = {} if n_choices is None else {"n_choices": n_choices, "N_max": 140, "requests": 30}
     kw["sweep_ranges"] = ranges
+    kw["lanes"] = lanes
     srv, subs, done, mats, dmats, stats = run_trace(btc, precision, budget=1 << 40, seed=11 + precision, **kw)
     assert len(done) == len(subs)
     assert stats["queued"] == 0 and stats["in_flight"] == 0
@@ -166,8 +170,9 @@ def test_admission_limits(btc):
     srv.close()
 
 
-def test_per_client_order_and_latency_fields(btc):
-    srv, subs, done, *_ = run_trace(btc, 0, budget=1 << 40, seed=3)
+@pytest.mark.parametrize("lanes", [0, 4])
+def test_per_client_order_and_latency_fields(btc, lanes):
+    srv, subs, done, *_ = run_trace(btc, 0, budget=1 << 40, seed=3, lanes=lanes)
     by_ticket = {d["ticket"]: d for d in done}
     last = {}
     for t, c, *_ in subs:
@@ -179,13 +184,14 @@ def test_per_client_order_and_latency_fields(btc):
     srv.close()
 
 
-def test_small_budget_evicts_and_readmits(btc):
+@pytest.mark.parametrize("lanes", [0, 3])
+def test_small_budget_evicts_and_readmits(btc, lanes):
     """A budget that fits about two clients at a time: clients are evicted and
     re-admitted (their solves then refactor with the last matrix), and every
     result still equals the one computed alone."""
     from paper_2601_03754_amd import btc as b
     budget = 2 * b.btc_footprint_bytes(300, 64, 0, 1)
-    srv, subs, done, mats, dmats, stats = run_trace(btc, 0, budget=budget, seed=7)
+    srv, subs, done, mats, dmats, stats = run_trace(btc, 0, budget=budget, seed=7, lanes=lanes)
     assert len(done) == len(subs)
     assert stats["resident_bytes"] <= budget
     # every request that brought a matrix refactored; evicted clients refactor again
