@@ -101,13 +101,14 @@ struct PanelRegs {
     static_assert(CNT * NT == TOTAL, "threads divide the panel");
     F v[CNT];
 
+    // k0: first index along the panel's long side (NP of them are taken)
     template <class S>
-    __device__ __forceinline__ void load(const S* __restrict__ src, int n, int r0, bool cols, int t) {
+    __device__ __forceinline__ void load(const S* __restrict__ src, int n, int r0, bool cols, int t, int k0 = 0) {
         const __amdgpu_buffer_rsrc_t rs = nn_rsrc(src, n);
 #pragma unroll
         for (int u = 0; u < CNT; ++u) {
             const int e = t + NT * u;
-            const int rr = cols ? e / R : r0 + e / NP, cc = cols ? r0 + e % R : e % NP;
+            const int rr = cols ? k0 + e / R : r0 + e / NP, cc = cols ? r0 + e % R : k0 + e % NP;
             S x;
             buf_ld(x, rs, elem_off<S>(rr, cc, n, rr < n && cc < n));
             v[u] = (F)x;
@@ -437,15 +438,22 @@ __global__ __launch_bounds__(NW * kWave, (NB * NW + 3) / 4) void k_tiled_potrf_t
 // ---------------------------------------------------------------------------
 // K4: tile number ty < NTRI32 of a node: lower tile of S_{i+s} -= R R^T (eagerly also
 // - T'^T T' with T' = T_{i+2s}, the separator's other contribution); else
-// fill tile -R T (row-major over the W32 x W32 tiles).
+// fill tile -R T (row-major over the W32 x W32 tiles).  The panels of a
+// product pass through LDS in KS ranges of the k index (FP64: two, so the
+// panels take half the LDS and more workgroups share a compute unit), the
+// next range's loads in flight while the current one is on the matrix
+// cores; the accumulation order over k is the same for any KS.
 template <int NP, bool MIXED, bool BF16>
 __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     using Pr = Prec<MIXED>;
     using F = typename Pr::F;
     using Cfg = TiledCfg<NP>;
-    constexpr int LDR = NP + 1;  // row panel [32][NP]
-    constexpr int LDP = 33;      // column panel [NP][32]
-    constexpr int PSZ = NP * LDP > 32 * LDR ? NP * LDP : 32 * LDR;
+    constexpr int KS = MIXED ? 1 : 2;
+    constexpr int KH = NP / KS;
+    static_assert(KH % 8 == 0, "whole k steps per range");
+    constexpr int LDR = KH + 1;  // row panel [32][KH]
+    constexpr int LDP = 33;      // column panel [KH][32]
+    constexpr int PSZ = KH * LDP > 32 * LDR ? KH * LDP : 32 * LDR;
     __shared__ F pa[PSZ];
     __shared__ F pb[PSZ];
     FactorDesc P;
@@ -473,15 +481,75 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     const int sr = w >> 1, sc = w & 1;
     const bool idle = sep && a == b && sr < sc;  // strictly upper sub-tile
     const bool eager = sep && (P.flags & kFactorEagerT) && d.i + 2 * d.s <= d.N;
-    // every global read up front: both panels of the first product and the
-    // Schur complement entries this thread updates
-    {
-        PanelRegs<NP, 32, 256, F> g1, g2;
-        g1.load(R, n, 32 * a, false, tid);
-        g2.load(sep ? R : T, n, 32 * b, !sep, tid);
-        g1.put(pa, LDR, false, tid);
-        g2.put(pb, sep ? LDR : LDP, !sep, tid);
-    }
+    const F* T2 = Pr::Tf(P) + (size_t)(eager ? perm_pos(d.N, lvl, d.i + 2 * d.s) : d.pi) * d.nn;
+    // phase ph: k range ph % KS of product ph / KS (0: R R^T or R T; 1: the
+    // right neighbour's T'^T T')
+    const int nph = KS * (eager ? 2 : 1);
+    using Pan = PanelRegs<KH, 32, 256, F>;
+    auto load_phase = [&](int ph, Pan& x, Pan& y) {
+        const int k0 = KH * (ph % KS);
+        if (ph < KS) {
+            x.load(R, n, 32 * a, false, tid, k0);
+            y.load(sep ? R : T, n, 32 * b, !sep, tid, k0);
+        } else {
+            x.load(T2, n, 32 * a, true, tid, k0);
+            y.load(T2, n, 32 * b, true, tid, k0);
+        }
+    };
+    typename Pr::Acc acc = {}, acc1 = {};
+    const int i = lane & 15, q = lane >> 4;
+    // a phase's panels into LDS
+    auto stage = [&](int ph, const Pan& ca, const Pan& cb) {
+        const bool second = ph >= KS;  // the T'^T T' product
+        ca.put(pa, second ? LDP : LDR, second, tid);
+        cb.put(pb, (second || !sep) ? LDP : LDR, second || !sep, tid);
+    };
+    // a phase's products from LDS
+    auto products = [&](int ph) {
+        if (idle) return;
+        const bool second = ph >= KS;
+        if constexpr (BF16) {
+            if (second)
+                mma_tile_bf16<LDP, LDP, true, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, KH);
+            else if (sep)
+                // R R^T (B[k][c] = R[c][k]) with BF16 operands
+                mma_tile_bf16<LDR, LDR, false, true, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, KH);
+            else
+                // R T (B[k][c] = T[k][c])
+                mma_tile_bf16<LDR, LDP, false, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, KH);
+        } else {
+            // two independent accumulation chains (hide the matrix-core latency)
+#pragma unroll 4
+            for (int k = 0; k < KH; k += 8) {
+                F a0, a1, b0, b1;
+                if (second) {
+                    a0 = pa[(k + q) * LDP + 16 * sr + i];
+                    a1 = pa[(k + 4 + q) * LDP + 16 * sr + i];
+                    b0 = pb[(k + q) * LDP + 16 * sc + i];
+                    b1 = pb[(k + 4 + q) * LDP + 16 * sc + i];
+                } else {
+                    a0 = pa[(16 * sr + i) * LDR + k + q];
+                    a1 = pa[(16 * sr + i) * LDR + k + 4 + q];
+                    b0 = sep ? pb[(16 * sc + i) * LDR + k + q] : pb[(k + q) * LDP + 16 * sc + i];
+                    b1 = sep ? pb[(16 * sc + i) * LDR + k + 4 + q] : pb[(k + 4 + q) * LDP + 16 * sc + i];
+                }
+                acc = Pr::mma(a0, b0, acc);
+                acc1 = Pr::mma(a1, b1, acc1);
+            }
+            if (ph % KS == KS - 1) {
+                // end of a product: fold its second chain
+                acc += acc1;
+                acc1 = {};
+            }
+        }
+    };
+    // phase 0's panels first, then the Schur complement entries this thread
+    // updates and the next phase's panels load while phase 0 computes; each
+    // later phase stages its panels once the previous one has read them (the
+    // panel register sets alternate between phases)
+    Pan g0a, g0b, g1a, g1b;
+    load_phase(0, g0a, g0b);
+    stage(0, g0a, g0b);
     double sv[4] = {0.0, 0.0, 0.0, 0.0};
     if (sep) {
         const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i + d.s - 1) * d.nn : P.Ld + (size_t)d.pr * d.nn;
@@ -492,56 +560,20 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
             buf_ld(sv[v], rsrc, elem_off<double>(r, c, n, !idle && r < n && c < n));
         }
     }
-    // the second product's panels (the right neighbour's T') load during the first
-    PanelRegs<NP, 32, 256, F> g3, g4;
-    const F* T2 = Pr::Tf(P) + (size_t)(eager ? perm_pos(d.N, lvl, d.i + 2 * d.s) : d.pi) * d.nn;
-    if (eager) {
-        g3.load(T2, n, 32 * a, true, tid);
-        g4.load(T2, n, 32 * b, true, tid);
-    }
+    if (nph > 1) load_phase(1, g1a, g1b);
     __syncthreads();
-    typename Pr::Acc acc = {};
-    const int i = lane & 15, q = lane >> 4;
-    if (!idle) {
-        if constexpr (BF16) {
-            // R R^T (B[k][c] = R[c][k]) or R T (B[k][c] = T[k][c]) with BF16 operands
-            if (sep)
-                mma_tile_bf16<LDR, LDR, false, true, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
-            else
-                mma_tile_bf16<LDR, LDP, false, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
-        } else {
-            // two independent accumulation chains (hide the matrix-core latency)
-            typename Pr::Acc acc1 = {};
-#pragma unroll 4
-            for (int k = 0; k < NP; k += 8) {
-                const F a0 = pa[(16 * sr + i) * LDR + k + q], a1 = pa[(16 * sr + i) * LDR + k + 4 + q];
-                const F b0 = sep ? pb[(16 * sc + i) * LDR + k + q] : pb[(k + q) * LDP + 16 * sc + i];
-                const F b1 = sep ? pb[(16 * sc + i) * LDR + k + 4 + q] : pb[(k + 4 + q) * LDP + 16 * sc + i];
-                acc = Pr::mma(a0, b0, acc);
-                acc1 = Pr::mma(a1, b1, acc1);
-            }
-            acc += acc1;
-        }
-    }
-    if (eager) {
-        // the right neighbour's T'^T T' (A[r][k] = T'[k][r], B[k][c] = T'[k][c])
+    products(0);
+    auto later = [&](int ph, const Pan& ca, const Pan& cb, Pan& na, Pan& nb) {
+        __syncthreads();  // the previous phase's products have read the panels
+        stage(ph, ca, cb);
+        if (ph + 1 < nph) load_phase(ph + 1, na, nb);
         __syncthreads();
-        g3.put(pa, LDP, true, tid);
-        g4.put(pb, LDP, true, tid);
-        __syncthreads();
-        if (!idle) {
-            if constexpr (BF16) {
-                mma_tile_bf16<LDP, LDP, true, false, false>(acc, pa, 16 * sr, 0, pb, 16 * sc, 0, NP);
-            } else {
-                typename Pr::Acc acc1 = {};
-#pragma unroll 4
-                for (int k = 0; k < NP; k += 8) {
-                    acc = Pr::mma(pa[(k + q) * LDP + 16 * sr + i], pb[(k + q) * LDP + 16 * sc + i], acc);
-                    acc1 = Pr::mma(pa[(k + 4 + q) * LDP + 16 * sr + i], pb[(k + 4 + q) * LDP + 16 * sc + i], acc1);
-                }
-                acc += acc1;
-            }
-        }
+        products(ph);
+    };
+    if (nph > 1) later(1, g1a, g1b, g0a, g0b);
+    if constexpr (KS > 1) {
+        if (nph > 2) later(2, g0a, g0b, g1a, g1b);
+        if (nph > 3) later(3, g1a, g1b, g0a, g0b);
     }
     if (idle) return;
     if (sep) {
