@@ -93,6 +93,12 @@ def test_argument_errors_before_device_work(lib):
     assert L.btc_solve_batched(None, 0, None, None, None, None, None) == -1
     assert L.btc_refine_info(None, None) == -1
     L.btc_runner_destroy(None)
+    # host-time counters and lanes: null handles are refused before any device work
+    assert L.btc_runner_host_stats(None, None, None, None, 0) == -1
+    assert L.btc_server_host_stats(None, None, None, 0) == -1
+    assert not L.btc_server_lane_runner(None, 0)
+    opt = lib.btc_server_options(0, 0, 0.0, 1 << 30, 0, 0, -1)  # negative lane count
+    assert L.btc_server_create(ctypes.byref(opt), None, ctypes.byref(h)) == -1
     assert "argument" in lib.btc_error_string(-3)
     assert "positive definite" in lib.btc_error_string(lib.BTC_ERR_NOT_SPD)
 
@@ -244,3 +250,45 @@ def test_tune_cache_persists_across_processes(lib, tmp_path):
     assert out == ["2", "1", "0"]
     with pytest.raises(lib.BtcError):
         lib.btc_tune_set(6, 0, 40, 0, 3)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The bench measures one GPU: any other count exits with a message before
+    touching a device."""
+    import subprocess, sys, os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_bench_sums_lane_profiles_and_host_counters():
+    """The served bench merges the launch profiles and host-time counters of
+    the server's lane runners: equal keys add up, the order is by time."""
+    import os, sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+
+    class FakeBtc:
+        prof = {1: [{"op": 0, "kind": 3, "np": 96, "part": 2, "launches": 2, "items": 10, "ms": 1.0, "bytes": 5.0,
+                     "flops": 7.0}],
+                2: [{"op": 0, "kind": 3, "np": 96, "part": 2, "launches": 1, "items": 4, "ms": 3.0, "bytes": 1.0,
+                     "flops": 1.0},
+                    {"op": 1, "kind": 1, "np": 32, "part": 0, "launches": 5, "items": 9, "ms": 2.0, "bytes": 2.0,
+                     "flops": 3.0}]}
+        host = {1: {"run_s": 1.0, "wait_s": 0.5, "calls": 3}, 2: {"run_s": 2.0, "wait_s": 0.25, "calls": 4}}
+
+        def runner_profile_read(self, r):
+            return self.prof[r]
+
+        def runner_host_stats(self, r, reset=False):
+            return self.host[r]
+
+    f = FakeBtc()
+    merged = bench.prof_read(f, [1, 2])
+    assert [(m["op"], m["np"]) for m in merged] == [(0, 96), (1, 32)]
+    assert merged[0]["launches"] == 3 and merged[0]["ms"] == 4.0 and merged[0]["bytes"] == 6.0
+    assert merged[0]["items"] == 14 and merged[0]["flops"] == 8.0
+    assert bench.host_stats(f, [1, 2]) == {"run_s": 3.0, "wait_s": 0.75, "calls": 7}
