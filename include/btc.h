@@ -429,9 +429,10 @@ BTC_API void btc_graph_destroy(btc_graph g);
  * keyed by operation, precision, block size n (through its padded size) and
  * level (bucket: level 0, levels >= 1):
  *   BTC_OP_FACTOR, BTC_FP64, n 9..32: 0 matrix-core kernel, 1 vector-ALU
- *     kernel; any precision, n 33..64: 0 one workgroup per node, 1 the
- *     tile-parallel level step (different rounding orders: results change at
- *     round-off level when the choice changes)
+ *     kernel, and for n 17..32 also 2 the tile-parallel level step; mixed
+ *     precisions, n 17..32, and any precision, n 33..64: 0 one workgroup per
+ *     node, 1 the tile-parallel level step (different rounding orders:
+ *     results change at round-off level when the choice changes)
  *   BTC_OP_FORWARD / BACKWARD / RESIDUAL (nrhs > 1; level ignored): 0 four
  *     right-hand-side columns per dependency-chain group, 1 one (identical
  *     results)

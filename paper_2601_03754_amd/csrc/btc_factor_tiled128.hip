@@ -14,6 +14,7 @@ hipError_t launch_factor_tiled128(const Launch<FactorDesc>& p, int mode, int par
 hipError_t launch_factor_tiled(const Launch<FactorDesc>& p, int np, int mode, int part, bool deferred,
                                int64_t items, hipStream_t st) {
     switch (np) {
+        case 32: return launch_factor_tiled32(p, mode, part, deferred, items, st);
         case 64: return launch_factor_tiled64(p, mode, part, deferred, items, st);
         case 96: return launch_factor_tiled96(p, mode, part, deferred, items, st);
         case 128: return launch_factor_tiled128(p, mode, part, deferred, items, st);

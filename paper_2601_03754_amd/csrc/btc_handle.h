@@ -373,20 +373,22 @@ void strategy_set(int64_t N, int64_t n, int32_t prec, int32_t strategy, int32_t 
 
 // Factor kernel family of a handle at a level: 0 VALU FP64 (np < 16, or
 // np 16/32 where the autotuner chose it), 1 MFMA FP64, 2 mixed,
-// 3 tile-parallel FP64 (np > 64, or np 64 where the autotuner chose it),
+// 3 tile-parallel FP64 (np > 64, or np 32/64 where the autotuner chose it),
 // 4 tile-parallel mixed, 5 mixed with BF16 products, 6 tile-parallel mixed
-// with BF16 products.
+// with BF16 products.  Variants of the tune table: np 64 and mixed np 32,
+// 1 tile-parallel; FP64 np 16/32, 1 VALU; FP64 np 32, 2 tile-parallel.
 inline int tuned_factor_kind(btc_handle h, int level) {
     const int np = factor_np(h);
     const bool mixed = is_mixed(h->precision);
     const int tiled = mixed ? (is_bf16(h->precision) ? 6 : 4) : 3;
     if (np > 64) return tiled;
     const int bucket = level > 0 ? 1 : 0;
-    if (np == 64 && tune_variant(BTC_OP_FACTOR, mixed ? (is_bf16(h->precision) ? 2 : 1) : 0, np, bucket) == 1)
-        return tiled;
-    if (mixed) return is_bf16(h->precision) ? 5 : 2;
+    const int v = tune_variant(BTC_OP_FACTOR, mixed ? (is_bf16(h->precision) ? 2 : 1) : 0, np, bucket);
+    if (np == 64 && v == 1) return tiled;
+    if (mixed) return (np == 32 && v == 1) ? tiled : (is_bf16(h->precision) ? 5 : 2);
     if (np < 16) return 0;
-    if (np <= 32 && tune_variant(BTC_OP_FACTOR, 0, np, bucket) == 1) return 0;
+    if (np == 32 && v == 2) return tiled;
+    if (np <= 32 && v == 1) return 0;
     return 1;
 }
 

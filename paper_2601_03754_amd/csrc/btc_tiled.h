@@ -626,6 +626,8 @@ hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int part, bool deferred,
 
 // Per padded size launchers (one translation unit each).
 // mode: 0 FP64, 1 mixed (FP32 products), 2 mixed with BF16 Schur / fill products
+hipError_t launch_factor_tiled32(const Launch<FactorDesc>& p, int mode, int part, bool deferred, int64_t items,
+                                 hipStream_t st);
 hipError_t launch_factor_tiled64(const Launch<FactorDesc>& p, int mode, int part, bool deferred, int64_t items,
                                  hipStream_t st);
 hipError_t launch_factor_tiled96(const Launch<FactorDesc>& p, int mode, int part, bool deferred, int64_t items,

@@ -142,8 +142,9 @@ bool tunable(int op, int32_t prec, int64_t n, int& kind, int& np, int& variants)
     np = btc::padded_block((int)n);
     if (op == BTC_OP_FACTOR) {
         kind = mixed ? (prec == BTC_BF16_IR ? 2 : 1) : 0;
-        variants = 2;
-        return np == 64 || (!mixed && (np == 16 || np == 32));
+        // FP64 np 32: MFMA, VALU, tile-parallel; else two families
+        variants = (!mixed && np == 32) ? 3 : 2;
+        return np == 64 || np == 32 || (!mixed && np == 16);
     }
     if (op == BTC_OP_FORWARD || op == BTC_OP_BACKWARD) {
         kind = mixed ? 1 : 0;

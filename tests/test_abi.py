@@ -178,11 +178,20 @@ def test_tune_table_host_only(lib):
     lib.btc_tune_set(FW, 1, 64, 0, 1)
     assert lib.btc_tune_get(FW, 1, 50, 7) == 1
     lib.btc_tune_set(FW, 1, 64, 0, 0)
-    lib.btc_tune_set(F, 1, 24, 0, 0)           # mixed factor: single variant
+    lib.btc_tune_set(F, 1, 12, 0, 0)           # mixed factor at padded 16: single variant
     with pytest.raises(lib.BtcError) as ei:
-        lib.btc_tune_set(F, 1, 24, 0, 1)
+        lib.btc_tune_set(F, 1, 12, 0, 1)
     assert ei.value.code == lib.BTC_ERR_UNSUPPORTED
+    # padded 32: mixed, 0 or 1 (the tile-parallel step); FP64, 0, 1 or 2
+    lib.btc_tune_set(F, 1, 24, 0, 1)
+    assert lib.btc_tune_get(F, 1, 30, 0) == 1
+    lib.btc_tune_set(F, 1, 24, 0, 0)
+    lib.btc_tune_set(F, 0, 24, 0, 2)
+    assert lib.btc_tune_get(F, 0, 24, 0) == 2
+    lib.btc_tune_set(F, 0, 24, 0, 0)
     L = lib.lib()
+    assert L.btc_tune_set(F, 0, 24, 0, 3) == -5
+    assert L.btc_tune_set(F, 1, 24, 0, 2) == -5
     v = ctypes.c_int32()
     assert L.btc_tune_get(9, 0, 8, 0, ctypes.byref(v)) == -1
     assert L.btc_tune_get(0, 5, 8, 0, ctypes.byref(v)) == -2

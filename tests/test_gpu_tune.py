@@ -40,8 +40,7 @@ def run(btc, p, precision=0):
     return X, blocks
 
 
-@pytest.mark.parametrize("n", [12, 24, 32])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("n,variant", [(12, 0), (12, 1), (24, 0), (24, 1), (24, 2), (32, 0), (32, 1), (32, 2)])
 def test_factor_variants_match_oracle(btc, n, variant):
     p = inputs.block_tridiag(77, n, seed=400 + n, nrhs=2)
     btc.btc_tune_set(0, 0, n, 0, variant)
@@ -101,6 +100,37 @@ def test_factor_families_mixed_across_levels(btc, precision, v0, v1):
     finally:
         btc.btc_tune_set(0, precision, n, 0, 1)
         btc.btc_tune_set(0, precision, n, 1, 1)
+    Ld, Rb, Tb, _ = oracle.factor_nd(p.D, p.E)
+    scale = max(np.abs(Ld).max(), 1.0)
+    ftol = {0: 1e-12, 1: 1e-4, 2: 3e-2}[precision]
+    for g, o in zip(blocks, (Ld, Rb, Tb)):
+        assert np.abs(g - o).max() <= ftol * scale
+    assert oracle.relres(p.D, p.E, X, p.B) <= (1e-12 if precision == 0 else 1e-10)
+    assert info["converged"]
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("v0,v1", [(1, 1), (1, 0), (0, 1)])
+def test_tiled_step_at_32(btc, precision, v0, v1):
+    """Padded size 32 through the tile-parallel level step at every level, at
+    level 0 only, or above level 0 only (FP64 variant 2, mixed variant 1;
+    the one-workgroup kernels elsewhere): oracle accuracy for FP64,
+    refinement target for mixed, no separator update lost or applied twice."""
+    n = 28
+    tiled = 2 if precision == 0 else 1
+    p = inputs.block_tridiag(300, n, seed=900 + 3 * v0 + v1, nrhs=2)
+    before = [btc.btc_tune_get(0, precision, n, lv) for lv in (0, 1)]
+    btc.btc_tune_set(0, precision, n, 0, tiled if v0 else 0)
+    btc.btc_tune_set(0, precision, n, 1, tiled if v1 else 0)
+    try:
+        f = btc.Factor(dev(p.D), dev(p.E), precision=precision)
+        X, info = f.solve(dev(p.B), want_info=True)
+        X = X.cpu().numpy()
+        blocks = f.export()
+        f.close()
+    finally:
+        btc.btc_tune_set(0, precision, n, 0, before[0])
+        btc.btc_tune_set(0, precision, n, 1, before[1])
     Ld, Rb, Tb, _ = oracle.factor_nd(p.D, p.E)
     scale = max(np.abs(Ld).max(), 1.0)
     ftol = {0: 1e-12, 1: 1e-4, 2: 3e-2}[precision]
