@@ -243,7 +243,8 @@ __global__ __launch_bounds__(256) void k_tiled_syrk_deferred(Launch<FactorDesc> 
 
 // ---------------------------------------------------------------------------
 // K2: pivot block factorization and the two triangular solves, one
-// workgroup (four wavefronts) per node.  S_i is staged in LDS and factored
+// workgroup per node (k2_waves wavefronts; twelve for launches of at most
+// one node per compute unit at padded size 96).  S_i is staged in LDS and factored
 // by the blocked Cholesky (which also leaves the inverted 16 x 16 diagonal
 // tiles in LDS); L_ii is stored; then every wavefront solves 16-row strips
 // of R_i = C_{i+s,i} L_ii^{-T} and 16-column strips of T_i = L_ii^{-1} C_{i,i-s}
