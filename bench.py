@@ -697,11 +697,10 @@ def main():
                     help="served workload: requests per step (16 per client by default)")
     ap.add_argument("--sweep-ranges", action="store_true",
                     help="served workload: one server tick per sweep level range instead of per level")
-    ap.add_argument("--lanes", type=int, default=3,
-                    help="served workload: server lanes (0 or 1: one tick over all clients; 2..4: clients "
-                         "split by padded block size class, each lane ticking on its own stream; three "
-                         "lanes keep the server's streams within the four hardware queues HIP opens by "
-                         "default)")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="served workload: server lanes (0: the library's choice, three; 1: one tick over all "
+                         "clients; 2..4: clients split by padded block size class, each lane ticking on its "
+                         "own stream)")
     ap.add_argument("--profile-all", action="store_true",
                     help="served workload: time every kernel group in the timed region too and report each "
                          "group's launches and algorithmic bytes over the whole run (group_totals), to set "
@@ -812,7 +811,7 @@ def main():
                    "clients": len(shapes), "step_requests": args.step_requests, "diag_shift": 4.0,
                    "relres_target": RELRES_TARGET,
                    "server_sweeps": "one tick per level range" if args.sweep_ranges else "one tick per level",
-                   "server_lanes": max(1, args.lanes)},
+                   "server_lanes": mixed["lanes"]},
         "p50_ms": mixed["p50_ms"],
         "p99_ms": mixed["p99_ms"],
         "max_relres_last": mixed["max_relres_last"],

@@ -601,13 +601,13 @@ typedef struct {
     int32_t sweep_ranges;  /* 0: one tick per sweep level; 1: sweeps in the library's level ranges
                               (btc_sweep_ranges), one tick per range (fewer ticks per request,
                               longer ticks: measured 4-6% fewer requests/s on the served mix) */
-    int32_t lanes;         /* 0 or 1: one tick at a time over all clients on the server's stream,
-                              its groups spread over four streams; 2..4: clients split by padded
-                              block size class (<= 16, 32, 64, 96 and 128) into that many lanes,
-                              each with its own ticks on a stream the server creates, so a lane of
-                              small blocks is not held to the pace of the largest; every lane tick
-                              first waits for the work queued on the server's stream so far (the
-                              requests' inputs) */
+    int32_t lanes;         /* 1: one tick at a time over all clients on the server's stream, its
+                              groups spread over four streams; 2..4: clients split by padded block
+                              size class (<= 16, 32, 64, 96 and 128) into that many lanes, each
+                              with its own ticks on a stream the server creates, so a lane of small
+                              blocks is not held to the pace of the largest; every lane tick first
+                              waits for the work queued on the server's stream so far (the
+                              requests' inputs); 0: the library's choice, three lanes */
 } btc_server_options;
 
 typedef struct {

@@ -601,6 +601,7 @@ class Server:
 
     def __init__(self, precision: int = BTC_FP64, hbm_budget: int = 1 << 40, max_refine: int = 0,
                  tol: float = 0.0, max_active: int = 0, stream=None, sweep_ranges: bool = False, lanes: int = 0):
+        # lanes: 0 the library's choice (three), 1 one tick over all clients, 2..4 lanes by block size
         self.stream = _stream(stream)
         opt = btc_server_options(precision, max_refine, tol, hbm_budget, max_active, 1 if sweep_ranges else 0,
                                  lanes)

@@ -153,6 +153,11 @@ struct Lane {
 // it, and one more being enqueued (the runner's two descriptor slots).
 constexpr size_t kLaneDepth = 3;
 constexpr int kSizeClasses = 4;
+// Lanes when the caller leaves the choice to the library: three keep the
+// server's streams, with the caller's, within the four hardware queues HIP
+// opens by default (measured on the served mix: one lane 8 200, two 10 400,
+// three 12 600, four 8 400 requests/s of the mixed path).
+constexpr int kDefaultLanes = 3;
 // Side streams of each lane's runner when there are several lanes: none
 // (measured on the served mix: with lanes, the fork and join of side
 // streams cost more than the concurrency they add, 30-60% fewer requests/s).
@@ -525,7 +530,7 @@ BTC_API int btc_server_create(const btc_server_options* opt, void* stream, btc_s
         s->opt.max_refine = is_bf16(s->opt.precision) ? BTC_DEFAULT_MAX_REFINE_BF16 : BTC_DEFAULT_MAX_REFINE;
     if (s->opt.tol == 0.0) s->opt.tol = BTC_DEFAULT_TOL;
     if (s->opt.max_active == 0) s->opt.max_active = 1 << 20;
-    const int nl = s->opt.lanes <= 1 ? 1 : std::min<int>(s->opt.lanes, kSizeClasses);
+    const int nl = s->opt.lanes == 0 ? kDefaultLanes : s->opt.lanes == 1 ? 1 : std::min<int>(s->opt.lanes, kSizeClasses);
     s->lanes.resize((size_t)nl);
     s->user_st = (hipStream_t)stream;
     int rc = BTC_OK;

@@ -70,11 +70,13 @@ BIG_BLOCKS = (12, 33, 64, 80, 96, 110, 128)
 
 
 @pytest.mark.parametrize("precision,n_choices,ranges,lanes", [
-    (0, None, False, 0), (1, None, False, 0), (0, BIG_BLOCKS, False, 0),
-    (1, BIG_BLOCKS, False, 0), (2, BIG_BLOCKS, False, 0),
-    (0, None, True, 0), (1, BIG_BLOCKS, True, 0), (2, BIG_BLOCKS, True, 0),
+    (0, None, False, 1), (1, None, False, 1), (0, BIG_BLOCKS, False, 1),
+    (1, BIG_BLOCKS, False, 1), (2, BIG_BLOCKS, False, 1),
+    (0, None, True, 1), (1, BIG_BLOCKS, True, 1), (2, BIG_BLOCKS, True, 1),
     # clients split into lanes by block size class, each lane ticking alone
-    (0, BIG_BLOCKS, False, 4), (1, BIG_BLOCKS, False, 4), (1, None, False, 2), (2, BIG_BLOCKS, True, 3)])
+    # (0: the library's default, three lanes)
+    (0, BIG_BLOCKS, False, 4), (1, BIG_BLOCKS, False, 4), (1, None, False, 2), (2, BIG_BLOCKS, True, 3),
+    (1, BIG_BLOCKS, False, 0)])
 def test_results_in_the_mix_equal_results_alone(btc, precision, n_choices, ranges, lanes):
     """Every result equals the same request alone, bit for bit, in both
     server plans (one tick per sweep level range, or per level) and with the
@@ -170,7 +172,7 @@ def test_admission_limits(btc):
     srv.close()
 
 
-@pytest.mark.parametrize("lanes", [0, 4])
+@pytest.mark.parametrize("lanes", [1, 0, 4])
 def test_per_client_order_and_latency_fields(btc, lanes):
     srv, subs, done, *_ = run_trace(btc, 0, budget=1 << 40, seed=3, lanes=lanes)
     by_ticket = {d["ticket"]: d for d in done}
@@ -184,7 +186,7 @@ def test_per_client_order_and_latency_fields(btc, lanes):
     srv.close()
 
 
-@pytest.mark.parametrize("lanes", [0, 3])
+@pytest.mark.parametrize("lanes", [1, 3])
 def test_small_budget_evicts_and_readmits(btc, lanes):
     """A budget that fits about two clients at a time: clients are evicted and
     re-admitted (their solves then refactor with the last matrix), and every
