@@ -171,17 +171,31 @@ __global__ __launch_bounds__(kWave) void k_chain_factor(ChainDesc P) {
 // kernels for these blocks), x to X.
 template <int NP>
 __global__ __launch_bounds__(kWave) void k_chain_solve(ChainDesc P) {
+    constexpr int LD = NP + 1;
+    // the blocks of the current chain step, staged by the whole wavefront
+    // (one round of loads instead of one dependent load per column)
+    __shared__ double sL[NP * LD];
+    __shared__ double sR[NP * LD];
     const int lane = threadIdx.x;
     if (*P.info != kInfoOk) return;
     const int n = P.n, k = P.k, m = P.m;
     const int64_t N = P.N, s = (int64_t)1 << k, M = N >> k;
     const size_t nn = (size_t)n * n, nm = (size_t)n * m;
+    auto stage = [&](const double* L, const double* R) {
+        wave_lds_sync();  // the previous step's reads are done
+        for (int e = lane; e < n * n; e += kWave) {
+            sL[(e / n) * LD + e % n] = L[e];
+            if (R) sR[(e / n) * LD + e % n] = R[e];
+        }
+        wave_lds_sync();
+    };
     for (int q = 0; q < m; ++q) {
         double yprev = 0.0;
         // forward
         for (int64_t j = 1; j <= M; ++j) {
             const int64_t c = chain_block(k, j);
             const int64_t pc = perm_pos(N, level_of(c), c);
+            stage(P.Ld + (size_t)pc * nn, j > 1 ? P.Rb + (size_t)perm_pos(N, level_of(c - s), c - s) * nn : nullptr);
             double a = 0.0;
             if (lane < n) {
                 a = P.B[((size_t)(c - 1) * n + lane) * m + q];
@@ -195,22 +209,18 @@ __global__ __launch_bounds__(kWave) void k_chain_solve(ChainDesc P) {
             }
             if (j > 1) {
                 // - R'_{j-1} y_{j-1}
-                const double* R = P.Rb + (size_t)perm_pos(N, level_of(c - s), c - s) * nn;
                 double v = 0.0;
                 for (int t = 0; t < n; ++t) {
                     const double yt = readlane_d(yprev, t);
-                    if (lane < n) v = fma(R[(size_t)lane * n + t], yt, v);
+                    if (lane < n) v = fma(sR[lane * LD + t], yt, v);
                 }
                 a -= v;
             }
             // y = L^{-1} a, column sweep with the pivot values broadcast
-            const double* L = P.Ld + (size_t)pc * nn;
-            const double lrow_dummy = 0.0;
-            (void)lrow_dummy;
             for (int t = 0; t < n; ++t) {
-                const double yt = readlane_d(a, t) / L[(size_t)t * n + t];
+                const double yt = readlane_d(a, t) / sL[t * LD + t];
                 if (lane == t) a = yt;
-                else if (lane > t && lane < n) a = fma(-L[(size_t)lane * n + t], yt, a);
+                else if (lane > t && lane < n) a = fma(-sL[lane * LD + t], yt, a);
             }
             if (lane < n) P.Y[(size_t)pc * nm + (size_t)lane * m + q] = a;
             yprev = a;
@@ -220,22 +230,21 @@ __global__ __launch_bounds__(kWave) void k_chain_solve(ChainDesc P) {
         for (int64_t j = M; j >= 1; --j) {
             const int64_t c = chain_block(k, j);
             const int64_t pc = perm_pos(N, level_of(c), c);
+            stage(P.Ld + (size_t)pc * nn, j < M ? P.Rb + (size_t)pc * nn : nullptr);
             double a = lane < n ? P.Y[(size_t)pc * nm + (size_t)lane * m + q] : 0.0;
             if (j < M) {
                 // - R'_j^T x_{j+1}
-                const double* R = P.Rb + (size_t)pc * nn;
                 double v = 0.0;
                 for (int t = 0; t < n; ++t) {
                     const double xt = readlane_d(xnext, t);
-                    if (lane < n) v = fma(R[(size_t)t * n + lane], xt, v);
+                    if (lane < n) v = fma(sR[t * LD + lane], xt, v);
                 }
                 a -= v;
             }
-            const double* L = P.Ld + (size_t)pc * nn;
             for (int t = n - 1; t >= 0; --t) {
-                const double xt = readlane_d(a, t) / L[(size_t)t * n + t];
+                const double xt = readlane_d(a, t) / sL[t * LD + t];
                 if (lane == t) a = xt;
-                else if (lane < t) a = fma(-L[(size_t)t * n + lane], xt, a);
+                else if (lane < t) a = fma(-sL[t * LD + lane], xt, a);
             }
             if (lane < n) P.X[((size_t)(c - 1) * n + lane) * m + q] = a;
             xnext = a;
