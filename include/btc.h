@@ -129,8 +129,7 @@ typedef enum {
  *                            permutation, 2 the two-stage variant.  FP64, n
  *                            <= 64, btc_factor / btc_solve only.
  *   BTC_STRATEGY_AUTO        the fastest of these for (N, n) as measured by
- *                            btc_autotune_strategy (else a rule: KSTAGE 0 for
- *                            N <= 32 with n <= 16, MULTISTAGE otherwise).
+ *                            btc_autotune_strategy (else MULTISTAGE).
  *   BTC_STRATEGY_PARTITION   the partition order of Algorithm 2 with
  *                            p = `stages` >= 2 chunks sized by Proposition 1
  *                            (the first chunk N_1 blocks, the others N_k,

@@ -113,15 +113,14 @@ void select_strategy(int64_t N, int64_t n, int32_t prec, int32_t* strategy, int3
             return;
         }
     }
-    // rule before any measurement: a short chain of small blocks is
-    // latency bound, and the sequential order needs one launch per phase
-    if (prec == BTC_FP64 && N <= 32 && n <= 16) {
-        *strategy = BTC_STRATEGY_KSTAGE;
-        *stages = 0;
-    } else {
-        *strategy = BTC_STRATEGY_MULTISTAGE;
-        *stages = 0;
-    }
+    // before any measurement: the multi-stage order (measured on MI355X
+    // the fastest also for the smallest shapes, N = 16, n = 8: levels spread
+    // over compute units beat a chain walked by one wavefront)
+    (void)N;
+    (void)n;
+    (void)prec;
+    *strategy = BTC_STRATEGY_MULTISTAGE;
+    *stages = 0;
 }
 
 void strategy_set(int64_t N, int64_t n, int32_t prec, int32_t strategy, int32_t stages) {

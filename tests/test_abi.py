@@ -301,3 +301,10 @@ def test_bench_sums_lane_profiles_and_host_counters():
     assert merged[0]["launches"] == 3 and merged[0]["ms"] == 4.0 and merged[0]["bytes"] == 6.0
     assert merged[0]["items"] == 14 and merged[0]["flops"] == 8.0
     assert bench.host_stats(f, [1, 2]) == {"run_s": 3.0, "wait_s": 0.75, "calls": 7}
+
+
+def test_auto_strategy_before_any_measurement(lib):
+    """Without a measured choice, BTC_STRATEGY_AUTO takes the multi-stage
+    order (measured the fastest also at the smallest shapes)."""
+    for N, n, prec in ((7, 5, 0), (16, 8, 0), (31, 16, 0), (5000, 64, 1)):
+        assert lib.btc_select_strategy(N, n, prec) == (lib.BTC_STRATEGY_MULTISTAGE, 0)
