@@ -175,6 +175,10 @@ def test_admission_limits(btc):
 @pytest.mark.parametrize("lanes", [1, 0, 4])
 def test_per_client_order_and_latency_fields(btc, lanes):
     srv, subs, done, *_ = run_trace(btc, 0, budget=1 << 40, seed=3, lanes=lanes)
+    # one runner per lane (0: the library's three); ticks counted over all lanes
+    assert len(srv.runner_handles()) == (3 if lanes == 0 else lanes)
+    hs = srv.host_stats()
+    assert hs["ticks"] > 0 and hs["wait_s"] >= 0.0
     by_ticket = {d["ticket"]: d for d in done}
     last = {}
     for t, c, *_ in subs:
