@@ -440,16 +440,18 @@ __global__ __launch_bounds__(NW * kWave, (NB * NW + 3) / 4) void k_tiled_potrf_t
 // K4: tile number ty < NTRI32 of a node: lower tile of S_{i+s} -= R R^T (eagerly also
 // - T'^T T' with T' = T_{i+2s}, the separator's other contribution); else
 // fill tile -R T (row-major over the W32 x W32 tiles).  The panels of a
-// product pass through LDS in KS ranges of the k index (FP64: two, so the
-// panels take half the LDS and more workgroups share a compute unit), the
-// next range's loads in flight while the current one is on the matrix
-// cores; the accumulation order over k is the same for any KS.
+// product pass through LDS in ranges of 32 along the k index (staged
+// panels then hold few registers and little LDS, so more workgroups share
+// a compute unit: at padded size 96, five FP64 or seven FP32 wavefronts
+// per SIMD against four and six with whole panels), the next range's loads
+// in flight while the current one is on the matrix cores; the accumulation
+// order over k is the same for any number of ranges.
 template <int NP, bool MIXED, bool BF16>
 __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     using Pr = Prec<MIXED>;
     using F = typename Pr::F;
     using Cfg = TiledCfg<NP>;
-    constexpr int KS = MIXED ? 1 : 2;
+    constexpr int KS = NP / 32;
     constexpr int KH = NP / KS;
     static_assert(KH % 8 == 0, "whole k steps per range");
     constexpr int LDR = KH + 1;  // row panel [32][KH]
@@ -571,10 +573,13 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
         __syncthreads();
         products(ph);
     };
-    if (nph > 1) later(1, g1a, g1b, g0a, g0b);
-    if constexpr (KS > 1) {
-        if (nph > 2) later(2, g0a, g0b, g1a, g1b);
-        if (nph > 3) later(3, g1a, g1b, g0a, g0b);
+#pragma unroll
+    for (int ph = 1; ph < 2 * KS; ++ph) {
+        if (ph >= nph) break;
+        if (ph & 1)
+            later(ph, g1a, g1b, g0a, g0b);
+        else
+            later(ph, g0a, g0b, g1a, g1b);
     }
     if (idle) return;
     if (sep) {
