@@ -442,8 +442,8 @@ __global__ __launch_bounds__(NW * kWave, (NB * NW + 3) / 4) void k_tiled_potrf_t
 // fill tile -R T (row-major over the W32 x W32 tiles).  The panels of a
 // product pass through LDS in ranges of 32 along the k index (staged
 // panels then hold few registers and little LDS, so more workgroups share
-// a compute unit: at padded size 96, five FP64 or seven FP32 wavefronts
-// per SIMD against four and six with whole panels), the next range's loads
+// a compute unit: at padded size 128, five FP64 or seven FP32 wavefronts
+// per SIMD against three and four with halves or whole panels), the next range's loads
 // in flight while the current one is on the matrix cores; the accumulation
 // order over k is the same for any number of ranges.
 template <int NP, bool MIXED, bool BF16>
@@ -548,11 +548,11 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
     };
     // phase 0's panels first, then the Schur complement entries this thread
     // updates and the next phase's panels load while phase 0 computes; each
-    // later phase stages its panels once the previous one has read them (the
-    // panel register sets alternate between phases)
-    Pan g0a, g0b, g1a, g1b;
-    load_phase(0, g0a, g0b);
-    stage(0, g0a, g0b);
+    // later phase stages its panels once the previous one has read them, and
+    // one register set carries every phase (a set is free again once staged)
+    Pan ga, gb;
+    load_phase(0, ga, gb);
+    stage(0, ga, gb);
     double sv[4] = {0.0, 0.0, 0.0, 0.0};
     if (sep) {
         const double* src = (lvl == 0) ? P.A_diag + (size_t)(d.i + d.s - 1) * d.nn : P.Ld + (size_t)d.pr * d.nn;
@@ -563,23 +563,17 @@ __global__ __launch_bounds__(256) void k_tiled_update(Launch<FactorDesc> L) {
             buf_ld(sv[v], rsrc, elem_off<double>(r, c, n, !idle && r < n && c < n));
         }
     }
-    if (nph > 1) load_phase(1, g1a, g1b);
+    if (nph > 1) load_phase(1, ga, gb);
     __syncthreads();
     products(0);
-    auto later = [&](int ph, const Pan& ca, const Pan& cb, Pan& na, Pan& nb) {
-        __syncthreads();  // the previous phase's products have read the panels
-        stage(ph, ca, cb);
-        if (ph + 1 < nph) load_phase(ph + 1, na, nb);
-        __syncthreads();
-        products(ph);
-    };
 #pragma unroll
     for (int ph = 1; ph < 2 * KS; ++ph) {
         if (ph >= nph) break;
-        if (ph & 1)
-            later(ph, g1a, g1b, g0a, g0b);
-        else
-            later(ph, g0a, g0b, g1a, g1b);
+        __syncthreads();  // the previous phase's products have read the panels
+        stage(ph, ga, gb);
+        if (ph + 1 < nph) load_phase(ph + 1, ga, gb);
+        __syncthreads();
+        products(ph);
     }
     if (idle) return;
     if (sep) {
