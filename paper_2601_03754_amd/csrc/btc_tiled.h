@@ -267,12 +267,15 @@ template <int NP>
 constexpr int k2_blocks() { return NP <= 64 ? 4 : NP <= 96 ? 2 : 1; }
 
 // A launch of at most one node per compute unit is bound by one node's
-// latency, not by the throughput of nodes sharing a unit: at padded size 96
-// it takes twelve wavefronts, one compute unit each, so that all twelve
-// strips are solved in one round (measured at N = 4096: 38 against 43 us per
-// launch of the upper levels, FP64; 44 against 53 mixed).
+// latency, not by the throughput of nodes sharing a unit: it takes one
+// wavefront per strip, so that all strips are solved in one round (padded
+// size 96: twelve wavefronts, measured at N = 4096: 38 against 43 us per
+// launch of the upper levels, FP64; 44 against 53 mixed; padded size 64:
+// eight).
 constexpr int kK2LatencyWaves = 12;
 constexpr int64_t kK2LatencyItems = 256;
+template <int NP>
+constexpr int k2_latency_waves() { return NP == 96 ? kK2LatencyWaves : NP == 64 ? 8 : 0; }
 
 template <int NP, bool MIXED, int NW = k2_waves<NP>(), int NB = k2_blocks<NP>()>
 __global__ __launch_bounds__(NW * kWave, (NB * NW + 3) / 4) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
@@ -606,10 +609,10 @@ hipError_t launch_tiled_np(const Launch<FactorDesc>& p, int part, bool deferred,
         hipLaunchKernelGGL((k_tiled_syrk_deferred<NP, MIXED, BF16>), dim3(g * 2 * Cfg::NTRI32), dim3(256), 0, st, p);
     if (part == 0 || part == 2) {
         bool done = false;
-        if constexpr (NP == 96) {
+        constexpr int LW = k2_latency_waves<NP>();
+        if constexpr (LW > 0) {
             if (items <= kK2LatencyItems) {
-                hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED, kK2LatencyWaves, 1>), dim3(g),
-                                   dim3(kK2LatencyWaves * kWave), 0, st, p);
+                hipLaunchKernelGGL((k_tiled_potrf_trsm<NP, MIXED, LW, 1>), dim3(g), dim3(LW * kWave), 0, st, p);
                 done = true;
             }
         }
