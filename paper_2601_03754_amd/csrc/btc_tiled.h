@@ -275,7 +275,7 @@ constexpr int k2_blocks() { return NP <= 64 ? 4 : NP <= 96 ? 2 : 1; }
 constexpr int kK2LatencyWaves = 12;
 constexpr int64_t kK2LatencyItems = 256;
 template <int NP>
-constexpr int k2_latency_waves() { return NP == 96 ? kK2LatencyWaves : NP == 64 ? 8 : 0; }
+constexpr int k2_latency_waves() { return NP == 128 ? 16 : NP == 96 ? kK2LatencyWaves : NP == 64 ? 8 : 0; }
 
 template <int NP, bool MIXED, int NW = k2_waves<NP>(), int NB = k2_blocks<NP>()>
 __global__ __launch_bounds__(NW * kWave, (NB * NW + 3) / 4) void k_tiled_potrf_trsm(Launch<FactorDesc> L) {
